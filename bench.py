@@ -1,0 +1,136 @@
+#!/usr/bin/env python3
+"""HAVSampler throughput on one MI355X.
+
+Workload: the scene-scale cloud (1,048,576 points: 40 % on 6 planes, 60 % in 200
+Gaussian blobs, 50 x 50 x 10 m, shuffled) sampled to 262,144 points with the default
+2-layer sampler. One step = one hav_sample call (bounding box, adaptive voxel search of
+both layers, centre-closest selection, exact-M trim/pad, masking, ascending output).
+Inputs are resident in HBM before the timed region; the timed region is bracketed by
+torch.cuda.synchronize() on both sides.
+
+Prints one JSON line: input Mpoints/s, the roofline of the dominant kernel and the CPU
+oracle timed on this host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def algorithmic_bytes(n: int, M: int, info: dict) -> float:
+    """Bytes the method streams for one stage: the bounding-box pass reads the cloud
+    once (12 B/pt); every voxel-counter evaluation and the selection pass of layer l
+    read the coordinates of the points still unsampled (12 B/pt) and, from layer 2 on,
+    the 1-byte sampled mask of every point; the output pass reads the mask and writes
+    one int32 per pick."""
+    total = 12.0 * n
+    remaining = n
+    for L in range(info["layers"]):
+        passes = info["evals"][L] + 1
+        total += passes * (12.0 * remaining + (n if L > 0 else 0))
+        remaining -= info["m"][L]
+    total += 2.0 * n + 4.0 * M
+    return total
+
+
+def cpu_baseline(x, M: int, budget_s: float) -> dict:
+    import oracle
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        st, _, _ = oracle.sample(x, M)
+        assert st == 0
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 20:
+            break
+    return {"value": round(x.shape[0] * reps / el / 1e6, 4), "unit": "Mpoints/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{reps} full runs of the same 1,048,576 -> 262,144 stage, single thread"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the sampler works on "
+              "one cloud per GPU and this build has no multi-GPU path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2305_14306_amd import hav, synth
+
+    x = synth.scene_planes_blobs(1 << 20, seed=3)
+    N = x.shape[0]
+    M = N // 4
+    dev = torch.device("cuda:0")
+    xd = torch.from_numpy(x).to(dev)
+    sampler = hav.Sampler(dev)
+    out = torch.empty(M, dtype=torch.int32, device=dev)
+    p = hav.params()
+    print(f"bench: N={N} M={M} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+
+    _, info = sampler.sample(xd, M, p, out=out, with_info=True)
+    for _ in range(args.warmup):
+        sampler.sample(xd, M, p, out=out)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        sampler.sample(xd, M, p, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    print(f"bench: {ms:.4f} ms/step (wall {wall * 1e3 / args.steps:.4f})", file=sys.stderr, flush=True)
+
+    value = N / (ms * 1e-3) / 1e6
+    b_alg = algorithmic_bytes(N, M, info)
+    achieved = b_alg / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "hav_sample (whole call)", "bytes_per_launch": b_alg}
+    result = {
+        "metric": "input Mpoints/s (1M->250k)",
+        "value": round(value, 3),
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "scene cloud 1,048,576 pts (6 planes + 200 blobs, shuffled) -> "
+                               "262,144 (2 layers, sigma 0.05, t_max 20)",
+                   "N": N, "M": M, "evals": info["evals"], "count": info["count"]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(x, M, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

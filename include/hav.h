@@ -1,0 +1,123 @@
+/* hav.h — C ABI of the HAVSampler library (libhav.so, HIP for gfx950).
+ *
+ * HAVSampler is the hierarchical adaptive voxel-guided point sampler of arXiv
+ * 2305.14306. A sampler S maps a cloud of n points to a subset of exactly m of them
+ * (Sec. 3.1, problem formulation); this library returns the subset as indices, so
+ * the sampled points are xyz[idx].
+ *
+ * Conventions for every entry point:
+ *   - All array pointers are DEVICE pointers owned by the caller, unless the name
+ *     says _host. The library never allocates, frees or keeps them.
+ *   - `stream` is a hipStream_t (NULL = the null stream). Calls only enqueue work on
+ *     it and return without synchronising; results (idx, info) are valid once the
+ *     stream reaches that point.
+ *   - Host-checkable argument errors return a status at once and enqueue nothing.
+ *     Data-dependent errors (non-finite coordinates, a frame the 21-bit voxel
+ *     coordinate cannot hold) are found on the device and reported in info->status;
+ *     idx is then unspecified.
+ *   - Results depend only on (xyz, M, params): never on the stream, the workspace
+ *     address or the launch shape. Two calls in flight at once need two workspaces.
+ */
+#ifndef HAV_H_
+#define HAV_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HAV_ABI_VERSION 1
+#define HAV_MAX_LAYERS 8
+
+typedef enum {
+  HAV_OK = 0,
+  HAV_ERR_INVALID_ARG = 1,         /* a host-checkable argument is out of range */
+  HAV_ERR_WORKSPACE_TOO_SMALL = 2, /* ws_bytes < the matching *_workspace_size() */
+  HAV_ERR_OUT_OF_MEMORY = 3,       /* reserved for entry points that allocate */
+  HAV_ERR_UNSUPPORTED = 4,         /* device: extent > 2^100, or a fixed voxel too small
+                                      for 21-bit voxel coordinates */
+  HAV_ERR_NONFINITE = 5,           /* device: a coordinate is NaN or infinite */
+  HAV_ERR_HIP = 6                  /* a HIP launch failed */
+} hav_status_t;
+
+/* flags */
+#define HAV_FIXED_VOXEL 1u /* use fixed_voxel[] instead of the adaptive search
+                              (the "Fix" setting of the ablation, Sec. 4.5 Table 6) */
+
+/* Sampling parameters. Start from hav_params_default(). */
+typedef struct {
+  int32_t abi_version; /* must be HAV_ABI_VERSION */
+  int32_t layers;      /* k, hierarchical layers, 1..8; default 2 (Sec. 4.1) */
+  int32_t layer_ratio; /* m_l = ratio * m_{l-1} (Sec. 3.4, Eq. 3), 2..16; default 4 */
+  int32_t t_max;       /* max voxel-counter evaluations per layer (Sec. 3.3), 1..20;
+                          default 20 (Sec. 4.1) */
+  double sigma;        /* tolerance: accept counts in [m, floor(m (1+sigma))] (Sec. 3.3),
+                          0..16; default 0.05 (Sec. 4.1) */
+  float aspect[3];     /* voxel shape v = s * aspect (Sec. 3.2, v = (vx, vy, vz)),
+                          each in [2^-16, 2^16]; default {1,1,1} */
+  uint32_t flags;      /* HAV_FIXED_VOXEL or 0 */
+  float fixed_voxel[3];/* used iff HAV_FIXED_VOXEL; each in [2^-100, 2^100] */
+} hav_params_t;
+
+/* Per-call report, written by the device into caller memory (info_dev). */
+typedef struct {
+  int32_t status;   /* hav_status_t of the device-side checks */
+  int32_t layers;   /* layers that ran (those with m_l > 0) */
+  float hi0;        /* search bracket: smallest power of two >= the largest
+                       extent/aspect of the cloud (floored at 2^-64) */
+  float mn[3];      /* grid origin = per-axis minimum of the cloud */
+  float mx[3];      /* per-axis maximum */
+  int32_t m[HAV_MAX_LAYERS];        /* points sampled by each layer */
+  float s[HAV_MAX_LAYERS];          /* chosen voxel scale (0 with HAV_FIXED_VOXEL) */
+  int32_t evals[HAV_MAX_LAYERS];    /* voxel-counter evaluations made */
+  int32_t count[HAV_MAX_LAYERS];    /* non-empty voxels at the chosen size */
+  int32_t accepted[HAV_MAX_LAYERS]; /* 1 if the count landed in the tolerance window */
+  int32_t trimmed[HAV_MAX_LAYERS];  /* voxels dropped to reach m exactly */
+  int32_t padded[HAV_MAX_LAYERS];   /* extra points added to reach m exactly */
+} hav_info_t;
+
+/* Defaults of Sec. 4.1 (2 layers, sigma 0.05, t_max 20) and Sec. 3.4 (ratio 4). */
+hav_params_t hav_params_default(void);
+
+/* Static string for a status code. */
+const char* hav_status_string(hav_status_t status);
+
+/* Bytes of device workspace hav_sample needs for N points (host-only, no GPU call).
+ * Returns 0 if the arguments are invalid. The workspace needs no initialisation. */
+size_t hav_workspace_size(int64_t N, int64_t M, const hav_params_t* params);
+
+/* Sample exactly M of the N points (Sec. 3, Eq. 3 with AVS of Sec. 3.3 and the
+ * centre-closest selection of Sec. 3.2).
+ *   xyz    [N][3] float32, row-major (x, y, z per point), device.
+ *   N, M   1 <= M <= N < 2^31.
+ *   idx    [M] int32, device: the picked indices in ascending order.
+ *   ws     device workspace of ws_bytes >= hav_workspace_size(N, M, params),
+ *          256-byte aligned; contents are scratch.
+ *   info_dev  device hav_info_t or NULL.
+ * M == N gives 0..N-1. Returns HAV_OK once the work is enqueued. */
+hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params_t* params,
+                        int32_t* idx, void* ws, size_t ws_bytes, hav_info_t* info_dev,
+                        void* stream);
+
+/* Workspace for hav_sample_chain with stage sizes M_host[0..n_stages-1]. */
+size_t hav_chain_workspace_size(int64_t N, const int64_t* M_host, int32_t n_stages,
+                                const hav_params_t* params);
+
+/* Chained down-sampling (the stage-wise "progressively downsamples" use of Sec. 3.1;
+ * Fig. 7 times three chained steps): stage j samples M_host[j] points of the cloud
+ * stage j-1 produced, i.e. of xyz[idx_{j-1}] taken in ascending index order.
+ *   M_host  host array, N >= M_host[0] >= M_host[1] >= ... >= 1.
+ *   idx_concat  [sum M_host] int32, device: stage j's picks as ORIGINAL indices
+ *               (ascending), stage after stage.
+ *   info_dev  device hav_info_t[n_stages] or NULL. */
+hav_status_t hav_sample_chain(const float* xyz, int64_t N, const int64_t* M_host,
+                              int32_t n_stages, const hav_params_t* params, int32_t* idx_concat,
+                              void* ws, size_t ws_bytes, hav_info_t* info_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HAV_H_ */

@@ -1,0 +1,239 @@
+"""ctypes binding of libhav.so (include/hav.h). Argument marshalling only.
+
+PyTorch supplies device memory and the current stream; every step of the sampler runs
+in the library's HIP kernels. If the library has not been built this module raises on
+first use: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhav.so")
+
+ABI_VERSION = 1
+MAX_LAYERS = 8
+FIXED_VOXEL = 1
+
+OK, ERR_INVALID_ARG, ERR_WORKSPACE_TOO_SMALL, ERR_OUT_OF_MEMORY, ERR_UNSUPPORTED, \
+    ERR_NONFINITE, ERR_HIP = range(7)
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32),
+        ("layers", C.c_int32),
+        ("layer_ratio", C.c_int32),
+        ("t_max", C.c_int32),
+        ("sigma", C.c_double),
+        ("aspect", C.c_float * 3),
+        ("flags", C.c_uint32),
+        ("fixed_voxel", C.c_float * 3),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32),
+        ("layers", C.c_int32),
+        ("hi0", C.c_float),
+        ("mn", C.c_float * 3),
+        ("mx", C.c_float * 3),
+        ("m", C.c_int32 * MAX_LAYERS),
+        ("s", C.c_float * MAX_LAYERS),
+        ("evals", C.c_int32 * MAX_LAYERS),
+        ("count", C.c_int32 * MAX_LAYERS),
+        ("accepted", C.c_int32 * MAX_LAYERS),
+        ("trimmed", C.c_int32 * MAX_LAYERS),
+        ("padded", C.c_int32 * MAX_LAYERS),
+    ]
+
+    def as_dict(self) -> dict:
+        L = self.layers
+        return {
+            "status": self.status,
+            "layers": L,
+            "hi0": self.hi0,
+            "mn": list(self.mn),
+            "m": list(self.m)[:L],
+            "s": list(self.s)[:L],
+            "evals": list(self.evals)[:L],
+            "count": list(self.count)[:L],
+            "accepted": list(self.accepted)[:L],
+            "trimmed": list(self.trimmed)[:L],
+            "padded": list(self.padded)[:L],
+        }
+
+
+class HavError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})" if what else status_string(status))
+
+
+_lib = None
+
+
+def lib():
+    """Load libhav.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2305_14306_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64p, i32p = C.c_void_p, C.POINTER(C.c_int64), C.c_void_p
+        L.hav_params_default.restype = Params
+        L.hav_params_default.argtypes = []
+        L.hav_status_string.restype = C.c_char_p
+        L.hav_status_string.argtypes = [C.c_int]
+        L.hav_workspace_size.restype = C.c_size_t
+        L.hav_workspace_size.argtypes = [C.c_int64, C.c_int64, C.POINTER(Params)]
+        L.hav_sample.restype = C.c_int
+        L.hav_sample.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(Params), i32p, vp, C.c_size_t,
+                                 vp, vp]
+        L.hav_chain_workspace_size.restype = C.c_size_t
+        L.hav_chain_workspace_size.argtypes = [C.c_int64, i64p, C.c_int32, C.POINTER(Params)]
+        L.hav_sample_chain.restype = C.c_int
+        L.hav_sample_chain.argtypes = [vp, C.c_int64, i64p, C.c_int32, C.POINTER(Params), i32p, vp,
+                                       C.c_size_t, vp, vp]
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().hav_status_string(int(status)).decode()
+
+
+def params(layers=2, layer_ratio=4, t_max=20, sigma=0.05, aspect=(1.0, 1.0, 1.0),
+           fixed_voxel=None) -> Params:
+    p = lib().hav_params_default()
+    p.layers, p.layer_ratio, p.t_max, p.sigma = layers, layer_ratio, t_max, sigma
+    for a in range(3):
+        p.aspect[a] = aspect[a]
+    if fixed_voxel is not None:
+        p.flags |= FIXED_VOXEL
+        fv = fixed_voxel if hasattr(fixed_voxel, "__len__") else (fixed_voxel,) * 3
+        for a in range(3):
+            p.fixed_voxel[a] = fv[a]
+    return p
+
+
+def workspace_size(N: int, M: int, p: Params | None = None) -> int:
+    p = p if p is not None else params()
+    return int(lib().hav_workspace_size(int(N), int(M), C.byref(p)))
+
+
+def chain_workspace_size(N: int, Ms, p: Params | None = None) -> int:
+    p = p if p is not None else params()
+    arr = (C.c_int64 * len(Ms))(*[int(m) for m in Ms])
+    return int(lib().hav_chain_workspace_size(int(N), arr, len(Ms), C.byref(p)))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_xyz(xyz):
+    torch = _torch()
+    if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda and xyz.dtype == torch.float32
+            and xyz.dim() == 2 and xyz.shape[1] == 3 and xyz.is_contiguous()):
+        raise ValueError("xyz must be a contiguous float32 CUDA tensor of shape [N, 3]")
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def read_info(info_dev, n: int = 1):
+    """Copy device hav_info_t records to the host (synchronises with the stream)."""
+    raw = info_dev.cpu().numpy().tobytes()
+    size = C.sizeof(Info)
+    return [Info.from_buffer_copy(raw[j * size:(j + 1) * size]).as_dict() for j in range(n)]
+
+
+class Sampler:
+    """Reusable caller-side state: a device workspace grown on demand and an info
+    record, so repeated calls on one stream allocate nothing."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.ws = None
+        self.info = None
+
+    def _workspace(self, nbytes: int):
+        torch = _torch()
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.ws
+
+    def _info(self, n: int):
+        torch = _torch()
+        if self.info is None or self.info.numel() < n * C.sizeof(Info):
+            self.info = torch.zeros(n * C.sizeof(Info), dtype=torch.uint8, device=self.device)
+        return self.info
+
+    def sample(self, xyz, M: int, p: Params | None = None, out=None, with_info: bool = False,
+               stream=None):
+        torch = _torch()
+        _check_xyz(xyz)
+        p = p if p is not None else params()
+        N = xyz.shape[0]
+        nbytes = workspace_size(N, M, p)
+        if nbytes == 0:
+            raise HavError(ERR_INVALID_ARG, "hav_workspace_size")
+        ws = self._workspace(nbytes)
+        idx = out if out is not None else torch.empty(int(M), dtype=torch.int32, device=xyz.device)
+        info = self._info(1) if with_info else None
+        st = lib().hav_sample(C.c_void_p(xyz.data_ptr()), N, int(M), C.byref(p),
+                              C.c_void_p(idx.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                              C.c_void_p(info.data_ptr()) if info is not None else None,
+                              _stream_ptr(stream))
+        if st != OK:
+            raise HavError(st, "hav_sample")
+        if with_info:
+            return idx, read_info(info[:C.sizeof(Info)])[0]
+        return idx
+
+    def chain(self, xyz, Ms, p: Params | None = None, out=None, with_info: bool = False,
+              stream=None):
+        torch = _torch()
+        _check_xyz(xyz)
+        p = p if p is not None else params()
+        N = xyz.shape[0]
+        nbytes = chain_workspace_size(N, Ms, p)
+        if nbytes == 0:
+            raise HavError(ERR_INVALID_ARG, "hav_chain_workspace_size")
+        ws = self._workspace(nbytes)
+        total = int(sum(int(m) for m in Ms))
+        idx = out if out is not None else torch.empty(total, dtype=torch.int32, device=xyz.device)
+        info = self._info(len(Ms)) if with_info else None
+        arr = (C.c_int64 * len(Ms))(*[int(m) for m in Ms])
+        st = lib().hav_sample_chain(C.c_void_p(xyz.data_ptr()), N, arr, len(Ms), C.byref(p),
+                                    C.c_void_p(idx.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                    ws.numel(),
+                                    C.c_void_p(info.data_ptr()) if info is not None else None,
+                                    _stream_ptr(stream))
+        if st != OK:
+            raise HavError(st, "hav_sample_chain")
+        parts, off = [], 0
+        for m in Ms:
+            parts.append(idx[off:off + int(m)])
+            off += int(m)
+        if with_info:
+            return parts, read_info(info[:len(Ms) * C.sizeof(Info)], len(Ms))
+        return parts
+
+
+def sample(xyz, M: int, p: Params | None = None, with_info: bool = False):
+    """One-shot hav_sample on the current stream: returns idx [M] int32 (ascending)."""
+    return Sampler(xyz.device).sample(xyz, M, p, with_info=with_info)
+
+
+def chain(xyz, Ms, p: Params | None = None, with_info: bool = False):
+    """One-shot hav_sample_chain: returns one original-index tensor per stage."""
+    return Sampler(xyz.device).chain(xyz, Ms, p, with_info=with_info)

@@ -1,0 +1,147 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the header
+declares, its struct layouts match the Python binding, and host-checkable argument
+errors are rejected before anything is enqueued."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER_DIR = os.path.join(ROOT, "include")
+
+
+def _declared_functions():
+    names = []
+    for fn in sorted(os.listdir(HEADER_DIR)):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(HEADER_DIR, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"#.*", "", text)
+        for m in re.finditer(r"\b(hav_\w+)\s*\(", text):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def hav():
+    from paper_2305_14306_amd import hav as h
+    h.lib()
+    return h
+
+
+def test_exports_every_declared_symbol(hav):
+    names = _declared_functions()
+    assert "hav_sample" in names and "hav_sample_chain" in names
+    for n in names:
+        assert hasattr(hav.lib(), n), n
+
+
+def test_struct_layout_matches_header(hav, tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "hav.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\n", sizeof(hav_params_t), offsetof(hav_params_t, sigma),
+         offsetof(hav_params_t, flags), offsetof(hav_params_t, fixed_voxel), sizeof(hav_info_t));
+  printf("%zu %zu %zu\n", offsetof(hav_info_t, m), offsetof(hav_info_t, count),
+         offsetof(hav_info_t, padded));
+  return 0;
+}
+''')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", HEADER_DIR, "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    P, I = hav.Params, hav.Info
+    want = [C.sizeof(P), P.sigma.offset, P.flags.offset, P.fixed_voxel.offset, C.sizeof(I),
+            I.m.offset, I.count.offset, I.padded.offset]
+    assert [int(x) for x in out] == want
+
+
+def test_params_default(hav):
+    p = hav.lib().hav_params_default()
+    assert p.abi_version == hav.ABI_VERSION
+    assert (p.layers, p.layer_ratio, p.t_max, p.flags) == (2, 4, 20, 0)
+    assert p.sigma == 0.05 and list(p.aspect) == [1.0, 1.0, 1.0]
+
+
+def test_status_strings(hav):
+    for s in range(7):
+        assert isinstance(hav.status_string(s), str) and hav.status_string(s)
+    assert hav.status_string(99) == "unknown status"
+
+
+def test_workspace_size(hav):
+    p = hav.params()
+    a = hav.workspace_size(16384, 4096, p)
+    b = hav.workspace_size(1 << 20, 1 << 18, p)
+    assert 0 < a < b
+    assert hav.workspace_size(0, 1, p) == 0
+    assert hav.workspace_size(10, 11, p) == 0
+    assert hav.workspace_size(10, 0, p) == 0
+    assert hav.workspace_size(1 << 31, 10, p) == 0
+    bad = hav.params(layers=9)
+    assert hav.workspace_size(100, 10, bad) == 0
+    assert hav.chain_workspace_size(1000, [500, 100], p) > hav.workspace_size(1000, 500, p)
+    assert hav.chain_workspace_size(1000, [100, 500], p) == 0  # stages must shrink
+
+
+def _call(hav, xyz=0x10000, N=100, M=10, p=None, idx=0x20000, ws=0x30000, ws_bytes=1 << 30,
+          info=None):
+    p = p if p is not None else hav.params()
+    return hav.lib().hav_sample(C.c_void_p(xyz), N, M, C.byref(p) if p is not False else None,
+                                C.c_void_p(idx), C.c_void_p(ws), ws_bytes, info, None)
+
+
+def test_host_rejects_bad_arguments(hav):
+    # every case below must be rejected on the host: nothing is launched, so the
+    # fake device addresses are never touched
+    E = hav.ERR_INVALID_ARG
+    assert _call(hav, xyz=0) == E
+    assert _call(hav, idx=0) == E
+    assert _call(hav, ws=0) == E
+    assert _call(hav, M=0) == E
+    assert _call(hav, M=101) == E
+    assert _call(hav, N=0, M=0) == E
+    assert _call(hav, N=1 << 31, M=5) == E
+    assert _call(hav, ws=0x30010) == E  # misaligned workspace
+    assert _call(hav, p=False) == E
+    for kw in (dict(layers=0), dict(layers=9), dict(layer_ratio=1), dict(layer_ratio=17),
+               dict(t_max=0), dict(t_max=21), dict(sigma=-1.0), dict(sigma=float("nan")),
+               dict(aspect=(1.0, 0.0, 1.0)), dict(aspect=(1.0, float("inf"), 1.0)),
+               dict(fixed_voxel=0.0), dict(fixed_voxel=float("nan"))):
+        assert _call(hav, p=hav.params(**kw)) == E, kw
+    p = hav.params()
+    p.abi_version = 2
+    assert _call(hav, p=p) == E
+    p = hav.params()
+    p.flags = 2
+    assert _call(hav, p=p) == E
+    need = hav.workspace_size(100, 10)
+    assert _call(hav, ws_bytes=need - 1) == hav.ERR_WORKSPACE_TOO_SMALL
+
+
+def test_chain_host_rejects_bad_arguments(hav):
+    p = hav.params()
+    L = hav.lib()
+
+    def call(Ms, ws_bytes=1 << 30, N=1000):
+        arr = (C.c_int64 * len(Ms))(*Ms)
+        return L.hav_sample_chain(C.c_void_p(0x10000), N, arr, len(Ms), C.byref(p),
+                                  C.c_void_p(0x20000), C.c_void_p(0x30000), ws_bytes, None, None)
+
+    assert call([2000]) == hav.ERR_INVALID_ARG
+    assert call([500, 600]) == hav.ERR_INVALID_ARG
+    assert call([500, 0]) == hav.ERR_INVALID_ARG
+    assert call([500, 100], ws_bytes=10) == hav.ERR_WORKSPACE_TOO_SMALL
+
+
+def test_binding_refuses_cpu_tensors(hav):
+    import torch
+    with pytest.raises(ValueError):
+        hav.sample(torch.zeros(10, 3), 5)

@@ -1,0 +1,183 @@
+"""GPU parity: libhav.so against the CPU oracle, bit for bit.
+
+Sampling is index selection, so the bar is exact: the same M indices, and the same
+per-layer search record (chosen scale, evaluations, voxel count, trim/pad), on the same
+seeded inputs. Sizes span several scan tiles and hash-table blocks and end in ragged
+tails; the full-size configurations run exactly as the bench launches them.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2305_14306_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_14306_amd import hav
+    hav.lib()
+    return hav
+
+
+def _note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _oracle_params(orc, p):
+    fv = tuple(p.fixed_voxel) if p.flags & 1 else None
+    return orc.params(layers=p.layers, layer_ratio=p.layer_ratio, t_max=p.t_max, sigma=p.sigma,
+                      aspect=tuple(p.aspect), fixed_voxel=fv)
+
+
+def _check(gpu, orc, x, M, p=None, label=""):
+    p = p if p is not None else gpu.params()
+    _note(f"case {label} N={x.shape[0]} M={M}")
+    st, want, winfo = orc.sample(x, M, _oracle_params(orc, p))
+    assert st == 0
+    idx, info = gpu.Sampler().sample(_to_dev(x), M, p, with_info=True)
+    got = idx.cpu().numpy()
+    assert info["status"] == 0
+    assert info == winfo, (info, winfo)
+    assert np.array_equal(got, want)
+    return got, info
+
+
+# ------------------------------------------------------------------ closed-form cases
+
+@pytest.mark.parametrize("layers,M", [(1, 64), (1, 8), (1, 512), (2, 60), (2, 100), (3, 300),
+                                      (2, 1), (2, 511)])
+def test_lattice(gpu, orc, layers, M):
+    _check(gpu, orc, synth.lattice(8), M, gpu.params(layers=layers), "lattice")
+
+
+def test_ties_lowest_index(gpu, orc):
+    pts = [(0.0, 0.0, 0.0)]
+    for k in range(64):
+        a, b = (2 * k + 0.5, 1.0, 1.0), (2 * k + 1.5, 1.0, 1.0)
+        pts += [a, b] if k % 2 == 0 else [b, a]
+    x = np.array(pts, dtype=np.float32)
+    _check(gpu, orc, x, 64, gpu.params(layers=1, fixed_voxel=2.0), "ties")
+    # subnormal squared distances must not be flushed to zero (they would tie):
+    # voxel 2^-60, centre 2^-61; point 1 is 2^-70 + 2^-80 off centre (d2 just above
+    # 2^-140, subnormal), point 2 is 2^-70 off (d2 = 2^-140): point 2 must win
+    c, d = 2.0 ** -61, 2.0 ** -70
+    y = np.array([[0, 0, 0], [c + d + 2.0 ** -80, c, c], [c + d, c, c]], dtype=np.float32)
+    got, _ = _check(gpu, orc, y, 1, gpu.params(layers=1, fixed_voxel=2.0 ** -60), "subnormal")
+    assert list(got) == [2]
+
+
+# ------------------------------------------------------------------ small and ragged clouds
+
+@pytest.mark.parametrize("kind", ["uniform", "clustered", "quantised"])
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 255, 1023, 1025, 4097, 9999])
+def test_small_ragged(gpu, orc, kind, n):
+    x = synth.random_cloud(n, n + 7, scale=8.0, kind=kind)
+    for M in sorted({1, max(1, n // 3), max(1, n - 1), n}):
+        _check(gpu, orc, x, M, label=kind)
+
+
+def test_degenerate(gpu, orc):
+    _check(gpu, orc, np.full((300, 3), 2.5, np.float32), 40, label="identical")
+    y = np.repeat(synth.random_cloud(50, 3), 7, axis=0)
+    _check(gpu, orc, y, 120, label="duplicates")
+    line = np.zeros((2000, 3), np.float32)
+    line[:, 0] = np.linspace(0, 1, 2000, dtype=np.float32)
+    _check(gpu, orc, line, 700, label="line")
+    _check(gpu, orc, -synth.random_cloud(3000, 4, scale=1e-3), 500, label="tiny extent")
+    big = synth.random_cloud(3000, 5, scale=1.0) * np.float32(1e25)
+    _check(gpu, orc, big, 500, label="huge extent")
+
+
+# ------------------------------------------------------------------ parameters
+
+@pytest.mark.parametrize("kw", [dict(), dict(layers=1), dict(layers=3), dict(layers=8, layer_ratio=2),
+                                dict(sigma=0.0), dict(sigma=0.5), dict(t_max=1), dict(t_max=5),
+                                dict(aspect=(1.0, 1.0, 0.5)), dict(aspect=(3.0, 0.75, 0.125)),
+                                dict(fixed_voxel=0.34), dict(fixed_voxel=(0.34, 0.34, 0.30)),
+                                dict(layers=1, fixed_voxel=2.0)])
+def test_config1_params(gpu, orc, kw):
+    x = synth.uniform_box_with_ground()
+    _check(gpu, orc, x, 4096, gpu.params(**kw), f"cfg1 {kw}")
+
+
+@pytest.mark.parametrize("M", [1, 100, 1000, 4096, 8191, 16383, 16384])
+def test_config1_sizes(gpu, orc, M):
+    _check(gpu, orc, synth.uniform_box_with_ground(), M, label="cfg1")
+
+
+# ------------------------------------------------------------------ device-side errors
+
+def test_device_errors(gpu, orc):
+    x = synth.random_cloud(5000, 1)
+    for bad, code in ((np.nan, gpu.ERR_NONFINITE), (np.inf, gpu.ERR_NONFINITE),
+                      (-np.inf, gpu.ERR_NONFINITE), (np.float32(2.0 ** 101), gpu.ERR_UNSUPPORTED)):
+        y = x.copy()
+        y[4321, 2] = bad
+        _note(f"case error {bad}")
+        _, info = gpu.Sampler().sample(_to_dev(y), 100, gpu.params(), with_info=True)
+        assert info["status"] == code
+        assert orc.sample(y, 100)[0] == code
+    _, info = gpu.Sampler().sample(_to_dev(x), 100, gpu.params(fixed_voxel=1e-6), with_info=True)
+    assert info["status"] == gpu.ERR_UNSUPPORTED
+    # the library keeps working after a device-side error
+    _check(gpu, orc, x, 100, label="after error")
+
+
+def test_determinism_and_workspace_independence(gpu, orc):
+    import torch
+    x = synth.scene_planes_blobs(200000, seed=9)
+    xd = _to_dev(x)
+    s1, s2 = gpu.Sampler(), gpu.Sampler()
+    a = s1.sample(xd, 50000).cpu().numpy()
+    # a dirty, larger workspace must not change anything
+    s2.ws = torch.full((gpu.workspace_size(200000, 50000) + 4096,), 0xAB, dtype=torch.uint8,
+                       device="cuda")
+    b = s2.sample(xd, 50000).cpu().numpy()
+    for _ in range(3):
+        assert np.array_equal(s1.sample(xd, 50000).cpu().numpy(), a)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, orc.sample(x, 50000)[1])
+
+
+# ------------------------------------------------------------------ workloads at full size
+
+def test_lidar_chain(gpu, orc):
+    x = synth.lidar_scan()
+    Ms = [16384, 4096, 1024, 256]
+    _note(f"case lidar chain N={x.shape[0]}")
+    st, want, winfo = orc.chain(x, Ms)
+    assert st == 0
+    parts, infos = gpu.Sampler().chain(_to_dev(x), Ms, with_info=True)
+    for j in range(len(Ms)):
+        assert infos[j] == winfo[j], j
+        assert np.array_equal(parts[j].cpu().numpy(), want[j]), j
+
+
+def test_scene_chain_1m(gpu, orc):
+    x = synth.scene_planes_blobs()
+    N = x.shape[0]
+    Ms = [N // 4, N // 16, N // 64]
+    _note(f"case scene chain N={N}")
+    st, want, winfo = orc.chain(x, Ms)
+    assert st == 0
+    parts, infos = gpu.Sampler().chain(_to_dev(x), Ms, with_info=True)
+    for j in range(len(Ms)):
+        assert infos[j] == winfo[j], j
+        assert np.array_equal(parts[j].cpu().numpy(), want[j]), j
+
+
+def test_scene_single_stage_1m(gpu, orc):
+    x = synth.scene_planes_blobs()
+    _check(gpu, orc, x, x.shape[0] // 4, label="scene 1M->262144")

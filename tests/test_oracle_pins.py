@@ -147,6 +147,12 @@ def test_ties_go_to_lowest_index(orc):
     y = np.array([[0, 0, 0], [1.5, 1, 1], [1, 0.5, 1], [1, 1, 1.5], [0.5, 1, 1]], dtype=np.float32)
     st, idx, _ = orc.sample(y, 1, orc.params(layers=1, fixed_voxel=2.0))
     assert st == 0 and list(idx) == [1]
+    # squared distances in the subnormal range still order (no flush to zero): voxel
+    # 2^-60 with centre 2^-61; point 1 is 2^-70 + 2^-80 off centre, point 2 is 2^-70 off
+    c, d = 2.0 ** -61, 2.0 ** -70
+    z = np.array([[0, 0, 0], [c + d + 2.0 ** -80, c, c], [c + d, c, c]], dtype=np.float32)
+    st, idx, _ = orc.sample(z, 1, orc.params(layers=1, fixed_voxel=2.0 ** -60))
+    assert st == 0 and list(idx) == [2]
 
 
 # ---------------------------------------------------------------- brute force, tiny clouds
