@@ -16,7 +16,13 @@
  *     coordinate cannot hold) are found on the device and reported in info->status;
  *     idx is then unspecified.
  *   - Results depend only on (xyz, M, params): never on the stream, the workspace
- *     address or the launch shape. Two calls in flight at once need two workspaces.
+ *     address, the tuning fields of hav_params_t or the launch shape.
+ *   - Workspace contract: a workspace is initialised once with hav_workspace_init for
+ *     a size N and a speculation depth, and then belongs to the library: every call
+ *     leaves it in the initialised state, so calls never clear whole tables. Do not
+ *     write into it between calls (re-initialise it if you do). Two calls in flight
+ *     at once need two workspaces. A call on a workspace initialised for another size
+ *     reports HAV_ERR_WORKSPACE_NOT_INIT in info->status and computes nothing.
  */
 #ifndef HAV_H_
 #define HAV_H_
@@ -39,7 +45,9 @@ typedef enum {
   HAV_ERR_UNSUPPORTED = 4,         /* device: extent > 2^100, or a fixed voxel too small
                                       for 21-bit voxel coordinates */
   HAV_ERR_NONFINITE = 5,           /* device: a coordinate is NaN or infinite */
-  HAV_ERR_HIP = 6                  /* a HIP launch failed */
+  HAV_ERR_HIP = 6,                 /* a HIP launch failed */
+  HAV_ERR_WORKSPACE_NOT_INIT = 7   /* device: workspace not initialised for this call's
+                                      size and depth (see hav_workspace_init) */
 } hav_status_t;
 
 /* flags */
@@ -59,6 +67,9 @@ typedef struct {
                           each in [2^-16, 2^16]; default {1,1,1} */
   uint32_t flags;      /* HAV_FIXED_VOXEL or 0 */
   float fixed_voxel[3];/* used iff HAV_FIXED_VOXEL; each in [2^-100, 2^100] */
+  int32_t spec_depth;  /* tuning only: bisection levels the device evaluates per pass of
+                          the voxel search, 1..4; 0 = library default. Results do not
+                          depend on it; workspace size does. */
 } hav_params_t;
 
 /* Per-call report, written by the device into caller memory (info_dev). */
@@ -85,8 +96,16 @@ hav_params_t hav_params_default(void);
 const char* hav_status_string(hav_status_t status);
 
 /* Bytes of device workspace hav_sample needs for N points (host-only, no GPU call).
- * Returns 0 if the arguments are invalid. The workspace needs no initialisation. */
+ * Depends on N and params->spec_depth. Returns 0 if the arguments are invalid. */
 size_t hav_workspace_size(int64_t N, int64_t M, const hav_params_t* params);
+
+/* Enqueue the one-time initialisation of a workspace for calls with N points (and for
+ * hav_sample_chain with first-stage size N) and params->spec_depth. ws is device
+ * memory of ws_bytes >= hav_workspace_size (or hav_chain_workspace_size), 256-byte
+ * aligned, arbitrary contents. Needed again only after the caller writes into the
+ * workspace or to switch N / depth. */
+hav_status_t hav_workspace_init(int64_t N, const hav_params_t* params, void* ws, size_t ws_bytes,
+                                void* stream);
 
 /* Sample exactly M of the N points (Sec. 3, Eq. 3 with AVS of Sec. 3.3 and the
  * centre-closest selection of Sec. 3.2).
@@ -94,14 +113,15 @@ size_t hav_workspace_size(int64_t N, int64_t M, const hav_params_t* params);
  *   N, M   1 <= M <= N < 2^31.
  *   idx    [M] int32, device: the picked indices in ascending order.
  *   ws     device workspace of ws_bytes >= hav_workspace_size(N, M, params),
- *          256-byte aligned; contents are scratch.
+ *          256-byte aligned, initialised by hav_workspace_init(N, params, ...).
  *   info_dev  device hav_info_t or NULL.
  * M == N gives 0..N-1. Returns HAV_OK once the work is enqueued. */
 hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params_t* params,
                         int32_t* idx, void* ws, size_t ws_bytes, hav_info_t* info_dev,
                         void* stream);
 
-/* Workspace for hav_sample_chain with stage sizes M_host[0..n_stages-1]. */
+/* Workspace for hav_sample_chain with stage sizes M_host[0..n_stages-1]; initialise it
+ * with hav_workspace_init(N, params, ...). */
 size_t hav_chain_workspace_size(int64_t N, const int64_t* M_host, int32_t n_stages,
                                 const hav_params_t* params);
 

@@ -1,19 +1,39 @@
 // HAVSampler for MI355X (gfx950): kernels and the C ABI of include/hav.h.
 //
-// One stage samples exactly M of N points (arXiv 2305.14306, Sec. 3):
-//   frame   per-axis min/max, grid origin = min corner, search bracket hi0
-//   layers  (Sec. 3.4, Eq. 3) for each layer l with budget m_l, on unsampled points:
-//     search  adaptive voxel search (Sec. 3.3): bisection on the voxel scale s; each
-//             step runs the voxel counter Cnt (Sec. 3.2 voxel hashing) and a one-thread
-//             controller on the device, so the host never waits for a count
-//     select  centre-closest point per occupied voxel (Sec. 3.2) via a 64-bit
-//             atomicMin of (bits(d^2) << 32 | index): ties go to the lowest index
-//     exact m trim by SplitMix64 priority of the voxel (radix select of the m-th
-//             smallest) or pad with the lowest-index unsampled points
-//     mask    tag[i] = layer number of the pick
-//   output  ascending indices by a two-level scan over tag
+// One stage samples exactly M of N points (arXiv 2305.14306, Sec. 3). Pipeline, all
+// on one stream, every decision taken on the device (no host round trip):
 //
-// All state lives in the caller's workspace; nothing is allocated here.
+//   k_bbox         per-block min/max of the cloud and the non-finite check
+//   k_bin_count    every block reduces the partial boxes (same result everywhere),
+//                  derives the stage frame (origin = min corner, search bracket hi0)
+//                  and a 12-bit Morton cell per point; per-block cell histograms
+//   k_bin_scan     exclusive scan of the (cell, block) histogram; initialises layer 1
+//   k_bin_scatter  counting sort by cell: points land in spatially compact tiles of
+//                  2048, stored as offsets r = p - origin (exactly what Eq. 2 uses)
+//   per layer (Sec. 3.4, Eq. 3):
+//     k_eval x P   adaptive voxel search (Sec. 3.3). Each pass evaluates the voxel
+//                  counter Cnt for the next `depth` levels of the bisection tree at
+//                  once (the decisions, and so the scales, are exactly the plain
+//                  bisection's). A tile dedups its voxels in LDS as 4x4x4 bricks with
+//                  64-bit occupancy masks, then does one CAS/atomicOr per distinct
+//                  brick in a global table; new bits = new voxels. The last block to
+//                  finish walks the tree and plans the next pass.
+//     k_select     centre-closest point per occupied voxel at the chosen size
+//                  (Sec. 3.2): LDS min of (bits(d^2) << 32 | index), then one global
+//                  atomicMin per tile-distinct voxel; ties go to the lowest index.
+//     k_trim_hist  radix select (8-bit digits) of the m-th smallest SplitMix64
+//                  priority when there are more voxels than m
+//     k_mark       keep the m smallest; the last block settles the boundary bucket
+//     k_pad_*      pad with the lowest-index unsampled points when there are fewer
+//   k_out_*        ascending output indices by a two-level scan
+//
+// Table hygiene: the workspace is initialised once (hav_workspace_init); each kernel
+// that fills a table records the slots it claimed, and a later kernel of the same
+// call empties exactly those, so every call leaves the workspace as it found it and
+// no call pays for clearing whole tables.
+//
+// Cross-block results (counts, histograms) go through two-level arrival counters
+// and per-group accumulators, so no address takes more than ~32 atomics.
 
 #include <hip/hip_runtime.h>
 
@@ -28,65 +48,229 @@ namespace hav {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kScanItems = 4;  // elements per thread in the scan kernels
-constexpr int kScanTile = kThreads * kScanItems;
-constexpr int kRadixBits = 8;
-constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kTile = 2048;                     // points per search/select tile
+constexpr int kPerThread = kTile / kThreads;    // 8
+constexpr int kLdsCap = 4096;                   // LDS hash entries (>= 2x distinct keys)
+constexpr int kMaxDepth = 4;
+constexpr int kMaxCand = (1 << kMaxDepth) - 1;  // 15
+constexpr int kDefaultDepth = 2;
+constexpr int kGroups = 16;
+constexpr int kStride = 32;                     // uint32 spacing of hot counters (128 B)
+constexpr int kBinBits = 12;
+constexpr int kBins = 1 << kBinBits;
+constexpr int kMaxBinBlocks = 128;
+constexpr int kMaxBBoxBlocks = 1024;
+constexpr int kScanTile = 4096;                 // tag scans: 16 per thread
+constexpr int kScanPer = kScanTile / kThreads;
+constexpr uint64_t kMagic = 0x4841565F57533031ull;
+
+// ----------------------------------------------------------------------------- state
 
 struct Frame {
-  uint32_t mn_ord[3];
-  uint32_t mx_ord[3];
-  int32_t nonfinite;
   int32_t status;
-  float mn[3];
-  float mx[3];
+  int32_t bbits[3];
+  float mn[3], mx[3];
   float hi0;
+  float bscale[3];
 };
 
 struct Ctrl {
-  float lo, hi, s;
-  float v[3], inv[3];  // voxel size and reciprocal of the size being evaluated / chosen
-  int32_t evals, done, accepted, layer;
-  uint32_t count;      // new keys found by the current evaluation
-  uint32_t c_lo, c_hi;
-  uint32_t ncand;      // occupied voxels at the chosen size
+  int32_t layer;
   uint32_t m, upper;
-  uint64_t prefix;     // radix select: priority bits fixed so far
-  uint32_t rank;       // rank sought inside the current prefix bucket
-  uint32_t trim;       // 1 if ncand > m
-  uint32_t ncap;       // candidate list capacity (points in the stage)
-  uint32_t hist[kRadixBins];
+  int32_t evals, done, accepted;
+  float lo, hi;
+  float s_final;
+  float v_final[3], inv_final[3];
+  int32_t nc;           // candidates of the next search pass
+  int32_t set;          // table set the next pass fills
+  int32_t pend_set, pend_nc;
+  float cand_s[kMaxCand];
+  float cand_inv[kMaxCand][3];
+  uint32_t ncand;       // occupied voxels at the chosen size
+  int32_t trim;
+  uint32_t need;        // pad count
+  uint32_t rank;        // radix select: rank sought inside the prefix bucket
+  uint64_t prefix;
+  int32_t rounds_done;
 };
 
-struct KParams {
+struct Plan {  // per-call constants (kernel argument)
+  int32_t nlayers;
+  int32_t t_max;
+  int32_t depth;
+  int32_t fixed;
+  uint32_t m[HAV_MAX_LAYERS];
+  uint32_t upper[HAV_MAX_LAYERS];
   float aspect[3];
   float fixed_v[3];
-  int32_t fixed;
+  uint64_t magic;
 };
 
-__device__ __forceinline__ bool failed(const Frame* f) { return f->status != HAV_OK; }
+struct alignas(256) Header {
+  uint64_t magic;
+  uint64_t pad0[31];
+  alignas(256) Frame frame;
+  alignas(256) Ctrl ctrl;
+  alignas(256) hav_info_t info;
+  alignas(256) uint32_t sync_top[kStride];
+  uint32_t sync_grp[kGroups][kStride];
+  uint32_t acc[kMaxCand][kGroups][kStride];
+  uint32_t hist[kGroups][256];
+  uint32_t tie_cur[kGroups][kStride];
+};
+
+// Device view of the workspace for one stage.
+struct Ws {
+  Header* h;
+  float *rx, *ry, *rz;           // sorted offsets from the origin
+  int32_t* ordi;                 // sorted position -> original index
+  int32_t* invp;                 // original index -> sorted position
+  uint8_t* tag_s;                // sorted order: layer that picked the point (0 = none)
+  uint8_t* tag_o;                // original order
+  uint32_t* part;                // k_bbox partials [nbbox][8]
+  uint32_t* bh;                  // cell histogram [kBins][nbb]
+  uint32_t* bsum;                // scan chunk sums [nbb]
+  unsigned long long* ckeys;     // brick tables [2][ncmax][cap_ws]
+  unsigned long long* cmasks;
+  int32_t* ccl;                  // claims [2][ncmax][ntile_ws][kTile]
+  int32_t* ccn;                  // claim counts [2][ncmax][ntile_ws]
+  unsigned long long* skeys;     // voxel table [cap_ws]
+  unsigned long long* svals;
+  int32_t* scl;                  // claims [ntile_ws][kTile]
+  int32_t* scn;                  // [ntile_ws]
+  uint64_t* tie_p;               // [kGroups][tie_seg]
+  int32_t* tie_o;
+  uint32_t* tcnt;                // scan tile counts [nscan_ws]
+  // sizes of this stage / of the workspace
+  int64_t n;
+  int32_t ntile, nscan, nbb, nbbox;
+  uint32_t cap, cmask;           // table capacity used by this stage
+  uint32_t cap_ws;
+  int32_t ntile_ws, ncmax;
+  int64_t tie_seg;
+};
+
+__device__ __forceinline__ unsigned long long* ctab_keys(const Ws& w, int set, int c) {
+  return w.ckeys + (static_cast<size_t>(set) * w.ncmax + c) * w.cap_ws;
+}
+__device__ __forceinline__ unsigned long long* ctab_masks(const Ws& w, int set, int c) {
+  return w.cmasks + (static_cast<size_t>(set) * w.ncmax + c) * w.cap_ws;
+}
+__device__ __forceinline__ int32_t* claims(const Ws& w, int set, int c, int tile) {
+  return w.ccl + ((static_cast<size_t>(set) * w.ncmax + c) * w.ntile_ws + tile) * kTile;
+}
+__device__ __forceinline__ int32_t* claim_n(const Ws& w, int set, int c, int tile) {
+  return w.ccn + (static_cast<size_t>(set) * w.ncmax + c) * w.ntile_ws + tile;
+}
+
+// Two-level arrival: returns true in exactly one block, the last to arrive. All of
+// the block's prior writes are made visible first (release), and the last block
+// sees everyone's (acquire). Counters are left at zero for the next kernel.
+__device__ bool arrive_last(Header* h, int nblocks) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int g = blockIdx.x & (kGroups - 1);
+    const int gsize = (nblocks - g + kGroups - 1) / kGroups;
+    const int ngroups = nblocks < kGroups ? nblocks : kGroups;
+    int last = 0;
+    const uint32_t a = atomicAdd(&h->sync_grp[g][0], 1u);
+    if (a == static_cast<uint32_t>(gsize - 1)) {
+      atomicExch(&h->sync_grp[g][0], 0u);
+      const uint32_t b = atomicAdd(&h->sync_top[0], 1u);
+      if (b == static_cast<uint32_t>(ngroups - 1)) {
+        atomicExch(&h->sync_top[0], 0u);
+        last = 1;
+      }
+    }
+    if (last) __threadfence();
+    s_last = last;
+  }
+  __syncthreads();
+  return s_last != 0;
+}
+
+__device__ __forceinline__ uint32_t load_acc(uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ----------------------------------------------------------------------------- search plan
+
+// Candidates of the next pass: the bisection subtree of `depth` levels below the
+// bracket [lo, hi], in heap order. Node k with bracket [a, b] evaluates s = (a+b)/2;
+// its child 2k+1 ([a, s]) is taken when the count is below m, 2k+2 ([s, b]) when
+// above the window -- the same arithmetic as one bisection step at a time.
+__device__ void plan_pass(Ctrl* c, const Plan& P) {
+  const int left = P.t_max - c->evals;
+  const int D = left < P.depth ? left : P.depth;
+  const int nc = (1 << D) - 1;
+  float a[kMaxCand], b[kMaxCand];
+  a[0] = c->lo;
+  b[0] = c->hi;
+  for (int k = 0; k < nc; ++k) {
+    const float s = (a[k] + b[k]) * 0.5f;
+    c->cand_s[k] = s;
+    for (int ax = 0; ax < 3; ++ax) {
+      const float v = s * P.aspect[ax];
+      c->cand_inv[k][ax] = 1.0f / v;
+    }
+    if (2 * k + 2 < nc) {
+      a[2 * k + 1] = a[k];
+      b[2 * k + 1] = s;
+      a[2 * k + 2] = s;
+      b[2 * k + 2] = b[k];
+    }
+  }
+  c->nc = nc;
+}
+
+__device__ void set_final(Ctrl* c, float s, const Plan& P) {
+  c->s_final = s;
+  for (int ax = 0; ax < 3; ++ax) {
+    c->v_final[ax] = s * P.aspect[ax];
+    c->inv_final[ax] = 1.0f / c->v_final[ax];
+  }
+}
+
+__device__ void layer_init(Header* h, const Plan& P, int L) {
+  Ctrl* c = &h->ctrl;
+  c->layer = L;
+  c->m = P.m[L];
+  c->upper = P.upper[L];
+  c->evals = 0;
+  c->accepted = 0;
+  c->lo = 0.0f;
+  c->hi = h->frame.hi0;
+  c->ncand = 0;
+  c->trim = 0;
+  c->need = 0;
+  c->rank = 0;
+  c->prefix = 0;
+  c->rounds_done = 0;
+  h->info.m[L] = static_cast<int32_t>(P.m[L]);
+  h->info.layers = L + 1;
+  if (P.fixed) {
+    c->done = 1;
+    c->nc = 0;
+    c->s_final = 0.0f;
+    for (int ax = 0; ax < 3; ++ax) {
+      c->v_final[ax] = P.fixed_v[ax];
+      c->inv_final[ax] = 1.0f / P.fixed_v[ax];
+    }
+  } else {
+    c->done = 0;
+    plan_pass(c, P);
+  }
+}
 
 // ----------------------------------------------------------------------------- frame
 
-__global__ void k_begin(Frame* f, hav_info_t* info) {
-  const int t = threadIdx.x;
-  if (t < 3) {
-    f->mn_ord[t] = 0xFFFFFFFFu;
-    f->mx_ord[t] = 0u;
-  }
-  if (t == 0) {
-    f->nonfinite = 0;
-    f->status = HAV_OK;
-  }
-  int32_t* w = reinterpret_cast<int32_t*>(info);
-  for (int i = t; i < static_cast<int>(sizeof(hav_info_t) / 4); i += blockDim.x) w[i] = 0;
-}
-
-__global__ void __launch_bounds__(kThreads) k_bbox(const float* __restrict__ xyz, int64_t n,
-                                                   Frame* f) {
+__global__ void __launch_bounds__(kThreads) k_bbox(const float* __restrict__ xyz, Ws w) {
   uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
   uint32_t hi[3] = {0u, 0u, 0u};
-  int bad = 0;
+  uint32_t bad = 0;
+  const int64_t n = w.n;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * kThreads) {
 #pragma unroll
@@ -97,457 +281,754 @@ __global__ void __launch_bounds__(kThreads) k_bbox(const float* __restrict__ xyz
       lo[a] = min(lo[a], o);
       hi[a] = max(hi[a], o);
     }
+    w.tag_o[i] = 0;
   }
-  __shared__ uint32_t s_lo[3][kThreads / 64], s_hi[3][kThreads / 64];
-  __shared__ int s_bad;
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
+  __shared__ uint32_t s_v[7][kThreads / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t vals[7] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], bad};
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const uint32_t l = wave_min_u32(lo[a]);
-    const uint32_t h = wave_max_u32(hi[a]);
-    if (lane == 0) {
-      s_lo[a][wv] = l;
-      s_hi[a][wv] = h;
+  for (int k = 0; k < 7; ++k) {
+    uint32_t v = vals[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t y = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), o, 64));
+      v = (k < 3) ? min(v, y) : ((k < 6) ? max(v, y) : (v | y));
     }
+    if (lane == 0) s_v[k][wv] = v;
   }
-  if (bad) s_bad = 1;
   __syncthreads();
-  if (threadIdx.x < 3) {
-    const int a = threadIdx.x;
-    uint32_t l = s_lo[a][0], h = s_hi[a][0];
-    for (int w = 1; w < kThreads / 64; ++w) {
-      l = min(l, s_lo[a][w]);
-      h = max(h, s_hi[a][w]);
-    }
-    atomicMin(&f->mn_ord[a], l);
-    atomicMax(&f->mx_ord[a], h);
+  if (threadIdx.x < 7) {
+    const int k = threadIdx.x;
+    uint32_t v = s_v[k][0];
+    for (int q = 1; q < kThreads / 64; ++q)
+      v = (k < 3) ? min(v, s_v[k][q]) : ((k < 6) ? max(v, s_v[k][q]) : (v | s_v[k][q]));
+    w.part[blockIdx.x * 8 + k] = v;
   }
-  if (threadIdx.x == 0 && s_bad) atomicOr(&f->nonfinite, 1);
 }
 
-// Single thread: decode the box, compute hi0 and check the frame.
-__global__ void k_frame(Frame* f, hav_info_t* info, KParams kp, int identity) {
-  if (threadIdx.x != 0) return;
-  if (f->nonfinite) {
-    f->status = HAV_ERR_NONFINITE;
-    info->status = HAV_ERR_NONFINITE;
-    return;
+// Reduce the k_bbox partials and derive the stage frame. Every block of the calling
+// kernel does this itself and gets the same bits; only block 0 publishes them.
+// Returns the status.
+__device__ int frame_from_partials(const Ws& w, const Plan& P, Frame* fr, int identity) {
+  __shared__ uint32_t s_v[7][kThreads / 64];
+  uint32_t v[7] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u};
+  for (int b = threadIdx.x; b < w.nbbox; b += kThreads) {
+    const uint32_t* p = w.part + b * 8;
+    for (int k = 0; k < 3; ++k) v[k] = min(v[k], p[k]);
+    for (int k = 3; k < 6; ++k) v[k] = max(v[k], p[k]);
+    v[6] |= p[6];
   }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    uint32_t x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t y = static_cast<uint32_t>(__shfl_xor(static_cast<int>(x), o, 64));
+      x = (k < 3) ? min(x, y) : ((k < 6) ? max(x, y) : (x | y));
+    }
+    if (lane == 0) s_v[k][wv] = x;
+  }
+  __syncthreads();
+  for (int k = 0; k < 7; ++k) {
+    uint32_t x = s_v[k][0];
+    for (int q = 1; q < kThreads / 64; ++q)
+      x = (k < 3) ? min(x, s_v[k][q]) : ((k < 6) ? max(x, s_v[k][q]) : (x | s_v[k][q]));
+    v[k] = x;
+  }
+  __syncthreads();
+  int status = HAV_OK;
+  if (w.h->magic != P.magic) status = HAV_ERR_WORKSPACE_NOT_INIT;
+  else if (v[6]) status = HAV_ERR_NONFINITE;
   float E = 0.0f;
   for (int a = 0; a < 3; ++a) {
-    f->mn[a] = ordered_to_float(f->mn_ord[a]);
-    f->mx[a] = ordered_to_float(f->mx_ord[a]);
-    info->mn[a] = f->mn[a];
-    info->mx[a] = f->mx[a];
-    const float ext = f->mx[a] - f->mn[a];
-    const float e = ext / kp.aspect[a];
+    fr->mn[a] = ordered_to_float(v[a]);
+    fr->mx[a] = ordered_to_float(v[3 + a]);
+    const float ext = fr->mx[a] - fr->mn[a];
+    const float e = ext / P.aspect[a];
     if (!(e <= E)) E = e;
   }
-  if (identity) return;  // M == N: every point is kept, no frame checks apply
-  if (!(E <= 0x1p100f)) {
-    f->status = HAV_ERR_UNSUPPORTED;
-    info->status = HAV_ERR_UNSUPPORTED;
-    return;
-  }
-  // smallest power of two >= max(E, 2^-64); E is then a normal number
-  const float Ec = E < 0x1p-64f ? 0x1p-64f : E;
-  const uint32_t bits = __float_as_uint(Ec);
-  const float hi0 = (bits & 0x7FFFFFu) ? __uint_as_float((bits & 0x7F800000u) + 0x00800000u) : Ec;
-  f->hi0 = hi0;
-  info->hi0 = hi0;
-  if (kp.fixed) {
-    for (int a = 0; a < 3; ++a) {
-      const float inv = 1.0f / kp.fixed_v[a];
-      const float q = (f->mx[a] - f->mn[a]) * inv;
-      if (!(q < kKeyLimit)) {
-        f->status = HAV_ERR_UNSUPPORTED;
-        info->status = HAV_ERR_UNSUPPORTED;
-        return;
+  fr->hi0 = 0.0f;
+  if (status == HAV_OK && !identity) {
+    if (!(E <= 0x1p100f)) {
+      status = HAV_ERR_UNSUPPORTED;
+    } else {
+      const float Ec = E < 0x1p-64f ? 0x1p-64f : E;
+      const uint32_t bits = __float_as_uint(Ec);
+      fr->hi0 = (bits & 0x7FFFFFu) ? __uint_as_float((bits & 0x7F800000u) + 0x00800000u) : Ec;
+      if (P.fixed) {
+        for (int a = 0; a < 3; ++a) {
+          const float inv = 1.0f / P.fixed_v[a];
+          const float q = (fr->mx[a] - fr->mn[a]) * inv;
+          if (!(q < kKeyLimit)) status = HAV_ERR_UNSUPPORTED;
+        }
       }
+    }
+  }
+  // spatial binning: 12 Morton bits shared out by extent (performance only)
+  float ext[3];
+  int bb[3] = {0, 0, 0};
+  for (int a = 0; a < 3; ++a) ext[a] = fr->mx[a] - fr->mn[a];
+  for (int k = 0; k < kBinBits; ++k) {
+    int best = 0;
+    float bv = -1.0f;
+    for (int a = 0; a < 3; ++a) {
+      const float q = ext[a] / static_cast<float>(1 << bb[a]);
+      if (q > bv) {
+        bv = q;
+        best = a;
+      }
+    }
+    bb[best] += 1;
+  }
+  for (int a = 0; a < 3; ++a) {
+    fr->bbits[a] = bb[a];
+    fr->bscale[a] = ext[a] > 0.0f ? static_cast<float>(1 << bb[a]) / ext[a] : 0.0f;
+    if (!isfinite(fr->bscale[a])) fr->bscale[a] = 0.0f;
+  }
+  fr->status = status;
+  return status;
+}
+
+__device__ void publish_frame(const Ws& w, const Frame& fr) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  w.h->frame = fr;
+  hav_info_t* info = &w.h->info;
+  int32_t* z = reinterpret_cast<int32_t*>(info);
+  for (int i = 0; i < static_cast<int>(sizeof(hav_info_t) / 4); ++i) z[i] = 0;
+  info->status = fr.status;
+  info->hi0 = fr.hi0;
+  for (int a = 0; a < 3; ++a) {
+    info->mn[a] = fr.mn[a];
+    info->mx[a] = fr.mx[a];
+  }
+}
+
+__device__ __forceinline__ uint32_t cell_code(float rx, float ry, float rz, const Frame& fr) {
+  const float r[3] = {rx, ry, rz};
+  uint32_t c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float q = r[a] * fr.bscale[a];
+    const uint32_t lim = (1u << fr.bbits[a]) - 1u;
+    c[a] = q >= static_cast<float>(lim) ? lim : static_cast<uint32_t>(q);
+  }
+  uint32_t code = 0;
+  int pos = 0;
+  for (int j = 0; j < kBinBits; ++j)
+    for (int a = 0; a < 3; ++a)
+      if (j < fr.bbits[a]) code |= ((c[a] >> j) & 1u) << pos++;
+  return code;
+}
+
+__global__ void __launch_bounds__(kThreads) k_identity(Ws w, Plan P, int32_t* idx,
+                                                       hav_info_t* info_dev) {
+  __shared__ Frame fr;
+  Frame f;
+  const int st = frame_from_partials(w, P, &f, 1);
+  if (threadIdx.x == 0) fr = f;
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    publish_frame(w, fr);
+    if (info_dev) *info_dev = w.h->info;
+  }
+  if (st != HAV_OK) return;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < w.n;
+       i += static_cast<int64_t>(gridDim.x) * kThreads)
+    idx[i] = static_cast<int32_t>(i);
+}
+
+// ----------------------------------------------------------------------------- binning
+
+__global__ void __launch_bounds__(kThreads) k_bin_count(const float* __restrict__ xyz, Ws w,
+                                                        Plan P) {
+  __shared__ Frame fr;
+  __shared__ uint32_t hist[kBins];
+  Frame f;
+  const int st = frame_from_partials(w, P, &f, 0);
+  if (threadIdx.x == 0) fr = f;
+  for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0;
+  __syncthreads();
+  publish_frame(w, fr);
+  if (st != HAV_OK) return;
+  const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
+  const int64_t beg = blockIdx.x * chunk, end = min(w.n, beg + chunk);
+  for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) {
+    const float rx = xyz[3 * i] - fr.mn[0];
+    const float ry = xyz[3 * i + 1] - fr.mn[1];
+    const float rz = xyz[3 * i + 2] - fr.mn[2];
+    atomicAdd(&hist[cell_code(rx, ry, rz, fr)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBins; b += kThreads) w.bh[static_cast<size_t>(b) * w.nbb + blockIdx.x] = hist[b];
+}
+
+// Exclusive scan of bh (kBins x nbb, bin-major) in kScanTile chunks; the last block
+// scans the chunk sums and starts layer 1.
+__global__ void __launch_bounds__(kThreads) k_bin_scan(Ws w, Plan P) {
+  if (w.h->frame.status != HAV_OK) return;
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  const int64_t total = static_cast<int64_t>(kBins) * w.nbb;
+  const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = base + k < total ? w.bh[base + k] : 0u;
+    sum += v[k];
+  }
+  uint32_t excl;
+  const uint32_t tot = block_exclusive_scan<kThreads>(sum, &excl, s_tmp);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < total) w.bh[base + k] = excl;
+    excl += v[k];
+  }
+  if (threadIdx.x == 0) w.bsum[blockIdx.x] = tot;
+  if (!arrive_last(w.h, gridDim.x)) return;
+  // last block: scan the chunk sums (<= kMaxBinBlocks of them)
+  const uint32_t x = threadIdx.x < static_cast<int>(gridDim.x) ? w.bsum[threadIdx.x] : 0u;
+  uint32_t ex;
+  block_exclusive_scan<kThreads>(x, &ex, s_tmp);
+  if (threadIdx.x < static_cast<int>(gridDim.x)) w.bsum[threadIdx.x] = ex;
+  if (threadIdx.x == 0) {
+    Ctrl* c = &w.h->ctrl;
+    c->set = 0;
+    c->pend_nc = 0;
+    c->pend_set = 0;
+    layer_init(w.h, P, 0);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_bin_scatter(const float* __restrict__ xyz, Ws w) {
+  if (w.h->frame.status != HAV_OK) return;
+  __shared__ Frame fr;
+  __shared__ uint32_t off[kBins];
+  if (threadIdx.x == 0) fr = w.h->frame;
+  for (int b = threadIdx.x; b < kBins; b += kThreads) {
+    const size_t e = static_cast<size_t>(b) * w.nbb + blockIdx.x;
+    off[b] = w.bh[e] + w.bsum[e / kScanTile];
+  }
+  __syncthreads();
+  const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
+  const int64_t beg = blockIdx.x * chunk, end = min(w.n, beg + chunk);
+  for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) {
+    const float rx = xyz[3 * i] - fr.mn[0];
+    const float ry = xyz[3 * i + 1] - fr.mn[1];
+    const float rz = xyz[3 * i + 2] - fr.mn[2];
+    const uint32_t pos = atomicAdd(&off[cell_code(rx, ry, rz, fr)], 1u);
+    if (pos < w.n) {
+      w.rx[pos] = rx;
+      w.ry[pos] = ry;
+      w.rz[pos] = rz;
+      w.ordi[pos] = static_cast<int32_t>(i);
+      w.tag_s[pos] = 0;
+      w.invp[i] = static_cast<int32_t>(pos);
     }
   }
 }
 
 // ----------------------------------------------------------------------------- search
 
-__device__ void set_scale(Ctrl* c, float s, const KParams& kp) {
-  for (int a = 0; a < 3; ++a) {
-    c->v[a] = s * kp.aspect[a];
-    c->inv[a] = 1.0f / c->v[a];
-  }
-}
-
-__global__ void k_layer_begin(const Frame* f, Ctrl* c, hav_info_t* info, KParams kp, int layer,
-                              uint32_t m, uint32_t upper, uint32_t ncap) {
-  if (threadIdx.x != 0 || failed(f)) return;
-  c->lo = 0.0f;
-  c->hi = f->hi0;
-  c->evals = 0;
-  c->accepted = 0;
-  c->count = 0;
-  c->c_lo = c->c_hi = 0;
-  c->ncand = 0;
-  c->ncap = ncap;
-  c->m = m;
-  c->upper = upper;
-  c->layer = layer;
-  info->m[layer] = static_cast<int32_t>(m);
-  info->layers = layer + 1;
-  if (kp.fixed) {
-    c->done = 1;
-    c->s = 0.0f;
-    for (int a = 0; a < 3; ++a) {
-      c->v[a] = kp.fixed_v[a];
-      c->inv[a] = 1.0f / kp.fixed_v[a];
+__device__ void clear_pending(const Ws& w, Ctrl* c) {
+  const int pn = c->pend_nc, ps = c->pend_set;
+  for (int k = 0; k < pn; ++k) {
+    int32_t* cn = claim_n(w, ps, k, blockIdx.x);
+    const int n = *cn;
+    const int32_t* list = claims(w, ps, k, blockIdx.x);
+    unsigned long long* keys = ctab_keys(w, ps, k);
+    unsigned long long* masks = ctab_masks(w, ps, k);
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+      const int32_t s = list[i];
+      keys[s] = kEmptyKey;
+      masks[s] = 0ull;
     }
-  } else {
-    c->done = 0;
-    c->s = (c->lo + c->hi) * 0.5f;
-    set_scale(c, c->s, kp);
+    __syncthreads();
+    if (threadIdx.x == 0) *cn = 0;
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_fill_u64(unsigned long long* p, int64_t n,
-                                                       unsigned long long value, const Frame* f,
-                                                       const Ctrl* c) {
-  if (failed(f) || (c && c->done)) return;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads)
-    p[i] = value;
-}
+// One search pass: Cnt at every candidate scale of the pass; the last block walks
+// the bisection tree and plans the next pass.
+__global__ void __launch_bounds__(kThreads) k_eval(Ws w, Plan P) {
+  Header* h = w.h;
+  if (h->frame.status != HAV_OK) return;
+  Ctrl* c = &h->ctrl;
+  const int tile = blockIdx.x;
+  clear_pending(w, c);
+  const int done = c->done;
+  const int nc = done ? 0 : c->nc;
+  const int set = c->set;
 
-// Voxel counter Cnt (Sec. 3.3): distinct voxel keys among the unsampled points.
-__global__ void __launch_bounds__(kThreads) k_count(const float* __restrict__ xyz, int64_t n,
-                                                    const uint8_t* __restrict__ tag,
-                                                    const Frame* f, Ctrl* c,
-                                                    unsigned long long* keys, uint32_t mask,
-                                                    int shift) {
-  if (failed(f) || c->done) return;
-  const float o0 = f->mn[0], o1 = f->mn[1], o2 = f->mn[2];
-  const float i0 = c->inv[0], i1 = c->inv[1], i2 = c->inv[2];
-  uint32_t mine = 0;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    if (tag[i]) continue;
-    float r;
-    const uint32_t gx = axis_coord(xyz[3 * i + 0], o0, i0, &r);
-    const uint32_t gy = axis_coord(xyz[3 * i + 1], o1, i1, &r);
-    const uint32_t gz = axis_coord(xyz[3 * i + 2], o2, i2, &r);
-    uint32_t slot;
-    mine += table_insert(keys, mask, shift, pack_key(gx, gy, gz), &slot) ? 1u : 0u;
+  extern __shared__ uint64_t lds[];
+  uint64_t* lkeys = lds;
+  uint64_t* lvals = lds + kLdsCap;
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  __shared__ int s_ncl;
+
+  if (nc > 0) {
+    float px[kPerThread], py[kPerThread], pz[kPerThread];
+    bool ok[kPerThread];
+    const int64_t base = static_cast<int64_t>(tile) * kTile;
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const int64_t i = base + k * kThreads + threadIdx.x;
+      ok[k] = i < w.n && w.tag_s[i] == 0;
+      px[k] = ok[k] ? w.rx[i] : 0.0f;
+      py[k] = ok[k] ? w.ry[i] : 0.0f;
+      pz[k] = ok[k] ? w.rz[i] : 0.0f;
+    }
+    for (int ci = 0; ci < nc; ++ci) {
+      for (int e = threadIdx.x; e < kLdsCap; e += kThreads) {
+        lkeys[e] = kEmptyKey;
+        lvals[e] = 0ull;
+      }
+      if (threadIdx.x == 0) s_ncl = 0;
+      const float ix = c->cand_inv[ci][0], iy = c->cand_inv[ci][1], iz = c->cand_inv[ci][2];
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        if (!ok[k]) continue;
+        const uint32_t gx = axis_coord(px[k], ix);
+        const uint32_t gy = axis_coord(py[k], iy);
+        const uint32_t gz = axis_coord(pz[k], iz);
+        lds_insert_or(lkeys, lvals, kLdsCap - 1, brick_key(gx, gy, gz), brick_bit(gx, gy, gz));
+      }
+      __syncthreads();
+      unsigned long long* gkeys = ctab_keys(w, set, ci);
+      unsigned long long* gmasks = ctab_masks(w, set, ci);
+      int32_t* list = claims(w, set, ci, tile);
+      uint32_t fresh = 0;
+      for (int e = threadIdx.x; e < kLdsCap; e += kThreads) {
+        const uint64_t key = lkeys[e];
+        if (key == kEmptyKey) continue;
+        const uint64_t bits = lvals[e];
+        bool claimed;
+        const uint32_t s = global_find_or_claim(gkeys, w.cmask, key, &claimed);
+        if (claimed) list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(s);
+        const unsigned long long old = atomicOr(&gmasks[s], static_cast<unsigned long long>(bits));
+        fresh += static_cast<uint32_t>(__popcll(bits & ~old));
+      }
+      const uint32_t tot = block_sum_u32<kThreads>(fresh, s_tmp);
+      if (threadIdx.x == 0) {
+        *claim_n(w, set, ci, tile) = s_ncl;
+        if (tot) atomicAdd(&h->acc[ci][tile & (kGroups - 1)][0], tot);
+      }
+      __syncthreads();
+    }
   }
-  __shared__ uint32_t s_sum;
-  if (threadIdx.x == 0) s_sum = 0;
-  __syncthreads();
-  if (mine) atomicAdd(&s_sum, mine);
-  __syncthreads();
-  if (threadIdx.x == 0 && s_sum) atomicAdd(&c->count, s_sum);
-}
-
-// One bisection step of the adaptive voxel search (Sec. 3.3).
-__global__ void k_ctrl(const Frame* f, Ctrl* c, hav_info_t* info, KParams kp, int t_max) {
-  if (threadIdx.x != 0 || failed(f) || c->done) return;
-  const uint32_t cnt = c->count;
-  c->count = 0;
-  c->evals += 1;
-  const float s = c->s;
-  const int L = c->layer;
-  if (cnt >= c->m && cnt <= c->upper) {
-    c->accepted = 1;
-    c->done = 1;  // v, inv already hold this size
-  } else {
-    if (cnt < c->m) {
+  if (!arrive_last(h, gridDim.x)) return;
+  if (threadIdx.x != 0) return;
+  // ---- controller (one thread of the last block)
+  c->pend_set = set;
+  c->pend_nc = nc;
+  if (done) {
+    c->pend_nc = 0;
+    return;
+  }
+  c->set = set ^ 1;
+  uint32_t cnt[kMaxCand];
+  for (int k = 0; k < nc; ++k) {
+    uint32_t s = 0;
+    for (int g = 0; g < kGroups; ++g) {
+      s += load_acc(&h->acc[k][g][0]);
+      h->acc[k][g][0] = 0;
+    }
+    cnt[k] = s;
+  }
+  int k = 0;
+  while (k < nc) {
+    const uint32_t cc = cnt[k];
+    const float s = c->cand_s[k];
+    c->evals += 1;
+    if (cc >= c->m && cc <= c->upper) {
+      c->accepted = 1;
+      c->done = 1;
+      set_final(c, s, P);
+      break;
+    }
+    if (cc < c->m) {
       c->hi = s;
-      c->c_hi = cnt;
+      k = 2 * k + 1;
     } else {
       c->lo = s;
-      c->c_lo = cnt;
-    }
-    if (c->evals >= t_max) {
-      // no size in the window: the finest size with too many voxels if any (trim),
-      // else the smallest size evaluated (pad)
-      c->s = (c->lo > 0.0f) ? c->lo : c->hi;
-      set_scale(c, c->s, kp);
-      c->done = 1;
-    } else {
-      c->s = (c->lo + c->hi) * 0.5f;
-      set_scale(c, c->s, kp);
+      k = 2 * k + 2;
     }
   }
-  info->evals[L] = c->evals;
-  info->accepted[L] = c->accepted;
-  info->s[L] = c->done ? c->s : 0.0f;
+  if (!c->done) {
+    if (c->evals >= P.t_max) {
+      c->done = 1;
+      set_final(c, c->lo > 0.0f ? c->lo : c->hi, P);
+    } else {
+      plan_pass(c, P);
+    }
+  }
+  const int L = c->layer;
+  h->info.evals[L] = c->evals;
+  h->info.accepted[L] = c->accepted;
+  if (c->done) h->info.s[L] = c->s_final;
 }
 
 // ----------------------------------------------------------------------------- select
 
-// Centre-closest representative of every occupied voxel at the chosen size.
-__global__ void __launch_bounds__(kThreads) k_select(const float* __restrict__ xyz, int64_t n,
-                                                     const uint8_t* __restrict__ tag,
-                                                     const Frame* f, Ctrl* c,
-                                                     unsigned long long* keys,
-                                                     unsigned long long* vals, uint32_t mask,
-                                                     int shift) {
-  if (failed(f)) return;
-  const float v[3] = {c->v[0], c->v[1], c->v[2]};
-  const float inv[3] = {c->inv[0], c->inv[1], c->inv[2]};
-  const float o[3] = {f->mn[0], f->mn[1], f->mn[2]};
-  uint32_t mine = 0;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    if (tag[i]) continue;
-    float r[3];
-    uint32_t g[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) g[a] = axis_coord(xyz[3 * i + a], o[a], inv[a], &r[a]);
-    uint32_t slot;
-    mine += table_insert(keys, mask, shift, pack_key(g[0], g[1], g[2]), &slot) ? 1u : 0u;
-    const float d2 = centre_dist2(r, g, v);
-    const unsigned long long packed =
-        (static_cast<unsigned long long>(__float_as_uint(d2)) << 32) | static_cast<uint32_t>(i);
-    atomicMin(&vals[slot], packed);
+__global__ void __launch_bounds__(kThreads) k_select(Ws w, Plan P) {
+  Header* h = w.h;
+  if (h->frame.status != HAV_OK) return;
+  Ctrl* c = &h->ctrl;
+  const int tile = blockIdx.x;
+  clear_pending(w, c);
+  extern __shared__ uint64_t lds[];
+  uint64_t* lkeys = lds;
+  uint64_t* lvals = lds + kLdsCap;
+  __shared__ int s_ncl;
+  const float vx = c->v_final[0], vy = c->v_final[1], vz = c->v_final[2];
+  const float ix = c->inv_final[0], iy = c->inv_final[1], iz = c->inv_final[2];
+  for (int e = threadIdx.x; e < kLdsCap; e += kThreads) {
+    lkeys[e] = kEmptyKey;
+    lvals[e] = ~0ull;
   }
-  __shared__ uint32_t s_sum;
-  if (threadIdx.x == 0) s_sum = 0;
+  if (threadIdx.x == 0) s_ncl = 0;
   __syncthreads();
-  if (mine) atomicAdd(&s_sum, mine);
+  const int64_t base = static_cast<int64_t>(tile) * kTile;
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t i = base + k * kThreads + threadIdx.x;
+    if (i >= w.n || w.tag_s[i] != 0) continue;
+    const float px = w.rx[i], py = w.ry[i], pz = w.rz[i];
+    const uint32_t gx = axis_coord(px, ix), gy = axis_coord(py, iy), gz = axis_coord(pz, iz);
+    const float d2 = centre_dist2(px, py, pz, gx, gy, gz, vx, vy, vz);
+    const uint64_t packed = (static_cast<uint64_t>(__float_as_uint(d2)) << 32) |
+                            static_cast<uint32_t>(w.ordi[i]);
+    lds_insert_min(lkeys, lvals, kLdsCap - 1, pack_key(gx, gy, gz), packed);
+  }
   __syncthreads();
-  if (threadIdx.x == 0 && s_sum) atomicAdd(&c->ncand, s_sum);
+  int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
+  for (int e = threadIdx.x; e < kLdsCap; e += kThreads) {
+    const uint64_t key = lkeys[e];
+    if (key == kEmptyKey) continue;
+    bool claimed;
+    const uint32_t s = global_find_or_claim(w.skeys, w.cmask, key, &claimed);
+    if (claimed) list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(s);
+    atomicMin(&w.svals[s], static_cast<unsigned long long>(lvals[e]));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    w.scn[tile] = s_ncl;
+    if (s_ncl) atomicAdd(&h->acc[0][tile & (kGroups - 1)][0], static_cast<uint32_t>(s_ncl));
+  }
+  if (!arrive_last(h, gridDim.x)) return;
+  if (threadIdx.x != 0) return;
+  uint32_t nvox = 0;
+  for (int g = 0; g < kGroups; ++g) {
+    nvox += load_acc(&h->acc[0][g][0]);
+    h->acc[0][g][0] = 0;
+  }
+  c->pend_nc = 0;
+  c->ncand = nvox;
+  c->trim = nvox > c->m ? 1 : 0;
+  c->need = nvox < c->m ? c->m - nvox : 0u;
+  c->prefix = 0;
+  c->rank = c->m - 1;
+  c->rounds_done = 0;
+  const int L = c->layer;
+  h->info.count[L] = static_cast<int32_t>(nvox);
+  h->info.trimmed[L] = nvox > c->m ? static_cast<int32_t>(nvox - c->m) : 0;
+  h->info.padded[L] = static_cast<int32_t>(c->need);
+  h->info.s[L] = c->s_final;
 }
 
-// Turn the occupied slots into a candidate list (priority, point index).
-__global__ void __launch_bounds__(kThreads) k_collect(const unsigned long long* keys,
-                                                      const unsigned long long* vals,
-                                                      uint32_t cap, const Frame* f, Ctrl* c,
-                                                      uint64_t* cand_prio, int32_t* cand_idx,
-                                                      uint32_t* cursor, int64_t n) {
-  if (failed(f)) return;
-  for (int64_t s = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; s < cap;
-       s += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const unsigned long long k = keys[s];
-    const bool occ = (k != kEmptyKey);
-    const uint64_t bal = __ballot(occ);
-    if (!bal) continue;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll(static_cast<unsigned long long>(bal)) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(cursor, static_cast<uint32_t>(__popcll(bal)));
-    base = __shfl(base, leader, 64);
-    if (occ) {
-      const uint32_t off = base + __popcll(bal & ((1ull << lane) - 1ull));
-      if (off < n) {  // at most n distinct keys; the bound only guards the store
-        cand_prio[off] = voxel_priority(k);
-        cand_idx[off] = static_cast<int32_t>(vals[s] & 0xFFFFFFFFu);
+// ----------------------------------------------------------------------------- trim
+
+__global__ void __launch_bounds__(kThreads) k_trim_hist(Ws w, int round) {
+  Header* h = w.h;
+  if (h->frame.status != HAV_OK) return;
+  Ctrl* c = &h->ctrl;
+  if (!c->trim) return;
+  __shared__ uint32_t lh[256];
+  for (int i = threadIdx.x; i < 256; i += kThreads) lh[i] = 0;
+  __syncthreads();
+  const int tile = blockIdx.x;
+  const int n = w.scn[tile];
+  const int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
+  const int dshift = 56 - 8 * round;
+  const uint64_t pref = c->prefix;
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const uint64_t p = voxel_priority(w.skeys[list[i]]);
+    if (round > 0 && (p >> (dshift + 8)) != (pref >> (dshift + 8))) continue;
+    atomicAdd(&lh[(p >> dshift) & 255u], 1u);
+  }
+  __syncthreads();
+  const int g = tile & (kGroups - 1);
+  for (int i = threadIdx.x; i < 256; i += kThreads)
+    if (lh[i]) atomicAdd(&h->hist[g][i], lh[i]);
+  if (!arrive_last(h, gridDim.x)) return;
+  // last block: total histogram, pick the digit holding rank
+  __shared__ uint32_t tot[256];
+  for (int i = threadIdx.x; i < 256; i += kThreads) {
+    uint32_t s = 0;
+    for (int q = 0; q < kGroups; ++q) {
+      s += load_acc(&h->hist[q][i]);
+      h->hist[q][i] = 0;
+    }
+    tot[i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t rank = c->rank, acc = 0;
+    int b = 0;
+    for (; b < 255; ++b) {
+      if (rank < acc + tot[b]) break;
+      acc += tot[b];
+    }
+    c->rank = rank - acc;
+    c->prefix |= static_cast<uint64_t>(b) << dshift;
+    c->rounds_done = round + 1;
+  }
+}
+
+// Keep the representatives below the prefix bucket, queue the bucket's members, and
+// empty the voxel table. The last block picks the exact rank inside the bucket.
+__global__ void __launch_bounds__(kThreads) k_mark(Ws w) {
+  Header* h = w.h;
+  if (h->frame.status != HAV_OK) return;
+  Ctrl* c = &h->ctrl;
+  const int tile = blockIdx.x;
+  const int n = w.scn[tile];
+  const int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
+  const int trim = c->trim;
+  const int R = c->rounds_done;
+  const int shift = 64 - 8 * R;  // bits below the decided prefix
+  const uint64_t pref_hi = shift >= 64 ? 0ull : (c->prefix >> shift);
+  const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
+  const int g = tile & (kGroups - 1);
+  __shared__ uint32_t s_base;
+  // ties are staged through registers: at most kPerThread per thread per chunk
+  for (int i0 = 0; i0 < n; i0 += kThreads) {
+    const int i = i0 + threadIdx.x;
+    bool tie = false;
+    uint64_t p = 0;
+    int32_t orig = 0;
+    if (i < n) {
+      const int32_t s = list[i];
+      const uint64_t key = w.skeys[s];
+      orig = static_cast<int32_t>(w.svals[s] & 0xFFFFFFFFull);
+      w.skeys[s] = kEmptyKey;
+      w.svals[s] = ~0ull;
+      bool keep = true;
+      if (trim) {
+        p = voxel_priority(key);
+        const uint64_t hi = shift >= 64 ? 0ull : (p >> shift);
+        keep = hi < pref_hi;
+        tie = hi == pref_hi;
+      }
+      if (keep && orig >= 0 && orig < w.n) {
+        w.tag_o[orig] = lt;
+        w.tag_s[w.invp[orig]] = lt;
+      }
+    }
+    // append ties of this chunk to the group's list
+    const uint64_t bal = __ballot(tie);
+    __shared__ uint32_t s_wbase[kThreads / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) s_wbase[wv] = static_cast<uint32_t>(__popcll(bal));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (int q = 0; q < kThreads / 64; ++q) {
+        const uint32_t t = s_wbase[q];
+        s_wbase[q] = tot;
+        tot += t;
+      }
+      s_base = tot ? atomicAdd(&h->tie_cur[g][0], tot) : 0u;
+    }
+    __syncthreads();
+    if (tie) {
+      const uint32_t pos = s_base + s_wbase[wv] + static_cast<uint32_t>(__popcll(bal & ((1ull << lane) - 1ull)));
+      if (pos < w.tie_seg) {
+        w.tie_p[g * w.tie_seg + pos] = p;
+        w.tie_o[g * w.tie_seg + pos] = orig;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) w.scn[tile] = 0;
+  if (!arrive_last(h, gridDim.x)) return;
+  // ---- last block: exact rank inside the bucket (radix select over the ties)
+  __shared__ uint32_t cnt_g[kGroups];
+  __shared__ uint32_t hst[256];
+  __shared__ uint64_t s_pref;
+  __shared__ uint32_t s_rank;
+  if (threadIdx.x < kGroups) {
+    const uint32_t t = load_acc(&h->tie_cur[threadIdx.x][0]);
+    cnt_g[threadIdx.x] = t < w.tie_seg ? t : static_cast<uint32_t>(w.tie_seg);
+    h->tie_cur[threadIdx.x][0] = 0;
+  }
+  if (threadIdx.x == 0) {
+    s_pref = c->prefix;
+    s_rank = c->rank;
+  }
+  __syncthreads();
+  if (!trim) return;
+  for (int sh = shift - 8; sh >= 0; sh -= 8) {
+    for (int i = threadIdx.x; i < 256; i += kThreads) hst[i] = 0;
+    __syncthreads();
+    const uint64_t pref = s_pref;
+    for (int q = 0; q < kGroups; ++q) {
+      for (uint32_t i = threadIdx.x; i < cnt_g[q]; i += kThreads) {
+        const uint64_t p = w.tie_p[q * w.tie_seg + i];
+        if (sh + 8 < 64 && (p >> (sh + 8)) != (pref >> (sh + 8))) continue;
+        atomicAdd(&hst[(p >> sh) & 255u], 1u);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t rank = s_rank, acc = 0;
+      int b = 0;
+      for (; b < 255; ++b) {
+        if (rank < acc + hst[b]) break;
+        acc += hst[b];
+      }
+      s_rank = rank - acc;
+      s_pref = pref | (static_cast<uint64_t>(b) << sh);
+    }
+    __syncthreads();
+  }
+  const uint64_t thr = s_pref;  // the rank-th smallest priority of the bucket
+  for (int q = 0; q < kGroups; ++q) {
+    for (uint32_t i = threadIdx.x; i < cnt_g[q]; i += kThreads) {
+      if (w.tie_p[q * w.tie_seg + i] <= thr) {
+        const int32_t orig = w.tie_o[q * w.tie_seg + i];
+        if (orig >= 0 && orig < w.n) {
+          w.tag_o[orig] = lt;
+          w.tag_s[w.invp[orig]] = lt;
+        }
       }
     }
   }
 }
 
-__global__ void k_trim_begin(const Frame* f, Ctrl* c, hav_info_t* info) {
-  if (failed(f)) return;
-  const int t = threadIdx.x;
-  for (int i = t; i < kRadixBins; i += blockDim.x) c->hist[i] = 0;
-  if (t == 0) {
-    const uint32_t nc = c->ncand;
-    const int L = c->layer;
-    c->trim = nc > c->m ? 1u : 0u;
-    c->prefix = 0;
-    c->rank = c->m - 1;  // 0-based rank of the m-th smallest priority
-    info->count[L] = static_cast<int32_t>(nc);
-    info->trimmed[L] = nc > c->m ? static_cast<int32_t>(nc - c->m) : 0;
-    info->padded[L] = nc < c->m ? static_cast<int32_t>(c->m - nc) : 0;
-    if (!c->accepted) info->s[L] = c->s;
-  }
-}
+// ----------------------------------------------------------------------------- scans over tag_o
 
-// Radix select over the 64-bit priorities, kRadixBits per pass from the top.
-__global__ void __launch_bounds__(kThreads) k_radix_hist(const uint64_t* __restrict__ prio,
-                                                         const Frame* f, Ctrl* c, int pass) {
-  if (failed(f) || !c->trim) return;
-  __shared__ uint32_t h[kRadixBins];
-  for (int i = threadIdx.x; i < kRadixBins; i += kThreads) h[i] = 0;
-  __syncthreads();
-  const uint32_t nc = min(c->ncand, c->ncap);
-  const int shift = 64 - kRadixBits * (pass + 1);
-  const int hi_shift = shift + kRadixBits;  // bits above this digit must equal prefix
-  const uint64_t pref = c->prefix;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < nc;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const uint64_t p = prio[i];
-    if (hi_shift < 64 && (p >> hi_shift) != (pref >> hi_shift)) continue;
-    atomicAdd(&h[(p >> shift) & (kRadixBins - 1)], 1u);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kRadixBins; i += kThreads)
-    if (h[i]) atomicAdd(&c->hist[i], h[i]);
-}
-
-__global__ void k_radix_pick(const Frame* f, Ctrl* c, int pass) {
-  if (failed(f) || !c->trim) return;
-  if (threadIdx.x == 0) {
-    const int shift = 64 - kRadixBits * (pass + 1);
-    uint32_t rank = c->rank;
-    uint32_t acc = 0;
-    int b = 0;
-    for (; b < kRadixBins; ++b) {
-      const uint32_t h = c->hist[b];
-      if (rank < acc + h) break;
-      acc += h;
-    }
-    c->rank = rank - acc;
-    c->prefix |= static_cast<uint64_t>(b) << shift;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kRadixBins; i += blockDim.x) c->hist[i] = 0;
-}
-
-// Mark the kept representatives: all of them, or those with priority <= the m-th
-// smallest (c->prefix after the last pass).
-__global__ void __launch_bounds__(kThreads) k_mark(const uint64_t* __restrict__ prio,
-                                                   const int32_t* __restrict__ idx,
-                                                   const Frame* f, const Ctrl* c, uint8_t* tag,
-                                                   int64_t n) {
-  if (failed(f)) return;
-  const uint32_t nc = min(static_cast<int64_t>(c->ncand), n);
-  const bool trim = c->trim;
-  const uint64_t thr = c->prefix;
-  const uint8_t t = static_cast<uint8_t>(c->layer + 1);
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < nc;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const int32_t j = idx[i];
-    if ((!trim || prio[i] <= thr) && j >= 0 && j < n) tag[j] = t;
-  }
-}
-
-// ----------------------------------------------------------------------------- scans
-
-// Block-exclusive scan of one value per thread; returns the block total.
-__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* excl) {
-  __shared__ uint32_t s_w[kThreads / 64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) s_w[wv] = x;
-  __syncthreads();
-  uint32_t wbase = 0, total = 0;
-  for (int w = 0; w < kThreads / 64; ++w) {
-    if (w < wv) wbase += s_w[w];
-    total += s_w[w];
-  }
-  *excl = wbase + x - v;
-  __syncthreads();
-  return total;
-}
-
-// mode 0: count tag == 0 (pad candidates); mode 1: count tag != 0 (output)
-__device__ __forceinline__ bool scan_pred(uint8_t t, int mode) { return mode ? (t != 0) : (t == 0); }
-
-__global__ void __launch_bounds__(kThreads) k_tile_count(const uint8_t* __restrict__ tag, int64_t n,
-                                                         uint32_t* tile_sums, int mode,
-                                                         const Frame* f, const Ctrl* c) {
-  if (failed(f)) return;
-  if (mode == 0 && c->ncand >= c->m) return;  // no pad needed
-  const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanItems;
+// mode 0: pad (count tag_o == 0), only when the layer is short; mode 1: output.
+__global__ void __launch_bounds__(kThreads) k_scan_count(Ws w, int mode) {
+  Header* h = w.h;
+  if (h->frame.status != HAV_OK) return;
+  if (mode == 0 && h->ctrl.need == 0) return;
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
   uint32_t cnt = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n && scan_pred(tag[base + k], mode)) ++cnt;
-  uint32_t excl;
-  const uint32_t tot = block_exclusive_scan(cnt, &excl);
-  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
-}
-
-// Exclusive scan of the tile sums in place (one block, sequential over chunks).
-__global__ void __launch_bounds__(kThreads) k_scan_tiles(uint32_t* tile_sums, int64_t ntiles,
-                                                         int mode, const Frame* f, const Ctrl* c) {
-  if (failed(f)) return;
-  if (mode == 0 && c->ncand >= c->m) return;
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < w.n) {
+      const uint8_t t = w.tag_o[base + k];
+      cnt += mode ? (t != 0) : (t == 0);
+    }
+  }
+  const uint32_t tot = block_sum_u32<kThreads>(cnt, s_tmp);
+  if (threadIdx.x == 0) w.tcnt[blockIdx.x] = tot;
+  if (!arrive_last(h, gridDim.x)) return;
+  // last block: exclusive scan of the tile counts
   uint32_t carry = 0;
-  for (int64_t b = 0; b < ntiles; b += kThreads) {
-    const int64_t i = b + threadIdx.x;
-    const uint32_t v = i < ntiles ? tile_sums[i] : 0u;
-    uint32_t excl;
-    const uint32_t tot = block_exclusive_scan(v, &excl);
-    if (i < ntiles) tile_sums[i] = carry + excl;
-    carry += tot;
+  for (int b0 = 0; b0 < static_cast<int>(gridDim.x); b0 += kThreads) {
+    const int b = b0 + threadIdx.x;
+    const uint32_t v = b < static_cast<int>(gridDim.x) ? w.tcnt[b] : 0u;
+    uint32_t ex;
+    const uint32_t t = block_exclusive_scan<kThreads>(v, &ex, s_tmp);
+    if (b < static_cast<int>(gridDim.x)) w.tcnt[b] = carry + ex;
+    carry += t;
+    __syncthreads();
   }
 }
 
-// Pad: mark the lowest-index unsampled points until the layer has m picks.
-__global__ void __launch_bounds__(kThreads) k_pad_mark(uint8_t* tag, int64_t n,
-                                                       const uint32_t* tile_sums, const Frame* f,
-                                                       const Ctrl* c) {
-  if (failed(f) || c->ncand >= c->m) return;
-  const uint32_t need = c->m - c->ncand;
+// Pad: mark the lowest-index unsampled points; then start the next layer.
+__global__ void __launch_bounds__(kThreads) k_pad_mark(Ws w, Plan P) {
+  Header* h = w.h;
+  if (h->frame.status != HAV_OK) return;
+  Ctrl* c = &h->ctrl;
+  const uint32_t need = c->need;
   const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
-  const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanItems;
-  uint8_t t[kScanItems];
-  uint32_t cnt = 0;
+  const int L = c->layer;
+  if (need > 0) {
+    __shared__ uint32_t s_tmp[kThreads / 64];
+    const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
+    uint8_t t[kScanPer];
+    uint32_t cnt = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    t[k] = base + k < n ? tag[base + k] : 1;
-    cnt += (t[k] == 0);
-  }
-  uint32_t excl;
-  block_exclusive_scan(cnt, &excl);
-  uint32_t r = tile_sums[blockIdx.x] + excl;
+    for (int k = 0; k < kScanPer; ++k) {
+      t[k] = base + k < w.n ? w.tag_o[base + k] : 1;
+      cnt += (t[k] == 0);
+    }
+    uint32_t ex;
+    block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
+    uint32_t r = w.tcnt[blockIdx.x] + ex;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (t[k] == 0) {
-      if (r < need) tag[base + k] = lt;
-      ++r;
+    for (int k = 0; k < kScanPer; ++k) {
+      if (t[k] == 0) {
+        if (r < need) {
+          w.tag_o[base + k] = lt;
+          w.tag_s[w.invp[base + k]] = lt;
+        }
+        ++r;
+      }
     }
   }
+  if (!arrive_last(h, gridDim.x)) return;
+  if (threadIdx.x == 0 && L + 1 < P.nlayers) layer_init(h, P, L + 1);
 }
 
-__global__ void __launch_bounds__(kThreads) k_out_write(const uint8_t* __restrict__ tag, int64_t n,
-                                                        const uint32_t* tile_sums, int32_t* idx,
-                                                        int64_t M, const Frame* f) {
-  if (failed(f)) return;
-  const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanItems;
-  uint8_t t[kScanItems];
+__global__ void __launch_bounds__(kThreads) k_out_write(Ws w, int32_t* idx, int64_t M,
+                                                        hav_info_t* info_dev) {
+  Header* h = w.h;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && info_dev) *info_dev = h->info;
+  if (h->frame.status != HAV_OK) return;
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
+  uint8_t t[kScanPer];
   uint32_t cnt = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    t[k] = base + k < n ? tag[base + k] : 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    t[k] = base + k < w.n ? w.tag_o[base + k] : 0;
     cnt += (t[k] != 0);
   }
-  uint32_t excl;
-  block_exclusive_scan(cnt, &excl);
-  uint32_t r = tile_sums[blockIdx.x] + excl;
+  uint32_t ex;
+  block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
+  uint32_t r = w.tcnt[blockIdx.x] + ex;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
+  for (int k = 0; k < kScanPer; ++k) {
     if (t[k]) {
       if (r < M) idx[r] = static_cast<int32_t>(base + k);
       ++r;
     }
+  }
 }
 
-__global__ void __launch_bounds__(kThreads) k_iota(int32_t* idx, int64_t n) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads)
-    idx[i] = static_cast<int32_t>(i);
+// ----------------------------------------------------------------------------- workspace init
+
+__global__ void __launch_bounds__(kThreads) k_ws_init(Ws w, size_t nct, size_t ncn, size_t nst,
+                                                      size_t nsn) {
+  const size_t stride = static_cast<size_t>(gridDim.x) * kThreads;
+  const size_t t0 = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
+  for (size_t i = t0; i < nct; i += stride) {
+    w.ckeys[i] = kEmptyKey;
+    w.cmasks[i] = 0ull;
+  }
+  for (size_t i = t0; i < ncn; i += stride) w.ccn[i] = 0;
+  for (size_t i = t0; i < nst; i += stride) {
+    w.skeys[i] = kEmptyKey;
+    w.svals[i] = ~0ull;
+  }
+  for (size_t i = t0; i < nsn; i += stride) w.scn[i] = 0;
+  uint32_t* hz = reinterpret_cast<uint32_t*>(w.h);
+  for (size_t i = t0; i < sizeof(Header) / 4; i += stride) hz[i] = 0;
 }
 
-__global__ void __launch_bounds__(kThreads) k_zero_u8(uint8_t* p, int64_t n) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads)
-    p[i] = 0;
+// The magic is written by a later kernel than the clearing, so it is only seen set
+// once everything else is.
+__global__ void k_ws_seal(Header* h, uint64_t magic) {
+  if (threadIdx.x == 0) h->magic = magic;
 }
 
-__global__ void k_copy_info(const hav_info_t* src, hav_info_t* dst) {
-  const int32_t* s = reinterpret_cast<const int32_t*>(src);
-  int32_t* d = reinterpret_cast<int32_t*>(dst);
-  for (int i = threadIdx.x; i < static_cast<int>(sizeof(hav_info_t) / 4); i += blockDim.x) d[i] = s[i];
-}
-
-// ----------------------------------------------------------------------------- chain
+// ----------------------------------------------------------------------------- chain helpers
 
 __global__ void __launch_bounds__(kThreads) k_gather(const float* __restrict__ xyz, int64_t n,
                                                      const int32_t* __restrict__ idx, int64_t m,
@@ -576,36 +1057,110 @@ __global__ void __launch_bounds__(kThreads) k_compose(const int32_t* __restrict_
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
-struct Layout {
-  size_t frame = 0, ctrl = 0, info = 0, cursor = 0, tag = 0, keys = 0, vals = 0, prio = 0,
-         cidx = 0, tiles = 0, total = 0;
-  uint32_t cap = 0;
-  int shift = 0;
-  int64_t ntiles = 0;
-};
+int depth_of(const hav_params_t* p) {
+  return p->spec_depth == 0 ? kDefaultDepth : p->spec_depth;
+}
 
-Layout make_layout(int64_t n) {
-  Layout L;
+uint32_t table_cap(int64_t n) {
   uint64_t cap = 1024;
   while (cap < 2 * static_cast<uint64_t>(n)) cap <<= 1;
-  L.cap = static_cast<uint32_t>(cap);
-  int lg = 0;
-  while ((1ull << lg) < cap) ++lg;
-  L.shift = 64 - lg;
-  L.ntiles = (n + kScanTile - 1) / kScanTile;
+  return static_cast<uint32_t>(cap);
+}
+
+int bbox_blocks(int64_t n) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kMaxBBoxBlocks, (n + 2047) / 2048)));
+}
+int bin_blocks(int64_t n) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kMaxBinBlocks, (n + 4095) / 4096)));
+}
+
+struct Layout {
+  size_t hdr, rx, ry, rz, ordi, invp, tag_s, tag_o, part, bh, bsum, ckeys, cmasks, ccl, ccn, skeys,
+      svals, scl, scn, tie_p, tie_o, tcnt, total;
+  int64_t n_ws;
+  uint32_t cap_ws;
+  int32_t ntile_ws, nscan_ws, ncmax;
+  int64_t tie_seg;
+};
+
+Layout make_layout(int64_t n, int depth) {
+  Layout L;
+  L.n_ws = n;
+  L.cap_ws = table_cap(n);
+  L.ntile_ws = static_cast<int32_t>((n + kTile - 1) / kTile);
+  L.nscan_ws = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
+  L.ncmax = (1 << depth) - 1;
+  L.tie_seg = static_cast<int64_t>((L.ntile_ws + kGroups - 1) / kGroups) * kTile;
+  const size_t N = static_cast<size_t>(n);
+  const size_t tabs = 2 * static_cast<size_t>(L.ncmax);
   size_t o = 0;
-  L.frame = o;  o = align_up(o + sizeof(Frame));
-  L.ctrl = o;   o = align_up(o + sizeof(Ctrl));
-  L.info = o;   o = align_up(o + sizeof(hav_info_t));
-  L.cursor = o; o = align_up(o + sizeof(uint32_t));
-  L.tag = o;    o = align_up(o + static_cast<size_t>(n));
-  L.keys = o;   o = align_up(o + cap * 8);
-  L.vals = o;   o = align_up(o + cap * 8);
-  L.prio = o;   o = align_up(o + static_cast<size_t>(n) * 8);
-  L.cidx = o;   o = align_up(o + static_cast<size_t>(n) * 4);
-  L.tiles = o;  o = align_up(o + static_cast<size_t>(L.ntiles) * 4);
+  L.hdr = o;    o = align_up(o + sizeof(Header));
+  L.rx = o;     o = align_up(o + N * 4);
+  L.ry = o;     o = align_up(o + N * 4);
+  L.rz = o;     o = align_up(o + N * 4);
+  L.ordi = o;   o = align_up(o + N * 4);
+  L.invp = o;   o = align_up(o + N * 4);
+  L.tag_s = o;  o = align_up(o + N);
+  L.tag_o = o;  o = align_up(o + N);
+  L.part = o;   o = align_up(o + static_cast<size_t>(kMaxBBoxBlocks) * 8 * 4);
+  L.bh = o;     o = align_up(o + static_cast<size_t>(kBins) * kMaxBinBlocks * 4);
+  L.bsum = o;   o = align_up(o + static_cast<size_t>(kMaxBinBlocks) * 4);
+  L.ckeys = o;  o = align_up(o + tabs * L.cap_ws * 8);
+  L.cmasks = o; o = align_up(o + tabs * L.cap_ws * 8);
+  L.ccl = o;    o = align_up(o + tabs * L.ntile_ws * kTile * 4);
+  L.ccn = o;    o = align_up(o + tabs * L.ntile_ws * 4);
+  L.skeys = o;  o = align_up(o + static_cast<size_t>(L.cap_ws) * 8);
+  L.svals = o;  o = align_up(o + static_cast<size_t>(L.cap_ws) * 8);
+  L.scl = o;    o = align_up(o + static_cast<size_t>(L.ntile_ws) * kTile * 4);
+  L.scn = o;    o = align_up(o + static_cast<size_t>(L.ntile_ws) * 4);
+  L.tie_p = o;  o = align_up(o + static_cast<size_t>(kGroups) * L.tie_seg * 8);
+  L.tie_o = o;  o = align_up(o + static_cast<size_t>(kGroups) * L.tie_seg * 4);
+  L.tcnt = o;   o = align_up(o + static_cast<size_t>(L.nscan_ws) * 4);
   L.total = o;
   return L;
+}
+
+uint64_t magic_of(const Layout& L) {
+  return kMagic ^ (static_cast<uint64_t>(L.n_ws) << 8) ^ (static_cast<uint64_t>(L.ncmax) << 56);
+}
+
+// Device view of the workspace for a stage of n points (n <= the workspace's size).
+Ws make_ws(char* base, const Layout& L, int64_t n) {
+  Ws w;
+  w.h = reinterpret_cast<Header*>(base + L.hdr);
+  w.rx = reinterpret_cast<float*>(base + L.rx);
+  w.ry = reinterpret_cast<float*>(base + L.ry);
+  w.rz = reinterpret_cast<float*>(base + L.rz);
+  w.ordi = reinterpret_cast<int32_t*>(base + L.ordi);
+  w.invp = reinterpret_cast<int32_t*>(base + L.invp);
+  w.tag_s = reinterpret_cast<uint8_t*>(base + L.tag_s);
+  w.tag_o = reinterpret_cast<uint8_t*>(base + L.tag_o);
+  w.part = reinterpret_cast<uint32_t*>(base + L.part);
+  w.bh = reinterpret_cast<uint32_t*>(base + L.bh);
+  w.bsum = reinterpret_cast<uint32_t*>(base + L.bsum);
+  w.ckeys = reinterpret_cast<unsigned long long*>(base + L.ckeys);
+  w.cmasks = reinterpret_cast<unsigned long long*>(base + L.cmasks);
+  w.ccl = reinterpret_cast<int32_t*>(base + L.ccl);
+  w.ccn = reinterpret_cast<int32_t*>(base + L.ccn);
+  w.skeys = reinterpret_cast<unsigned long long*>(base + L.skeys);
+  w.svals = reinterpret_cast<unsigned long long*>(base + L.svals);
+  w.scl = reinterpret_cast<int32_t*>(base + L.scl);
+  w.scn = reinterpret_cast<int32_t*>(base + L.scn);
+  w.tie_p = reinterpret_cast<uint64_t*>(base + L.tie_p);
+  w.tie_o = reinterpret_cast<int32_t*>(base + L.tie_o);
+  w.tcnt = reinterpret_cast<uint32_t*>(base + L.tcnt);
+  w.n = n;
+  w.ntile = static_cast<int32_t>((n + kTile - 1) / kTile);
+  w.nscan = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
+  w.nbb = bin_blocks(n);
+  w.nbbox = bbox_blocks(n);
+  w.cap = table_cap(n);
+  w.cmask = w.cap - 1;
+  w.cap_ws = L.cap_ws;
+  w.ntile_ws = L.ntile_ws;
+  w.ncmax = L.ncmax;
+  w.tie_seg = L.tie_seg;
+  return w;
 }
 
 bool params_ok(const hav_params_t* p) {
@@ -615,6 +1170,7 @@ bool params_ok(const hav_params_t* p) {
   if (p->t_max < 1 || p->t_max > 20) return false;
   if (!std::isfinite(p->sigma) || p->sigma < 0.0 || p->sigma > 16.0) return false;
   if (p->flags & ~HAV_FIXED_VOXEL) return false;
+  if (p->spec_depth < 0 || p->spec_depth > kMaxDepth) return false;
   for (int a = 0; a < 3; ++a) {
     const float as = p->aspect[a];
     if (!std::isfinite(as) || as < 0x1p-16f || as > 0x1p16f) return false;
@@ -640,94 +1196,73 @@ void layer_sizes(int64_t M, int k, int r, int64_t* m) {
   m[k - 1] = M - used;
 }
 
-int grid_for(int64_t work, int per_block = kThreads) {
-  const int64_t g = (work + per_block - 1) / per_block;
+int grid_for(int64_t work) {
+  const int64_t g = (work + kThreads - 1) / kThreads;
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, 4096)));
 }
 
-#define HAV_LAUNCH(...)                              \
-  do {                                               \
-    hipLaunchKernelGGL(__VA_ARGS__);                 \
-    if (hipGetLastError() != hipSuccess) return HAV_ERR_HIP; \
+// Radix rounds over the top priority bits before the last block settles the bucket:
+// enough that the expected bucket (n / 256^R) stays small.
+int trim_rounds(int64_t n) {
+  int R = 1;
+  while (R < 7 && (n >> (8 * R)) > 2048) ++R;
+  return R;
+}
+
+#define HAV_LAUNCH(...)                                          \
+  do {                                                           \
+    hipLaunchKernelGGL(__VA_ARGS__);                             \
+    if (hipGetLastError() != hipSuccess) return HAV_ERR_HIP;     \
   } while (0)
 
+constexpr size_t kLdsBytes = 2 * kLdsCap * sizeof(uint64_t);
+
 hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_t* p, int32_t* idx,
-                       char* ws, hav_info_t* info_dev, hipStream_t st) {
-  const Layout L = make_layout(N);
-  Frame* f = reinterpret_cast<Frame*>(ws + L.frame);
-  Ctrl* c = reinterpret_cast<Ctrl*>(ws + L.ctrl);
-  hav_info_t* info = reinterpret_cast<hav_info_t*>(ws + L.info);
-  uint32_t* cursor = reinterpret_cast<uint32_t*>(ws + L.cursor);
-  uint8_t* tag = reinterpret_cast<uint8_t*>(ws + L.tag);
-  unsigned long long* keys = reinterpret_cast<unsigned long long*>(ws + L.keys);
-  unsigned long long* vals = reinterpret_cast<unsigned long long*>(ws + L.vals);
-  uint64_t* prio = reinterpret_cast<uint64_t*>(ws + L.prio);
-  int32_t* cidx = reinterpret_cast<int32_t*>(ws + L.cidx);
-  uint32_t* tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
-
-  KParams kp{};
+                       char* ws, const Layout& L, hav_info_t* info_dev, hipStream_t st) {
+  Ws w = make_ws(ws, L, N);
+  Plan P;
+  std::memset(&P, 0, sizeof(P));
+  P.t_max = p->t_max;
+  P.depth = depth_of(p);
+  P.fixed = (p->flags & HAV_FIXED_VOXEL) ? 1 : 0;
+  P.magic = magic_of(L);
   for (int a = 0; a < 3; ++a) {
-    kp.aspect[a] = p->aspect[a];
-    kp.fixed_v[a] = p->fixed_voxel[a];
+    P.aspect[a] = p->aspect[a];
+    P.fixed_v[a] = p->fixed_voxel[a];
   }
-  kp.fixed = (p->flags & HAV_FIXED_VOXEL) ? 1 : 0;
-  const bool identity = (M == N);
+  int64_t m[HAV_MAX_LAYERS];
+  layer_sizes(M, p->layers, p->layer_ratio, m);
+  int nl = 0;
+  for (int l = 0; l < p->layers; ++l) {
+    if (m[l] == 0) continue;
+    const double up = std::floor(static_cast<double>(m[l]) * (1.0 + p->sigma));
+    P.m[nl] = static_cast<uint32_t>(m[l]);
+    P.upper[nl] = up >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(up);
+    ++nl;
+  }
+  P.nlayers = nl;
 
-  HAV_LAUNCH(k_begin, dim3(1), dim3(64), 0, st, f, info);
-  HAV_LAUNCH(k_bbox, dim3(grid_for(N)), dim3(kThreads), 0, st, xyz, N, f);
-  HAV_LAUNCH(k_frame, dim3(1), dim3(1), 0, st, f, info, kp, identity ? 1 : 0);
-  if (identity) {
-    HAV_LAUNCH(k_iota, dim3(grid_for(N)), dim3(kThreads), 0, st, idx, N);
-  } else {
-    HAV_LAUNCH(k_zero_u8, dim3(grid_for(N)), dim3(kThreads), 0, st, tag, N);
-    int64_t m[HAV_MAX_LAYERS];
-    layer_sizes(M, p->layers, p->layer_ratio, m);
-    int out_layer = 0;
-    for (int l = 0; l < p->layers; ++l) {
-      if (m[l] == 0) continue;
-      const int lay = out_layer++;
-      const double up = std::floor(static_cast<double>(m[l]) * (1.0 + p->sigma));
-      const uint32_t upper = up >= 2147483647.0 ? 0x7FFFFFFFu : static_cast<uint32_t>(up);
-      HAV_LAUNCH(k_layer_begin, dim3(1), dim3(1), 0, st, f, c, info, kp, lay,
-                 static_cast<uint32_t>(m[l]), upper, static_cast<uint32_t>(N));
-      if (!kp.fixed) {
-        for (int t = 0; t < p->t_max; ++t) {
-          HAV_LAUNCH(k_fill_u64, dim3(grid_for(L.cap)), dim3(kThreads), 0, st, keys,
-                     static_cast<int64_t>(L.cap), kEmptyKey, f, c);
-          HAV_LAUNCH(k_count, dim3(grid_for(N)), dim3(kThreads), 0, st, xyz, N, tag, f, c, keys,
-                     L.cap - 1, L.shift);
-          HAV_LAUNCH(k_ctrl, dim3(1), dim3(1), 0, st, f, c, info, kp, p->t_max);
-        }
-      }
-      HAV_LAUNCH(k_fill_u64, dim3(grid_for(L.cap)), dim3(kThreads), 0, st, keys,
-                 static_cast<int64_t>(L.cap), kEmptyKey, f, nullptr);
-      HAV_LAUNCH(k_fill_u64, dim3(grid_for(L.cap)), dim3(kThreads), 0, st, vals,
-                 static_cast<int64_t>(L.cap), ~0ull, f, nullptr);
-      HAV_LAUNCH(k_fill_u64, dim3(1), dim3(64), 0, st,
-                 reinterpret_cast<unsigned long long*>(cursor), 1, 0ull, f, nullptr);
-      HAV_LAUNCH(k_select, dim3(grid_for(N)), dim3(kThreads), 0, st, xyz, N, tag, f, c, keys, vals,
-                 L.cap - 1, L.shift);
-      HAV_LAUNCH(k_collect, dim3(grid_for(L.cap)), dim3(kThreads), 0, st, keys, vals, L.cap, f, c,
-                 prio, cidx, cursor, N);
-      HAV_LAUNCH(k_trim_begin, dim3(1), dim3(kThreads), 0, st, f, c, info);
-      for (int pass = 0; pass < 64 / kRadixBits; ++pass) {
-        HAV_LAUNCH(k_radix_hist, dim3(grid_for(N)), dim3(kThreads), 0, st, prio, f, c, pass);
-        HAV_LAUNCH(k_radix_pick, dim3(1), dim3(kThreads), 0, st, f, c, pass);
-      }
-      HAV_LAUNCH(k_mark, dim3(grid_for(N)), dim3(kThreads), 0, st, prio, cidx, f, c, tag, N);
-      HAV_LAUNCH(k_tile_count, dim3(static_cast<unsigned>(L.ntiles)), dim3(kThreads), 0, st, tag, N,
-                 tiles, 0, f, c);
-      HAV_LAUNCH(k_scan_tiles, dim3(1), dim3(kThreads), 0, st, tiles, L.ntiles, 0, f, c);
-      HAV_LAUNCH(k_pad_mark, dim3(static_cast<unsigned>(L.ntiles)), dim3(kThreads), 0, st, tag, N,
-                 tiles, f, c);
-    }
-    HAV_LAUNCH(k_tile_count, dim3(static_cast<unsigned>(L.ntiles)), dim3(kThreads), 0, st, tag, N,
-               tiles, 1, f, c);
-    HAV_LAUNCH(k_scan_tiles, dim3(1), dim3(kThreads), 0, st, tiles, L.ntiles, 1, f, c);
-    HAV_LAUNCH(k_out_write, dim3(static_cast<unsigned>(L.ntiles)), dim3(kThreads), 0, st, tag, N,
-               tiles, idx, M, f);
+  HAV_LAUNCH(k_bbox, dim3(w.nbbox), dim3(kThreads), 0, st, xyz, w);
+  if (M == N) {
+    HAV_LAUNCH(k_identity, dim3(grid_for(N)), dim3(kThreads), 0, st, w, P, idx, info_dev);
+    return HAV_OK;
   }
-  if (info_dev) HAV_LAUNCH(k_copy_info, dim3(1), dim3(64), 0, st, info, info_dev);
+  HAV_LAUNCH(k_bin_count, dim3(w.nbb), dim3(kThreads), 0, st, xyz, w, P);
+  HAV_LAUNCH(k_bin_scan, dim3(w.nbb), dim3(kThreads), 0, st, w, P);
+  HAV_LAUNCH(k_bin_scatter, dim3(w.nbb), dim3(kThreads), 0, st, xyz, w);
+  const int passes = P.fixed ? 0 : (p->t_max + P.depth - 1) / P.depth;
+  const int R = trim_rounds(N);
+  for (int l = 0; l < nl; ++l) {
+    for (int q = 0; q < passes; ++q)
+      HAV_LAUNCH(k_eval, dim3(w.ntile), dim3(kThreads), kLdsBytes, st, w, P);
+    HAV_LAUNCH(k_select, dim3(w.ntile), dim3(kThreads), kLdsBytes, st, w, P);
+    for (int r = 0; r < R; ++r) HAV_LAUNCH(k_trim_hist, dim3(w.ntile), dim3(kThreads), 0, st, w, r);
+    HAV_LAUNCH(k_mark, dim3(w.ntile), dim3(kThreads), 0, st, w);
+    HAV_LAUNCH(k_scan_count, dim3(w.nscan), dim3(kThreads), 0, st, w, 0);
+    HAV_LAUNCH(k_pad_mark, dim3(w.nscan), dim3(kThreads), 0, st, w, P);
+  }
+  HAV_LAUNCH(k_scan_count, dim3(w.nscan), dim3(kThreads), 0, st, w, 1);
+  HAV_LAUNCH(k_out_write, dim3(w.nscan), dim3(kThreads), 0, st, w, idx, M, info_dev);
   return HAV_OK;
 }
 
@@ -742,19 +1277,29 @@ bool chain_sizes_ok(int64_t N, const int64_t* M, int32_t n) {
 }
 
 struct ChainLayout {
-  size_t stage_ws = 0, buf0 = 0, buf1 = 0, local = 0, total = 0;
+  Layout stage;
+  size_t buf0 = 0, buf1 = 0, local = 0, total = 0;
 };
 
-ChainLayout make_chain_layout(int64_t N, const int64_t* M, int32_t n) {
+ChainLayout make_chain_layout(int64_t N, const int64_t* M, int depth) {
   ChainLayout C;
-  C.stage_ws = 0;
-  size_t o = align_up(make_layout(N).total);  // stage 0 is the largest stage
-  C.buf0 = o; o = align_up(o + static_cast<size_t>(M[0]) * 12);
-  C.buf1 = o; o = align_up(o + static_cast<size_t>(M[0]) * 12);
+  C.stage = make_layout(N, depth);
+  size_t o = align_up(C.stage.total);
+  C.buf0 = o;  o = align_up(o + static_cast<size_t>(M[0]) * 12);
+  C.buf1 = o;  o = align_up(o + static_cast<size_t>(M[0]) * 12);
   C.local = o; o = align_up(o + static_cast<size_t>(M[0]) * 4);
   C.total = o;
-  (void)n;
   return C;
+}
+
+hav_status_t init_ws(char* base, const Layout& L, hipStream_t st) {
+  Ws w = make_ws(base, L, L.n_ws);
+  const size_t nct = 2 * static_cast<size_t>(L.ncmax) * L.cap_ws;
+  const size_t ncn = 2 * static_cast<size_t>(L.ncmax) * L.ntile_ws;
+  HAV_LAUNCH(k_ws_init, dim3(2048), dim3(kThreads), 0, st, w, nct, ncn,
+             static_cast<size_t>(L.cap_ws), static_cast<size_t>(L.ntile_ws));
+  HAV_LAUNCH(k_ws_seal, dim3(1), dim3(64), 0, st, w.h, magic_of(L));
+  return HAV_OK;
 }
 
 }  // namespace
@@ -777,6 +1322,7 @@ hav_params_t hav_params_default(void) {
     p.fixed_voxel[a] = 1.0f;
   }
   p.flags = 0;
+  p.spec_depth = 0;
   return p;
 }
 
@@ -789,13 +1335,23 @@ const char* hav_status_string(hav_status_t s) {
     case HAV_ERR_UNSUPPORTED: return "unsupported input frame";
     case HAV_ERR_NONFINITE: return "non-finite coordinate";
     case HAV_ERR_HIP: return "HIP error";
+    case HAV_ERR_WORKSPACE_NOT_INIT: return "workspace not initialised for this size";
   }
   return "unknown status";
 }
 
 size_t hav_workspace_size(int64_t N, int64_t M, const hav_params_t* params) {
   if (N < 1 || M < 1 || M > N || N >= (int64_t(1) << 31) || !params_ok(params)) return 0;
-  return make_layout(N).total;
+  return make_layout(N, depth_of(params)).total;
+}
+
+hav_status_t hav_workspace_init(int64_t N, const hav_params_t* params, void* ws, size_t ws_bytes,
+                                void* stream) {
+  if (!ws || N < 1 || N >= (int64_t(1) << 31) || !params_ok(params)) return HAV_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
+  const Layout L = make_layout(N, depth_of(params));
+  if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
+  return init_ws(static_cast<char*>(ws), L, static_cast<hipStream_t>(stream));
 }
 
 hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params_t* params,
@@ -805,8 +1361,9 @@ hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params
       !params_ok(params))
     return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
-  if (ws_bytes < make_layout(N).total) return HAV_ERR_WORKSPACE_TOO_SMALL;
-  return run_stage(xyz, N, M, params, idx, static_cast<char*>(ws), info_dev,
+  const Layout L = make_layout(N, depth_of(params));
+  if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
+  return run_stage(xyz, N, M, params, idx, static_cast<char*>(ws), L, info_dev,
                    static_cast<hipStream_t>(stream));
 }
 
@@ -815,7 +1372,7 @@ size_t hav_chain_workspace_size(int64_t N, const int64_t* M_host, int32_t n_stag
   if (N < 1 || N >= (int64_t(1) << 31) || !params_ok(params) ||
       !chain_sizes_ok(N, M_host, n_stages))
     return 0;
-  return make_chain_layout(N, M_host, n_stages).total;
+  return make_chain_layout(N, M_host, depth_of(params)).total;
 }
 
 hav_status_t hav_sample_chain(const float* xyz, int64_t N, const int64_t* M_host,
@@ -825,7 +1382,7 @@ hav_status_t hav_sample_chain(const float* xyz, int64_t N, const int64_t* M_host
       !chain_sizes_ok(N, M_host, n_stages))
     return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
-  const ChainLayout C = make_chain_layout(N, M_host, n_stages);
+  const ChainLayout C = make_chain_layout(N, M_host, depth_of(params));
   if (ws_bytes < C.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
@@ -838,7 +1395,8 @@ hav_status_t hav_sample_chain(const float* xyz, int64_t N, const int64_t* M_host
     const int64_t m = M_host[j];
     int32_t* out = idx_concat + off;
     int32_t* dst = (j == 0) ? out : local;
-    const hav_status_t s = run_stage(cur, n, m, params, dst, base, info_dev ? info_dev + j : nullptr, st);
+    const hav_status_t s =
+        run_stage(cur, n, m, params, dst, base, C.stage, info_dev ? info_dev + j : nullptr, st);
     if (s != HAV_OK) return s;
     if (j > 0)
       HAV_LAUNCH(k_compose, dim3(grid_for(m)), dim3(kThreads), 0, st, local, m,

@@ -9,30 +9,28 @@
 
 namespace hav {
 
-constexpr uint64_t kEmptyKey = ~0ull;  // packed voxel keys use 63 bits, never all ones
-constexpr int kKeyBits = 21;           // bits per voxel coordinate in a packed key
-constexpr float kKeyLimit = 2097152.0f;  // 2^21
+constexpr uint64_t kEmptyKey = ~0ull;      // packed keys use < 64 bits, never all ones
+constexpr int kKeyBits = 21;               // bits per voxel coordinate in a packed key
+constexpr float kKeyLimit = 2097152.0f;    // 2^21
+constexpr int kBrickShift = 2;             // bricks of 4 x 4 x 4 voxels
+constexpr int kBrickCoordBits = 19;        // 21 - 2
 
 // Monotone map from a float to uint32 (IEEE total order: -0 < +0), so that the
-// bounding box can be reduced with integer atomics.
+// bounding box can be reduced with integer min/max.
 __device__ __forceinline__ uint32_t float_to_ordered(float f) {
   const uint32_t u = __float_as_uint(f);
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
-__host__ __device__ __forceinline__ float ordered_to_float(uint32_t k) {
+__device__ __forceinline__ float ordered_to_float(uint32_t k) {
   const uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
-  float f;
-  __builtin_memcpy(&f, &u, 4);
-  return f;
+  return __uint_as_float(u);
 }
 
-// Voxel coordinate along one axis (Sec. 3.2, Eq. 2) in the stage frame:
-// g = floor(fl(fl(p - origin) * inv)), with inv = fl(1 / v).
-__device__ __forceinline__ uint32_t axis_coord(float p, float origin, float inv, float* r_out) {
-  const float r = p - origin;
+// Voxel coordinate along one axis (Sec. 3.2, Eq. 2) of a point already shifted into
+// the stage frame (r = p - origin): g = floor(fl(r * inv)), inv = fl(1 / v).
+__device__ __forceinline__ uint32_t axis_coord(float r, float inv) {
   const float q = r * inv;
-  *r_out = r;
-  return static_cast<uint32_t>(floorf(q));  // q in [0, 2^21): floor then exact convert
+  return static_cast<uint32_t>(floorf(q));  // q in [0, 2^21): floor, then exact convert
 }
 
 __device__ __forceinline__ uint64_t pack_key(uint32_t gx, uint32_t gy, uint32_t gz) {
@@ -40,21 +38,32 @@ __device__ __forceinline__ uint64_t pack_key(uint32_t gx, uint32_t gy, uint32_t 
          (static_cast<uint64_t>(gz) << (2 * kKeyBits));
 }
 
+// Brick holding a voxel (4 x 4 x 4 voxels) and the voxel's bit inside the brick's
+// 64-bit occupancy mask.
+__device__ __forceinline__ uint64_t brick_key(uint32_t gx, uint32_t gy, uint32_t gz) {
+  return static_cast<uint64_t>(gx >> kBrickShift) |
+         (static_cast<uint64_t>(gy >> kBrickShift) << kBrickCoordBits) |
+         (static_cast<uint64_t>(gz >> kBrickShift) << (2 * kBrickCoordBits));
+}
+__device__ __forceinline__ uint64_t brick_bit(uint32_t gx, uint32_t gy, uint32_t gz) {
+  return 1ull << ((gx & 3u) | ((gy & 3u) << 2) | ((gz & 3u) << 4));
+}
+
 // Squared distance of a point to its voxel centre v * (g + 0.5) (Sec. 3.2, d_i),
 // in the fixed order ((dx*dx + dy*dy) + dz*dz). Never negative, so its bit pattern
 // orders like its value.
-__device__ __forceinline__ float centre_dist2(const float r[3], const uint32_t g[3],
-                                              const float v[3]) {
-  float d[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float gc = static_cast<float>(g[a]) + 0.5f;
-    const float centre = v[a] * gc;
-    d[a] = r[a] - centre;
-  }
-  const float xx = d[0] * d[0];
-  const float yy = d[1] * d[1];
-  const float zz = d[2] * d[2];
+__device__ __forceinline__ float centre_dist2(float rx, float ry, float rz, uint32_t gx,
+                                              uint32_t gy, uint32_t gz, float vx, float vy,
+                                              float vz) {
+  const float cx = vx * (static_cast<float>(gx) + 0.5f);
+  const float cy = vy * (static_cast<float>(gy) + 0.5f);
+  const float cz = vz * (static_cast<float>(gz) + 0.5f);
+  const float dx = rx - cx;
+  const float dy = ry - cy;
+  const float dz = rz - cz;
+  const float xx = dx * dx;
+  const float yy = dy * dy;
+  const float zz = dz * dz;
   const float xy = xx + yy;
   return xy + zz;
 }
@@ -68,49 +77,120 @@ __device__ __forceinline__ uint64_t voxel_priority(uint64_t key) {
   return z ^ (z >> 31);
 }
 
-// Home slot of a key in a power-of-two open-addressing table (multiplicative
-// hashing, top bits).
-__device__ __forceinline__ uint32_t home_slot(uint64_t key, int shift) {
-  return static_cast<uint32_t>((key * 0xD6E8FEB86659FD93ull) >> shift);
+// Table hashing: 64-bit finaliser (two multiplies) so that structured keys spread.
+__device__ __forceinline__ uint32_t table_hash(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xFF51AFD7ED558CCDull;
+  k ^= k >> 33;
+  k *= 0xC4CEB9FE1A85EC53ull;
+  k ^= k >> 33;
+  return static_cast<uint32_t>(k);
 }
 
-// Insert-or-find with linear probing. Returns true if this call stored the key.
-// A plain load first: a slot changes at most once (empty -> key) between clears,
-// so a stale read can only show it empty, and the CAS then settles it.
-__device__ __forceinline__ bool table_insert(unsigned long long* keys, uint32_t mask, int shift,
-                                             uint64_t key, uint32_t* slot_out) {
-  uint32_t s = home_slot(key, shift);
+// Compare-and-swap returning the previous value.
+__device__ __forceinline__ uint64_t lds_cas(uint64_t* p, uint64_t expected, uint64_t desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+  return expected;
+}
+
+// ------------------------------------------------------------------ LDS hash map
+// Open addressing over `cap` (power of two) entries; keys kEmptyKey when free.
+// mode OR: value |= v;  mode MIN: value = min(value, v).
+__device__ __forceinline__ void lds_insert_or(uint64_t* keys, uint64_t* vals, uint32_t mask,
+                                              uint64_t key, uint64_t v) {
+  uint32_t h = table_hash(key) & mask;
+  while (true) {
+    uint64_t k = keys[h];
+    if (k == kEmptyKey) {
+      k = lds_cas(&keys[h], kEmptyKey, key);
+    }
+    if (k == kEmptyKey || k == key) {
+      __hip_atomic_fetch_or(&vals[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ __forceinline__ void lds_insert_min(uint64_t* keys, uint64_t* vals, uint32_t mask,
+                                               uint64_t key, uint64_t v) {
+  uint32_t h = table_hash(key) & mask;
+  while (true) {
+    uint64_t k = keys[h];
+    if (k == kEmptyKey) {
+      k = lds_cas(&keys[h], kEmptyKey, key);
+    }
+    if (k == kEmptyKey || k == key) {
+      __hip_atomic_fetch_min(&vals[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+// ------------------------------------------------------------------ global table
+// Find or claim the slot of `key`; *claimed is set when this call stored the key.
+// A slot changes at most once (empty -> key) between clears, and clears happen in
+// an earlier kernel, so a plain load can only be stale by showing the slot empty;
+// the CAS then settles it.
+__device__ __forceinline__ uint32_t global_find_or_claim(unsigned long long* keys, uint32_t mask,
+                                                         uint64_t key, bool* claimed) {
+  uint32_t s = table_hash(key) & mask;
+  *claimed = false;
   while (true) {
     const unsigned long long k = keys[s];
-    if (k == key) {
-      *slot_out = s;
-      return false;
-    }
+    if (k == key) return s;
     if (k == kEmptyKey) {
       const unsigned long long prev = atomicCAS(&keys[s], kEmptyKey, key);
       if (prev == kEmptyKey) {
-        *slot_out = s;
-        return true;
+        *claimed = true;
+        return s;
       }
-      if (prev == key) {
-        *slot_out = s;
-        return false;
-      }
+      if (prev == key) return s;
     }
     s = (s + 1) & mask;
   }
 }
 
-// Wave64 reductions.
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+// ------------------------------------------------------------------ block helpers
+
+template <int kThreads>
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* s_tmp) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), o, 64)));
-  return v;
+  for (int o = 32; o > 0; o >>= 1) v += static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), o, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) s_tmp[wv] = v;
+  __syncthreads();
+  uint32_t t = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) t += s_tmp[w];
+  return t;
 }
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+
+// Exclusive scan of one value per thread across the block; returns the block total.
+template <int kThreads>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* excl,
+                                                         uint32_t* s_tmp) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t x = v;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), o, 64)));
-  return v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = static_cast<uint32_t>(__shfl_up(static_cast<int>(x), o, 64));
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) s_tmp[wv] = x;
+  __syncthreads();
+  uint32_t wbase = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    if (w < wv) wbase += s_tmp[w];
+    total += s_tmp[w];
+  }
+  *excl = wbase + x - v;
+  return total;
 }
 
 }  // namespace hav

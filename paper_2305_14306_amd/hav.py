@@ -17,7 +17,7 @@ MAX_LAYERS = 8
 FIXED_VOXEL = 1
 
 OK, ERR_INVALID_ARG, ERR_WORKSPACE_TOO_SMALL, ERR_OUT_OF_MEMORY, ERR_UNSUPPORTED, \
-    ERR_NONFINITE, ERR_HIP = range(7)
+    ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE_NOT_INIT = range(8)
 
 
 class Params(C.Structure):
@@ -30,6 +30,7 @@ class Params(C.Structure):
         ("aspect", C.c_float * 3),
         ("flags", C.c_uint32),
         ("fixed_voxel", C.c_float * 3),
+        ("spec_depth", C.c_int32),
     ]
 
 
@@ -90,6 +91,8 @@ def lib():
         L.hav_status_string.argtypes = [C.c_int]
         L.hav_workspace_size.restype = C.c_size_t
         L.hav_workspace_size.argtypes = [C.c_int64, C.c_int64, C.POINTER(Params)]
+        L.hav_workspace_init.restype = C.c_int
+        L.hav_workspace_init.argtypes = [C.c_int64, C.POINTER(Params), vp, C.c_size_t, vp]
         L.hav_sample.restype = C.c_int
         L.hav_sample.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(Params), i32p, vp, C.c_size_t,
                                  vp, vp]
@@ -107,9 +110,10 @@ def status_string(status: int) -> str:
 
 
 def params(layers=2, layer_ratio=4, t_max=20, sigma=0.05, aspect=(1.0, 1.0, 1.0),
-           fixed_voxel=None) -> Params:
+           fixed_voxel=None, spec_depth=0) -> Params:
     p = lib().hav_params_default()
     p.layers, p.layer_ratio, p.t_max, p.sigma = layers, layer_ratio, t_max, sigma
+    p.spec_depth = spec_depth
     for a in range(3):
         p.aspect[a] = aspect[a]
     if fixed_voxel is not None:
@@ -157,19 +161,33 @@ def read_info(info_dev, n: int = 1):
 
 
 class Sampler:
-    """Reusable caller-side state: a device workspace grown on demand and an info
-    record, so repeated calls on one stream allocate nothing."""
+    """Reusable caller-side state: a device workspace (grown on demand and initialised
+    with hav_workspace_init whenever the problem size or speculation depth changes) and
+    an info record, so repeated calls on one stream allocate and clear nothing."""
 
     def __init__(self, device="cuda"):
         self.device = device
         self.ws = None
+        self.ws_key = None
         self.info = None
 
-    def _workspace(self, nbytes: int):
+    def _workspace(self, nbytes: int, N: int, p: Params, stream=None):
         torch = _torch()
         if self.ws is None or self.ws.numel() < nbytes:
             self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            self.ws_key = None
+        key = (int(N), int(p.spec_depth))
+        if self.ws_key != key:
+            st = lib().hav_workspace_init(int(N), C.byref(p), C.c_void_p(self.ws.data_ptr()),
+                                          self.ws.numel(), _stream_ptr(stream))
+            if st != OK:
+                raise HavError(st, "hav_workspace_init")
+            self.ws_key = key
         return self.ws
+
+    def invalidate(self):
+        """Forget the initialisation (call after writing into the workspace)."""
+        self.ws_key = None
 
     def _info(self, n: int):
         torch = _torch()
@@ -186,7 +204,7 @@ class Sampler:
         nbytes = workspace_size(N, M, p)
         if nbytes == 0:
             raise HavError(ERR_INVALID_ARG, "hav_workspace_size")
-        ws = self._workspace(nbytes)
+        ws = self._workspace(nbytes, N, p, stream)
         idx = out if out is not None else torch.empty(int(M), dtype=torch.int32, device=xyz.device)
         info = self._info(1) if with_info else None
         st = lib().hav_sample(C.c_void_p(xyz.data_ptr()), N, int(M), C.byref(p),
@@ -208,7 +226,7 @@ class Sampler:
         nbytes = chain_workspace_size(N, Ms, p)
         if nbytes == 0:
             raise HavError(ERR_INVALID_ARG, "hav_chain_workspace_size")
-        ws = self._workspace(nbytes)
+        ws = self._workspace(nbytes, N, p, stream)
         total = int(sum(int(m) for m in Ms))
         idx = out if out is not None else torch.empty(total, dtype=torch.int32, device=xyz.device)
         info = self._info(len(Ms)) if with_info else None

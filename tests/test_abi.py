@@ -71,7 +71,7 @@ def test_params_default(hav):
 
 
 def test_status_strings(hav):
-    for s in range(7):
+    for s in range(8):
         assert isinstance(hav.status_string(s), str) and hav.status_string(s)
     assert hav.status_string(99) == "unknown status"
 

@@ -181,3 +181,55 @@ def test_scene_chain_1m(gpu, orc):
 def test_scene_single_stage_1m(gpu, orc):
     x = synth.scene_planes_blobs()
     _check(gpu, orc, x, x.shape[0] // 4, label="scene 1M->262144")
+
+
+# ------------------------------------------------------------------ workspace contract, tuning
+
+def test_uninitialised_workspace_is_reported(gpu):
+    import ctypes as C
+    import torch
+    x = _to_dev(synth.random_cloud(5000, 2))
+    p = gpu.params()
+    ws = torch.zeros(gpu.workspace_size(5000, 100, p), dtype=torch.uint8, device="cuda")
+    idx = torch.empty(100, dtype=torch.int32, device="cuda")
+    info = torch.zeros(C.sizeof(gpu.Info), dtype=torch.uint8, device="cuda")
+    st = gpu.lib().hav_sample(C.c_void_p(x.data_ptr()), 5000, 100, C.byref(p),
+                              C.c_void_p(idx.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                              C.c_void_p(info.data_ptr()), gpu._stream_ptr())
+    assert st == gpu.OK
+    assert gpu.read_info(info)[0]["status"] == gpu.ERR_WORKSPACE_NOT_INIT
+    # initialised for another size: also refused
+    big = gpu.workspace_size(8000, 100, p)
+    ws2 = torch.zeros(big, dtype=torch.uint8, device="cuda")
+    assert gpu.lib().hav_workspace_init(8000, C.byref(p), C.c_void_p(ws2.data_ptr()), big,
+                                        gpu._stream_ptr()) == gpu.OK
+    st = gpu.lib().hav_sample(C.c_void_p(x.data_ptr()), 5000, 100, C.byref(p),
+                              C.c_void_p(idx.data_ptr()), C.c_void_p(ws2.data_ptr()), big,
+                              C.c_void_p(info.data_ptr()), gpu._stream_ptr())
+    assert st == gpu.OK
+    assert gpu.read_info(info)[0]["status"] == gpu.ERR_WORKSPACE_NOT_INIT
+
+
+def test_workspace_reuse_across_sizes(gpu, orc):
+    # one sampler, alternating sizes and parameters: every call leaves the workspace
+    # clean, and a size change re-initialises it
+    s = gpu.Sampler()
+    clouds = [synth.random_cloud(n, n, scale=20.0, kind="clustered") for n in (30000, 7000, 30000)]
+    for rep in range(2):
+        for x in clouds:
+            for M, kw in ((x.shape[0] // 4, {}), (x.shape[0] // 10, dict(layers=3)),
+                          (500, dict(fixed_voxel=0.7))):
+                p = gpu.params(**kw)
+                _note(f"case reuse rep={rep} N={x.shape[0]} M={M} {kw}")
+                idx, info = s.sample(_to_dev(x), M, p, with_info=True)
+                st, want, winfo = orc.sample(x, M, _oracle_params(orc, p))
+                assert info == winfo
+                assert np.array_equal(idx.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3, 4])
+def test_spec_depth_does_not_change_results(gpu, orc, depth):
+    x = synth.scene_planes_blobs(100000, seed=21)
+    for M in (25000, 6000):
+        _check(gpu, orc, x, M, gpu.params(spec_depth=depth), f"depth {depth}")
+    _check(gpu, orc, synth.lattice(8), 60, gpu.params(spec_depth=depth), f"lattice depth {depth}")
