@@ -4,36 +4,42 @@
 // on one stream, every decision taken on the device (no host round trip):
 //
 //   k_bbox         per-block min/max of the cloud and the non-finite check
-//   k_bin_count    every block reduces the partial boxes (same result everywhere),
+//   k_bin_count    every block reduces the partial boxes (same bits everywhere),
 //                  derives the stage frame (origin = min corner, search bracket hi0)
 //                  and a 12-bit Morton cell per point; per-block cell histograms
-//   k_bin_scan     exclusive scan of the (cell, block) histogram; initialises layer 1
-//   k_bin_scatter  counting sort by cell: points land in spatially compact tiles of
-//                  2048, stored as offsets r = p - origin (exactly what Eq. 2 uses)
+//   k_bin_scan     exclusive scan of the (cell, block) histogram; starts layer 1
+//   k_bin_scatter  counting sort by cell into 16-byte records (r = p - origin, which
+//                  is exactly what Eq. 2 consumes, and the original index), so each
+//                  2048-point tile is spatially compact
 //   per layer (Sec. 3.4, Eq. 3):
-//     k_eval x P   adaptive voxel search (Sec. 3.3). Each pass evaluates the voxel
+//     k_eval x P   adaptive voxel search (Sec. 3.3). A pass evaluates the voxel
 //                  counter Cnt for the next `depth` levels of the bisection tree at
-//                  once (the decisions, and so the scales, are exactly the plain
-//                  bisection's). A tile dedups its voxels in LDS as 4x4x4 bricks with
-//                  64-bit occupancy masks, then does one CAS/atomicOr per distinct
-//                  brick in a global table; new bits = new voxels. The last block to
-//                  finish walks the tree and plans the next pass.
+//                  once; the decisions, and so the scales, are exactly those of one
+//                  bisection step at a time. A tile dedups its voxels in LDS as 4x4x4
+//                  bricks with 64-bit occupancy masks, then makes one find-or-claim
+//                  and at most one atomicOr per distinct brick in a global table; the
+//                  newly set bits are newly seen voxels. The last block to finish
+//                  walks the tree and plans the next pass.
 //     k_select     centre-closest point per occupied voxel at the chosen size
-//                  (Sec. 3.2): LDS min of (bits(d^2) << 32 | index), then one global
-//                  atomicMin per tile-distinct voxel; ties go to the lowest index.
-//     k_trim_hist  radix select (8-bit digits) of the m-th smallest SplitMix64
+//                  (Sec. 3.2): LDS min of (bits(d^2) << 32 | index), then at most one
+//                  global atomicMin per tile-distinct voxel; ties go to the lowest index
+//     k_trim_hist  radix select (8-bit digits) of the m-th smallest SplitMix64 voxel
 //                  priority when there are more voxels than m
-//     k_mark       keep the m smallest; the last block settles the boundary bucket
-//     k_pad_*      pad with the lowest-index unsampled points when there are fewer
-//   k_out_*        ascending output indices by a two-level scan
+//     k_mark       keep the voxels below the selected bucket, queue the bucket
+//     k_ties       one block settles the exact rank inside the bucket
+//     k_scan_count / k_pad_mark   pad with the lowest-index unsampled points when
+//                  there are fewer voxels than m
+//   k_scan_count / k_out_write    ascending output indices by a two-level scan
 //
-// Table hygiene: the workspace is initialised once (hav_workspace_init); each kernel
-// that fills a table records the slots it claimed, and a later kernel of the same
-// call empties exactly those, so every call leaves the workspace as it found it and
-// no call pays for clearing whole tables.
+// Table hygiene: a workspace is initialised once (hav_workspace_init). Each kernel
+// that fills a table records the slots it claimed and a later kernel of the same call
+// empties exactly those, so every call leaves the workspace as it found it and no call
+// clears whole tables.
 //
-// Cross-block results (counts, histograms) go through two-level arrival counters
-// and per-group accumulators, so no address takes more than ~32 atomics.
+// Cross-block reductions: blocks publish partial results with atomic RMWs into
+// per-group accumulators (<= ~32 atomics per address), wait for them to complete
+// (s_waitcnt 0), then arrive on two-level counters; the last block reads the partials
+// back with RMWs. Data written with plain stores is only read by later kernels.
 
 #include <hip/hip_runtime.h>
 
@@ -50,18 +56,23 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kTile = 2048;                     // points per search/select tile
 constexpr int kPerThread = kTile / kThreads;    // 8
-constexpr int kLdsCap = 4096;                   // LDS hash entries (>= 2x distinct keys)
-constexpr int kMaxDepth = 4;
-constexpr int kMaxCand = (1 << kMaxDepth) - 1;  // 15
+constexpr int kLdsCap = 4096;                   // select: LDS voxel map entries (2x tile)
+constexpr int kBrickCap = 1024;                 // search: LDS brick table per candidate
+constexpr int kBrickProbe = 64;                 // LDS probes before a point goes global
+constexpr int kMaxDepth = 3;
+constexpr int kMaxCand = (1 << kMaxDepth) - 1;  // 7
 constexpr int kDefaultDepth = 2;
 constexpr int kGroups = 16;
 constexpr int kStride = 32;                     // uint32 spacing of hot counters (128 B)
 constexpr int kBinBits = 12;
 constexpr int kBins = 1 << kBinBits;
-constexpr int kMaxBinBlocks = 128;
+constexpr int kMaxBinBlocks = 512;
+constexpr int kBinChunk = 16;                   // bins per block of the histogram scan
+constexpr int kBinChunks = kBins / kBinChunk;
 constexpr int kMaxBBoxBlocks = 1024;
 constexpr int kScanTile = 4096;                 // tag scans: 16 per thread
 constexpr int kScanPer = kScanTile / kThreads;
+constexpr int kSelDense = 4;                    // voxel value slots per brick-table slot
 constexpr uint64_t kMagic = 0x4841565F57533031ull;
 
 // ----------------------------------------------------------------------------- state
@@ -86,6 +97,11 @@ struct Ctrl {
   int32_t pend_set, pend_nc;
   float cand_s[kMaxCand];
   float cand_inv[kMaxCand][3];
+  int32_t cand_dense[kMaxCand];   // 1: brick grid fits the table, index it directly
+  int32_t cand_hot[kMaxCand];     // 1: few bricks, read before the atomic
+  uint32_t cand_nb[kMaxCand][2];  // brick grid x, y extents (dense mode)
+  int32_t sel_dense;              // 1: voxel grid at the chosen size fits, index directly
+  uint32_t sel_nv[2];             // voxel grid x, y extents (dense mode)
   uint32_t ncand;       // occupied voxels at the chosen size
   int32_t trim;
   uint32_t need;        // pad count
@@ -104,6 +120,8 @@ struct Plan {  // per-call constants (kernel argument)
   float aspect[3];
   float fixed_v[3];
   uint64_t magic;
+  uint32_t cap;       // brick table slots: dense brick grids up to this size
+  uint32_t sel_cap;   // voxel value slots: dense voxel grids up to this size
 };
 
 struct alignas(256) Header {
@@ -122,14 +140,14 @@ struct alignas(256) Header {
 // Device view of the workspace for one stage.
 struct Ws {
   Header* h;
-  float *rx, *ry, *rz;           // sorted offsets from the origin
-  int32_t* ordi;                 // sorted position -> original index
+  float4* pts;                   // sorted: (r_x, r_y, r_z, original index as bits)
   int32_t* invp;                 // original index -> sorted position
   uint8_t* tag_s;                // sorted order: layer that picked the point (0 = none)
   uint8_t* tag_o;                // original order
   uint32_t* part;                // k_bbox partials [nbbox][8]
-  uint32_t* bh;                  // cell histogram [kBins][nbb]
-  uint32_t* bsum;                // scan chunk sums [nbb]
+  uint32_t* bh;                  // cell histogram [nbb][kBins], then offsets within a cell
+  uint32_t* binpre;              // [kBins] offset of a cell inside its chunk of cells
+  uint32_t* bsum;                // [kBinChunks] chunk sums, then chunk offsets
   unsigned long long* ckeys;     // brick tables [2][ncmax][cap_ws]
   unsigned long long* cmasks;
   int32_t* ccl;                  // claims [2][ncmax][ntile_ws][kTile]
@@ -141,8 +159,8 @@ struct Ws {
   uint64_t* tie_p;               // [kGroups][tie_seg]
   int32_t* tie_o;
   uint32_t* tcnt;                // scan tile counts [nscan_ws]
-  // sizes of this stage / of the workspace
   int64_t n;
+  int64_t npad;                  // slots of the sorted arrays: ntile * kTile
   int32_t ntile, nscan, nbb, nbbox;
   uint32_t cap, cmask;           // table capacity used by this stage
   uint32_t cap_ws;
@@ -163,14 +181,29 @@ __device__ __forceinline__ int32_t* claim_n(const Ws& w, int set, int c, int til
   return w.ccn + (static_cast<size_t>(set) * w.ncmax + c) * w.ntile_ws + tile;
 }
 
-// Two-level arrival: returns true in exactly one block, the last to arrive. All of
-// the block's prior writes are made visible first (release), and the last block
-// sees everyone's (acquire). Counters are left at zero for the next kernel.
+// Sorted storage is transposed inside each tile: the tile's (kPerThread*t + k)-th
+// point sits in slot k*kThreads + t, so a coalesced load (lane t, rows k) hands
+// thread t kPerThread neighbouring points. Slots past the cloud hold no point.
+__device__ __forceinline__ int64_t slot_of(int64_t L) {
+  const int64_t tile = L / kTile;
+  const int j = static_cast<int>(L - tile * kTile);
+  return tile * kTile + (j % kPerThread) * kThreads + j / kPerThread;
+}
+__device__ __forceinline__ int64_t logical_of(int64_t S) {
+  const int64_t tile = S / kTile;
+  const int j = static_cast<int>(S - tile * kTile);
+  return tile * kTile + (j % kThreads) * kPerThread + j / kThreads;
+}
+
+// Two-level arrival: true in exactly one block, the last to arrive. Every thread
+// first waits for its own memory operations to complete, so the partial results the
+// block published with atomic RMWs are in place before the arrival is counted; the
+// last block reads them back with RMWs. Counters are left at zero.
 __device__ bool arrive_last(Header* h, int nblocks) {
   __shared__ int s_last;
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
     const int g = blockIdx.x & (kGroups - 1);
     const int gsize = (nblocks - g + kGroups - 1) / kGroups;
     const int ngroups = nblocks < kGroups ? nblocks : kGroups;
@@ -184,16 +217,15 @@ __device__ bool arrive_last(Header* h, int nblocks) {
         last = 1;
       }
     }
-    if (last) __threadfence();
     s_last = last;
   }
   __syncthreads();
   return s_last != 0;
 }
 
-__device__ __forceinline__ uint32_t load_acc(uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Read-and-reset of an accumulator other blocks filled with atomics; plain read.
+__device__ __forceinline__ uint32_t take(uint32_t* p) { return atomicExch(p, 0u); }
+__device__ __forceinline__ uint32_t peek(uint32_t* p) { return atomicAdd(p, 0u); }
 
 // ----------------------------------------------------------------------------- search plan
 
@@ -201,7 +233,13 @@ __device__ __forceinline__ uint32_t load_acc(uint32_t* p) {
 // bracket [lo, hi], in heap order. Node k with bracket [a, b] evaluates s = (a+b)/2;
 // its child 2k+1 ([a, s]) is taken when the count is below m, 2k+2 ([s, b]) when
 // above the window -- the same arithmetic as one bisection step at a time.
-__device__ void plan_pass(Ctrl* c, const Plan& P) {
+// Largest voxel coordinate per axis at reciprocal size inv: the coordinate of the
+// cloud's max corner (r = mx - mn), the largest r any point has.
+__device__ __forceinline__ void max_coords(const Frame& fr, const float* inv, uint32_t* mk) {
+  for (int ax = 0; ax < 3; ++ax) mk[ax] = axis_coord(fr.mx[ax] - fr.mn[ax], inv[ax]);
+}
+
+__device__ void plan_pass(Ctrl* c, const Plan& P, const Frame& fr) {
   const int left = P.t_max - c->evals;
   const int D = left < P.depth ? left : P.depth;
   const int nc = (1 << D) - 1;
@@ -215,6 +253,15 @@ __device__ void plan_pass(Ctrl* c, const Plan& P) {
       const float v = s * P.aspect[ax];
       c->cand_inv[k][ax] = 1.0f / v;
     }
+    uint32_t mk[3];
+    max_coords(fr, c->cand_inv[k], mk);
+    const uint64_t nbx = (mk[0] >> kBrickShift) + 1, nby = (mk[1] >> kBrickShift) + 1,
+                   nbz = (mk[2] >> kBrickShift) + 1;
+    const uint64_t nb = nbx * nby * nbz;
+    c->cand_dense[k] = nb <= P.cap ? 1 : 0;
+    c->cand_hot[k] = nb <= 4096 ? 1 : 0;
+    c->cand_nb[k][0] = static_cast<uint32_t>(nbx);
+    c->cand_nb[k][1] = static_cast<uint32_t>(nby);
     if (2 * k + 2 < nc) {
       a[2 * k + 1] = a[k];
       b[2 * k + 1] = s;
@@ -225,12 +272,22 @@ __device__ void plan_pass(Ctrl* c, const Plan& P) {
   c->nc = nc;
 }
 
-__device__ void set_final(Ctrl* c, float s, const Plan& P) {
+__device__ void set_select_grid(Ctrl* c, const Plan& P, const Frame& fr) {
+  uint32_t mk[3];
+  max_coords(fr, c->inv_final, mk);
+  const uint64_t nv = (uint64_t(mk[0]) + 1) * (uint64_t(mk[1]) + 1) * (uint64_t(mk[2]) + 1);
+  c->sel_dense = nv <= P.sel_cap ? 1 : 0;
+  c->sel_nv[0] = mk[0] + 1;
+  c->sel_nv[1] = mk[1] + 1;
+}
+
+__device__ void set_final(Ctrl* c, float s, const Plan& P, const Frame& fr) {
   c->s_final = s;
   for (int ax = 0; ax < 3; ++ax) {
     c->v_final[ax] = s * P.aspect[ax];
     c->inv_final[ax] = 1.0f / c->v_final[ax];
   }
+  set_select_grid(c, P, fr);
 }
 
 __device__ void layer_init(Header* h, const Plan& P, int L) {
@@ -258,9 +315,10 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
       c->v_final[ax] = P.fixed_v[ax];
       c->inv_final[ax] = 1.0f / P.fixed_v[ax];
     }
+    set_select_grid(c, P, h->frame);
   } else {
     c->done = 0;
-    plan_pass(c, P);
+    plan_pass(c, P, h->frame);
   }
 }
 
@@ -283,6 +341,9 @@ __global__ void __launch_bounds__(kThreads) k_bbox(const float* __restrict__ xyz
     }
     w.tag_o[i] = 0;
   }
+  for (int64_t S = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; S < w.npad;
+       S += static_cast<int64_t>(gridDim.x) * kThreads)
+    w.tag_s[S] = logical_of(S) < n ? 0 : 0xFF;  // 0xFF: empty slot, never a point
   __shared__ uint32_t s_v[7][kThreads / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t vals[7] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], bad};
@@ -365,7 +426,7 @@ __device__ int frame_from_partials(const Ws& w, const Plan& P, Frame* fr, int id
       }
     }
   }
-  // spatial binning: 12 Morton bits shared out by extent (performance only)
+  // spatial binning: 12 Morton bits shared out by extent (affects speed only)
   float ext[3];
   int bb[3] = {0, 0, 0};
   for (int a = 0; a < 3; ++a) ext[a] = fr->mx[a] - fr->mn[a];
@@ -460,37 +521,53 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(const float* __restrict_
     atomicAdd(&hist[cell_code(rx, ry, rz, fr)], 1u);
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < kBins; b += kThreads) w.bh[static_cast<size_t>(b) * w.nbb + blockIdx.x] = hist[b];
+  for (int b = threadIdx.x; b < kBins; b += kThreads)
+    w.bh[static_cast<size_t>(blockIdx.x) * kBins + b] = hist[b];
 }
 
-// Exclusive scan of bh (kBins x nbb, bin-major) in kScanTile chunks; the last block
-// scans the chunk sums and starts layer 1.
+// Offsets of every (block, cell) run of the counting sort. Block c of this kernel owns
+// cells [16c, 16c+16): sixteen threads per cell scan its counts over the binning
+// blocks (a sixteenth of them each), then the block scans its cells' totals; the
+// last block scans the chunk totals and starts layer 1.
 __global__ void __launch_bounds__(kThreads) k_bin_scan(Ws w, Plan P) {
   if (w.h->frame.status != HAV_OK) return;
+  constexpr int kParts = kThreads / kBinChunk;  // 16
   __shared__ uint32_t s_tmp[kThreads / 64];
-  const int64_t total = static_cast<int64_t>(kBins) * w.nbb;
-  const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
-  uint32_t v[kScanPer];
+  __shared__ uint32_t s_q[kParts][kBinChunk];
+  __shared__ uint32_t s_tot[kBinChunk];
+  const int lb = threadIdx.x & (kBinChunk - 1);
+  const int bin = blockIdx.x * kBinChunk + lb;
+  const int q = threadIdx.x / kBinChunk;
+  const int nq = (w.nbb + kParts - 1) / kParts;
+  const int b0 = q * nq, b1 = min(w.nbb, b0 + nq);
   uint32_t sum = 0;
+  for (int b = b0; b < b1; ++b) sum += w.bh[static_cast<size_t>(b) * kBins + bin];
+  s_q[q][lb] = sum;
+  __syncthreads();
+  uint32_t run = 0;
+  for (int qq = 0; qq < q; ++qq) run += s_q[qq][lb];
+  if (q == kParts - 1) s_tot[lb] = run + sum;
+  for (int b = b0; b < b1; b += 8) {
+    uint32_t v[8];
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    v[k] = base + k < total ? w.bh[base + k] : 0u;
-    sum += v[k];
-  }
-  uint32_t excl;
-  const uint32_t tot = block_exclusive_scan<kThreads>(sum, &excl, s_tmp);
+    for (int j = 0; j < 8; ++j) v[j] = b + j < b1 ? w.bh[static_cast<size_t>(b + j) * kBins + bin] : 0u;
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < total) w.bh[base + k] = excl;
-    excl += v[k];
+    for (int j = 0; j < 8; ++j) {
+      if (b + j < b1) w.bh[static_cast<size_t>(b + j) * kBins + bin] = run;
+      run += v[j];
+    }
   }
-  if (threadIdx.x == 0) w.bsum[blockIdx.x] = tot;
-  if (!arrive_last(w.h, gridDim.x)) return;
-  // last block: scan the chunk sums (<= kMaxBinBlocks of them)
-  const uint32_t x = threadIdx.x < static_cast<int>(gridDim.x) ? w.bsum[threadIdx.x] : 0u;
+  __syncthreads();
+  const uint32_t x = threadIdx.x < kBinChunk ? s_tot[threadIdx.x] : 0u;
   uint32_t ex;
-  block_exclusive_scan<kThreads>(x, &ex, s_tmp);
-  if (threadIdx.x < static_cast<int>(gridDim.x)) w.bsum[threadIdx.x] = ex;
+  const uint32_t chunk_total = block_exclusive_scan<kThreads>(x, &ex, s_tmp);
+  if (threadIdx.x < kBinChunk) w.binpre[blockIdx.x * kBinChunk + threadIdx.x] = ex;
+  if (threadIdx.x == 0) atomicExch(&w.bsum[blockIdx.x], chunk_total);
+  if (!arrive_last(w.h, gridDim.x)) return;
+  const uint32_t y = threadIdx.x < static_cast<int>(gridDim.x) ? peek(&w.bsum[threadIdx.x]) : 0u;
+  uint32_t ey;
+  block_exclusive_scan<kThreads>(y, &ey, s_tmp);
+  if (threadIdx.x < static_cast<int>(gridDim.x)) w.bsum[threadIdx.x] = ey;
   if (threadIdx.x == 0) {
     Ctrl* c = &w.h->ctrl;
     c->set = 0;
@@ -505,10 +582,8 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(const float* __restric
   __shared__ Frame fr;
   __shared__ uint32_t off[kBins];
   if (threadIdx.x == 0) fr = w.h->frame;
-  for (int b = threadIdx.x; b < kBins; b += kThreads) {
-    const size_t e = static_cast<size_t>(b) * w.nbb + blockIdx.x;
-    off[b] = w.bh[e] + w.bsum[e / kScanTile];
-  }
+  for (int b = threadIdx.x; b < kBins; b += kThreads)
+    off[b] = w.bh[static_cast<size_t>(blockIdx.x) * kBins + b] + w.binpre[b] + w.bsum[b / kBinChunk];
   __syncthreads();
   const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
   const int64_t beg = blockIdx.x * chunk, end = min(w.n, beg + chunk);
@@ -518,23 +593,23 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(const float* __restric
     const float rz = xyz[3 * i + 2] - fr.mn[2];
     const uint32_t pos = atomicAdd(&off[cell_code(rx, ry, rz, fr)], 1u);
     if (pos < w.n) {
-      w.rx[pos] = rx;
-      w.ry[pos] = ry;
-      w.rz[pos] = rz;
-      w.ordi[pos] = static_cast<int32_t>(i);
-      w.tag_s[pos] = 0;
-      w.invp[i] = static_cast<int32_t>(pos);
+      const int64_t S = slot_of(pos);
+      w.pts[S] = make_float4(rx, ry, rz, __int_as_float(static_cast<int32_t>(i)));
+      w.invp[i] = static_cast<int32_t>(S);
     }
   }
 }
 
 // ----------------------------------------------------------------------------- search
 
-__device__ void clear_pending(const Ws& w, Ctrl* c) {
+// Empty the table slots the previous search pass claimed (its claim lists for this
+// tile), leaving the tables as initialised.
+__device__ void clear_pending(const Ws& w, const Ctrl* c) {
   const int pn = c->pend_nc, ps = c->pend_set;
   for (int k = 0; k < pn; ++k) {
     int32_t* cn = claim_n(w, ps, k, blockIdx.x);
     const int n = *cn;
+    if (n == 0) continue;
     const int32_t* list = claims(w, ps, k, blockIdx.x);
     unsigned long long* keys = ctab_keys(w, ps, k);
     unsigned long long* masks = ctab_masks(w, ps, k);
@@ -548,94 +623,284 @@ __device__ void clear_pending(const Ws& w, Ctrl* c) {
   }
 }
 
+// OR `bits` into the global brick table entry of `key`; returns the number of bits
+// that were not set before. A plain read of the mask can only be stale by missing
+// bits, so when it already holds all of ours the atomic is skipped.
+__device__ __forceinline__ uint32_t global_or(unsigned long long* keys, unsigned long long* masks,
+                                              uint32_t cmask, uint64_t key, uint64_t bits,
+                                              int32_t* list, int* s_ncl) {
+  uint32_t s = table_hash(key) & cmask;
+  while (true) {
+    const unsigned long long k = keys[s];
+    const unsigned long long m = masks[s];
+    if (k == key) {
+      if ((m & bits) == bits) return 0;
+      const unsigned long long old = atomicOr(&masks[s], static_cast<unsigned long long>(bits));
+      return static_cast<uint32_t>(__popcll(bits & ~old));
+    }
+    if (k == kEmptyKey) {
+      const unsigned long long prev = atomicCAS(&keys[s], kEmptyKey, key);
+      if (prev == kEmptyKey || prev == key) {
+        if (prev == kEmptyKey) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(s);
+        const unsigned long long old = atomicOr(&masks[s], static_cast<unsigned long long>(bits));
+        return static_cast<uint32_t>(__popcll(bits & ~old));
+      }
+    }
+    s = (s + 1) & cmask;
+  }
+}
+
+// Dense brick table: `bits` ORed into word `slot`; the tile whose atomic finds the
+// word empty records it for clearing. With `hot` (few bricks, so many tiles share
+// each word) a plain read first skips the atomic when it would add nothing; a stale
+// read can only miss bits, never show extra ones.
+__device__ __forceinline__ uint32_t dense_or(unsigned long long* masks, uint32_t slot,
+                                             uint64_t bits, bool hot, int32_t* list, int* s_ncl) {
+  if (hot) {
+    const unsigned long long m = masks[slot];
+    if ((m & bits) == bits) return 0;
+  }
+  const unsigned long long old = atomicOr(&masks[slot], static_cast<unsigned long long>(bits));
+  if (old == 0ull) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(slot);
+  return static_cast<uint32_t>(__popcll(bits & ~old));
+}
+
+// LDS insert of one (key, bits) run into a candidate's hash table, at most
+// kBrickProbe probes. Returns false if the table was too crowded.
+template <int kCap>
+__device__ __forceinline__ bool lds_try_or(uint64_t* tk, uint64_t* tv, uint64_t key, uint64_t bits) {
+  uint32_t hs = table_hash(key) & (kCap - 1);
+  for (int pr = 0; pr < kBrickProbe; ++pr) {
+    uint64_t kk = tk[hs];
+    if (kk == kEmptyKey) kk = lds_cas(&tk[hs], kEmptyKey, key);
+    if (kk == kEmptyKey || kk == key) {
+      __hip_atomic_fetch_or(&tv[hs], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return true;
+    }
+    hs = (hs + 1) & (kCap - 1);
+  }
+  return false;
+}
+
 // One search pass: Cnt at every candidate scale of the pass; the last block walks
 // the bisection tree and plans the next pass.
+//
+// Per tile and candidate the voxels are first merged in LDS. When the tile's bricks
+// fit a box of kBrickCap bricks (the usual case: tiles are spatially compact) the box
+// is a dense LDS array written with plain LDS ORs; otherwise an LDS hash is used.
 __global__ void __launch_bounds__(kThreads) k_eval(Ws w, Plan P) {
   Header* h = w.h;
   if (h->frame.status != HAV_OK) return;
   Ctrl* c = &h->ctrl;
   const int tile = blockIdx.x;
   clear_pending(w, c);
-  const int done = c->done;
-  const int nc = done ? 0 : c->nc;
+  if (c->done) return;  // a finished search: only the cleanup above was due
+  const int nc = c->nc;
   const int set = c->set;
 
   extern __shared__ uint64_t lds[];
-  uint64_t* lkeys = lds;
-  uint64_t* lvals = lds + kLdsCap;
-  __shared__ uint32_t s_tmp[kThreads / 64];
-  __shared__ int s_ncl;
+  uint64_t* lvals = lds;  // [nc][kBrickCap]: box words or hash values
+  uint64_t* lkeys = lds + static_cast<size_t>(nc) * kBrickCap;  // [nc][kBrickCap] hash keys
+  __shared__ int s_ncl[kMaxCand];
+  __shared__ uint32_t s_fresh[kMaxCand];
+  __shared__ float s_inv[kMaxCand][3];
+  __shared__ int s_dense[kMaxCand], s_hot[kMaxCand];
+  __shared__ uint32_t s_nb[kMaxCand][2];
+  __shared__ uint32_t s_box[kMaxCand][6];  // brick box: lo x,y,z, extent x,y, volume (0: hash)
+  __shared__ uint32_t s_red[kThreads / 64][6];
 
-  if (nc > 0) {
-    float px[kPerThread], py[kPerThread], pz[kPerThread];
-    bool ok[kPerThread];
-    const int64_t base = static_cast<int64_t>(tile) * kTile;
+  for (int e = threadIdx.x; e < nc * kBrickCap; e += kThreads) {
+    lkeys[e] = kEmptyKey;
+    lvals[e] = 0ull;
+  }
+  if (threadIdx.x < nc) {
+    const int k = threadIdx.x;
+    s_ncl[k] = 0;
+    s_fresh[k] = 0;
+    for (int a = 0; a < 3; ++a) s_inv[k][a] = c->cand_inv[k][a];
+    s_dense[k] = c->cand_dense[k];
+    s_hot[k] = c->cand_hot[k];
+    s_nb[k][0] = c->cand_nb[k][0];
+    s_nb[k][1] = c->cand_nb[k][1];
+  }
+  // thread t's points: the tile's points kPerThread*t .. +kPerThread-1 (neighbours in
+  // the binned order, so they often share a brick and merge in registers)
+  const int64_t base = static_cast<int64_t>(tile) * kTile + threadIdx.x;
+  float4 pt[kPerThread];
+  uint32_t live = 0;
+  uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k) {
-      const int64_t i = base + k * kThreads + threadIdx.x;
-      ok[k] = i < w.n && w.tag_s[i] == 0;
-      px[k] = ok[k] ? w.rx[i] : 0.0f;
-      py[k] = ok[k] ? w.ry[i] : 0.0f;
-      pz[k] = ok[k] ? w.rz[i] : 0.0f;
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t S = base + k * kThreads;
+    const bool ok = w.tag_s[S] == 0;
+    pt[k] = ok ? w.pts[S] : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ok) {
+      live |= 1u << k;
+      // offsets are >= +0, so their bit patterns order like their values
+      const uint32_t bx = __float_as_uint(pt[k].x), by = __float_as_uint(pt[k].y),
+                     bz = __float_as_uint(pt[k].z);
+      lo[0] = min(lo[0], bx); lo[1] = min(lo[1], by); lo[2] = min(lo[2], bz);
+      hi[0] = max(hi[0], bx); hi[1] = max(hi[1], by); hi[2] = max(hi[2], bz);
     }
-    for (int ci = 0; ci < nc; ++ci) {
-      for (int e = threadIdx.x; e < kLdsCap; e += kThreads) {
-        lkeys[e] = kEmptyKey;
-        lvals[e] = 0ull;
+  }
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t r[6];
+    for (int a = 0; a < 3; ++a) {
+      r[a] = __ockl_wfred_min_u32(lo[a]);
+      r[3 + a] = __ockl_wfred_max_u32(hi[a]);
+    }
+    if (lane == 0)
+      for (int q = 0; q < 6; ++q) s_red[wv][q] = r[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < nc) {
+    // brick box of the tile at this candidate: brick of the tile's min / max offset
+    const int k = threadIdx.x;
+    uint32_t l[3], u[3];
+    for (int a = 0; a < 3; ++a) {
+      uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+      for (int q = 0; q < kThreads / 64; ++q) {
+        mn = min(mn, s_red[q][a]);
+        mx = max(mx, s_red[q][3 + a]);
       }
-      if (threadIdx.x == 0) s_ncl = 0;
-      const float ix = c->cand_inv[ci][0], iy = c->cand_inv[ci][1], iz = c->cand_inv[ci][2];
-      __syncthreads();
+      if (mn > mx) { mn = 0; mx = 0; }  // no live point
+      l[a] = axis_coord(__uint_as_float(mn), s_inv[k][a]) >> kBrickShift;
+      u[a] = axis_coord(__uint_as_float(mx), s_inv[k][a]) >> kBrickShift;
+    }
+    const uint64_t dx = u[0] - l[0] + 1, dy = u[1] - l[1] + 1, dz = u[2] - l[2] + 1;
+    const uint64_t vol = dx * dy * dz;
+    s_box[k][0] = l[0];
+    s_box[k][1] = l[1];
+    s_box[k][2] = l[2];
+    s_box[k][3] = static_cast<uint32_t>(dx);
+    s_box[k][4] = static_cast<uint32_t>(dy);
+    s_box[k][5] = vol <= static_cast<uint64_t>(kBrickCap) ? static_cast<uint32_t>(vol) : 0u;
+  }
+  __syncthreads();
+
+  // 1. every candidate: runs of equal bricks among the thread's points merge in a
+  //    running register pair, then go to LDS
+  for (int ci = 0; ci < nc; ++ci) {
+    const float ix = s_inv[ci][0], iy = s_inv[ci][1], iz = s_inv[ci][2];
+    uint64_t* tv = lvals + ci * kBrickCap;
+    if (s_box[ci][5] != 0) {
+      const uint32_t bl0 = s_box[ci][0], bl1 = s_box[ci][1], bl2 = s_box[ci][2];
+      const uint32_t bdx = s_box[ci][3], bdy = s_box[ci][4];
+      uint32_t cur = 0xFFFFFFFFu;
+      uint64_t cb = 0ull;
 #pragma unroll
       for (int k = 0; k < kPerThread; ++k) {
-        if (!ok[k]) continue;
-        const uint32_t gx = axis_coord(px[k], ix);
-        const uint32_t gy = axis_coord(py[k], iy);
-        const uint32_t gz = axis_coord(pz[k], iz);
-        lds_insert_or(lkeys, lvals, kLdsCap - 1, brick_key(gx, gy, gz), brick_bit(gx, gy, gz));
+        if (!(live & (1u << k))) continue;
+        const uint32_t gx = axis_coord(pt[k].x, ix);
+        const uint32_t gy = axis_coord(pt[k].y, iy);
+        const uint32_t gz = axis_coord(pt[k].z, iz);
+        const uint32_t loc = ((gx >> kBrickShift) - bl0) +
+                             bdx * (((gy >> kBrickShift) - bl1) + bdy * ((gz >> kBrickShift) - bl2));
+        const uint64_t bit = brick_bit(gx, gy, gz);
+        if (loc == cur) {
+          cb |= bit;
+        } else {
+          if (cur != 0xFFFFFFFFu)
+            __hip_atomic_fetch_or(&tv[cur], cb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          cur = loc;
+          cb = bit;
+        }
       }
-      __syncthreads();
-      unsigned long long* gkeys = ctab_keys(w, set, ci);
-      unsigned long long* gmasks = ctab_masks(w, set, ci);
-      int32_t* list = claims(w, set, ci, tile);
-      uint32_t fresh = 0;
-      for (int e = threadIdx.x; e < kLdsCap; e += kThreads) {
-        const uint64_t key = lkeys[e];
-        if (key == kEmptyKey) continue;
-        const uint64_t bits = lvals[e];
-        bool claimed;
-        const uint32_t s = global_find_or_claim(gkeys, w.cmask, key, &claimed);
-        if (claimed) list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(s);
-        const unsigned long long old = atomicOr(&gmasks[s], static_cast<unsigned long long>(bits));
-        fresh += static_cast<uint32_t>(__popcll(bits & ~old));
-      }
-      const uint32_t tot = block_sum_u32<kThreads>(fresh, s_tmp);
-      if (threadIdx.x == 0) {
-        *claim_n(w, set, ci, tile) = s_ncl;
-        if (tot) atomicAdd(&h->acc[ci][tile & (kGroups - 1)][0], tot);
-      }
-      __syncthreads();
+      if (cur != 0xFFFFFFFFu)
+        __hip_atomic_fetch_or(&tv[cur], cb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      continue;
     }
+    // sparse tile: LDS hash on the brick id
+    const int dense = s_dense[ci];
+    const uint64_t nbx = s_nb[ci][0], nby = s_nb[ci][1];
+    uint64_t* tk = lkeys + ci * kBrickCap;
+    uint64_t cur = kEmptyKey, cb = 0ull;
+    for (int k = 0; k <= kPerThread; ++k) {
+      uint64_t key = kEmptyKey, bit = 0ull;
+      if (k < kPerThread && (live & (1u << k))) {
+        const uint32_t gx = axis_coord(pt[k].x, ix);
+        const uint32_t gy = axis_coord(pt[k].y, iy);
+        const uint32_t gz = axis_coord(pt[k].z, iz);
+        key = dense ? (static_cast<uint64_t>(gx >> kBrickShift) +
+                       nbx * (static_cast<uint64_t>(gy >> kBrickShift) + nby * (gz >> kBrickShift)))
+                    : brick_key(gx, gy, gz);
+        bit = brick_bit(gx, gy, gz);
+      } else if (k < kPerThread) {
+        continue;
+      }
+      if (key == cur && k < kPerThread) {
+        cb |= bit;
+        continue;
+      }
+      if (cur != kEmptyKey && !lds_try_or<kBrickCap>(tk, tv, cur, cb)) {
+        // crowded tile: straight to the global table
+        const uint32_t f =
+            dense ? dense_or(ctab_masks(w, set, ci), static_cast<uint32_t>(cur), cb, s_hot[ci],
+                             claims(w, set, ci, tile), &s_ncl[ci])
+                  : global_or(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, cur, cb,
+                              claims(w, set, ci, tile), &s_ncl[ci]);
+        if (f) atomicAdd(&s_fresh[ci], f);
+      }
+      cur = key;
+      cb = bit;
+    }
+  }
+  __syncthreads();
+
+  // 2. one global update per distinct brick of the tile, all candidates at once
+  for (int e = threadIdx.x; e < nc * kBrickCap; e += kThreads) {
+    const int ci = e / kBrickCap;
+    const int le = e - ci * kBrickCap;
+    const uint32_t vol = s_box[ci][5];
+    uint64_t key;
+    if (vol) {
+      if (le >= static_cast<int>(vol)) continue;
+      const uint64_t bits = lvals[e];
+      if (!bits) continue;
+      const uint32_t bdx = s_box[ci][3], bdy = s_box[ci][4];
+      const uint32_t bx = s_box[ci][0] + le % bdx;
+      const uint32_t t2 = le / bdx;
+      const uint32_t by = s_box[ci][1] + t2 % bdy;
+      const uint32_t bz = s_box[ci][2] + t2 / bdy;
+      key = s_dense[ci] ? (bx + static_cast<uint64_t>(s_nb[ci][0]) *
+                                    (by + static_cast<uint64_t>(s_nb[ci][1]) * bz))
+                        : (static_cast<uint64_t>(bx) | (static_cast<uint64_t>(by) << kBrickCoordBits) |
+                           (static_cast<uint64_t>(bz) << (2 * kBrickCoordBits)));
+    } else {
+      key = lkeys[e];
+      if (key == kEmptyKey) continue;
+    }
+    const uint64_t bits = lvals[e];
+    const uint32_t f =
+        s_dense[ci] ? dense_or(ctab_masks(w, set, ci), static_cast<uint32_t>(key), bits,
+                               s_hot[ci], claims(w, set, ci, tile), &s_ncl[ci])
+                    : global_or(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, key, bits,
+                                claims(w, set, ci, tile), &s_ncl[ci]);
+    if (f) atomicAdd(&s_fresh[ci], f);
+  }
+  __syncthreads();
+  if (threadIdx.x < nc) {
+    const int ci = threadIdx.x;
+    *claim_n(w, set, ci, tile) = s_ncl[ci];
+    if (s_fresh[ci]) atomicAdd(&h->acc[ci][tile & (kGroups - 1)][0], s_fresh[ci]);
   }
   if (!arrive_last(h, gridDim.x)) return;
+
+  // ---- controller (last block)
+  __shared__ uint32_t cnt[kMaxCand];
+  if (threadIdx.x < nc) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  if (threadIdx.x < nc * kGroups) {
+    const int ci = threadIdx.x / kGroups, g = threadIdx.x % kGroups;
+    const uint32_t v = take(&h->acc[ci][g][0]);
+    if (v) atomicAdd(&cnt[ci], v);
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  // ---- controller (one thread of the last block)
   c->pend_set = set;
   c->pend_nc = nc;
-  if (done) {
-    c->pend_nc = 0;
-    return;
-  }
   c->set = set ^ 1;
-  uint32_t cnt[kMaxCand];
-  for (int k = 0; k < nc; ++k) {
-    uint32_t s = 0;
-    for (int g = 0; g < kGroups; ++g) {
-      s += load_acc(&h->acc[k][g][0]);
-      h->acc[k][g][0] = 0;
-    }
-    cnt[k] = s;
-  }
   int k = 0;
   while (k < nc) {
     const uint32_t cc = cnt[k];
@@ -644,7 +909,7 @@ __global__ void __launch_bounds__(kThreads) k_eval(Ws w, Plan P) {
     if (cc >= c->m && cc <= c->upper) {
       c->accepted = 1;
       c->done = 1;
-      set_final(c, s, P);
+      set_final(c, s, P, h->frame);
       break;
     }
     if (cc < c->m) {
@@ -657,10 +922,12 @@ __global__ void __launch_bounds__(kThreads) k_eval(Ws w, Plan P) {
   }
   if (!c->done) {
     if (c->evals >= P.t_max) {
+      // no size in the window: the finest size with too many voxels if there was
+      // one (then trim), else the smallest size evaluated (then pad)
       c->done = 1;
-      set_final(c, c->lo > 0.0f ? c->lo : c->hi, P);
+      set_final(c, c->lo > 0.0f ? c->lo : c->hi, P, h->frame);
     } else {
-      plan_pass(c, P);
+      plan_pass(c, P, h->frame);
     }
   }
   const int L = c->layer;
@@ -671,45 +938,184 @@ __global__ void __launch_bounds__(kThreads) k_eval(Ws w, Plan P) {
 
 // ----------------------------------------------------------------------------- select
 
-__global__ void __launch_bounds__(kThreads) k_select(Ws w, Plan P) {
+// Packed voxel coordinate of a selection-table slot (dense: decoded from the slot).
+__device__ __forceinline__ uint64_t sel_key(const Ws& w, const Ctrl* c, int32_t slot) {
+  if (!c->sel_dense) return w.skeys[slot];
+  const uint32_t nx = c->sel_nv[0], ny = c->sel_nv[1];
+  const uint32_t u = static_cast<uint32_t>(slot);
+  const uint32_t gx = u % nx, t = u / nx;
+  return pack_key(gx, t % ny, t / ny);
+}
+
+__device__ __forceinline__ bool lds_try_min(uint64_t* tk, uint64_t* tv, uint64_t key, uint64_t v) {
+  uint32_t hs = table_hash(key) & (kLdsCap - 1);
+  for (int pr = 0; pr < kLdsCap; ++pr) {
+    uint64_t kk = tk[hs];
+    if (kk == kEmptyKey) kk = lds_cas(&tk[hs], kEmptyKey, key);
+    if (kk == kEmptyKey || kk == key) {
+      __hip_atomic_fetch_min(&tv[hs], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return true;
+    }
+    hs = (hs + 1) & (kLdsCap - 1);
+  }
+  return false;  // unreachable: the map holds twice the tile's points
+}
+
+// Global selection-table update of voxel `key` (dense: slot index) with `val`.
+__device__ __forceinline__ void select_global(const Ws& w, int dense, uint64_t key, uint64_t val,
+                                              int32_t* list, int* s_ncl) {
+  if (dense) {
+    // a plain read can only be stale by being too large: skip when ours is not
+    // smaller; the tile whose atomic finds the slot empty records it
+    const uint32_t sl = static_cast<uint32_t>(key);
+    if (val < w.svals[sl]) {
+      const unsigned long long old = atomicMin(&w.svals[sl], static_cast<unsigned long long>(val));
+      if (old == ~0ull) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(sl);
+    }
+    return;
+  }
+  uint32_t sl = table_hash(key) & w.cmask;
+  while (true) {
+    const unsigned long long k = w.skeys[sl];
+    const unsigned long long cur = w.svals[sl];
+    if (k == key) {
+      if (val < cur) atomicMin(&w.svals[sl], static_cast<unsigned long long>(val));
+      return;
+    }
+    if (k == kEmptyKey) {
+      const unsigned long long prev = atomicCAS(&w.skeys[sl], kEmptyKey, key);
+      if (prev == kEmptyKey || prev == key) {
+        if (prev == kEmptyKey) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(sl);
+        atomicMin(&w.svals[sl], static_cast<unsigned long long>(val));
+        return;
+      }
+    }
+    sl = (sl + 1) & w.cmask;
+  }
+}
+
+// Centre-closest point of every occupied voxel at the chosen size (Sec. 3.2): the
+// tile's minimum of (bits(d^2) << 32 | index) per voxel in LDS (a dense box array
+// when the tile's voxels fit one), then one global atomicMin per voxel of the tile.
+__global__ void __launch_bounds__(kThreads) k_select(Ws w) {
   Header* h = w.h;
   if (h->frame.status != HAV_OK) return;
   Ctrl* c = &h->ctrl;
   const int tile = blockIdx.x;
   clear_pending(w, c);
   extern __shared__ uint64_t lds[];
-  uint64_t* lkeys = lds;
-  uint64_t* lvals = lds + kLdsCap;
+  uint64_t* lvals = lds;
+  uint64_t* lkeys = lds + kLdsCap;
   __shared__ int s_ncl;
+  __shared__ uint32_t s_red[kThreads / 64][6];
+  __shared__ uint32_t s_box[6];
   const float vx = c->v_final[0], vy = c->v_final[1], vz = c->v_final[2];
   const float ix = c->inv_final[0], iy = c->inv_final[1], iz = c->inv_final[2];
+  const int dense = c->sel_dense;
+  const uint64_t nx = c->sel_nv[0], ny = c->sel_nv[1];
   for (int e = threadIdx.x; e < kLdsCap; e += kThreads) {
     lkeys[e] = kEmptyKey;
     lvals[e] = ~0ull;
   }
   if (threadIdx.x == 0) s_ncl = 0;
-  __syncthreads();
-  const int64_t base = static_cast<int64_t>(tile) * kTile;
+  const int64_t base = static_cast<int64_t>(tile) * kTile + threadIdx.x;
+  float4 pt[kPerThread];
+  uint32_t live = 0;
+  uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
-    const int64_t i = base + k * kThreads + threadIdx.x;
-    if (i >= w.n || w.tag_s[i] != 0) continue;
-    const float px = w.rx[i], py = w.ry[i], pz = w.rz[i];
-    const uint32_t gx = axis_coord(px, ix), gy = axis_coord(py, iy), gz = axis_coord(pz, iz);
-    const float d2 = centre_dist2(px, py, pz, gx, gy, gz, vx, vy, vz);
-    const uint64_t packed = (static_cast<uint64_t>(__float_as_uint(d2)) << 32) |
-                            static_cast<uint32_t>(w.ordi[i]);
-    lds_insert_min(lkeys, lvals, kLdsCap - 1, pack_key(gx, gy, gz), packed);
+    const int64_t S = base + k * kThreads;
+    const bool ok = w.tag_s[S] == 0;
+    pt[k] = ok ? w.pts[S] : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ok) {
+      live |= 1u << k;
+      const uint32_t bx = __float_as_uint(pt[k].x), by = __float_as_uint(pt[k].y),
+                     bz = __float_as_uint(pt[k].z);
+      lo[0] = min(lo[0], bx); lo[1] = min(lo[1], by); lo[2] = min(lo[2], bz);
+      hi[0] = max(hi[0], bx); hi[1] = max(hi[1], by); hi[2] = max(hi[2], bz);
+    }
+  }
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t r[6];
+    for (int a = 0; a < 3; ++a) {
+      r[a] = __ockl_wfred_min_u32(lo[a]);
+      r[3 + a] = __ockl_wfred_max_u32(hi[a]);
+    }
+    if (lane == 0)
+      for (int q = 0; q < 6; ++q) s_red[wv][q] = r[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float inv[3] = {ix, iy, iz};
+    uint32_t l[3], u[3];
+    for (int a = 0; a < 3; ++a) {
+      uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+      for (int q = 0; q < kThreads / 64; ++q) {
+        mn = min(mn, s_red[q][a]);
+        mx = max(mx, s_red[q][3 + a]);
+      }
+      if (mn > mx) { mn = 0; mx = 0; }
+      l[a] = axis_coord(__uint_as_float(mn), inv[a]);
+      u[a] = axis_coord(__uint_as_float(mx), inv[a]);
+    }
+    const uint64_t dx = u[0] - l[0] + 1, dy = u[1] - l[1] + 1, dz = u[2] - l[2] + 1;
+    const uint64_t vol = dx * dy * dz;
+    s_box[0] = l[0];
+    s_box[1] = l[1];
+    s_box[2] = l[2];
+    s_box[3] = static_cast<uint32_t>(dx);
+    s_box[4] = static_cast<uint32_t>(dy);
+    s_box[5] = vol <= static_cast<uint64_t>(kLdsCap) ? static_cast<uint32_t>(vol) : 0u;
+  }
+  __syncthreads();
+  const uint32_t bl0 = s_box[0], bl1 = s_box[1], bl2 = s_box[2], bdx = s_box[3], bdy = s_box[4];
+  const uint32_t vol = s_box[5];
+  {
+    // runs of equal voxels among the thread's points merge (min) in registers
+    uint64_t cur = kEmptyKey, cv = ~0ull;
+    for (int k = 0; k <= kPerThread; ++k) {
+      uint64_t key = kEmptyKey, val = ~0ull;
+      if (k < kPerThread) {
+        if (!(live & (1u << k))) continue;
+        const float4 p = pt[k];
+        const uint32_t gx = axis_coord(p.x, ix), gy = axis_coord(p.y, iy), gz = axis_coord(p.z, iz);
+        const float d2 = centre_dist2(p.x, p.y, p.z, gx, gy, gz, vx, vy, vz);
+        val = (static_cast<uint64_t>(__float_as_uint(d2)) << 32) |
+              static_cast<uint32_t>(__float_as_int(p.w));
+        key = vol ? static_cast<uint64_t>((gx - bl0) + bdx * ((gy - bl1) + bdy * (gz - bl2)))
+                  : (dense ? gx + nx * (gy + ny * gz) : pack_key(gx, gy, gz));
+        if (key == cur) {
+          cv = val < cv ? val : cv;
+          continue;
+        }
+      }
+      if (cur != kEmptyKey) {
+        if (vol)
+          __hip_atomic_fetch_min(&lvals[cur], cv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+          lds_try_min(lkeys, lvals, cur, cv);
+      }
+      cur = key;
+      cv = val;
+    }
   }
   __syncthreads();
   int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
   for (int e = threadIdx.x; e < kLdsCap; e += kThreads) {
-    const uint64_t key = lkeys[e];
-    if (key == kEmptyKey) continue;
-    bool claimed;
-    const uint32_t s = global_find_or_claim(w.skeys, w.cmask, key, &claimed);
-    if (claimed) list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(s);
-    atomicMin(&w.svals[s], static_cast<unsigned long long>(lvals[e]));
+    const uint64_t val = lvals[e];
+    if (val == ~0ull) continue;
+    uint64_t key;
+    if (vol) {
+      if (e >= static_cast<int>(vol)) continue;
+      const uint32_t gx = bl0 + static_cast<uint32_t>(e) % bdx;
+      const uint32_t t2 = static_cast<uint32_t>(e) / bdx;
+      const uint32_t gy = bl1 + t2 % bdy, gz = bl2 + t2 / bdy;
+      key = dense ? gx + nx * (gy + ny * gz) : pack_key(gx, gy, gz);
+    } else {
+      key = lkeys[e];
+    }
+    select_global(w, dense, key, val, list, &s_ncl);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -717,12 +1123,16 @@ __global__ void __launch_bounds__(kThreads) k_select(Ws w, Plan P) {
     if (s_ncl) atomicAdd(&h->acc[0][tile & (kGroups - 1)][0], static_cast<uint32_t>(s_ncl));
   }
   if (!arrive_last(h, gridDim.x)) return;
-  if (threadIdx.x != 0) return;
-  uint32_t nvox = 0;
-  for (int g = 0; g < kGroups; ++g) {
-    nvox += load_acc(&h->acc[0][g][0]);
-    h->acc[0][g][0] = 0;
+  __shared__ uint32_t s_nvox;
+  if (threadIdx.x == 0) s_nvox = 0;
+  __syncthreads();
+  if (threadIdx.x < kGroups) {
+    const uint32_t v = take(&h->acc[0][threadIdx.x][0]);
+    if (v) atomicAdd(&s_nvox, v);
   }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const uint32_t nvox = s_nvox;
   c->pend_nc = 0;
   c->ncand = nvox;
   c->trim = nvox > c->m ? 1 : 0;
@@ -739,6 +1149,29 @@ __global__ void __launch_bounds__(kThreads) k_select(Ws w, Plan P) {
 
 // ----------------------------------------------------------------------------- trim
 
+// The digit whose bucket holds rank (0-based) in a 256-bin histogram, and the rank
+// inside that bucket: one bin per thread and a block scan. Every thread gets both.
+__device__ void find_digit(const uint32_t* hist, uint32_t rank, int* digit, uint32_t* rest) {
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  __shared__ int s_d;
+  __shared__ uint32_t s_r;
+  const uint32_t v = threadIdx.x < 256 ? hist[threadIdx.x] : 0u;
+  if (threadIdx.x == 0) {
+    s_d = 255;
+    s_r = 0;
+  }
+  uint32_t ex;
+  block_exclusive_scan<kThreads>(v, &ex, s_tmp);
+  if (threadIdx.x < 256 && rank >= ex && rank < ex + v) {
+    s_d = threadIdx.x;
+    s_r = rank - ex;
+  }
+  __syncthreads();
+  *digit = s_d;
+  *rest = s_r;
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(kThreads) k_trim_hist(Ws w, int round) {
   Header* h = w.h;
   if (h->frame.status != HAV_OK) return;
@@ -753,7 +1186,7 @@ __global__ void __launch_bounds__(kThreads) k_trim_hist(Ws w, int round) {
   const int dshift = 56 - 8 * round;
   const uint64_t pref = c->prefix;
   for (int i = threadIdx.x; i < n; i += kThreads) {
-    const uint64_t p = voxel_priority(w.skeys[list[i]]);
+    const uint64_t p = voxel_priority(sel_key(w, c, list[i]));
     if (round > 0 && (p >> (dshift + 8)) != (pref >> (dshift + 8))) continue;
     atomicAdd(&lh[(p >> dshift) & 255u], 1u);
   }
@@ -766,43 +1199,37 @@ __global__ void __launch_bounds__(kThreads) k_trim_hist(Ws w, int round) {
   __shared__ uint32_t tot[256];
   for (int i = threadIdx.x; i < 256; i += kThreads) {
     uint32_t s = 0;
-    for (int q = 0; q < kGroups; ++q) {
-      s += load_acc(&h->hist[q][i]);
-      h->hist[q][i] = 0;
-    }
+    for (int q = 0; q < kGroups; ++q) s += take(&h->hist[q][i]);
     tot[i] = s;
   }
   __syncthreads();
+  int b;
+  uint32_t rest;
+  find_digit(tot, c->rank, &b, &rest);
   if (threadIdx.x == 0) {
-    uint32_t rank = c->rank, acc = 0;
-    int b = 0;
-    for (; b < 255; ++b) {
-      if (rank < acc + tot[b]) break;
-      acc += tot[b];
-    }
-    c->rank = rank - acc;
+    c->rank = rest;
     c->prefix |= static_cast<uint64_t>(b) << dshift;
     c->rounds_done = round + 1;
   }
 }
 
-// Keep the representatives below the prefix bucket, queue the bucket's members, and
-// empty the voxel table. The last block picks the exact rank inside the bucket.
+// Keep the representatives below the prefix bucket, queue the bucket's members for
+// k_ties, and empty the selection table.
 __global__ void __launch_bounds__(kThreads) k_mark(Ws w) {
   Header* h = w.h;
   if (h->frame.status != HAV_OK) return;
-  Ctrl* c = &h->ctrl;
+  const Ctrl* c = &h->ctrl;
   const int tile = blockIdx.x;
   const int n = w.scn[tile];
   const int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
   const int trim = c->trim;
-  const int R = c->rounds_done;
-  const int shift = 64 - 8 * R;  // bits below the decided prefix
+  const int dense = c->sel_dense;
+  const int shift = 64 - 8 * c->rounds_done;  // bits below the decided prefix
   const uint64_t pref_hi = shift >= 64 ? 0ull : (c->prefix >> shift);
   const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
   const int g = tile & (kGroups - 1);
   __shared__ uint32_t s_base;
-  // ties are staged through registers: at most kPerThread per thread per chunk
+  __shared__ uint32_t s_wbase[kThreads / 64];
   for (int i0 = 0; i0 < n; i0 += kThreads) {
     const int i = i0 + threadIdx.x;
     bool tie = false;
@@ -810,9 +1237,9 @@ __global__ void __launch_bounds__(kThreads) k_mark(Ws w) {
     int32_t orig = 0;
     if (i < n) {
       const int32_t s = list[i];
-      const uint64_t key = w.skeys[s];
+      const uint64_t key = sel_key(w, c, s);
       orig = static_cast<int32_t>(w.svals[s] & 0xFFFFFFFFull);
-      w.skeys[s] = kEmptyKey;
+      if (!dense) w.skeys[s] = kEmptyKey;
       w.svals[s] = ~0ull;
       bool keep = true;
       if (trim) {
@@ -826,9 +1253,7 @@ __global__ void __launch_bounds__(kThreads) k_mark(Ws w) {
         w.tag_s[w.invp[orig]] = lt;
       }
     }
-    // append ties of this chunk to the group's list
     const uint64_t bal = __ballot(tie);
-    __shared__ uint32_t s_wbase[kThreads / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (lane == 0) s_wbase[wv] = static_cast<uint32_t>(__popcll(bal));
     __syncthreads();
@@ -843,7 +1268,8 @@ __global__ void __launch_bounds__(kThreads) k_mark(Ws w) {
     }
     __syncthreads();
     if (tie) {
-      const uint32_t pos = s_base + s_wbase[wv] + static_cast<uint32_t>(__popcll(bal & ((1ull << lane) - 1ull)));
+      const uint32_t pos =
+          s_base + s_wbase[wv] + static_cast<uint32_t>(__popcll(bal & ((1ull << lane) - 1ull)));
       if (pos < w.tie_seg) {
         w.tie_p[g * w.tie_seg + pos] = p;
         w.tie_o[g * w.tie_seg + pos] = orig;
@@ -852,56 +1278,84 @@ __global__ void __launch_bounds__(kThreads) k_mark(Ws w) {
     __syncthreads();
   }
   if (threadIdx.x == 0) w.scn[tile] = 0;
-  if (!arrive_last(h, gridDim.x)) return;
-  // ---- last block: exact rank inside the bucket (radix select over the ties)
-  __shared__ uint32_t cnt_g[kGroups];
+}
+
+// One block: the rank-th smallest priority inside the bucket (radix select over the
+// bits below the prefix), then mark every queued voxel up to it. The bucket is
+// staged in LDS when it fits (it normally holds a handful of voxels).
+constexpr int kTieLds = 4096;
+
+__global__ void __launch_bounds__(kThreads) k_ties(Ws w) {
+  Header* h = w.h;
+  if (h->frame.status != HAV_OK) return;
+  Ctrl* c = &h->ctrl;
+  __shared__ uint32_t cnt_g[kGroups + 1];  // exclusive prefix over groups
   __shared__ uint32_t hst[256];
   __shared__ uint64_t s_pref;
   __shared__ uint32_t s_rank;
-  if (threadIdx.x < kGroups) {
-    const uint32_t t = load_acc(&h->tie_cur[threadIdx.x][0]);
-    cnt_g[threadIdx.x] = t < w.tie_seg ? t : static_cast<uint32_t>(w.tie_seg);
-    h->tie_cur[threadIdx.x][0] = 0;
-  }
+  __shared__ uint64_t lp[kTieLds];
+  __shared__ int32_t lo[kTieLds];
   if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int q = 0; q < kGroups; ++q) {
+      const uint32_t t = h->tie_cur[q][0];
+      cnt_g[q] = acc;
+      acc += t < w.tie_seg ? t : static_cast<uint32_t>(w.tie_seg);
+    }
+    cnt_g[kGroups] = acc;
     s_pref = c->prefix;
     s_rank = c->rank;
   }
   __syncthreads();
-  if (!trim) return;
+  if (threadIdx.x < kGroups) h->tie_cur[threadIdx.x][0] = 0;
+  if (!c->trim) return;
+  const uint32_t total = cnt_g[kGroups];
+  const bool staged = total <= static_cast<uint32_t>(kTieLds);
+  // item j of the bucket: group q with cnt_g[q] <= j < cnt_g[q+1]
+  auto locate = [&](uint32_t j) -> int64_t {
+    int q = 0;
+    while (j >= cnt_g[q + 1]) ++q;
+    return static_cast<int64_t>(q) * w.tie_seg + (j - cnt_g[q]);
+  };
+  if (staged) {
+    for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
+      const int64_t at = locate(j);
+      lp[j] = w.tie_p[at];
+      lo[j] = w.tie_o[at];
+    }
+    __syncthreads();
+  }
+  const int shift = 64 - 8 * c->rounds_done;
+  const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
   for (int sh = shift - 8; sh >= 0; sh -= 8) {
     for (int i = threadIdx.x; i < 256; i += kThreads) hst[i] = 0;
     __syncthreads();
     const uint64_t pref = s_pref;
-    for (int q = 0; q < kGroups; ++q) {
-      for (uint32_t i = threadIdx.x; i < cnt_g[q]; i += kThreads) {
-        const uint64_t p = w.tie_p[q * w.tie_seg + i];
-        if (sh + 8 < 64 && (p >> (sh + 8)) != (pref >> (sh + 8))) continue;
-        atomicAdd(&hst[(p >> sh) & 255u], 1u);
-      }
+    for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
+      const uint64_t p = staged ? lp[j] : w.tie_p[locate(j)];
+      if (sh + 8 < 64 && (p >> (sh + 8)) != (pref >> (sh + 8))) continue;
+      atomicAdd(&hst[(p >> sh) & 255u], 1u);
     }
     __syncthreads();
+    int b;
+    uint32_t rest;
+    find_digit(hst, s_rank, &b, &rest);
     if (threadIdx.x == 0) {
-      uint32_t rank = s_rank, acc = 0;
-      int b = 0;
-      for (; b < 255; ++b) {
-        if (rank < acc + hst[b]) break;
-        acc += hst[b];
-      }
-      s_rank = rank - acc;
+      s_rank = rest;
       s_pref = pref | (static_cast<uint64_t>(b) << sh);
     }
     __syncthreads();
   }
   const uint64_t thr = s_pref;  // the rank-th smallest priority of the bucket
-  for (int q = 0; q < kGroups; ++q) {
-    for (uint32_t i = threadIdx.x; i < cnt_g[q]; i += kThreads) {
-      if (w.tie_p[q * w.tie_seg + i] <= thr) {
-        const int32_t orig = w.tie_o[q * w.tie_seg + i];
-        if (orig >= 0 && orig < w.n) {
-          w.tag_o[orig] = lt;
-          w.tag_s[w.invp[orig]] = lt;
-        }
+  for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
+    int64_t at = 0;
+    if (!staged) at = locate(j);
+    const uint64_t p = staged ? lp[j] : w.tie_p[at];
+    if (p <= thr) {
+      const int32_t orig = staged ? lo[j] : w.tie_o[at];
+      if (orig >= 0 && orig < w.n) {
+        w.tag_o[orig] = lt;
+        w.tag_s[w.invp[orig]] = lt;
       }
     }
   }
@@ -925,13 +1379,13 @@ __global__ void __launch_bounds__(kThreads) k_scan_count(Ws w, int mode) {
     }
   }
   const uint32_t tot = block_sum_u32<kThreads>(cnt, s_tmp);
-  if (threadIdx.x == 0) w.tcnt[blockIdx.x] = tot;
+  if (threadIdx.x == 0) atomicExch(&w.tcnt[blockIdx.x], tot);
   if (!arrive_last(h, gridDim.x)) return;
   // last block: exclusive scan of the tile counts
   uint32_t carry = 0;
   for (int b0 = 0; b0 < static_cast<int>(gridDim.x); b0 += kThreads) {
     const int b = b0 + threadIdx.x;
-    const uint32_t v = b < static_cast<int>(gridDim.x) ? w.tcnt[b] : 0u;
+    const uint32_t v = b < static_cast<int>(gridDim.x) ? peek(&w.tcnt[b]) : 0u;
     uint32_t ex;
     const uint32_t t = block_exclusive_scan<kThreads>(v, &ex, s_tmp);
     if (b < static_cast<int>(gridDim.x)) w.tcnt[b] = carry + ex;
@@ -1005,7 +1459,7 @@ __global__ void __launch_bounds__(kThreads) k_out_write(Ws w, int32_t* idx, int6
 // ----------------------------------------------------------------------------- workspace init
 
 __global__ void __launch_bounds__(kThreads) k_ws_init(Ws w, size_t nct, size_t ncn, size_t nst,
-                                                      size_t nsn) {
+                                                      size_t nsv, size_t nsn) {
   const size_t stride = static_cast<size_t>(gridDim.x) * kThreads;
   const size_t t0 = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
   for (size_t i = t0; i < nct; i += stride) {
@@ -1013,10 +1467,8 @@ __global__ void __launch_bounds__(kThreads) k_ws_init(Ws w, size_t nct, size_t n
     w.cmasks[i] = 0ull;
   }
   for (size_t i = t0; i < ncn; i += stride) w.ccn[i] = 0;
-  for (size_t i = t0; i < nst; i += stride) {
-    w.skeys[i] = kEmptyKey;
-    w.svals[i] = ~0ull;
-  }
+  for (size_t i = t0; i < nst; i += stride) w.skeys[i] = kEmptyKey;
+  for (size_t i = t0; i < nsv; i += stride) w.svals[i] = ~0ull;
   for (size_t i = t0; i < nsn; i += stride) w.scn[i] = 0;
   uint32_t* hz = reinterpret_cast<uint32_t*>(w.h);
   for (size_t i = t0; i < sizeof(Header) / 4; i += stride) hz[i] = 0;
@@ -1075,8 +1527,8 @@ int bin_blocks(int64_t n) {
 }
 
 struct Layout {
-  size_t hdr, rx, ry, rz, ordi, invp, tag_s, tag_o, part, bh, bsum, ckeys, cmasks, ccl, ccn, skeys,
-      svals, scl, scn, tie_p, tie_o, tcnt, total;
+  size_t hdr, pts, invp, tag_s, tag_o, part, bh, binpre, bsum, ckeys, cmasks, ccl, ccn, skeys, svals, scl,
+      scn, tie_p, tie_o, tcnt, total;
   int64_t n_ws;
   uint32_t cap_ws;
   int32_t ntile_ws, nscan_ws, ncmax;
@@ -1092,25 +1544,24 @@ Layout make_layout(int64_t n, int depth) {
   L.ncmax = (1 << depth) - 1;
   L.tie_seg = static_cast<int64_t>((L.ntile_ws + kGroups - 1) / kGroups) * kTile;
   const size_t N = static_cast<size_t>(n);
+  const size_t NP = static_cast<size_t>(L.ntile_ws) * kTile;
   const size_t tabs = 2 * static_cast<size_t>(L.ncmax);
   size_t o = 0;
   L.hdr = o;    o = align_up(o + sizeof(Header));
-  L.rx = o;     o = align_up(o + N * 4);
-  L.ry = o;     o = align_up(o + N * 4);
-  L.rz = o;     o = align_up(o + N * 4);
-  L.ordi = o;   o = align_up(o + N * 4);
+  L.pts = o;    o = align_up(o + NP * 16);
   L.invp = o;   o = align_up(o + N * 4);
-  L.tag_s = o;  o = align_up(o + N);
+  L.tag_s = o;  o = align_up(o + NP);
   L.tag_o = o;  o = align_up(o + N);
   L.part = o;   o = align_up(o + static_cast<size_t>(kMaxBBoxBlocks) * 8 * 4);
   L.bh = o;     o = align_up(o + static_cast<size_t>(kBins) * kMaxBinBlocks * 4);
-  L.bsum = o;   o = align_up(o + static_cast<size_t>(kMaxBinBlocks) * 4);
+  L.binpre = o; o = align_up(o + static_cast<size_t>(kBins) * 4);
+  L.bsum = o;   o = align_up(o + static_cast<size_t>(kBinChunks) * 4);
   L.ckeys = o;  o = align_up(o + tabs * L.cap_ws * 8);
   L.cmasks = o; o = align_up(o + tabs * L.cap_ws * 8);
   L.ccl = o;    o = align_up(o + tabs * L.ntile_ws * kTile * 4);
   L.ccn = o;    o = align_up(o + tabs * L.ntile_ws * 4);
   L.skeys = o;  o = align_up(o + static_cast<size_t>(L.cap_ws) * 8);
-  L.svals = o;  o = align_up(o + static_cast<size_t>(L.cap_ws) * 8);
+  L.svals = o;  o = align_up(o + static_cast<size_t>(L.cap_ws) * kSelDense * 8);
   L.scl = o;    o = align_up(o + static_cast<size_t>(L.ntile_ws) * kTile * 4);
   L.scn = o;    o = align_up(o + static_cast<size_t>(L.ntile_ws) * 4);
   L.tie_p = o;  o = align_up(o + static_cast<size_t>(kGroups) * L.tie_seg * 8);
@@ -1128,15 +1579,13 @@ uint64_t magic_of(const Layout& L) {
 Ws make_ws(char* base, const Layout& L, int64_t n) {
   Ws w;
   w.h = reinterpret_cast<Header*>(base + L.hdr);
-  w.rx = reinterpret_cast<float*>(base + L.rx);
-  w.ry = reinterpret_cast<float*>(base + L.ry);
-  w.rz = reinterpret_cast<float*>(base + L.rz);
-  w.ordi = reinterpret_cast<int32_t*>(base + L.ordi);
+  w.pts = reinterpret_cast<float4*>(base + L.pts);
   w.invp = reinterpret_cast<int32_t*>(base + L.invp);
   w.tag_s = reinterpret_cast<uint8_t*>(base + L.tag_s);
   w.tag_o = reinterpret_cast<uint8_t*>(base + L.tag_o);
   w.part = reinterpret_cast<uint32_t*>(base + L.part);
   w.bh = reinterpret_cast<uint32_t*>(base + L.bh);
+  w.binpre = reinterpret_cast<uint32_t*>(base + L.binpre);
   w.bsum = reinterpret_cast<uint32_t*>(base + L.bsum);
   w.ckeys = reinterpret_cast<unsigned long long*>(base + L.ckeys);
   w.cmasks = reinterpret_cast<unsigned long long*>(base + L.cmasks);
@@ -1151,6 +1600,7 @@ Ws make_ws(char* base, const Layout& L, int64_t n) {
   w.tcnt = reinterpret_cast<uint32_t*>(base + L.tcnt);
   w.n = n;
   w.ntile = static_cast<int32_t>((n + kTile - 1) / kTile);
+  w.npad = static_cast<int64_t>(w.ntile) * kTile;
   w.nscan = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
   w.nbb = bin_blocks(n);
   w.nbbox = bbox_blocks(n);
@@ -1201,7 +1651,7 @@ int grid_for(int64_t work) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, 4096)));
 }
 
-// Radix rounds over the top priority bits before the last block settles the bucket:
+// Radix rounds over the top priority bits before one block settles the bucket:
 // enough that the expected bucket (n / 256^R) stays small.
 int trim_rounds(int64_t n) {
   int R = 1;
@@ -1215,8 +1665,6 @@ int trim_rounds(int64_t n) {
     if (hipGetLastError() != hipSuccess) return HAV_ERR_HIP;     \
   } while (0)
 
-constexpr size_t kLdsBytes = 2 * kLdsCap * sizeof(uint64_t);
-
 hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_t* p, int32_t* idx,
                        char* ws, const Layout& L, hav_info_t* info_dev, hipStream_t st) {
   Ws w = make_ws(ws, L, N);
@@ -1226,6 +1674,8 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
   P.depth = depth_of(p);
   P.fixed = (p->flags & HAV_FIXED_VOXEL) ? 1 : 0;
   P.magic = magic_of(L);
+  P.cap = w.cap;
+  P.sel_cap = w.cap * static_cast<uint32_t>(kSelDense);
   for (int a = 0; a < 3; ++a) {
     P.aspect[a] = p->aspect[a];
     P.fixed_v[a] = p->fixed_voxel[a];
@@ -1248,16 +1698,19 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
     return HAV_OK;
   }
   HAV_LAUNCH(k_bin_count, dim3(w.nbb), dim3(kThreads), 0, st, xyz, w, P);
-  HAV_LAUNCH(k_bin_scan, dim3(w.nbb), dim3(kThreads), 0, st, w, P);
+  HAV_LAUNCH(k_bin_scan, dim3(kBinChunks), dim3(kThreads), 0, st, w, P);
   HAV_LAUNCH(k_bin_scatter, dim3(w.nbb), dim3(kThreads), 0, st, xyz, w);
   const int passes = P.fixed ? 0 : (p->t_max + P.depth - 1) / P.depth;
   const int R = trim_rounds(N);
+  const size_t eval_lds = 2 * static_cast<size_t>((1 << P.depth) - 1) * kBrickCap * sizeof(uint64_t);
+  const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
   for (int l = 0; l < nl; ++l) {
     for (int q = 0; q < passes; ++q)
-      HAV_LAUNCH(k_eval, dim3(w.ntile), dim3(kThreads), kLdsBytes, st, w, P);
-    HAV_LAUNCH(k_select, dim3(w.ntile), dim3(kThreads), kLdsBytes, st, w, P);
+      HAV_LAUNCH(k_eval, dim3(w.ntile), dim3(kThreads), eval_lds, st, w, P);
+    HAV_LAUNCH(k_select, dim3(w.ntile), dim3(kThreads), sel_lds, st, w);
     for (int r = 0; r < R; ++r) HAV_LAUNCH(k_trim_hist, dim3(w.ntile), dim3(kThreads), 0, st, w, r);
     HAV_LAUNCH(k_mark, dim3(w.ntile), dim3(kThreads), 0, st, w);
+    HAV_LAUNCH(k_ties, dim3(1), dim3(kThreads), 0, st, w);
     HAV_LAUNCH(k_scan_count, dim3(w.nscan), dim3(kThreads), 0, st, w, 0);
     HAV_LAUNCH(k_pad_mark, dim3(w.nscan), dim3(kThreads), 0, st, w, P);
   }
@@ -1297,7 +1750,8 @@ hav_status_t init_ws(char* base, const Layout& L, hipStream_t st) {
   const size_t nct = 2 * static_cast<size_t>(L.ncmax) * L.cap_ws;
   const size_t ncn = 2 * static_cast<size_t>(L.ncmax) * L.ntile_ws;
   HAV_LAUNCH(k_ws_init, dim3(2048), dim3(kThreads), 0, st, w, nct, ncn,
-             static_cast<size_t>(L.cap_ws), static_cast<size_t>(L.ntile_ws));
+             static_cast<size_t>(L.cap_ws), static_cast<size_t>(L.cap_ws) * kSelDense,
+             static_cast<size_t>(L.ntile_ws));
   HAV_LAUNCH(k_ws_seal, dim3(1), dim3(64), 0, st, w.h, magic_of(L));
   return HAV_OK;
 }

@@ -30,7 +30,9 @@ __device__ __forceinline__ float ordered_to_float(uint32_t k) {
 // the stage frame (r = p - origin): g = floor(fl(r * inv)), inv = fl(1 / v).
 __device__ __forceinline__ uint32_t axis_coord(float r, float inv) {
   const float q = r * inv;
-  return static_cast<uint32_t>(floorf(q));  // q in [0, 2^21): floor, then exact convert
+  // q is never negative (r >= +0, inv > 0) and below 2^21, so converting with
+  // truncation toward zero is exactly its floor
+  return static_cast<uint32_t>(q);
 }
 
 __device__ __forceinline__ uint64_t pack_key(uint32_t gx, uint32_t gy, uint32_t gz) {
@@ -92,65 +94,6 @@ __device__ __forceinline__ uint64_t lds_cas(uint64_t* p, uint64_t expected, uint
   __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
   return expected;
-}
-
-// ------------------------------------------------------------------ LDS hash map
-// Open addressing over `cap` (power of two) entries; keys kEmptyKey when free.
-// mode OR: value |= v;  mode MIN: value = min(value, v).
-__device__ __forceinline__ void lds_insert_or(uint64_t* keys, uint64_t* vals, uint32_t mask,
-                                              uint64_t key, uint64_t v) {
-  uint32_t h = table_hash(key) & mask;
-  while (true) {
-    uint64_t k = keys[h];
-    if (k == kEmptyKey) {
-      k = lds_cas(&keys[h], kEmptyKey, key);
-    }
-    if (k == kEmptyKey || k == key) {
-      __hip_atomic_fetch_or(&vals[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      return;
-    }
-    h = (h + 1) & mask;
-  }
-}
-
-__device__ __forceinline__ void lds_insert_min(uint64_t* keys, uint64_t* vals, uint32_t mask,
-                                               uint64_t key, uint64_t v) {
-  uint32_t h = table_hash(key) & mask;
-  while (true) {
-    uint64_t k = keys[h];
-    if (k == kEmptyKey) {
-      k = lds_cas(&keys[h], kEmptyKey, key);
-    }
-    if (k == kEmptyKey || k == key) {
-      __hip_atomic_fetch_min(&vals[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      return;
-    }
-    h = (h + 1) & mask;
-  }
-}
-
-// ------------------------------------------------------------------ global table
-// Find or claim the slot of `key`; *claimed is set when this call stored the key.
-// A slot changes at most once (empty -> key) between clears, and clears happen in
-// an earlier kernel, so a plain load can only be stale by showing the slot empty;
-// the CAS then settles it.
-__device__ __forceinline__ uint32_t global_find_or_claim(unsigned long long* keys, uint32_t mask,
-                                                         uint64_t key, bool* claimed) {
-  uint32_t s = table_hash(key) & mask;
-  *claimed = false;
-  while (true) {
-    const unsigned long long k = keys[s];
-    if (k == key) return s;
-    if (k == kEmptyKey) {
-      const unsigned long long prev = atomicCAS(&keys[s], kEmptyKey, key);
-      if (prev == kEmptyKey) {
-        *claimed = true;
-        return s;
-      }
-      if (prev == key) return s;
-    }
-    s = (s + 1) & mask;
-  }
 }
 
 // ------------------------------------------------------------------ block helpers
