@@ -44,6 +44,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 
@@ -74,6 +75,7 @@ constexpr int kScanTile = 4096;                 // tag scans: 16 per thread
 constexpr int kScanPer = kScanTile / kThreads;
 constexpr int kSelDense = 4;                    // voxel value slots per brick-table slot
 constexpr uint64_t kMagic = 0x4841565F57533031ull;
+constexpr int kMaxDevices = 64;
 
 // ----------------------------------------------------------------------------- state
 
@@ -122,6 +124,7 @@ struct Plan {  // per-call constants (kernel argument)
   uint64_t magic;
   uint32_t cap;       // brick table slots: dense brick grids up to this size
   uint32_t sel_cap;   // voxel value slots: dense voxel grids up to this size
+  float spec_mult;    // speculation budget of the search, in multiples of the window top
 };
 
 struct alignas(256) Header {
@@ -135,6 +138,12 @@ struct alignas(256) Header {
   uint32_t acc[kMaxCand][kGroups][kStride];
   uint32_t hist[kGroups][256];
   uint32_t tie_cur[kGroups][kStride];
+  // persistent search: double-buffered per-pass counts and the grid barrier
+  uint32_t sacc[2][kMaxCand][kGroups][kStride];
+  uint32_t bar_grp[kGroups][kStride];
+  uint32_t bar_top[kStride];
+  uint32_t bar_gen[kStride];
+  uint32_t bar_err[kStride];
 };
 
 // Device view of the workspace for one stage.
@@ -307,6 +316,13 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
   c->rounds_done = 0;
   h->info.m[L] = static_cast<int32_t>(P.m[L]);
   h->info.layers = L + 1;
+  for (int b = 0; b < 2; ++b)
+    for (int k = 0; k < kMaxCand; ++k)
+      for (int g = 0; g < kGroups; ++g) h->sacc[b][k][g][0] = 0;
+  h->bar_gen[0] = 0;
+  h->bar_err[0] = 0;
+  h->bar_top[0] = 0;
+  for (int g = 0; g < kGroups; ++g) h->bar_grp[g][0] = 0;
   if (P.fixed) {
     c->done = 1;
     c->nc = 0;
@@ -934,6 +950,506 @@ __global__ void __launch_bounds__(kThreads) k_eval(Ws w, Plan P) {
   h->info.evals[L] = c->evals;
   h->info.accepted[L] = c->accepted;
   if (c->done) h->info.s[L] = c->s_final;
+}
+
+// ----------------------------------------------------------------------------- persistent search
+
+// One launch runs the whole adaptive voxel search of a layer: every block evaluates
+// its tiles at the pass's candidate scales, the blocks meet at a grid barrier, and
+// each block then reads the pass's counts and runs the same controller step, so all
+// blocks agree on the next pass without a kernel boundary. Within this kernel every
+// cross-block access is an atomic RMW or an agent-scope atomic load (tables, clears,
+// counts, barrier), never plain memory another block wrote.
+
+constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr float kSpecMult = 16.0f;
+
+struct SState {
+  float lo, hi;
+  uint32_t c_hi;  // count at hi (0: hi is the initial bracket, never evaluated)
+  int32_t evals, done, accepted;
+  int32_t nc, set, prev_set, prev_nc;
+  uint32_t prev_dense;  // bit k: candidate k of the previous pass used a dense table
+  float s_final;
+  float cand_s[kMaxCand];
+  float cand_inv[kMaxCand][3];
+  int32_t cand_dense[kMaxCand], cand_hot[kMaxCand];
+  uint32_t cand_nb[kMaxCand][2];
+};
+
+struct EvalShared {
+  int ncl[kMaxCand];
+  uint32_t fresh[kMaxCand];
+  uint32_t box[kMaxCand][6];  // brick box: lo x,y,z, extent x,y, volume (0: hash)
+  uint32_t red[kThreads / 64][6];
+  uint32_t tb[6];             // tile's min (0..2) and max (3..5) offset bits per axis
+};
+
+__device__ __forceinline__ unsigned long long ld_agent(unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// global_or / dense_or for the persistent search: the tables are cleared and refilled
+// inside one launch, so every read of them is an agent-scope atomic load (a plain load
+// could return a line this compute die cached in an earlier pass).
+__device__ __forceinline__ uint32_t global_or_c(unsigned long long* keys, unsigned long long* masks,
+                                                uint32_t cmask, uint64_t key, uint64_t bits,
+                                                int32_t* list, int* s_ncl) {
+  uint32_t s = table_hash(key) & cmask;
+  while (true) {
+    const unsigned long long k = ld_agent(&keys[s]);
+    if (k == key) {
+      const unsigned long long old = atomicOr(&masks[s], static_cast<unsigned long long>(bits));
+      return static_cast<uint32_t>(__popcll(bits & ~old));
+    }
+    if (k == kEmptyKey) {
+      const unsigned long long prev = atomicCAS(&keys[s], kEmptyKey, key);
+      if (prev == kEmptyKey || prev == key) {
+        if (prev == kEmptyKey) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(s);
+        const unsigned long long old = atomicOr(&masks[s], static_cast<unsigned long long>(bits));
+        return static_cast<uint32_t>(__popcll(bits & ~old));
+      }
+    }
+    s = (s + 1) & cmask;
+  }
+}
+
+__device__ __forceinline__ uint32_t dense_or_c(unsigned long long* masks, uint32_t slot,
+                                               uint64_t bits, bool hot, int32_t* list, int* s_ncl) {
+  if (hot && (ld_agent(&masks[slot]) & bits) == bits) return 0;
+  const unsigned long long old = atomicOr(&masks[slot], static_cast<unsigned long long>(bits));
+  if (old == 0ull) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(slot);
+  return static_cast<uint32_t>(__popcll(bits & ~old));
+}
+
+// Candidates of the next pass (heap order below the bracket, as plan_pass). The
+// scales are those of plain bisection whatever the depth; the depth only says how
+// many future steps are evaluated at once. It is lowered while the finest candidate
+// would be much finer than a scale whose count is known (the count grows at most
+// with the cube of the scale ratio), since such candidates cost the most and are
+// rarely the ones the search takes.
+__device__ void plan_search(SState* st, const Plan& P, const Frame& fr, uint32_t upper) {
+  const int left = P.t_max - st->evals;
+  int D = left < P.depth ? left : P.depth;
+  const float cref = st->c_hi ? static_cast<float>(st->c_hi) : 1.0f;
+  const float budget = P.spec_mult * static_cast<float>(upper) + 64.0f;
+  while (D > 1) {
+    const float smin = st->lo + (st->hi - st->lo) / static_cast<float>(1 << D);
+    const float ratio = st->hi / smin;
+    if (cref * ratio * ratio * ratio <= budget) break;
+    --D;
+  }
+  const int nc = (1 << D) - 1;
+  float a[kMaxCand], b[kMaxCand];
+  a[0] = st->lo;
+  b[0] = st->hi;
+  for (int k = 0; k < nc; ++k) {
+    const float s = (a[k] + b[k]) * 0.5f;
+    st->cand_s[k] = s;
+    for (int ax = 0; ax < 3; ++ax) {
+      const float v = s * P.aspect[ax];
+      st->cand_inv[k][ax] = 1.0f / v;
+    }
+    uint32_t mk[3];
+    max_coords(fr, st->cand_inv[k], mk);
+    const uint64_t nbx = (mk[0] >> kBrickShift) + 1, nby = (mk[1] >> kBrickShift) + 1,
+                   nbz = (mk[2] >> kBrickShift) + 1;
+    const uint64_t nb = nbx * nby * nbz;
+    st->cand_dense[k] = nb <= P.cap ? 1 : 0;
+    st->cand_hot[k] = nb <= 4096 ? 1 : 0;
+    st->cand_nb[k][0] = static_cast<uint32_t>(nbx);
+    st->cand_nb[k][1] = static_cast<uint32_t>(nby);
+    if (2 * k + 2 < nc) {
+      a[2 * k + 1] = a[k];
+      b[2 * k + 1] = s;
+      a[2 * k + 2] = s;
+      b[2 * k + 2] = b[k];
+    }
+  }
+  st->nc = nc;
+}
+
+// One controller step on a pass's counts; every block runs it on the same counts.
+__device__ void search_step(SState* st, const uint32_t* cnt, const Plan& P, const Frame& fr,
+                            uint32_t m, uint32_t upper) {
+  st->prev_set = st->set;
+  st->prev_nc = st->nc;
+  uint32_t dm = 0;
+  for (int k = 0; k < st->nc; ++k) dm |= static_cast<uint32_t>(st->cand_dense[k] != 0) << k;
+  st->prev_dense = dm;
+  st->set ^= 1;
+  int k = 0;
+  while (k < st->nc) {
+    const uint32_t cc = cnt[k];
+    const float s = st->cand_s[k];
+    st->evals += 1;
+    if (cc >= m && cc <= upper) {
+      st->accepted = 1;
+      st->done = 1;
+      st->s_final = s;
+      return;
+    }
+    if (cc < m) {
+      st->hi = s;
+      st->c_hi = cc;
+      k = 2 * k + 1;
+    } else {
+      st->lo = s;
+      k = 2 * k + 2;
+    }
+  }
+  if (st->evals >= P.t_max) {
+    // no size in the window: the finest size with too many voxels if there was one
+    // (then trim), else the smallest size evaluated (then pad)
+    st->done = 1;
+    st->s_final = st->lo > 0.0f ? st->lo : st->hi;
+    return;
+  }
+  plan_search(st, P, fr, upper);
+}
+
+// The tile's live points into registers (thread t: the tile's points 8t..8t+7) and
+// the tile's offset range into sh.tb.
+__device__ __forceinline__ void load_tile(const Ws& w, int tile, float4 (&pt)[kPerThread],
+                                          uint32_t& live, EvalShared& sh) {
+  const int64_t base = static_cast<int64_t>(tile) * kTile + threadIdx.x;
+  live = 0;
+  uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t S = base + k * kThreads;
+    const bool ok = w.tag_s[S] == 0;
+    pt[k] = ok ? w.pts[S] : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ok) {
+      live |= 1u << k;
+      // offsets are >= +0, so their bit patterns order like their values
+      const uint32_t bx = __float_as_uint(pt[k].x), by = __float_as_uint(pt[k].y),
+                     bz = __float_as_uint(pt[k].z);
+      lo[0] = min(lo[0], bx); lo[1] = min(lo[1], by); lo[2] = min(lo[2], bz);
+      hi[0] = max(hi[0], bx); hi[1] = max(hi[1], by); hi[2] = max(hi[2], bz);
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t r[6];
+  for (int a = 0; a < 3; ++a) {
+    r[a] = __ockl_wfred_min_u32(lo[a]);
+    r[3 + a] = __ockl_wfred_max_u32(hi[a]);
+  }
+  if (lane == 0)
+    for (int q = 0; q < 6; ++q) sh.red[wv][q] = r[q];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int q = threadIdx.x;
+    uint32_t v = q < 3 ? 0xFFFFFFFFu : 0u;
+    for (int j = 0; j < kThreads / 64; ++j) v = q < 3 ? min(v, sh.red[j][q]) : max(v, sh.red[j][q]);
+    sh.tb[q] = v;
+  }
+  __syncthreads();
+}
+
+// Cnt contributions of one loaded tile at the pass's candidates, added to sh.fresh.
+// The LDS tables (lvals: box words or hash values, lkeys: hash keys; slots per
+// candidate fixed by the launch's depth) are clean on entry and left clean.
+__device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState& st,
+                                            EvalShared& sh, uint64_t* lvals, uint64_t* lkeys,
+                                            const float4 (&pt)[kPerThread], uint32_t live) {
+  const int nc = st.nc, set = st.set;
+  if (threadIdx.x < nc) {
+    const int k = threadIdx.x;
+    sh.ncl[k] = 0;
+    uint32_t l[3], u[3];
+    for (int a = 0; a < 3; ++a) {
+      uint32_t mn = sh.tb[a], mx = sh.tb[3 + a];
+      if (mn > mx) { mn = 0; mx = 0; }  // no live point
+      l[a] = axis_coord(__uint_as_float(mn), st.cand_inv[k][a]) >> kBrickShift;
+      u[a] = axis_coord(__uint_as_float(mx), st.cand_inv[k][a]) >> kBrickShift;
+    }
+    const uint64_t dx = u[0] - l[0] + 1, dy = u[1] - l[1] + 1, dz = u[2] - l[2] + 1;
+    const uint64_t vol = dx * dy * dz;
+    sh.box[k][0] = l[0];
+    sh.box[k][1] = l[1];
+    sh.box[k][2] = l[2];
+    sh.box[k][3] = static_cast<uint32_t>(dx);
+    sh.box[k][4] = static_cast<uint32_t>(dy);
+    sh.box[k][5] = vol <= static_cast<uint64_t>(kBrickCap) ? static_cast<uint32_t>(vol) : 0u;
+  }
+  __syncthreads();
+  for (int ci = 0; ci < nc; ++ci) {
+    const float ix = st.cand_inv[ci][0], iy = st.cand_inv[ci][1], iz = st.cand_inv[ci][2];
+    uint64_t* tv = lvals + ci * kBrickCap;
+    if (sh.box[ci][5] != 0) {
+      const uint32_t bl0 = sh.box[ci][0], bl1 = sh.box[ci][1], bl2 = sh.box[ci][2];
+      const uint32_t bdx = sh.box[ci][3], bdy = sh.box[ci][4];
+      uint32_t cur = 0xFFFFFFFFu;
+      uint64_t cb = 0ull;
+#pragma unroll
+      for (int k = 0; k < kPerThread; ++k) {
+        if (!(live & (1u << k))) continue;
+        const uint32_t gx = axis_coord(pt[k].x, ix);
+        const uint32_t gy = axis_coord(pt[k].y, iy);
+        const uint32_t gz = axis_coord(pt[k].z, iz);
+        const uint32_t loc = ((gx >> kBrickShift) - bl0) +
+                             bdx * (((gy >> kBrickShift) - bl1) + bdy * ((gz >> kBrickShift) - bl2));
+        const uint64_t bit = brick_bit(gx, gy, gz);
+        if (loc == cur) {
+          cb |= bit;
+        } else {
+          if (cur != 0xFFFFFFFFu)
+            __hip_atomic_fetch_or(&tv[cur], cb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          cur = loc;
+          cb = bit;
+        }
+      }
+      if (cur != 0xFFFFFFFFu)
+        __hip_atomic_fetch_or(&tv[cur], cb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      continue;
+    }
+    // sparse tile: LDS hash on the brick id, overflow straight to the global table
+    const int dense = st.cand_dense[ci];
+    const uint64_t nbx = st.cand_nb[ci][0], nby = st.cand_nb[ci][1];
+    uint64_t* tk = lkeys + ci * kBrickCap;
+    uint64_t cur = kEmptyKey, cb = 0ull;
+    for (int k = 0; k <= kPerThread; ++k) {
+      uint64_t key = kEmptyKey, bit = 0ull;
+      if (k < kPerThread) {
+        if (!(live & (1u << k))) continue;
+        const uint32_t gx = axis_coord(pt[k].x, ix);
+        const uint32_t gy = axis_coord(pt[k].y, iy);
+        const uint32_t gz = axis_coord(pt[k].z, iz);
+        key = dense ? (static_cast<uint64_t>(gx >> kBrickShift) +
+                       nbx * (static_cast<uint64_t>(gy >> kBrickShift) + nby * (gz >> kBrickShift)))
+                    : brick_key(gx, gy, gz);
+        bit = brick_bit(gx, gy, gz);
+        if (key == cur) {
+          cb |= bit;
+          continue;
+        }
+      }
+      if (cur != kEmptyKey && !lds_try_or<kBrickCap>(tk, tv, cur, cb)) {
+        const uint32_t f =
+            dense ? dense_or_c(ctab_masks(w, set, ci), static_cast<uint32_t>(cur), cb,
+                               st.cand_hot[ci], claims(w, set, ci, tile), &sh.ncl[ci])
+                  : global_or_c(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, cur, cb,
+                                claims(w, set, ci, tile), &sh.ncl[ci]);
+        if (f) atomicAdd(&sh.fresh[ci], f);
+      }
+      cur = key;
+      cb = bit;
+    }
+  }
+  __syncthreads();
+  // one global update per distinct brick of the tile; LDS entries are emptied as read
+  for (int e = threadIdx.x; e < nc * kBrickCap; e += kThreads) {
+    const int ci = e / kBrickCap;
+    const int le = e - ci * kBrickCap;
+    const uint32_t vol = sh.box[ci][5];
+    uint64_t key, bits;
+    if (vol) {
+      if (le >= static_cast<int>(vol)) continue;
+      bits = lvals[e];
+      if (!bits) continue;
+      lvals[e] = 0ull;
+      const uint32_t bdx = sh.box[ci][3], bdy = sh.box[ci][4];
+      const uint32_t bx = sh.box[ci][0] + le % bdx;
+      const uint32_t t2 = le / bdx;
+      const uint32_t by = sh.box[ci][1] + t2 % bdy;
+      const uint32_t bz = sh.box[ci][2] + t2 / bdy;
+      key = st.cand_dense[ci]
+                ? (bx + static_cast<uint64_t>(st.cand_nb[ci][0]) *
+                            (by + static_cast<uint64_t>(st.cand_nb[ci][1]) * bz))
+                : (static_cast<uint64_t>(bx) | (static_cast<uint64_t>(by) << kBrickCoordBits) |
+                   (static_cast<uint64_t>(bz) << (2 * kBrickCoordBits)));
+    } else {
+      key = lkeys[e];
+      if (key == kEmptyKey) continue;
+      bits = lvals[e];
+      lkeys[e] = kEmptyKey;
+      lvals[e] = 0ull;
+    }
+    const uint32_t f =
+        st.cand_dense[ci]
+            ? dense_or_c(ctab_masks(w, set, ci), static_cast<uint32_t>(key), bits, st.cand_hot[ci],
+                         claims(w, set, ci, tile), &sh.ncl[ci])
+            : global_or_c(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, key, bits,
+                          claims(w, set, ci, tile), &sh.ncl[ci]);
+    if (f) atomicAdd(&sh.fresh[ci], f);
+  }
+  __syncthreads();
+  if (threadIdx.x < nc) *claim_n(w, set, threadIdx.x, tile) = sh.ncl[threadIdx.x];
+}
+
+// Grid barrier of the persistent search; `target` is the pass number + 1. The last
+// block to arrive empties the accumulators the next pass fills, then releases the
+// others. Every thread first waits for its own memory operations to complete, so a
+// block's table updates and counts are in place before it is counted as arrived. A
+// block that waits longer than kSpinLimit polls gives up and raises bar_err, which
+// every other waiter also takes as a failure, so a launch whose blocks are not all
+// resident ends instead of hanging. Returns false on failure.
+__device__ bool grid_sync(Header* h, int nblocks, uint32_t target, int next_par) {
+  __shared__ int s_last, s_ok;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int g = blockIdx.x & (kGroups - 1);
+    const int gsize = (nblocks - g + kGroups - 1) / kGroups;
+    const int ngroups = nblocks < kGroups ? nblocks : kGroups;
+    int last = 0;
+    const uint32_t a = atomicAdd(&h->bar_grp[g][0], 1u);
+    if (a == static_cast<uint32_t>(gsize - 1)) {
+      atomicExch(&h->bar_grp[g][0], 0u);
+      const uint32_t b = atomicAdd(&h->bar_top[0], 1u);
+      if (b == static_cast<uint32_t>(ngroups - 1)) {
+        atomicExch(&h->bar_top[0], 0u);
+        last = 1;
+      }
+    }
+    s_last = last;
+    s_ok = 1;
+  }
+  __syncthreads();
+  if (s_last) {
+    if (threadIdx.x < kMaxCand * kGroups)
+      atomicExch(&h->sacc[next_par][threadIdx.x / kGroups][threadIdx.x % kGroups][0], 0u);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicExch(&h->bar_gen[0], target);
+  } else if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(&h->bar_gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(&h->bar_err[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        s_ok = 0;
+        break;
+      }
+      if (++spins > kSpinLimit) {
+        atomicOr(&h->bar_err[0], 1u);
+        s_ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// One launch runs the whole adaptive voxel search of a layer (Sec. 3.3): every block
+// evaluates its tiles at the pass's candidate scales, the blocks meet at a grid
+// barrier, and each block then reads the pass's counts and runs the same controller
+// step, so all blocks agree on the next pass without a kernel boundary. Launched
+// cooperatively (all blocks resident); with one tile per block the tile's points stay
+// in registers for the whole search. Within the launch every access to memory another
+// block writes is an atomic RMW or an agent-scope atomic load.
+__global__ void __launch_bounds__(kThreads) k_search(Ws w, Plan P) {
+  Header* h = w.h;
+  if (h->frame.status != HAV_OK) return;
+  Ctrl* c = &h->ctrl;
+  if (c->done) return;  // fixed voxel size: no search
+  extern __shared__ uint64_t lds[];
+  __shared__ SState st;
+  __shared__ EvalShared sh;
+  __shared__ uint32_t s_cnt[kMaxCand];
+  __shared__ int s_ok;
+  const int ncap = (1 << P.depth) - 1;
+  uint64_t* lvals = lds;
+  uint64_t* lkeys = lds + static_cast<size_t>(ncap) * kBrickCap;
+  for (int e = threadIdx.x; e < ncap * kBrickCap; e += kThreads) {
+    lvals[e] = 0ull;
+    lkeys[e] = kEmptyKey;
+  }
+  const uint32_t m = c->m, upper = c->upper;
+  const Frame fr = h->frame;
+  if (threadIdx.x == 0) {
+    st.lo = c->lo;
+    st.hi = c->hi;
+    st.c_hi = 0;
+    st.evals = 0;
+    st.done = 0;
+    st.accepted = 0;
+    st.set = c->set;
+    st.prev_set = 0;
+    st.prev_nc = 0;
+    st.prev_dense = 0;
+    st.s_final = 0.0f;
+    plan_search(&st, P, fr, upper);
+    s_ok = 1;
+  }
+  __syncthreads();
+  const int G = gridDim.x;
+  const bool resident = w.ntile <= G;  // then G == ntile: one tile per block
+  float4 pt[kPerThread];
+  uint32_t live = 0;
+  if (resident) load_tile(w, blockIdx.x, pt, live, sh);
+  for (int pass = 0;; ++pass) {
+    const int nc = st.nc, par = pass & 1;
+    // empty the slots this block's tiles claimed in the previous pass (other set)
+    for (int t = blockIdx.x; t < w.ntile; t += G) {
+      for (int k = 0; k < st.prev_nc; ++k) {
+        int32_t* cn = claim_n(w, st.prev_set, k, t);
+        const int n = *cn;
+        const int32_t* list = claims(w, st.prev_set, k, t);
+        const bool dense = (st.prev_dense >> k) & 1u;
+        unsigned long long* keys = ctab_keys(w, st.prev_set, k);
+        unsigned long long* masks = ctab_masks(w, st.prev_set, k);
+        for (int i = threadIdx.x; i < n; i += kThreads) {
+          const int32_t sl = list[i];
+          if (!dense) atomicExch(&keys[sl], static_cast<unsigned long long>(kEmptyKey));
+          atomicExch(&masks[sl], 0ull);
+        }
+      }
+    }
+    if (threadIdx.x < nc) sh.fresh[threadIdx.x] = 0;
+    __syncthreads();
+    if (resident) {
+      eval_loaded(w, blockIdx.x, st, sh, lvals, lkeys, pt, live);
+    } else {
+      for (int t = blockIdx.x; t < w.ntile; t += G) {
+        load_tile(w, t, pt, live, sh);
+        eval_loaded(w, t, st, sh, lvals, lkeys, pt, live);
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < nc && sh.fresh[threadIdx.x])
+      atomicAdd(&h->sacc[par][threadIdx.x][blockIdx.x & (kGroups - 1)][0], sh.fresh[threadIdx.x]);
+    if (!grid_sync(h, G, static_cast<uint32_t>(pass + 1), par ^ 1)) {
+      if (threadIdx.x == 0) s_ok = 0;
+      __syncthreads();
+      break;
+    }
+    if (threadIdx.x < nc) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    if (threadIdx.x < nc * kGroups) {
+      const uint32_t v = __hip_atomic_load(&h->sacc[par][threadIdx.x / kGroups][threadIdx.x % kGroups][0],
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (v) atomicAdd(&s_cnt[threadIdx.x / kGroups], v);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) search_step(&st, s_cnt, P, fr, m, upper);
+    __syncthreads();
+    if (st.done) break;
+  }
+  // block 0 publishes the outcome for the kernels that follow
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (!s_ok) {
+    // tables may hold claims nobody cleared: the workspace needs hav_workspace_init
+    h->frame.status = HAV_ERR_HIP;
+    h->info.status = HAV_ERR_HIP;
+    h->magic = 0;
+    return;
+  }
+  c->evals = st.evals;
+  c->accepted = st.accepted;
+  c->lo = st.lo;
+  c->hi = st.hi;
+  c->done = 1;
+  c->set = st.set;
+  c->pend_set = st.prev_set;
+  c->pend_nc = st.prev_nc;
+  set_final(c, st.s_final, P, fr);
+  const int L = c->layer;
+  h->info.evals[L] = st.evals;
+  h->info.accepted[L] = st.accepted;
+  h->info.s[L] = st.s_final;
 }
 
 // ----------------------------------------------------------------------------- select
@@ -1659,6 +2175,28 @@ int trim_rounds(int64_t n) {
   return R;
 }
 
+// Blocks of the persistent search: one per tile when the device can hold them all at
+// once, else as many as it can (0 if the cooperative launch is not available).
+int search_grid(int ntile, int depth) {
+  static std::atomic<int> cache[kMaxDevices][kMaxDepth + 1];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+  int cap = cache[dev][depth].load(std::memory_order_relaxed);
+  if (cap == 0) {
+    const size_t lds = 2 * static_cast<size_t>((1 << depth) - 1) * kBrickCap * sizeof(uint64_t);
+    int per_cu = 0, cus = 0, coop = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_search),
+                                                     kThreads, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess)
+      return 0;
+    cap = coop ? per_cu * cus : -1;
+    if (cap == 0) cap = -1;
+    cache[dev][depth].store(cap, std::memory_order_relaxed);
+  }
+  return cap < 0 ? 0 : std::min(ntile, cap);
+}
+
 #define HAV_LAUNCH(...)                                          \
   do {                                                           \
     hipLaunchKernelGGL(__VA_ARGS__);                             \
@@ -1676,6 +2214,7 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
   P.magic = magic_of(L);
   P.cap = w.cap;
   P.sel_cap = w.cap * static_cast<uint32_t>(kSelDense);
+  P.spec_mult = kSpecMult;
   for (int a = 0; a < 3; ++a) {
     P.aspect[a] = p->aspect[a];
     P.fixed_v[a] = p->fixed_voxel[a];
@@ -1701,12 +2240,21 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
   HAV_LAUNCH(k_bin_scan, dim3(kBinChunks), dim3(kThreads), 0, st, w, P);
   HAV_LAUNCH(k_bin_scatter, dim3(w.nbb), dim3(kThreads), 0, st, xyz, w);
   const int passes = P.fixed ? 0 : (p->t_max + P.depth - 1) / P.depth;
+  const int sgrid = P.fixed ? 0 : search_grid(w.ntile, P.depth);
   const int R = trim_rounds(N);
   const size_t eval_lds = 2 * static_cast<size_t>((1 << P.depth) - 1) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
   for (int l = 0; l < nl; ++l) {
-    for (int q = 0; q < passes; ++q)
-      HAV_LAUNCH(k_eval, dim3(w.ntile), dim3(kThreads), eval_lds, st, w, P);
+    if (sgrid > 0) {
+      void* args[] = {&w, &P};
+      if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_search), dim3(sgrid),
+                                     dim3(kThreads), args, static_cast<unsigned>(eval_lds),
+                                     st) != hipSuccess)
+        return HAV_ERR_HIP;
+    } else {
+      for (int q = 0; q < passes; ++q)
+        HAV_LAUNCH(k_eval, dim3(w.ntile), dim3(kThreads), eval_lds, st, w, P);
+    }
     HAV_LAUNCH(k_select, dim3(w.ntile), dim3(kThreads), sel_lds, st, w);
     for (int r = 0; r < R; ++r) HAV_LAUNCH(k_trim_hist, dim3(w.ntile), dim3(kThreads), 0, st, w, r);
     HAV_LAUNCH(k_mark, dim3(w.ntile), dim3(kThreads), 0, st, w);
