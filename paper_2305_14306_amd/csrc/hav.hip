@@ -76,6 +76,10 @@ constexpr int kScanPer = kScanTile / kThreads;
 constexpr int kSelDense = 4;                    // voxel value slots per brick-table slot
 constexpr uint64_t kMagic = 0x4841565F57533031ull;
 constexpr int kMaxDevices = 64;
+constexpr int kHotCap = 4096;                   // brick grids this small use replicas
+constexpr int kReps = 16;                       // replicas of a hot brick table
+constexpr int kClaimCap = 2 * kTile;            // claims per tile and candidate
+constexpr int64_t kMaxPoints = (int64_t(1) << 30) - 1;  // table slots stay below 2^31
 
 // ----------------------------------------------------------------------------- state
 
@@ -94,14 +98,9 @@ struct Ctrl {
   float lo, hi;
   float s_final;
   float v_final[3], inv_final[3];
-  int32_t nc;           // candidates of the next search pass
-  int32_t set;          // table set the next pass fills
-  int32_t pend_set, pend_nc;
-  float cand_s[kMaxCand];
-  float cand_inv[kMaxCand][3];
-  int32_t cand_dense[kMaxCand];   // 1: brick grid fits the table, index it directly
-  int32_t cand_hot[kMaxCand];     // 1: few bricks, read before the atomic
-  uint32_t cand_nb[kMaxCand][2];  // brick grid x, y extents (dense mode)
+  int32_t set;          // table set the next search pass fills
+  int32_t pend_set, pend_nc;  // table set and candidates whose claims are still to clear
+  uint32_t pend_hashed;       // bit k: candidate k of that pass used a hashed table
   int32_t sel_dense;              // 1: voxel grid at the chosen size fits, index directly
   uint32_t sel_nv[2];             // voxel grid x, y extents (dense mode)
   uint32_t ncand;       // occupied voxels at the chosen size
@@ -110,6 +109,21 @@ struct Ctrl {
   uint32_t rank;        // radix select: rank sought inside the prefix bucket
   uint64_t prefix;
   int32_t rounds_done;
+};
+
+// State of the voxel search between passes (Sec. 3.3): the bracket, the outcome so
+// far and the next pass's candidate scales. Published as 32-bit words.
+struct SState {
+  float lo, hi;
+  uint32_t c_hi;  // count at hi (0: hi is the initial bracket, never evaluated)
+  int32_t evals, done, accepted;
+  int32_t nc, set, prev_set, prev_nc;
+  uint32_t prev_hashed;  // bit k: candidate k of the previous pass used a hashed table
+  float s_final;
+  float cand_s[kMaxCand];
+  float cand_inv[kMaxCand][3];
+  int32_t cand_dense[kMaxCand], cand_hot[kMaxCand];
+  uint32_t cand_nb[kMaxCand][2];
 };
 
 struct Plan {  // per-call constants (kernel argument)
@@ -127,6 +141,9 @@ struct Plan {  // per-call constants (kernel argument)
   float spec_mult;    // speculation budget of the search, in multiples of the window top
 };
 
+constexpr int kPubWords = static_cast<int>(sizeof(SState) / 4);
+static_assert(sizeof(SState) % 4 == 0 && kPubWords <= kThreads, "search state words");
+
 struct alignas(256) Header {
   uint64_t magic;
   uint64_t pad0[31];
@@ -138,12 +155,15 @@ struct alignas(256) Header {
   uint32_t acc[kMaxCand][kGroups][kStride];
   uint32_t hist[kGroups][256];
   uint32_t tie_cur[kGroups][kStride];
-  // persistent search: double-buffered per-pass counts and the grid barrier
+  // voxel search: double-buffered per-pass counts, tile tickets, completed tiles,
+  // the pass whose candidates are published, finish and failure flags
   uint32_t sacc[2][kMaxCand][kGroups][kStride];
-  uint32_t bar_grp[kGroups][kStride];
-  uint32_t bar_top[kStride];
-  uint32_t bar_gen[kStride];
-  uint32_t bar_err[kStride];
+  uint32_t sq_ticket[kStride];
+  uint32_t sq_done[kStride];
+  uint32_t sq_gen[kStride];
+  uint32_t sq_fin[kStride];
+  uint32_t sq_err[kStride];
+  alignas(256) uint32_t pub[kPubWords];
 };
 
 // Device view of the workspace for one stage.
@@ -159,7 +179,8 @@ struct Ws {
   uint32_t* bsum;                // [kBinChunks] chunk sums, then chunk offsets
   unsigned long long* ckeys;     // brick tables [2][ncmax][cap_ws]
   unsigned long long* cmasks;
-  int32_t* ccl;                  // claims [2][ncmax][ntile_ws][kTile]
+  int32_t* ccl;                  // claims [2][ncmax][ntile_ws][kClaimCap]
+  unsigned long long* hrep;      // hot table replicas [2][ncmax][kReps][kHotCap]
   int32_t* ccn;                  // claim counts [2][ncmax][ntile_ws]
   unsigned long long* skeys;     // voxel table [cap_ws]
   unsigned long long* svals;
@@ -184,7 +205,10 @@ __device__ __forceinline__ unsigned long long* ctab_masks(const Ws& w, int set, 
   return w.cmasks + (static_cast<size_t>(set) * w.ncmax + c) * w.cap_ws;
 }
 __device__ __forceinline__ int32_t* claims(const Ws& w, int set, int c, int tile) {
-  return w.ccl + ((static_cast<size_t>(set) * w.ncmax + c) * w.ntile_ws + tile) * kTile;
+  return w.ccl + ((static_cast<size_t>(set) * w.ncmax + c) * w.ntile_ws + tile) * kClaimCap;
+}
+__device__ __forceinline__ unsigned long long* hrep_of(const Ws& w, int set, int c, int r) {
+  return w.hrep + ((static_cast<size_t>(set) * w.ncmax + c) * kReps + r) * kHotCap;
 }
 __device__ __forceinline__ int32_t* claim_n(const Ws& w, int set, int c, int tile) {
   return w.ccn + (static_cast<size_t>(set) * w.ncmax + c) * w.ntile_ws + tile;
@@ -238,39 +262,50 @@ __device__ __forceinline__ uint32_t peek(uint32_t* p) { return atomicAdd(p, 0u);
 
 // ----------------------------------------------------------------------------- search plan
 
-// Candidates of the next pass: the bisection subtree of `depth` levels below the
-// bracket [lo, hi], in heap order. Node k with bracket [a, b] evaluates s = (a+b)/2;
-// its child 2k+1 ([a, s]) is taken when the count is below m, 2k+2 ([s, b]) when
-// above the window -- the same arithmetic as one bisection step at a time.
 // Largest voxel coordinate per axis at reciprocal size inv: the coordinate of the
 // cloud's max corner (r = mx - mn), the largest r any point has.
 __device__ __forceinline__ void max_coords(const Frame& fr, const float* inv, uint32_t* mk) {
   for (int ax = 0; ax < 3; ++ax) mk[ax] = axis_coord(fr.mx[ax] - fr.mn[ax], inv[ax]);
 }
 
-__device__ void plan_pass(Ctrl* c, const Plan& P, const Frame& fr) {
-  const int left = P.t_max - c->evals;
-  const int D = left < P.depth ? left : P.depth;
+// Candidates of the next pass: the bisection subtree of up to P.depth levels below
+// the bracket [lo, hi], in heap order. Node k with bracket [a, b] evaluates
+// s = (a+b)/2; its child 2k+1 ([a, s]) is taken when the count is below m, 2k+2
+// ([s, b]) when above the window -- the same arithmetic as one bisection step at a
+// time. The depth is lowered while the finest candidate would be much finer than a
+// scale whose count is known (the count grows at most with the cube of the scale
+// ratio), since such candidates cost the most and are rarely the ones taken.
+__device__ void plan_search(SState* st, const Plan& P, const Frame& fr, uint32_t upper) {
+  const int left = P.t_max - st->evals;
+  int D = left < P.depth ? left : P.depth;
+  const float cref = st->c_hi ? static_cast<float>(st->c_hi) : 1.0f;
+  const float budget = P.spec_mult * static_cast<float>(upper) + 64.0f;
+  while (D > 1) {
+    const float smin = st->lo + (st->hi - st->lo) / static_cast<float>(1 << D);
+    const float ratio = st->hi / smin;
+    if (cref * ratio * ratio * ratio <= budget) break;
+    --D;
+  }
   const int nc = (1 << D) - 1;
   float a[kMaxCand], b[kMaxCand];
-  a[0] = c->lo;
-  b[0] = c->hi;
+  a[0] = st->lo;
+  b[0] = st->hi;
   for (int k = 0; k < nc; ++k) {
     const float s = (a[k] + b[k]) * 0.5f;
-    c->cand_s[k] = s;
+    st->cand_s[k] = s;
     for (int ax = 0; ax < 3; ++ax) {
       const float v = s * P.aspect[ax];
-      c->cand_inv[k][ax] = 1.0f / v;
+      st->cand_inv[k][ax] = 1.0f / v;
     }
     uint32_t mk[3];
-    max_coords(fr, c->cand_inv[k], mk);
+    max_coords(fr, st->cand_inv[k], mk);
     const uint64_t nbx = (mk[0] >> kBrickShift) + 1, nby = (mk[1] >> kBrickShift) + 1,
                    nbz = (mk[2] >> kBrickShift) + 1;
     const uint64_t nb = nbx * nby * nbz;
-    c->cand_dense[k] = nb <= P.cap ? 1 : 0;
-    c->cand_hot[k] = nb <= 4096 ? 1 : 0;
-    c->cand_nb[k][0] = static_cast<uint32_t>(nbx);
-    c->cand_nb[k][1] = static_cast<uint32_t>(nby);
+    st->cand_dense[k] = nb <= P.cap ? 1 : 0;
+    st->cand_hot[k] = nb <= static_cast<uint64_t>(kHotCap) ? 1 : 0;
+    st->cand_nb[k][0] = static_cast<uint32_t>(nbx);
+    st->cand_nb[k][1] = static_cast<uint32_t>(nby);
     if (2 * k + 2 < nc) {
       a[2 * k + 1] = a[k];
       b[2 * k + 1] = s;
@@ -278,7 +313,47 @@ __device__ void plan_pass(Ctrl* c, const Plan& P, const Frame& fr) {
       b[2 * k + 2] = b[k];
     }
   }
-  c->nc = nc;
+  st->nc = nc;
+}
+
+// One bisection step per evaluated candidate on a pass's counts, walking the
+// pass's subtree; then the next pass's candidates, or the final scale.
+__device__ void search_step(SState* st, const uint32_t* cnt, const Plan& P, const Frame& fr,
+                            uint32_t m, uint32_t upper) {
+  st->prev_set = st->set;
+  st->prev_nc = st->nc;
+  uint32_t hm = 0;
+  for (int k = 0; k < st->nc; ++k) hm |= static_cast<uint32_t>(st->cand_dense[k] == 0) << k;
+  st->prev_hashed = hm;
+  st->set ^= 1;
+  int k = 0;
+  while (k < st->nc) {
+    const uint32_t cc = cnt[k];
+    const float s = st->cand_s[k];
+    st->evals += 1;
+    if (cc >= m && cc <= upper) {
+      st->accepted = 1;
+      st->done = 1;
+      st->s_final = s;
+      return;
+    }
+    if (cc < m) {
+      st->hi = s;
+      st->c_hi = cc;
+      k = 2 * k + 1;
+    } else {
+      st->lo = s;
+      k = 2 * k + 2;
+    }
+  }
+  if (st->evals >= P.t_max) {
+    // no size in the window: the finest size with too many voxels if there was one
+    // (then trim), else the smallest size evaluated (then pad)
+    st->done = 1;
+    st->s_final = st->lo > 0.0f ? st->lo : st->hi;
+    return;
+  }
+  plan_search(st, P, fr, upper);
 }
 
 __device__ void set_select_grid(Ctrl* c, const Plan& P, const Frame& fr) {
@@ -319,13 +394,13 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
   for (int b = 0; b < 2; ++b)
     for (int k = 0; k < kMaxCand; ++k)
       for (int g = 0; g < kGroups; ++g) h->sacc[b][k][g][0] = 0;
-  h->bar_gen[0] = 0;
-  h->bar_err[0] = 0;
-  h->bar_top[0] = 0;
-  for (int g = 0; g < kGroups; ++g) h->bar_grp[g][0] = 0;
+  h->sq_ticket[0] = 0;
+  h->sq_done[0] = 0;
+  h->sq_gen[0] = 0;
+  h->sq_fin[0] = 0;
+  h->sq_err[0] = 0;
   if (P.fixed) {
     c->done = 1;
-    c->nc = 0;
     c->s_final = 0.0f;
     for (int ax = 0; ax < 3; ++ax) {
       c->v_final[ax] = P.fixed_v[ax];
@@ -333,8 +408,23 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
     }
     set_select_grid(c, P, h->frame);
   } else {
+    // the first pass's candidates, published for the search kernel
     c->done = 0;
-    plan_pass(c, P, h->frame);
+    SState s0;
+    s0.lo = 0.0f;
+    s0.hi = h->frame.hi0;
+    s0.c_hi = 0;
+    s0.evals = 0;
+    s0.done = 0;
+    s0.accepted = 0;
+    s0.set = c->set;
+    s0.prev_set = 0;
+    s0.prev_nc = 0;
+    s0.prev_hashed = 0;
+    s0.s_final = 0.0f;
+    plan_search(&s0, P, h->frame, c->upper);
+    const uint32_t* wd = reinterpret_cast<const uint32_t*>(&s0);
+    for (int i = 0; i < kPubWords; ++i) h->pub[i] = wd[i];
   }
 }
 
@@ -589,6 +679,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Ws w, Plan P) {
     c->set = 0;
     c->pend_nc = 0;
     c->pend_set = 0;
+    c->pend_hashed = 0;
     layer_init(w.h, P, 0);
   }
 }
@@ -618,67 +709,48 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(const float* __restric
 
 // ----------------------------------------------------------------------------- search
 
-// Empty the table slots the previous search pass claimed (its claim lists for this
-// tile), leaving the tables as initialised.
+template <typename T>
+__device__ __forceinline__ T ld_agent(T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Empty the table words one tile claimed in a search pass over `nc` candidates of
+// table set `set`, leaving the tables as initialised. A claim is a brick table slot
+// (>= 0), or -(1 + r * kHotCap + slot) for a word of hot replica r. Bit k of
+// `hashed` marks candidates whose brick table is hashed (its keys are cleared too).
+// Uses block-shared s_cn[kMaxCand + 1]; all threads call it.
+__device__ void clear_claims(const Ws& w, int set, int nc, uint32_t hashed, int tile, int* s_cn) {
+  if (threadIdx.x < nc) s_cn[threadIdx.x + 1] = ld_agent(claim_n(w, set, threadIdx.x, tile));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_cn[0] = 0;
+    for (int k = 0; k < nc; ++k) s_cn[k + 1] += s_cn[k];
+  }
+  __syncthreads();
+  const int total = s_cn[nc];
+  for (int e = threadIdx.x; e < total; e += kThreads) {
+    int k = 0;
+    while (e >= s_cn[k + 1]) ++k;
+    const int32_t id = ld_agent(claims(w, set, k, tile) + (e - s_cn[k]));
+    if (id >= 0) {
+      if ((hashed >> k) & 1u) atomicExch(ctab_keys(w, set, k) + id, static_cast<unsigned long long>(kEmptyKey));
+      atomicExch(ctab_masks(w, set, k) + id, 0ull);
+    } else {
+      const int32_t q = -1 - id;
+      atomicExch(hrep_of(w, set, k, q / kHotCap) + (q % kHotCap), 0ull);
+    }
+  }
+  __syncthreads();
+}
+
+// The claims of the search's last pass, for this block's tile.
 __device__ void clear_pending(const Ws& w, const Ctrl* c) {
-  const int pn = c->pend_nc, ps = c->pend_set;
-  for (int k = 0; k < pn; ++k) {
-    int32_t* cn = claim_n(w, ps, k, blockIdx.x);
-    const int n = *cn;
-    if (n == 0) continue;
-    const int32_t* list = claims(w, ps, k, blockIdx.x);
-    unsigned long long* keys = ctab_keys(w, ps, k);
-    unsigned long long* masks = ctab_masks(w, ps, k);
-    for (int i = threadIdx.x; i < n; i += kThreads) {
-      const int32_t s = list[i];
-      keys[s] = kEmptyKey;
-      masks[s] = 0ull;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *cn = 0;
-  }
-}
-
-// OR `bits` into the global brick table entry of `key`; returns the number of bits
-// that were not set before. A plain read of the mask can only be stale by missing
-// bits, so when it already holds all of ours the atomic is skipped.
-__device__ __forceinline__ uint32_t global_or(unsigned long long* keys, unsigned long long* masks,
-                                              uint32_t cmask, uint64_t key, uint64_t bits,
-                                              int32_t* list, int* s_ncl) {
-  uint32_t s = table_hash(key) & cmask;
-  while (true) {
-    const unsigned long long k = keys[s];
-    const unsigned long long m = masks[s];
-    if (k == key) {
-      if ((m & bits) == bits) return 0;
-      const unsigned long long old = atomicOr(&masks[s], static_cast<unsigned long long>(bits));
-      return static_cast<uint32_t>(__popcll(bits & ~old));
-    }
-    if (k == kEmptyKey) {
-      const unsigned long long prev = atomicCAS(&keys[s], kEmptyKey, key);
-      if (prev == kEmptyKey || prev == key) {
-        if (prev == kEmptyKey) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(s);
-        const unsigned long long old = atomicOr(&masks[s], static_cast<unsigned long long>(bits));
-        return static_cast<uint32_t>(__popcll(bits & ~old));
-      }
-    }
-    s = (s + 1) & cmask;
-  }
-}
-
-// Dense brick table: `bits` ORed into word `slot`; the tile whose atomic finds the
-// word empty records it for clearing. With `hot` (few bricks, so many tiles share
-// each word) a plain read first skips the atomic when it would add nothing; a stale
-// read can only miss bits, never show extra ones.
-__device__ __forceinline__ uint32_t dense_or(unsigned long long* masks, uint32_t slot,
-                                             uint64_t bits, bool hot, int32_t* list, int* s_ncl) {
-  if (hot) {
-    const unsigned long long m = masks[slot];
-    if ((m & bits) == bits) return 0;
-  }
-  const unsigned long long old = atomicOr(&masks[slot], static_cast<unsigned long long>(bits));
-  if (old == 0ull) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(slot);
-  return static_cast<uint32_t>(__popcll(bits & ~old));
+  __shared__ int s_cn[kMaxCand + 1];
+  clear_claims(w, c->pend_set, c->pend_nc, c->pend_hashed, blockIdx.x, s_cn);
 }
 
 // LDS insert of one (key, bits) run into a candidate's hash table, at most
@@ -698,284 +770,8 @@ __device__ __forceinline__ bool lds_try_or(uint64_t* tk, uint64_t* tv, uint64_t 
   return false;
 }
 
-// One search pass: Cnt at every candidate scale of the pass; the last block walks
-// the bisection tree and plans the next pass.
-//
-// Per tile and candidate the voxels are first merged in LDS. When the tile's bricks
-// fit a box of kBrickCap bricks (the usual case: tiles are spatially compact) the box
-// is a dense LDS array written with plain LDS ORs; otherwise an LDS hash is used.
-__global__ void __launch_bounds__(kThreads) k_eval(Ws w, Plan P) {
-  Header* h = w.h;
-  if (h->frame.status != HAV_OK) return;
-  Ctrl* c = &h->ctrl;
-  const int tile = blockIdx.x;
-  clear_pending(w, c);
-  if (c->done) return;  // a finished search: only the cleanup above was due
-  const int nc = c->nc;
-  const int set = c->set;
-
-  extern __shared__ uint64_t lds[];
-  uint64_t* lvals = lds;  // [nc][kBrickCap]: box words or hash values
-  uint64_t* lkeys = lds + static_cast<size_t>(nc) * kBrickCap;  // [nc][kBrickCap] hash keys
-  __shared__ int s_ncl[kMaxCand];
-  __shared__ uint32_t s_fresh[kMaxCand];
-  __shared__ float s_inv[kMaxCand][3];
-  __shared__ int s_dense[kMaxCand], s_hot[kMaxCand];
-  __shared__ uint32_t s_nb[kMaxCand][2];
-  __shared__ uint32_t s_box[kMaxCand][6];  // brick box: lo x,y,z, extent x,y, volume (0: hash)
-  __shared__ uint32_t s_red[kThreads / 64][6];
-
-  for (int e = threadIdx.x; e < nc * kBrickCap; e += kThreads) {
-    lkeys[e] = kEmptyKey;
-    lvals[e] = 0ull;
-  }
-  if (threadIdx.x < nc) {
-    const int k = threadIdx.x;
-    s_ncl[k] = 0;
-    s_fresh[k] = 0;
-    for (int a = 0; a < 3; ++a) s_inv[k][a] = c->cand_inv[k][a];
-    s_dense[k] = c->cand_dense[k];
-    s_hot[k] = c->cand_hot[k];
-    s_nb[k][0] = c->cand_nb[k][0];
-    s_nb[k][1] = c->cand_nb[k][1];
-  }
-  // thread t's points: the tile's points kPerThread*t .. +kPerThread-1 (neighbours in
-  // the binned order, so they often share a brick and merge in registers)
-  const int64_t base = static_cast<int64_t>(tile) * kTile + threadIdx.x;
-  float4 pt[kPerThread];
-  uint32_t live = 0;
-  uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    const int64_t S = base + k * kThreads;
-    const bool ok = w.tag_s[S] == 0;
-    pt[k] = ok ? w.pts[S] : make_float4(0.f, 0.f, 0.f, 0.f);
-    if (ok) {
-      live |= 1u << k;
-      // offsets are >= +0, so their bit patterns order like their values
-      const uint32_t bx = __float_as_uint(pt[k].x), by = __float_as_uint(pt[k].y),
-                     bz = __float_as_uint(pt[k].z);
-      lo[0] = min(lo[0], bx); lo[1] = min(lo[1], by); lo[2] = min(lo[2], bz);
-      hi[0] = max(hi[0], bx); hi[1] = max(hi[1], by); hi[2] = max(hi[2], bz);
-    }
-  }
-  {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t r[6];
-    for (int a = 0; a < 3; ++a) {
-      r[a] = __ockl_wfred_min_u32(lo[a]);
-      r[3 + a] = __ockl_wfred_max_u32(hi[a]);
-    }
-    if (lane == 0)
-      for (int q = 0; q < 6; ++q) s_red[wv][q] = r[q];
-  }
-  __syncthreads();
-  if (threadIdx.x < nc) {
-    // brick box of the tile at this candidate: brick of the tile's min / max offset
-    const int k = threadIdx.x;
-    uint32_t l[3], u[3];
-    for (int a = 0; a < 3; ++a) {
-      uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-      for (int q = 0; q < kThreads / 64; ++q) {
-        mn = min(mn, s_red[q][a]);
-        mx = max(mx, s_red[q][3 + a]);
-      }
-      if (mn > mx) { mn = 0; mx = 0; }  // no live point
-      l[a] = axis_coord(__uint_as_float(mn), s_inv[k][a]) >> kBrickShift;
-      u[a] = axis_coord(__uint_as_float(mx), s_inv[k][a]) >> kBrickShift;
-    }
-    const uint64_t dx = u[0] - l[0] + 1, dy = u[1] - l[1] + 1, dz = u[2] - l[2] + 1;
-    const uint64_t vol = dx * dy * dz;
-    s_box[k][0] = l[0];
-    s_box[k][1] = l[1];
-    s_box[k][2] = l[2];
-    s_box[k][3] = static_cast<uint32_t>(dx);
-    s_box[k][4] = static_cast<uint32_t>(dy);
-    s_box[k][5] = vol <= static_cast<uint64_t>(kBrickCap) ? static_cast<uint32_t>(vol) : 0u;
-  }
-  __syncthreads();
-
-  // 1. every candidate: runs of equal bricks among the thread's points merge in a
-  //    running register pair, then go to LDS
-  for (int ci = 0; ci < nc; ++ci) {
-    const float ix = s_inv[ci][0], iy = s_inv[ci][1], iz = s_inv[ci][2];
-    uint64_t* tv = lvals + ci * kBrickCap;
-    if (s_box[ci][5] != 0) {
-      const uint32_t bl0 = s_box[ci][0], bl1 = s_box[ci][1], bl2 = s_box[ci][2];
-      const uint32_t bdx = s_box[ci][3], bdy = s_box[ci][4];
-      uint32_t cur = 0xFFFFFFFFu;
-      uint64_t cb = 0ull;
-#pragma unroll
-      for (int k = 0; k < kPerThread; ++k) {
-        if (!(live & (1u << k))) continue;
-        const uint32_t gx = axis_coord(pt[k].x, ix);
-        const uint32_t gy = axis_coord(pt[k].y, iy);
-        const uint32_t gz = axis_coord(pt[k].z, iz);
-        const uint32_t loc = ((gx >> kBrickShift) - bl0) +
-                             bdx * (((gy >> kBrickShift) - bl1) + bdy * ((gz >> kBrickShift) - bl2));
-        const uint64_t bit = brick_bit(gx, gy, gz);
-        if (loc == cur) {
-          cb |= bit;
-        } else {
-          if (cur != 0xFFFFFFFFu)
-            __hip_atomic_fetch_or(&tv[cur], cb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          cur = loc;
-          cb = bit;
-        }
-      }
-      if (cur != 0xFFFFFFFFu)
-        __hip_atomic_fetch_or(&tv[cur], cb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      continue;
-    }
-    // sparse tile: LDS hash on the brick id
-    const int dense = s_dense[ci];
-    const uint64_t nbx = s_nb[ci][0], nby = s_nb[ci][1];
-    uint64_t* tk = lkeys + ci * kBrickCap;
-    uint64_t cur = kEmptyKey, cb = 0ull;
-    for (int k = 0; k <= kPerThread; ++k) {
-      uint64_t key = kEmptyKey, bit = 0ull;
-      if (k < kPerThread && (live & (1u << k))) {
-        const uint32_t gx = axis_coord(pt[k].x, ix);
-        const uint32_t gy = axis_coord(pt[k].y, iy);
-        const uint32_t gz = axis_coord(pt[k].z, iz);
-        key = dense ? (static_cast<uint64_t>(gx >> kBrickShift) +
-                       nbx * (static_cast<uint64_t>(gy >> kBrickShift) + nby * (gz >> kBrickShift)))
-                    : brick_key(gx, gy, gz);
-        bit = brick_bit(gx, gy, gz);
-      } else if (k < kPerThread) {
-        continue;
-      }
-      if (key == cur && k < kPerThread) {
-        cb |= bit;
-        continue;
-      }
-      if (cur != kEmptyKey && !lds_try_or<kBrickCap>(tk, tv, cur, cb)) {
-        // crowded tile: straight to the global table
-        const uint32_t f =
-            dense ? dense_or(ctab_masks(w, set, ci), static_cast<uint32_t>(cur), cb, s_hot[ci],
-                             claims(w, set, ci, tile), &s_ncl[ci])
-                  : global_or(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, cur, cb,
-                              claims(w, set, ci, tile), &s_ncl[ci]);
-        if (f) atomicAdd(&s_fresh[ci], f);
-      }
-      cur = key;
-      cb = bit;
-    }
-  }
-  __syncthreads();
-
-  // 2. one global update per distinct brick of the tile, all candidates at once
-  for (int e = threadIdx.x; e < nc * kBrickCap; e += kThreads) {
-    const int ci = e / kBrickCap;
-    const int le = e - ci * kBrickCap;
-    const uint32_t vol = s_box[ci][5];
-    uint64_t key;
-    if (vol) {
-      if (le >= static_cast<int>(vol)) continue;
-      const uint64_t bits = lvals[e];
-      if (!bits) continue;
-      const uint32_t bdx = s_box[ci][3], bdy = s_box[ci][4];
-      const uint32_t bx = s_box[ci][0] + le % bdx;
-      const uint32_t t2 = le / bdx;
-      const uint32_t by = s_box[ci][1] + t2 % bdy;
-      const uint32_t bz = s_box[ci][2] + t2 / bdy;
-      key = s_dense[ci] ? (bx + static_cast<uint64_t>(s_nb[ci][0]) *
-                                    (by + static_cast<uint64_t>(s_nb[ci][1]) * bz))
-                        : (static_cast<uint64_t>(bx) | (static_cast<uint64_t>(by) << kBrickCoordBits) |
-                           (static_cast<uint64_t>(bz) << (2 * kBrickCoordBits)));
-    } else {
-      key = lkeys[e];
-      if (key == kEmptyKey) continue;
-    }
-    const uint64_t bits = lvals[e];
-    const uint32_t f =
-        s_dense[ci] ? dense_or(ctab_masks(w, set, ci), static_cast<uint32_t>(key), bits,
-                               s_hot[ci], claims(w, set, ci, tile), &s_ncl[ci])
-                    : global_or(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, key, bits,
-                                claims(w, set, ci, tile), &s_ncl[ci]);
-    if (f) atomicAdd(&s_fresh[ci], f);
-  }
-  __syncthreads();
-  if (threadIdx.x < nc) {
-    const int ci = threadIdx.x;
-    *claim_n(w, set, ci, tile) = s_ncl[ci];
-    if (s_fresh[ci]) atomicAdd(&h->acc[ci][tile & (kGroups - 1)][0], s_fresh[ci]);
-  }
-  if (!arrive_last(h, gridDim.x)) return;
-
-  // ---- controller (last block)
-  __shared__ uint32_t cnt[kMaxCand];
-  if (threadIdx.x < nc) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  if (threadIdx.x < nc * kGroups) {
-    const int ci = threadIdx.x / kGroups, g = threadIdx.x % kGroups;
-    const uint32_t v = take(&h->acc[ci][g][0]);
-    if (v) atomicAdd(&cnt[ci], v);
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  c->pend_set = set;
-  c->pend_nc = nc;
-  c->set = set ^ 1;
-  int k = 0;
-  while (k < nc) {
-    const uint32_t cc = cnt[k];
-    const float s = c->cand_s[k];
-    c->evals += 1;
-    if (cc >= c->m && cc <= c->upper) {
-      c->accepted = 1;
-      c->done = 1;
-      set_final(c, s, P, h->frame);
-      break;
-    }
-    if (cc < c->m) {
-      c->hi = s;
-      k = 2 * k + 1;
-    } else {
-      c->lo = s;
-      k = 2 * k + 2;
-    }
-  }
-  if (!c->done) {
-    if (c->evals >= P.t_max) {
-      // no size in the window: the finest size with too many voxels if there was
-      // one (then trim), else the smallest size evaluated (then pad)
-      c->done = 1;
-      set_final(c, c->lo > 0.0f ? c->lo : c->hi, P, h->frame);
-    } else {
-      plan_pass(c, P, h->frame);
-    }
-  }
-  const int L = c->layer;
-  h->info.evals[L] = c->evals;
-  h->info.accepted[L] = c->accepted;
-  if (c->done) h->info.s[L] = c->s_final;
-}
-
-// ----------------------------------------------------------------------------- persistent search
-
-// One launch runs the whole adaptive voxel search of a layer: every block evaluates
-// its tiles at the pass's candidate scales, the blocks meet at a grid barrier, and
-// each block then reads the pass's counts and runs the same controller step, so all
-// blocks agree on the next pass without a kernel boundary. Within this kernel every
-// cross-block access is an atomic RMW or an agent-scope atomic load (tables, clears,
-// counts, barrier), never plain memory another block wrote.
-
 constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr float kSpecMult = 16.0f;
-
-struct SState {
-  float lo, hi;
-  uint32_t c_hi;  // count at hi (0: hi is the initial bracket, never evaluated)
-  int32_t evals, done, accepted;
-  int32_t nc, set, prev_set, prev_nc;
-  uint32_t prev_dense;  // bit k: candidate k of the previous pass used a dense table
-  float s_final;
-  float cand_s[kMaxCand];
-  float cand_inv[kMaxCand][3];
-  int32_t cand_dense[kMaxCand], cand_hot[kMaxCand];
-  uint32_t cand_nb[kMaxCand][2];
-};
 
 struct EvalShared {
   int ncl[kMaxCand];
@@ -985,14 +781,14 @@ struct EvalShared {
   uint32_t tb[6];             // tile's min (0..2) and max (3..5) offset bits per axis
 };
 
-__device__ __forceinline__ unsigned long long ld_agent(unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Inside the search launch, memory that another block writes (tables, claim lists,
+// counts, the published state) is only written with atomics and read with
+// agent-scope atomic loads: a plain load could return a line this compute die's L2
+// cached in an earlier pass.
 
-// global_or / dense_or for the persistent search: the tables are cleared and refilled
-// inside one launch, so every read of them is an agent-scope atomic load (a plain load
-// could return a line this compute die cached in an earlier pass).
-__device__ __forceinline__ uint32_t global_or_c(unsigned long long* keys, unsigned long long* masks,
+// OR `bits` into the brick table entry of `key` (hashed table); returns the number
+// of bits that were not set before. A tile that claims an empty slot records it.
+__device__ __forceinline__ uint32_t global_or(unsigned long long* keys, unsigned long long* masks,
                                                 uint32_t cmask, uint64_t key, uint64_t bits,
                                                 int32_t* list, int* s_ncl) {
   uint32_t s = table_hash(key) & cmask;
@@ -1005,7 +801,7 @@ __device__ __forceinline__ uint32_t global_or_c(unsigned long long* keys, unsign
     if (k == kEmptyKey) {
       const unsigned long long prev = atomicCAS(&keys[s], kEmptyKey, key);
       if (prev == kEmptyKey || prev == key) {
-        if (prev == kEmptyKey) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(s);
+        if (prev == kEmptyKey) st_agent(&list[atomicAdd(s_ncl, 1)], static_cast<int32_t>(s));
         const unsigned long long old = atomicOr(&masks[s], static_cast<unsigned long long>(bits));
         return static_cast<uint32_t>(__popcll(bits & ~old));
       }
@@ -1014,112 +810,37 @@ __device__ __forceinline__ uint32_t global_or_c(unsigned long long* keys, unsign
   }
 }
 
-__device__ __forceinline__ uint32_t dense_or_c(unsigned long long* masks, uint32_t slot,
-                                               uint64_t bits, bool hot, int32_t* list, int* s_ncl) {
-  if (hot && (ld_agent(&masks[slot]) & bits) == bits) return 0;
+// Dense brick table: `bits` ORed into word `slot`; the tile whose atomic finds the
+// word empty records it.
+__device__ __forceinline__ uint32_t dense_or(unsigned long long* masks, uint32_t slot,
+                                             uint64_t bits, int32_t* list, int* s_ncl) {
   const unsigned long long old = atomicOr(&masks[slot], static_cast<unsigned long long>(bits));
-  if (old == 0ull) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(slot);
+  if (old == 0ull) st_agent(&list[atomicAdd(s_ncl, 1)], static_cast<int32_t>(slot));
   return static_cast<uint32_t>(__popcll(bits & ~old));
 }
 
-// Candidates of the next pass (heap order below the bracket, as plan_pass). The
-// scales are those of plain bisection whatever the depth; the depth only says how
-// many future steps are evaluated at once. It is lowered while the finest candidate
-// would be much finer than a scale whose count is known (the count grows at most
-// with the cube of the scale ratio), since such candidates cost the most and are
-// rarely the ones the search takes.
-__device__ void plan_search(SState* st, const Plan& P, const Frame& fr, uint32_t upper) {
-  const int left = P.t_max - st->evals;
-  int D = left < P.depth ? left : P.depth;
-  const float cref = st->c_hi ? static_cast<float>(st->c_hi) : 1.0f;
-  const float budget = P.spec_mult * static_cast<float>(upper) + 64.0f;
-  while (D > 1) {
-    const float smin = st->lo + (st->hi - st->lo) / static_cast<float>(1 << D);
-    const float ratio = st->hi / smin;
-    if (cref * ratio * ratio * ratio <= budget) break;
-    --D;
-  }
-  const int nc = (1 << D) - 1;
-  float a[kMaxCand], b[kMaxCand];
-  a[0] = st->lo;
-  b[0] = st->hi;
-  for (int k = 0; k < nc; ++k) {
-    const float s = (a[k] + b[k]) * 0.5f;
-    st->cand_s[k] = s;
-    for (int ax = 0; ax < 3; ++ax) {
-      const float v = s * P.aspect[ax];
-      st->cand_inv[k][ax] = 1.0f / v;
-    }
-    uint32_t mk[3];
-    max_coords(fr, st->cand_inv[k], mk);
-    const uint64_t nbx = (mk[0] >> kBrickShift) + 1, nby = (mk[1] >> kBrickShift) + 1,
-                   nbz = (mk[2] >> kBrickShift) + 1;
-    const uint64_t nb = nbx * nby * nbz;
-    st->cand_dense[k] = nb <= P.cap ? 1 : 0;
-    st->cand_hot[k] = nb <= 4096 ? 1 : 0;
-    st->cand_nb[k][0] = static_cast<uint32_t>(nbx);
-    st->cand_nb[k][1] = static_cast<uint32_t>(nby);
-    if (2 * k + 2 < nc) {
-      a[2 * k + 1] = a[k];
-      b[2 * k + 1] = s;
-      a[2 * k + 2] = s;
-      b[2 * k + 2] = b[k];
-    }
-  }
-  st->nc = nc;
-}
-
-// One controller step on a pass's counts; every block runs it on the same counts.
-__device__ void search_step(SState* st, const uint32_t* cnt, const Plan& P, const Frame& fr,
-                            uint32_t m, uint32_t upper) {
-  st->prev_set = st->set;
-  st->prev_nc = st->nc;
-  uint32_t dm = 0;
-  for (int k = 0; k < st->nc; ++k) dm |= static_cast<uint32_t>(st->cand_dense[k] != 0) << k;
-  st->prev_dense = dm;
-  st->set ^= 1;
-  int k = 0;
-  while (k < st->nc) {
-    const uint32_t cc = cnt[k];
-    const float s = st->cand_s[k];
-    st->evals += 1;
-    if (cc >= m && cc <= upper) {
-      st->accepted = 1;
-      st->done = 1;
-      st->s_final = s;
-      return;
-    }
-    if (cc < m) {
-      st->hi = s;
-      st->c_hi = cc;
-      k = 2 * k + 1;
-    } else {
-      st->lo = s;
-      k = 2 * k + 2;
-    }
-  }
-  if (st->evals >= P.t_max) {
-    // no size in the window: the finest size with too many voxels if there was one
-    // (then trim), else the smallest size evaluated (then pad)
-    st->done = 1;
-    st->s_final = st->lo > 0.0f ? st->lo : st->hi;
-    return;
-  }
-  plan_search(st, P, fr, upper);
-}
-
-// The tile's live points into registers (thread t: the tile's points 8t..8t+7) and
-// the tile's offset range into sh.tb.
-__device__ __forceinline__ void load_tile(const Ws& w, int tile, float4 (&pt)[kPerThread],
-                                          uint32_t& live, EvalShared& sh) {
+// Issue the loads of a tile's points (thread t: the tile's points 8t..8t+7) and
+// their layer tags; every slot of a tile exists, so no load depends on another.
+__device__ __forceinline__ void issue_tile(const Ws& w, int tile, float4 (&pt)[kPerThread],
+                                           uint32_t (&tg)[kPerThread]) {
   const int64_t base = static_cast<int64_t>(tile) * kTile + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t S = base + k * kThreads;
+    tg[k] = w.tag_s[S];
+    pt[k] = w.pts[S];
+  }
+}
+
+// Keep the live points (tag 0) and reduce the tile's offset range into sh.tb.
+__device__ __forceinline__ void finish_tile(float4 (&pt)[kPerThread], const uint32_t (&tg)[kPerThread],
+                                            uint32_t& live, EvalShared& sh) {
   live = 0;
   uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
-    const int64_t S = base + k * kThreads;
-    const bool ok = w.tag_s[S] == 0;
-    pt[k] = ok ? w.pts[S] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool ok = tg[k] == 0;
+    if (!ok) pt[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (ok) {
       live |= 1u << k;
       // offsets are >= +0, so their bit patterns order like their values
@@ -1227,9 +948,9 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
       }
       if (cur != kEmptyKey && !lds_try_or<kBrickCap>(tk, tv, cur, cb)) {
         const uint32_t f =
-            dense ? dense_or_c(ctab_masks(w, set, ci), static_cast<uint32_t>(cur), cb,
-                               st.cand_hot[ci], claims(w, set, ci, tile), &sh.ncl[ci])
-                  : global_or_c(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, cur, cb,
+            dense ? dense_or(ctab_masks(w, set, ci), static_cast<uint32_t>(cur), cb,
+                             claims(w, set, ci, tile), &sh.ncl[ci])
+                  : global_or(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, cur, cb,
                                 claims(w, set, ci, tile), &sh.ncl[ci]);
         if (f) atomicAdd(&sh.fresh[ci], f);
       }
@@ -1238,107 +959,110 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
     }
   }
   __syncthreads();
-  // one global update per distinct brick of the tile; LDS entries are emptied as read
-  for (int e = threadIdx.x; e < nc * kBrickCap; e += kThreads) {
-    const int ci = e / kBrickCap;
-    const int le = e - ci * kBrickCap;
-    const uint32_t vol = sh.box[ci][5];
-    uint64_t key, bits;
-    if (vol) {
-      if (le >= static_cast<int>(vol)) continue;
-      bits = lvals[e];
-      if (!bits) continue;
-      lvals[e] = 0ull;
-      const uint32_t bdx = sh.box[ci][3], bdy = sh.box[ci][4];
-      const uint32_t bx = sh.box[ci][0] + le % bdx;
-      const uint32_t t2 = le / bdx;
-      const uint32_t by = sh.box[ci][1] + t2 % bdy;
-      const uint32_t bz = sh.box[ci][2] + t2 / bdy;
-      key = st.cand_dense[ci]
-                ? (bx + static_cast<uint64_t>(st.cand_nb[ci][0]) *
-                            (by + static_cast<uint64_t>(st.cand_nb[ci][1]) * bz))
-                : (static_cast<uint64_t>(bx) | (static_cast<uint64_t>(by) << kBrickCoordBits) |
-                   (static_cast<uint64_t>(bz) << (2 * kBrickCoordBits)));
-    } else {
-      key = lkeys[e];
-      if (key == kEmptyKey) continue;
-      bits = lvals[e];
-      lkeys[e] = kEmptyKey;
-      lvals[e] = 0ull;
+  // One global update per distinct brick of the tile, LDS entries emptied as read.
+  // Thread t owns entries t + j*kThreads (j < 4) of each candidate; the updates of up
+  // to three candidates are issued together so that their round trips overlap. A hot
+  // table (a brick grid of at most kHotCap words, shared by very many tiles) is first
+  // ORed into the tile's replica (one of kReps, so a word sees a 1/kReps share of the
+  // tiles) and only the bits new to the replica go on to the table; every bit still
+  // reaches the table, so the fresh count stays exact.
+  static_assert(kBrickCap == 4 * kThreads, "four flush entries per thread");
+  constexpr int kGrp = 3;
+  const int rep = tile & (kReps - 1);
+  for (int c0 = 0; c0 < nc; c0 += kGrp) {
+    uint32_t slot[4 * kGrp];
+    uint64_t bits[4 * kGrp];
+    uint32_t valid = 0, hot = 0;
+    uint32_t f[kGrp] = {};
+#pragma unroll
+    for (int q = 0; q < 4 * kGrp; ++q) {
+      const int ci = c0 + q / 4;
+      const int le = (q % 4) * kThreads + threadIdx.x;
+      const int e = ci * kBrickCap + le;
+      slot[q] = 0;
+      bits[q] = 0ull;
+      if (ci >= nc) continue;
+      const uint32_t vol = sh.box[ci][5];
+      const int dense = st.cand_dense[ci];
+      uint64_t key, b;
+      if (vol) {
+        if (le >= static_cast<int>(vol)) continue;
+        b = lvals[e];
+        if (!b) continue;
+        lvals[e] = 0ull;
+        const uint32_t bdx = sh.box[ci][3], bdy = sh.box[ci][4];
+        const uint32_t bx = sh.box[ci][0] + le % bdx;
+        const uint32_t t2 = le / bdx;
+        const uint32_t by = sh.box[ci][1] + t2 % bdy;
+        const uint32_t bz = sh.box[ci][2] + t2 / bdy;
+        key = dense ? (bx + static_cast<uint64_t>(st.cand_nb[ci][0]) *
+                                (by + static_cast<uint64_t>(st.cand_nb[ci][1]) * bz))
+                    : (static_cast<uint64_t>(bx) | (static_cast<uint64_t>(by) << kBrickCoordBits) |
+                       (static_cast<uint64_t>(bz) << (2 * kBrickCoordBits)));
+      } else {
+        key = lkeys[e];
+        if (key == kEmptyKey) continue;
+        b = lvals[e];
+        lkeys[e] = kEmptyKey;
+        lvals[e] = 0ull;
+      }
+      if (!dense) {  // hashed table: probe one entry at a time
+        f[q / 4] += global_or(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, key, b,
+                              claims(w, set, ci, tile), &sh.ncl[ci]);
+        continue;
+      }
+      slot[q] = static_cast<uint32_t>(key);
+      bits[q] = b;
+      valid |= 1u << q;
+      if (st.cand_hot[ci]) hot |= 1u << q;
     }
-    const uint32_t f =
-        st.cand_dense[ci]
-            ? dense_or_c(ctab_masks(w, set, ci), static_cast<uint32_t>(key), bits, st.cand_hot[ci],
-                         claims(w, set, ci, tile), &sh.ncl[ci])
-            : global_or_c(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, key, bits,
-                          claims(w, set, ci, tile), &sh.ncl[ci]);
-    if (f) atomicAdd(&sh.fresh[ci], f);
+    // hot words: the tile's replica first
+    uint64_t old[4 * kGrp];
+#pragma unroll
+    for (int q = 0; q < 4 * kGrp; ++q)
+      old[q] = ((hot >> q) & 1u)
+                   ? atomicOr(hrep_of(w, set, c0 + q / 4, rep) + slot[q],
+                              static_cast<unsigned long long>(bits[q]))
+                   : 0ull;
+#pragma unroll
+    for (int q = 0; q < 4 * kGrp; ++q) {
+      if (!((hot >> q) & 1u)) continue;
+      if (old[q] == 0ull)
+        st_agent(claims(w, set, c0 + q / 4, tile) + atomicAdd(&sh.ncl[c0 + q / 4], 1),
+                 static_cast<int32_t>(-1 - (rep * kHotCap + static_cast<int32_t>(slot[q]))));
+      bits[q] &= ~old[q];
+      if (!bits[q]) valid &= ~(1u << q);
+    }
+    // the tables
+#pragma unroll
+    for (int q = 0; q < 4 * kGrp; ++q)
+      old[q] = ((valid >> q) & 1u)
+                   ? atomicOr(ctab_masks(w, set, c0 + q / 4) + slot[q],
+                              static_cast<unsigned long long>(bits[q]))
+                   : ~0ull;
+#pragma unroll
+    for (int q = 0; q < 4 * kGrp; ++q) {
+      if (!((valid >> q) & 1u)) continue;
+      f[q / 4] += static_cast<uint32_t>(__popcll(bits[q] & ~old[q]));
+      if (old[q] == 0ull)
+        st_agent(claims(w, set, c0 + q / 4, tile) + atomicAdd(&sh.ncl[c0 + q / 4], 1),
+                 static_cast<int32_t>(slot[q]));
+    }
+#pragma unroll
+    for (int k = 0; k < kGrp; ++k)
+      if (f[k]) atomicAdd(&sh.fresh[c0 + k], f[k]);
   }
   __syncthreads();
-  if (threadIdx.x < nc) *claim_n(w, set, threadIdx.x, tile) = sh.ncl[threadIdx.x];
+  if (threadIdx.x < nc) st_agent(claim_n(w, set, threadIdx.x, tile), static_cast<int32_t>(sh.ncl[threadIdx.x]));
 }
 
-// Grid barrier of the persistent search; `target` is the pass number + 1. The last
-// block to arrive empties the accumulators the next pass fills, then releases the
-// others. Every thread first waits for its own memory operations to complete, so a
-// block's table updates and counts are in place before it is counted as arrived. A
-// block that waits longer than kSpinLimit polls gives up and raises bar_err, which
-// every other waiter also takes as a failure, so a launch whose blocks are not all
-// resident ends instead of hanging. Returns false on failure.
-__device__ bool grid_sync(Header* h, int nblocks, uint32_t target, int next_par) {
-  __shared__ int s_last, s_ok;
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int g = blockIdx.x & (kGroups - 1);
-    const int gsize = (nblocks - g + kGroups - 1) / kGroups;
-    const int ngroups = nblocks < kGroups ? nblocks : kGroups;
-    int last = 0;
-    const uint32_t a = atomicAdd(&h->bar_grp[g][0], 1u);
-    if (a == static_cast<uint32_t>(gsize - 1)) {
-      atomicExch(&h->bar_grp[g][0], 0u);
-      const uint32_t b = atomicAdd(&h->bar_top[0], 1u);
-      if (b == static_cast<uint32_t>(ngroups - 1)) {
-        atomicExch(&h->bar_top[0], 0u);
-        last = 1;
-      }
-    }
-    s_last = last;
-    s_ok = 1;
-  }
-  __syncthreads();
-  if (s_last) {
-    if (threadIdx.x < kMaxCand * kGroups)
-      atomicExch(&h->sacc[next_par][threadIdx.x / kGroups][threadIdx.x % kGroups][0], 0u);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) atomicExch(&h->bar_gen[0], target);
-  } else if (threadIdx.x == 0) {
-    uint32_t spins = 0;
-    while (__hip_atomic_load(&h->bar_gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(&h->bar_err[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        s_ok = 0;
-        break;
-      }
-      if (++spins > kSpinLimit) {
-        atomicOr(&h->bar_err[0], 1u);
-        s_ok = 0;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-  }
-  __syncthreads();
-  return s_ok != 0;
-}
-
-// One launch runs the whole adaptive voxel search of a layer (Sec. 3.3): every block
-// evaluates its tiles at the pass's candidate scales, the blocks meet at a grid
-// barrier, and each block then reads the pass's counts and runs the same controller
-// step, so all blocks agree on the next pass without a kernel boundary. Launched
-// cooperatively (all blocks resident); with one tile per block the tile's points stay
-// in registers for the whole search. Within the launch every access to memory another
-// block writes is an atomic RMW or an agent-scope atomic load.
+// The adaptive voxel search of a layer (Sec. 3.3) in one launch. The passes' work
+// is a queue of tickets: ticket t is tile t % ntile of pass t / ntile. A block takes
+// a ticket, waits until that pass's candidates are published, counts the tile's
+// voxels at every candidate scale and adds them to the pass's counts; the block that
+// completes the pass's last tile runs the bisection step and publishes the next
+// pass (or the end). A block only ever waits for tiles that running blocks hold, so
+// the launch needs no co-resident grid and no kernel boundary per pass.
 __global__ void __launch_bounds__(kThreads) k_search(Ws w, Plan P) {
   Header* h = w.h;
   if (h->frame.status != HAV_OK) return;
@@ -1348,7 +1072,8 @@ __global__ void __launch_bounds__(kThreads) k_search(Ws w, Plan P) {
   __shared__ SState st;
   __shared__ EvalShared sh;
   __shared__ uint32_t s_cnt[kMaxCand];
-  __shared__ int s_ok;
+  __shared__ int s_cn[kMaxCand + 1];
+  __shared__ int s_tile, s_pass, s_go, s_last;
   const int ncap = (1 << P.depth) - 1;
   uint64_t* lvals = lds;
   uint64_t* lkeys = lds + static_cast<size_t>(ncap) * kBrickCap;
@@ -1358,98 +1083,109 @@ __global__ void __launch_bounds__(kThreads) k_search(Ws w, Plan P) {
   }
   const uint32_t m = c->m, upper = c->upper;
   const Frame fr = h->frame;
-  if (threadIdx.x == 0) {
-    st.lo = c->lo;
-    st.hi = c->hi;
-    st.c_hi = 0;
-    st.evals = 0;
-    st.done = 0;
-    st.accepted = 0;
-    st.set = c->set;
-    st.prev_set = 0;
-    st.prev_nc = 0;
-    st.prev_dense = 0;
-    st.s_final = 0.0f;
-    plan_search(&st, P, fr, upper);
-    s_ok = 1;
-  }
-  __syncthreads();
-  const int G = gridDim.x;
-  const bool resident = w.ntile <= G;  // then G == ntile: one tile per block
+  const int ntile = w.ntile;
+  int cur = -1;  // pass whose state st holds
   float4 pt[kPerThread];
-  uint32_t live = 0;
-  if (resident) load_tile(w, blockIdx.x, pt, live, sh);
-  for (int pass = 0;; ++pass) {
-    const int nc = st.nc, par = pass & 1;
-    // empty the slots this block's tiles claimed in the previous pass (other set)
-    for (int t = blockIdx.x; t < w.ntile; t += G) {
-      for (int k = 0; k < st.prev_nc; ++k) {
-        int32_t* cn = claim_n(w, st.prev_set, k, t);
-        const int n = *cn;
-        const int32_t* list = claims(w, st.prev_set, k, t);
-        const bool dense = (st.prev_dense >> k) & 1u;
-        unsigned long long* keys = ctab_keys(w, st.prev_set, k);
-        unsigned long long* masks = ctab_masks(w, st.prev_set, k);
-        for (int i = threadIdx.x; i < n; i += kThreads) {
-          const int32_t sl = list[i];
-          if (!dense) atomicExch(&keys[sl], static_cast<unsigned long long>(kEmptyKey));
-          atomicExch(&masks[sl], 0ull);
+  uint32_t live;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const uint32_t t = atomicAdd(&h->sq_ticket[0], 1u);
+      const int p = static_cast<int>(t / static_cast<uint32_t>(ntile));
+      int go = p < P.t_max;  // every pass makes at least one evaluation
+      if (go && p != cur) {
+        uint32_t spins = 0;
+        while (ld_agent(&h->sq_gen[0]) < static_cast<uint32_t>(p)) {
+          if (ld_agent(&h->sq_fin[0]) || ld_agent(&h->sq_err[0])) {
+            go = 0;
+            break;
+          }
+          if (++spins > kSpinLimit) {
+            atomicOr(&h->sq_err[0], 1u);
+            go = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
         }
       }
+      s_pass = p;
+      s_tile = static_cast<int>(t - static_cast<uint32_t>(p) * static_cast<uint32_t>(ntile));
+      s_go = go;
     }
+    __syncthreads();
+    if (!s_go) break;
+    const int p = s_pass, tile = s_tile;
+    uint32_t tg[kPerThread];
+    issue_tile(w, tile, pt, tg);  // in flight while the state and claims are read
+    if (p != cur) {
+      if (threadIdx.x < kPubWords)
+        reinterpret_cast<uint32_t*>(&st)[threadIdx.x] = ld_agent(&h->pub[threadIdx.x]);
+      __syncthreads();
+      if (st.done) break;  // the search ended with the previous pass
+      cur = p;
+    }
+    const int nc = st.nc;
+    // empty the words this tile claimed in the previous pass (the other table set)
+    clear_claims(w, st.prev_set, st.prev_nc, st.prev_hashed, tile, s_cn);
     if (threadIdx.x < nc) sh.fresh[threadIdx.x] = 0;
     __syncthreads();
-    if (resident) {
-      eval_loaded(w, blockIdx.x, st, sh, lvals, lkeys, pt, live);
-    } else {
-      for (int t = blockIdx.x; t < w.ntile; t += G) {
-        load_tile(w, t, pt, live, sh);
-        eval_loaded(w, t, st, sh, lvals, lkeys, pt, live);
-        __syncthreads();
-      }
-    }
+    finish_tile(pt, tg, live, sh);
+    eval_loaded(w, tile, st, sh, lvals, lkeys, pt, live);
     __syncthreads();
     if (threadIdx.x < nc && sh.fresh[threadIdx.x])
-      atomicAdd(&h->sacc[par][threadIdx.x][blockIdx.x & (kGroups - 1)][0], sh.fresh[threadIdx.x]);
-    if (!grid_sync(h, G, static_cast<uint32_t>(pass + 1), par ^ 1)) {
-      if (threadIdx.x == 0) s_ok = 0;
-      __syncthreads();
-      break;
+      atomicAdd(&h->sacc[p & 1][threadIdx.x][tile & (kGroups - 1)][0], sh.fresh[threadIdx.x]);
+    // this tile's clears, table updates and counts are complete before it counts as done
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t d = atomicAdd(&h->sq_done[0], 1u);
+      s_last = (d % static_cast<uint32_t>(ntile)) == static_cast<uint32_t>(ntile - 1);
     }
+    __syncthreads();
+    if (!s_last) continue;
+    // ---- last tile of pass p: bisection step, then publish pass p + 1 or the end
     if (threadIdx.x < nc) s_cnt[threadIdx.x] = 0;
     __syncthreads();
     if (threadIdx.x < nc * kGroups) {
-      const uint32_t v = __hip_atomic_load(&h->sacc[par][threadIdx.x / kGroups][threadIdx.x % kGroups][0],
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t v = atomicExch(&h->sacc[p & 1][threadIdx.x / kGroups][threadIdx.x % kGroups][0], 0u);
       if (v) atomicAdd(&s_cnt[threadIdx.x / kGroups], v);
     }
     __syncthreads();
     if (threadIdx.x == 0) search_step(&st, s_cnt, P, fr, m, upper);
     __syncthreads();
-    if (st.done) break;
+    if (st.done) {
+      if (threadIdx.x == 0) {
+        c->evals = st.evals;
+        c->accepted = st.accepted;
+        c->lo = st.lo;
+        c->hi = st.hi;
+        c->done = 1;
+        c->set = st.set;
+        c->pend_set = st.prev_set;
+        c->pend_nc = st.prev_nc;
+        c->pend_hashed = st.prev_hashed;
+        set_final(c, st.s_final, P, fr);
+        const int L = c->layer;
+        h->info.evals[L] = st.evals;
+        h->info.accepted[L] = st.accepted;
+        h->info.s[L] = st.s_final;
+        atomicExch(&h->sq_fin[0], 1u);
+      }
+      break;
+    }
+    if (threadIdx.x < kPubWords)
+      st_agent(&h->pub[threadIdx.x], reinterpret_cast<const uint32_t*>(&st)[threadIdx.x]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicExch(&h->sq_gen[0], static_cast<uint32_t>(p + 1));
+    cur = p + 1;
   }
-  // block 0 publishes the outcome for the kernels that follow
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  if (!s_ok) {
-    // tables may hold claims nobody cleared: the workspace needs hav_workspace_init
+  if (threadIdx.x == 0 && ld_agent(&h->sq_err[0])) {
+    // a wait gave up: tables may hold claims nobody cleared, so the workspace needs
+    // hav_workspace_init again
     h->frame.status = HAV_ERR_HIP;
     h->info.status = HAV_ERR_HIP;
     h->magic = 0;
-    return;
   }
-  c->evals = st.evals;
-  c->accepted = st.accepted;
-  c->lo = st.lo;
-  c->hi = st.hi;
-  c->done = 1;
-  c->set = st.set;
-  c->pend_set = st.prev_set;
-  c->pend_nc = st.prev_nc;
-  set_final(c, st.s_final, P, fr);
-  const int L = c->layer;
-  h->info.evals[L] = st.evals;
-  h->info.accepted[L] = st.accepted;
-  h->info.s[L] = st.s_final;
 }
 
 // ----------------------------------------------------------------------------- select
@@ -1975,7 +1711,7 @@ __global__ void __launch_bounds__(kThreads) k_out_write(Ws w, int32_t* idx, int6
 // ----------------------------------------------------------------------------- workspace init
 
 __global__ void __launch_bounds__(kThreads) k_ws_init(Ws w, size_t nct, size_t ncn, size_t nst,
-                                                      size_t nsv, size_t nsn) {
+                                                      size_t nsv, size_t nsn, size_t nhr) {
   const size_t stride = static_cast<size_t>(gridDim.x) * kThreads;
   const size_t t0 = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
   for (size_t i = t0; i < nct; i += stride) {
@@ -1983,6 +1719,7 @@ __global__ void __launch_bounds__(kThreads) k_ws_init(Ws w, size_t nct, size_t n
     w.cmasks[i] = 0ull;
   }
   for (size_t i = t0; i < ncn; i += stride) w.ccn[i] = 0;
+  for (size_t i = t0; i < nhr; i += stride) w.hrep[i] = 0ull;
   for (size_t i = t0; i < nst; i += stride) w.skeys[i] = kEmptyKey;
   for (size_t i = t0; i < nsv; i += stride) w.svals[i] = ~0ull;
   for (size_t i = t0; i < nsn; i += stride) w.scn[i] = 0;
@@ -2043,7 +1780,7 @@ int bin_blocks(int64_t n) {
 }
 
 struct Layout {
-  size_t hdr, pts, invp, tag_s, tag_o, part, bh, binpre, bsum, ckeys, cmasks, ccl, ccn, skeys, svals, scl,
+  size_t hdr, pts, invp, tag_s, tag_o, part, bh, binpre, bsum, ckeys, cmasks, ccl, hrep, ccn, skeys, svals, scl,
       scn, tie_p, tie_o, tcnt, total;
   int64_t n_ws;
   uint32_t cap_ws;
@@ -2074,7 +1811,8 @@ Layout make_layout(int64_t n, int depth) {
   L.bsum = o;   o = align_up(o + static_cast<size_t>(kBinChunks) * 4);
   L.ckeys = o;  o = align_up(o + tabs * L.cap_ws * 8);
   L.cmasks = o; o = align_up(o + tabs * L.cap_ws * 8);
-  L.ccl = o;    o = align_up(o + tabs * L.ntile_ws * kTile * 4);
+  L.ccl = o;    o = align_up(o + tabs * L.ntile_ws * kClaimCap * 4);
+  L.hrep = o;   o = align_up(o + tabs * kReps * kHotCap * 8);
   L.ccn = o;    o = align_up(o + tabs * L.ntile_ws * 4);
   L.skeys = o;  o = align_up(o + static_cast<size_t>(L.cap_ws) * 8);
   L.svals = o;  o = align_up(o + static_cast<size_t>(L.cap_ws) * kSelDense * 8);
@@ -2106,6 +1844,7 @@ Ws make_ws(char* base, const Layout& L, int64_t n) {
   w.ckeys = reinterpret_cast<unsigned long long*>(base + L.ckeys);
   w.cmasks = reinterpret_cast<unsigned long long*>(base + L.cmasks);
   w.ccl = reinterpret_cast<int32_t*>(base + L.ccl);
+  w.hrep = reinterpret_cast<unsigned long long*>(base + L.hrep);
   w.ccn = reinterpret_cast<int32_t*>(base + L.ccn);
   w.skeys = reinterpret_cast<unsigned long long*>(base + L.skeys);
   w.svals = reinterpret_cast<unsigned long long*>(base + L.svals);
@@ -2175,26 +1914,29 @@ int trim_rounds(int64_t n) {
   return R;
 }
 
-// Blocks of the persistent search: one per tile when the device can hold them all at
-// once, else as many as it can (0 if the cooperative launch is not available).
+// Blocks of the search launch: one per tile, at most as many as the device holds at
+// once (more would only wait for tickets). The limit is cached per device and depth.
 int search_grid(int ntile, int depth) {
   static std::atomic<int> cache[kMaxDevices][kMaxDepth + 1];
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
-  int cap = cache[dev][depth].load(std::memory_order_relaxed);
-  if (cap == 0) {
-    const size_t lds = 2 * static_cast<size_t>((1 << depth) - 1) * kBrickCap * sizeof(uint64_t);
-    int per_cu = 0, cus = 0, coop = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_search),
-                                                     kThreads, lds) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess)
-      return 0;
-    cap = coop ? per_cu * cus : -1;
-    if (cap == 0) cap = -1;
-    cache[dev][depth].store(cap, std::memory_order_relaxed);
+  int cap = 1024;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) {
+    int c = cache[dev][depth].load(std::memory_order_relaxed);
+    if (c == 0) {
+      const size_t lds = 2 * static_cast<size_t>((1 << depth) - 1) * kBrickCap * sizeof(uint64_t);
+      int per_cu = 0, cus = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &per_cu, reinterpret_cast<const void*>(&k_search), kThreads, lds) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+          per_cu > 0 && cus > 0)
+        c = per_cu * cus;
+      else
+        c = cap;
+      cache[dev][depth].store(c, std::memory_order_relaxed);
+    }
+    cap = c;
   }
-  return cap < 0 ? 0 : std::min(ntile, cap);
+  return std::max(1, std::min(ntile, cap));
 }
 
 #define HAV_LAUNCH(...)                                          \
@@ -2239,22 +1981,12 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
   HAV_LAUNCH(k_bin_count, dim3(w.nbb), dim3(kThreads), 0, st, xyz, w, P);
   HAV_LAUNCH(k_bin_scan, dim3(kBinChunks), dim3(kThreads), 0, st, w, P);
   HAV_LAUNCH(k_bin_scatter, dim3(w.nbb), dim3(kThreads), 0, st, xyz, w);
-  const int passes = P.fixed ? 0 : (p->t_max + P.depth - 1) / P.depth;
-  const int sgrid = P.fixed ? 0 : search_grid(w.ntile, P.depth);
+  const int sgrid = search_grid(w.ntile, P.depth);
   const int R = trim_rounds(N);
   const size_t eval_lds = 2 * static_cast<size_t>((1 << P.depth) - 1) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
   for (int l = 0; l < nl; ++l) {
-    if (sgrid > 0) {
-      void* args[] = {&w, &P};
-      if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_search), dim3(sgrid),
-                                     dim3(kThreads), args, static_cast<unsigned>(eval_lds),
-                                     st) != hipSuccess)
-        return HAV_ERR_HIP;
-    } else {
-      for (int q = 0; q < passes; ++q)
-        HAV_LAUNCH(k_eval, dim3(w.ntile), dim3(kThreads), eval_lds, st, w, P);
-    }
+    if (!P.fixed) HAV_LAUNCH(k_search, dim3(sgrid), dim3(kThreads), eval_lds, st, w, P);
     HAV_LAUNCH(k_select, dim3(w.ntile), dim3(kThreads), sel_lds, st, w);
     for (int r = 0; r < R; ++r) HAV_LAUNCH(k_trim_hist, dim3(w.ntile), dim3(kThreads), 0, st, w, r);
     HAV_LAUNCH(k_mark, dim3(w.ntile), dim3(kThreads), 0, st, w);
@@ -2299,7 +2031,8 @@ hav_status_t init_ws(char* base, const Layout& L, hipStream_t st) {
   const size_t ncn = 2 * static_cast<size_t>(L.ncmax) * L.ntile_ws;
   HAV_LAUNCH(k_ws_init, dim3(2048), dim3(kThreads), 0, st, w, nct, ncn,
              static_cast<size_t>(L.cap_ws), static_cast<size_t>(L.cap_ws) * kSelDense,
-             static_cast<size_t>(L.ntile_ws));
+             static_cast<size_t>(L.ntile_ws),
+             2 * static_cast<size_t>(L.ncmax) * kReps * kHotCap);
   HAV_LAUNCH(k_ws_seal, dim3(1), dim3(64), 0, st, w.h, magic_of(L));
   return HAV_OK;
 }
@@ -2343,13 +2076,13 @@ const char* hav_status_string(hav_status_t s) {
 }
 
 size_t hav_workspace_size(int64_t N, int64_t M, const hav_params_t* params) {
-  if (N < 1 || M < 1 || M > N || N >= (int64_t(1) << 31) || !params_ok(params)) return 0;
+  if (N < 1 || M < 1 || M > N || N > kMaxPoints || !params_ok(params)) return 0;
   return make_layout(N, depth_of(params)).total;
 }
 
 hav_status_t hav_workspace_init(int64_t N, const hav_params_t* params, void* ws, size_t ws_bytes,
                                 void* stream) {
-  if (!ws || N < 1 || N >= (int64_t(1) << 31) || !params_ok(params)) return HAV_ERR_INVALID_ARG;
+  if (!ws || N < 1 || N > kMaxPoints || !params_ok(params)) return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
   const Layout L = make_layout(N, depth_of(params));
   if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
@@ -2359,7 +2092,7 @@ hav_status_t hav_workspace_init(int64_t N, const hav_params_t* params, void* ws,
 hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params_t* params,
                         int32_t* idx, void* ws, size_t ws_bytes, hav_info_t* info_dev,
                         void* stream) {
-  if (!xyz || !idx || !ws || N < 1 || M < 1 || M > N || N >= (int64_t(1) << 31) ||
+  if (!xyz || !idx || !ws || N < 1 || M < 1 || M > N || N > kMaxPoints ||
       !params_ok(params))
     return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
@@ -2371,7 +2104,7 @@ hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params
 
 size_t hav_chain_workspace_size(int64_t N, const int64_t* M_host, int32_t n_stages,
                                 const hav_params_t* params) {
-  if (N < 1 || N >= (int64_t(1) << 31) || !params_ok(params) ||
+  if (N < 1 || N > kMaxPoints || !params_ok(params) ||
       !chain_sizes_ok(N, M_host, n_stages))
     return 0;
   return make_chain_layout(N, M_host, depth_of(params)).total;
@@ -2380,7 +2113,7 @@ size_t hav_chain_workspace_size(int64_t N, const int64_t* M_host, int32_t n_stag
 hav_status_t hav_sample_chain(const float* xyz, int64_t N, const int64_t* M_host,
                               int32_t n_stages, const hav_params_t* params, int32_t* idx_concat,
                               void* ws, size_t ws_bytes, hav_info_t* info_dev, void* stream) {
-  if (!xyz || !idx_concat || !ws || N < 1 || N >= (int64_t(1) << 31) || !params_ok(params) ||
+  if (!xyz || !idx_concat || !ws || N < 1 || N > kMaxPoints || !params_ok(params) ||
       !chain_sizes_ok(N, M_host, n_stages))
     return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
