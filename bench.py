@@ -8,8 +8,9 @@ both layers, centre-closest selection, exact-M trim/pad, masking, ascending outp
 Inputs are resident in HBM before the timed region; the timed region is bracketed by
 torch.cuda.synchronize() on both sides.
 
-Prints one JSON line: input Mpoints/s, the roofline of the dominant kernel and the CPU
-oracle timed on this host as a baseline.
+Prints one JSON line: input Mpoints/s, the roofline of the dominant kernel (the voxel
+search, k_search, timed live with HIP events on the call's stream) and the CPU oracle
+timed on this host as a baseline.
 """
 from __future__ import annotations
 
@@ -24,6 +25,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+DOMINANT = "k_search"
+KERNELS = ("k_bbox", "k_identity", "k_bin_count", "k_bin_scan", "k_bin_scatter", "k_search",
+           "k_select", "k_trim_hist", "k_mark", "k_ties", "k_scan_count", "k_pad_mark",
+           "k_out_write", "k_ws_init", "k_ws_seal", "k_compose", "k_gather")
+PMC_FILE = os.path.join(ROOT, "profiles", "k_search_scene1M_pmc.txt")
 
 
 def algorithmic_bytes(n: int, M: int, info: dict) -> float:
@@ -40,6 +46,35 @@ def algorithmic_bytes(n: int, M: int, info: dict) -> float:
         remaining -= info["m"][L]
     total += 2.0 * n + 4.0 * M
     return total
+
+
+def search_bytes(n: int, info: dict) -> list:
+    """Algorithmic bytes of each voxel-search launch (one per layer): every evaluation
+    reads the coordinates of the points still unsampled (12 B each) and, from layer 2
+    on, the 1-byte sampled mask of every point."""
+    out, remaining = [], n
+    for L in range(info["layers"]):
+        out.append(info["evals"][L] * (12.0 * remaining + (n if L > 0 else 0)))
+        remaining -= info["m"][L]
+    return out
+
+
+def measured_traffic():
+    """HBM bytes per search launch from the committed counter summary, or None when it
+    is missing or was taken on other kernel sources."""
+    from paper_2305_14306_amd.profile_report import source_digest
+    try:
+        kv = {}
+        with open(PMC_FILE) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("source_digest") != source_digest():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(x, M: int, budget_s: float) -> dict:
@@ -64,6 +99,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter "
+                         "calibration for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the sampler works on "
@@ -102,12 +140,36 @@ def main() -> int:
     ms = ev0.elapsed_time(ev1) / args.steps
     print(f"bench: {ms:.4f} ms/step (wall {wall * 1e3 / args.steps:.4f})", file=sys.stderr, flush=True)
 
+    # dominant kernel: HIP events around each launch of the voxel search, on the stream
+    # the library launches it on (the call's stream)
+    hav.timing_enable(True)
+    for _ in range(args.steps):
+        sampler.sample(xd, M, p, out=out)
+    torch.cuda.synchronize()
+    hav.timing_enable(False)
+    launches, k_ms = hav.timing_collect(DOMINANT)
+    for k in KERNELS:
+        hav.timing_collect(k)
+    per_call = search_bytes(N, info)
+    assert launches == args.steps * len(per_call), (launches, per_call)
+    launch_bytes = sum(per_call) / len(per_call)
+    launch_ms = k_ms / launches
+    achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
+    print(f"bench: {DOMINANT} {launch_ms * 1e3:.1f} us/launch over {launches} launches", file=sys.stderr,
+          flush=True)
+
+    if args.copy_calib:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+
     value = N / (ms * 1e-3) / 1e6
-    b_alg = algorithmic_bytes(N, M, info)
-    achieved = b_alg / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "hav_sample (whole call)", "bytes_per_launch": b_alg}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                "kernel": DOMINANT, "launch_us": round(launch_ms * 1e3, 2),
+                "bytes_per_launch": launch_bytes,
+                "whole_call_alg_bytes": algorithmic_bytes(N, M, info)}
     result = {
         "metric": "input Mpoints/s (1M->250k)",
         "value": round(value, 3),

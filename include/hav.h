@@ -136,6 +136,17 @@ hav_status_t hav_sample_chain(const float* xyz, int64_t N, const int64_t* M_host
                               int32_t n_stages, const hav_params_t* params, int32_t* idx_concat,
                               void* ws, size_t ws_bytes, hav_info_t* info_dev, void* stream);
 
+/* Measurement support. While enabled (on != 0), every kernel launch the library makes
+ * is bracketed by a pair of HIP events recorded on the call's stream; the events are
+ * kept by the library. Off by default; timing adds the event records to the stream. */
+hav_status_t hav_timing_enable(int32_t on);
+
+/* Wait for and release the kept event pairs of the kernel named `kernel` (the device
+ * function's name, e.g. "k_search"; other kernels' pairs are kept). Writes the number
+ * of launches and their summed duration in milliseconds. HAV_ERR_HIP if an event could
+ * not be read (its duration then counts as 0). */
+hav_status_t hav_timing_collect(const char* kernel, int32_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

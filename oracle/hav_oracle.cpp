@@ -17,15 +17,15 @@
 //   3. Per layer, on the not-yet-sampled points R:
 //      a. voxel coordinates (Sec. 3.2, Eq. 2) g = floor(r * (1/v)), r = p - origin;
 //      b. the voxel counter Cnt(R, v) = number of distinct voxel coordinates
-//         (Sec. 3.2 "Sparse Voxelization via Voxel-Hashing", Sec. 3.3);
+//         (the hashed sparse voxelization of Sec. 3.2, and Sec. 3.3);
 //      c. adaptive voxel search (Sec. 3.3): bisection on the voxel scale s until the
 //         count is in [m, (1+sigma) m] or t_max evaluations have been made;
-//      d. centre-closest representative per occupied voxel (Sec. 3.2
-//         "Center-closest Point Sampling"), ties to the lowest index;
+//      d. centre-closest representative per occupied voxel (the centre-closest
+//         point sampling of Sec. 3.2), ties to the lowest index;
 //      e. exactly m picks: trim by a fixed hash priority of the voxel coordinate
 //         when there are too many representatives, pad with the lowest unsampled
 //         indices when there are too few (Sec. 3.3 says the surplus or deficit has to
-//         be "resampled or cut off" without fixing how);
+//         be made up or dropped without fixing how);
 //      f. mask the picks out of R (Sec. 3.4).
 //   4. Output: the picks of all layers in ascending index order (Sec. 3.4 gathers the
 //      layer subsets; the order is this implementation's choice).
@@ -61,7 +61,7 @@ constexpr int kMaxLayers = 8;
 extern "C" {
 
 // Parameters, laid out for ctypes. Defaults: 2 layers, ratio 4, sigma 0.05,
-// t_max 20 (Sec. 4.1 "Implementation Details"; ratio from Sec. 3.4).
+// t_max 20 (the implementation details of Sec. 4.1; ratio from Sec. 3.4).
 typedef struct {
   int32_t layers;
   int32_t layer_ratio;

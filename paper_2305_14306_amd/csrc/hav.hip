@@ -45,6 +45,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
+#include <vector>
 #include <cmath>
 #include <cstring>
 
@@ -159,6 +161,7 @@ struct alignas(256) Header {
   // the pass whose candidates are published, finish and failure flags
   uint32_t sacc[2][kMaxCand][kGroups][kStride];
   uint32_t sq_ticket[kStride];
+  uint32_t sq_dgrp[kGroups][kStride];
   uint32_t sq_done[kStride];
   uint32_t sq_gen[kStride];
   uint32_t sq_fin[kStride];
@@ -396,6 +399,7 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
       for (int g = 0; g < kGroups; ++g) h->sacc[b][k][g][0] = 0;
   h->sq_ticket[0] = 0;
   h->sq_done[0] = 0;
+  for (int g = 0; g < kGroups; ++g) h->sq_dgrp[g][0] = 0;
   h->sq_gen[0] = 0;
   h->sq_fin[0] = 0;
   h->sq_err[0] = 0;
@@ -777,6 +781,7 @@ struct EvalShared {
   int ncl[kMaxCand];
   uint32_t fresh[kMaxCand];
   uint32_t box[kMaxCand][6];  // brick box: lo x,y,z, extent x,y, volume (0: hash)
+  float boxr[kMaxCand][2];    // 1 / extent x, y
   uint32_t red[kThreads / 64][6];
   uint32_t tb[6];             // tile's min (0..2) and max (3..5) offset bits per axis
 };
@@ -817,6 +822,13 @@ __device__ __forceinline__ uint32_t dense_or(unsigned long long* masks, uint32_t
   const unsigned long long old = atomicOr(&masks[slot], static_cast<unsigned long long>(bits));
   if (old == 0ull) st_agent(&list[atomicAdd(s_ncl, 1)], static_cast<int32_t>(slot));
   return static_cast<uint32_t>(__popcll(bits & ~old));
+}
+
+// a / d for a < 1024 and 1 <= d <= 1024, from r = fl(1/d): the product's error is
+// far below the 1/2048 added, and a non-multiple of d is at least 1/1024 below the
+// next integer, so the truncation is exact.
+__device__ __forceinline__ uint32_t box_div(uint32_t a, float r) {
+  return static_cast<uint32_t>(static_cast<float>(a) * r + (1.0f / 2048.0f));
 }
 
 // Issue the loads of a tile's points (thread t: the tile's points 8t..8t+7) and
@@ -893,6 +905,8 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
     sh.box[k][3] = static_cast<uint32_t>(dx);
     sh.box[k][4] = static_cast<uint32_t>(dy);
     sh.box[k][5] = vol <= static_cast<uint64_t>(kBrickCap) ? static_cast<uint32_t>(vol) : 0u;
+    sh.boxr[k][0] = 1.0f / static_cast<float>(static_cast<uint32_t>(dx));
+    sh.boxr[k][1] = 1.0f / static_cast<float>(static_cast<uint32_t>(dy));
   }
   __syncthreads();
   for (int ci = 0; ci < nc; ++ci) {
@@ -991,10 +1005,11 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
         if (!b) continue;
         lvals[e] = 0ull;
         const uint32_t bdx = sh.box[ci][3], bdy = sh.box[ci][4];
-        const uint32_t bx = sh.box[ci][0] + le % bdx;
-        const uint32_t t2 = le / bdx;
-        const uint32_t by = sh.box[ci][1] + t2 % bdy;
-        const uint32_t bz = sh.box[ci][2] + t2 / bdy;
+        const uint32_t t2 = box_div(static_cast<uint32_t>(le), sh.boxr[ci][0]);
+        const uint32_t t3 = box_div(t2, sh.boxr[ci][1]);
+        const uint32_t bx = sh.box[ci][0] + (static_cast<uint32_t>(le) - t2 * bdx);
+        const uint32_t by = sh.box[ci][1] + (t2 - t3 * bdy);
+        const uint32_t bz = sh.box[ci][2] + t3;
         key = dense ? (bx + static_cast<uint64_t>(st.cand_nb[ci][0]) *
                                 (by + static_cast<uint64_t>(st.cand_nb[ci][1]) * bz))
                     : (static_cast<uint64_t>(bx) | (static_cast<uint64_t>(by) << kBrickCoordBits) |
@@ -1137,8 +1152,18 @@ __global__ void __launch_bounds__(kThreads) k_search(Ws w, Plan P) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-      const uint32_t d = atomicAdd(&h->sq_done[0], 1u);
-      s_last = (d % static_cast<uint32_t>(ntile)) == static_cast<uint32_t>(ntile - 1);
+      // two-level completion count: a pass's tiles of group g = tile % kGroups,
+      // then the groups (every pass adds exactly gsize and ngroups)
+      const int g = tile & (kGroups - 1);
+      const uint32_t gsize = static_cast<uint32_t>((ntile - g + kGroups - 1) / kGroups);
+      const uint32_t ngroups = static_cast<uint32_t>(ntile < kGroups ? ntile : kGroups);
+      int last = 0;
+      const uint32_t d = atomicAdd(&h->sq_dgrp[g][0], 1u);
+      if (d % gsize == gsize - 1) {
+        const uint32_t e = atomicAdd(&h->sq_done[0], 1u);
+        last = (e % ngroups) == ngroups - 1;
+      }
+      s_last = last;
     }
     __syncthreads();
     if (!s_last) continue;
@@ -1939,10 +1964,46 @@ int search_grid(int ntile, int depth) {
   return std::max(1, std::min(ntile, cap));
 }
 
-#define HAV_LAUNCH(...)                                          \
-  do {                                                           \
-    hipLaunchKernelGGL(__VA_ARGS__);                             \
-    if (hipGetLastError() != hipSuccess) return HAV_ERR_HIP;     \
+// Kernel timing for measurement (hav_timing_enable): a pair of HIP events on the
+// launch stream around every launch, kept until hav_timing_collect reads them.
+struct TimedLaunch {
+  const char* name;
+  hipEvent_t e0, e1;
+};
+std::mutex g_timing_mu;
+std::atomic<int> g_timing_on{0};
+std::vector<TimedLaunch> g_timed;
+
+hipEvent_t timing_mark(hipStream_t st) {
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventRecord(e, st) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    return nullptr;
+  }
+  return e;
+}
+
+void timing_keep(const char* name, hipEvent_t e0, hipEvent_t e1) {
+  if (!e0 || !e1) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  g_timed.push_back({name, e0, e1});
+}
+
+#define HAV_LAUNCH(kern, grid, block, lds, st, ...)                              \
+  do {                                                                           \
+    const bool tm_ = g_timing_on.load(std::memory_order_relaxed) != 0;           \
+    hipEvent_t e0_ = tm_ ? timing_mark(st) : nullptr;                            \
+    hipLaunchKernelGGL(kern, grid, block, lds, st, __VA_ARGS__);                 \
+    if (hipGetLastError() != hipSuccess) {                                       \
+      if (e0_) (void)hipEventDestroy(e0_);                                       \
+      return HAV_ERR_HIP;                                                        \
+    }                                                                            \
+    if (tm_) timing_keep(#kern, e0_, timing_mark(st));                           \
   } while (0)
 
 hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_t* p, int32_t* idx,
@@ -2100,6 +2161,37 @@ hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params
   if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   return run_stage(xyz, N, M, params, idx, static_cast<char*>(ws), L, info_dev,
                    static_cast<hipStream_t>(stream));
+}
+
+hav_status_t hav_timing_enable(int32_t on) {
+  g_timing_on.store(on ? 1 : 0, std::memory_order_relaxed);
+  return HAV_OK;
+}
+
+hav_status_t hav_timing_collect(const char* kernel, int32_t* launches, double* total_ms) {
+  if (!kernel || !launches || !total_ms) return HAV_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  int32_t n = 0;
+  double ms = 0.0;
+  hav_status_t status = HAV_OK;
+  std::vector<TimedLaunch> rest;
+  for (const TimedLaunch& t : g_timed) {
+    if (std::strcmp(t.name, kernel) != 0) {
+      rest.push_back(t);
+      continue;
+    }
+    float e = 0.0f;
+    if (hipEventSynchronize(t.e1) != hipSuccess || hipEventElapsedTime(&e, t.e0, t.e1) != hipSuccess)
+      status = HAV_ERR_HIP;
+    ms += e;
+    ++n;
+    (void)hipEventDestroy(t.e0);
+    (void)hipEventDestroy(t.e1);
+  }
+  g_timed.swap(rest);
+  *launches = n;
+  *total_ms = ms;
+  return status;
 }
 
 size_t hav_chain_workspace_size(int64_t N, const int64_t* M_host, int32_t n_stages,

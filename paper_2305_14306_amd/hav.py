@@ -101,8 +101,26 @@ def lib():
         L.hav_sample_chain.restype = C.c_int
         L.hav_sample_chain.argtypes = [vp, C.c_int64, i64p, C.c_int32, C.POINTER(Params), i32p, vp,
                                        C.c_size_t, vp, vp]
+        L.hav_timing_enable.restype = C.c_int
+        L.hav_timing_enable.argtypes = [C.c_int32]
+        L.hav_timing_collect.restype = C.c_int
+        L.hav_timing_collect.argtypes = [C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         _lib = L
     return _lib
+
+
+def timing_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch with HIP events on its stream."""
+    lib().hav_timing_enable(1 if on else 0)
+
+
+def timing_collect(kernel: str):
+    """(launches, total_ms) of the kept event pairs of one kernel; waits for them."""
+    n, ms = C.c_int32(0), C.c_double(0.0)
+    st = lib().hav_timing_collect(kernel.encode(), C.byref(n), C.byref(ms))
+    if st != OK:
+        raise HavError(st, "hav_timing_collect")
+    return n.value, ms.value
 
 
 def status_string(status: int) -> str:
