@@ -110,7 +110,7 @@ hav_status_t hav_workspace_init(int64_t N, const hav_params_t* params, void* ws,
 /* Sample exactly M of the N points (Sec. 3, Eq. 3 with AVS of Sec. 3.3 and the
  * centre-closest selection of Sec. 3.2).
  *   xyz    [N][3] float32, row-major (x, y, z per point), device.
- *   N, M   1 <= M <= N < 2^31.
+ *   N, M   1 <= M <= N <= 2^30 - 1.
  *   idx    [M] int32, device: the picked indices in ascending order.
  *   ws     device workspace of ws_bytes >= hav_workspace_size(N, M, params),
  *          256-byte aligned, initialised by hav_workspace_init(N, params, ...).
@@ -135,6 +135,36 @@ size_t hav_chain_workspace_size(int64_t N, const int64_t* M_host, int32_t n_stag
 hav_status_t hav_sample_chain(const float* xyz, int64_t N, const int64_t* M_host,
                               int32_t n_stages, const hav_params_t* params, int32_t* idx_concat,
                               void* ws, size_t ws_bytes, hav_info_t* info_dev, void* stream);
+
+/* ---- Batched calls: many clouds of uneven size in one launch sequence.
+ * Every kernel of the stage runs once for the whole batch: one grid covers the tiles
+ * of all clouds, each cloud keeps its own workspace segment, voxel search controller
+ * and output, and the result of each cloud is the one hav_sample gives it alone. */
+
+/* Bytes of workspace for a batch of B clouds of N_host[i] points (M_host may be NULL
+ * when only the size is wanted; else each 1 <= M_host[i] <= N_host[i]). 0 if the
+ * arguments are invalid. 1 <= B <= 4096, 1 <= N_host[i] <= 2^30 - 1. */
+size_t hav_batch_workspace_size(int32_t B, const int64_t* N_host, const int64_t* M_host,
+                                const hav_params_t* params);
+
+/* One-time initialisation of a batch workspace for clouds of N_host[i] points (same
+ * contract as hav_workspace_init, per cloud segment). */
+hav_status_t hav_batch_workspace_init(int32_t B, const int64_t* N_host, const hav_params_t* params,
+                                      void* ws, size_t ws_bytes, void* stream);
+
+/* Sample M_host[i] of the points of each cloud i of a batch.
+ *   xyz_concat    [sum N][3] float32, device: cloud i is rows offsets_host[i] ..
+ *                 offsets_host[i+1]-1.
+ *   offsets_host  host, B+1 entries, offsets_host[0] = 0, non-decreasing.
+ *   M_host        host, B entries.
+ *   idx_concat    [sum M] int32, device: cloud i's picks as indices into cloud i
+ *                 (0-based, ascending), at offset M_host[0] + ... + M_host[i-1].
+ *   ws            initialised with hav_batch_workspace_init for the same N.
+ *   info_dev      device hav_info_t[B] or NULL. */
+hav_status_t hav_sample_batch(const float* xyz_concat, const int64_t* offsets_host,
+                              const int64_t* M_host, int32_t B, const hav_params_t* params,
+                              int32_t* idx_concat, void* ws, size_t ws_bytes, hav_info_t* info_dev,
+                              void* stream);
 
 /* Measurement support. While enabled (on != 0), every kernel launch the library makes
  * is bracketed by a pair of HIP events recorded on the call's stream; the events are

@@ -141,6 +141,8 @@ struct Plan {  // per-call constants (kernel argument)
   uint32_t cap;       // brick table slots: dense brick grids up to this size
   uint32_t sel_cap;   // voxel value slots: dense voxel grids up to this size
   float spec_mult;    // speculation budget of the search, in multiples of the window top
+  int32_t identity;   // M == N: output 0..N-1, nothing else runs
+  int32_t rounds;     // radix rounds of the trim before the bucket is settled
 };
 
 constexpr int kPubWords = static_cast<int>(sizeof(SState) / 4);
@@ -199,6 +201,10 @@ struct Ws {
   uint32_t cap_ws;
   int32_t ntile_ws, ncmax;
   int64_t tie_seg;
+  const float* xyz;              // the cloud, [n][3]
+  int32_t* idx;                  // output [M]
+  hav_info_t* info_dev;          // caller's report or null
+  int64_t M;
 };
 
 __device__ __forceinline__ unsigned long long* ctab_keys(const Ws& w, int set, int c) {
@@ -231,16 +237,80 @@ __device__ __forceinline__ int64_t logical_of(int64_t S) {
   return tile * kTile + (j % kThreads) * kPerThread + j / kThreads;
 }
 
+// ----------------------------------------------------------------------------- clouds
+
+// A cloud's device view and per-call constants. The single-cloud path passes it to
+// every kernel by value (One); the batched path (Many) gives each kernel one grid over
+// all clouds, and a block finds its cloud and its block index within that cloud's
+// share of the grid in a block map built at the start of the call.
+struct Cloud {
+  Ws w;
+  Plan P;
+};
+
+// Grid kinds: how many blocks a kernel gives a cloud of n points.
+enum Kind : int { kKBBox = 0, kKBin, kKBScan, kKTile, kKOne, kKScan, kKinds };
+
+__host__ __device__ inline int64_t blocks_of(int kind, int64_t n) {
+  switch (kind) {
+    case kKBBox: return n < 2048 ? 1 : (n + 2047) / 2048 < kMaxBBoxBlocks ? (n + 2047) / 2048 : kMaxBBoxBlocks;
+    case kKBin: return n < 4096 ? 1 : (n + 4095) / 4096 < kMaxBinBlocks ? (n + 4095) / 4096 : kMaxBinBlocks;
+    case kKBScan: return kBinChunks;
+    case kKTile: return (n + kTile - 1) / kTile;
+    case kKOne: return 1;
+    default: return (n + kScanTile - 1) / kScanTile;
+  }
+}
+
+struct BlockRef {
+  int32_t c, b, nb, pad;  // cloud, block within the cloud's grid, the cloud's grid size
+};
+
+struct alignas(256) BatchDev {
+  int32_t B;
+  int32_t depth;               // speculation depth (the same for every cloud of a call)
+  int32_t kind_off[kKinds];    // where each kind's block map starts in bmap
+  int32_t kind_total[kKinds];
+  int32_t nact;                // clouds searching in the current layer
+  int32_t pad[2];
+  Cloud* clouds;               // [B]
+  BlockRef* bmap;              // [sum of kind_total]
+  int32_t* act;                // [B] the searching clouds
+  alignas(128) uint32_t nfin[kStride];  // searching clouds that have finished
+  uint32_t err[kStride];
+};
+
+struct One {
+  Cloud c;
+};
+struct Many {
+  BatchDev* bd;
+};
+
+// The block's cloud (by reference: fields are loaded where they are used) and its
+// block index and grid size within that cloud's share of the launch.
+__device__ __forceinline__ const Cloud& cloud_of(const One& s, int, int& b, int& nb) {
+  b = blockIdx.x;
+  nb = gridDim.x;
+  return s.c;
+}
+__device__ __forceinline__ const Cloud& cloud_of(const Many& s, int kind, int& b, int& nb) {
+  const BlockRef r = s.bd->bmap[s.bd->kind_off[kind] + static_cast<int>(blockIdx.x)];
+  b = r.b;
+  nb = r.nb;
+  return s.bd->clouds[r.c];
+}
+
 // Two-level arrival: true in exactly one block, the last to arrive. Every thread
 // first waits for its own memory operations to complete, so the partial results the
 // block published with atomic RMWs are in place before the arrival is counted; the
 // last block reads them back with RMWs. Counters are left at zero.
-__device__ bool arrive_last(Header* h, int nblocks) {
+__device__ bool arrive_last(Header* h, int block, int nblocks) {
   __shared__ int s_last;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int g = blockIdx.x & (kGroups - 1);
+    const int g = block & (kGroups - 1);
     const int gsize = (nblocks - g + kGroups - 1) / kGroups;
     const int ngroups = nblocks < kGroups ? nblocks : kGroups;
     int last = 0;
@@ -414,33 +484,36 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
   } else {
     // the first pass's candidates, published for the search kernel
     c->done = 0;
-    SState s0;
-    s0.lo = 0.0f;
-    s0.hi = h->frame.hi0;
-    s0.c_hi = 0;
-    s0.evals = 0;
-    s0.done = 0;
-    s0.accepted = 0;
-    s0.set = c->set;
-    s0.prev_set = 0;
-    s0.prev_nc = 0;
-    s0.prev_hashed = 0;
-    s0.s_final = 0.0f;
-    plan_search(&s0, P, h->frame, c->upper);
-    const uint32_t* wd = reinterpret_cast<const uint32_t*>(&s0);
-    for (int i = 0; i < kPubWords; ++i) h->pub[i] = wd[i];
+    SState* s0 = reinterpret_cast<SState*>(h->pub);
+    s0->lo = 0.0f;
+    s0->hi = h->frame.hi0;
+    s0->c_hi = 0;
+    s0->evals = 0;
+    s0->done = 0;
+    s0->accepted = 0;
+    s0->set = c->set;
+    s0->prev_set = 0;
+    s0->prev_nc = 0;
+    s0->prev_hashed = 0;
+    s0->s_final = 0.0f;
+    plan_search(s0, P, h->frame, c->upper);
   }
 }
 
 // ----------------------------------------------------------------------------- frame
 
-__global__ void __launch_bounds__(kThreads) k_bbox(const float* __restrict__ xyz, Ws w) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_bbox(Src src) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKBBox, bx, gx);
+  const Ws& w = cd.w;
+  const float* __restrict__ xyz = w.xyz;
   uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
   uint32_t hi[3] = {0u, 0u, 0u};
   uint32_t bad = 0;
   const int64_t n = w.n;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads) {
+  for (int64_t i = bx * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gx) * kThreads) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const float c = xyz[3 * i + a];
@@ -451,8 +524,8 @@ __global__ void __launch_bounds__(kThreads) k_bbox(const float* __restrict__ xyz
     }
     w.tag_o[i] = 0;
   }
-  for (int64_t S = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; S < w.npad;
-       S += static_cast<int64_t>(gridDim.x) * kThreads)
+  for (int64_t S = bx * static_cast<int64_t>(kThreads) + threadIdx.x; S < w.npad;
+       S += static_cast<int64_t>(gx) * kThreads)
     w.tag_s[S] = logical_of(S) < n ? 0 : 0xFF;  // 0xFF: empty slot, never a point
   __shared__ uint32_t s_v[7][kThreads / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -473,7 +546,7 @@ __global__ void __launch_bounds__(kThreads) k_bbox(const float* __restrict__ xyz
     uint32_t v = s_v[k][0];
     for (int q = 1; q < kThreads / 64; ++q)
       v = (k < 3) ? min(v, s_v[k][q]) : ((k < 6) ? max(v, s_v[k][q]) : (v | s_v[k][q]));
-    w.part[blockIdx.x * 8 + k] = v;
+    w.part[bx * 8 + k] = v;
   }
 }
 
@@ -561,8 +634,8 @@ __device__ int frame_from_partials(const Ws& w, const Plan& P, Frame* fr, int id
   return status;
 }
 
-__device__ void publish_frame(const Ws& w, const Frame& fr) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+__device__ void publish_frame(const Ws& w, const Frame& fr, int block) {
+  if (block != 0 || threadIdx.x != 0) return;
   w.h->frame = fr;
   hav_info_t* info = &w.h->info;
   int32_t* z = reinterpret_cast<int32_t*>(info);
@@ -592,27 +665,40 @@ __device__ __forceinline__ uint32_t cell_code(float rx, float ry, float rz, cons
   return code;
 }
 
-__global__ void __launch_bounds__(kThreads) k_identity(Ws w, Plan P, int32_t* idx,
-                                                       hav_info_t* info_dev) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_identity(Src src) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKScan, bx, gx);
+  const Ws& w = cd.w;
+  const Plan& P = cd.P;
+  if (!P.identity) return;
+  int32_t* idx = w.idx;
+  hav_info_t* info_dev = w.info_dev;
   __shared__ Frame fr;
   Frame f;
   const int st = frame_from_partials(w, P, &f, 1);
   if (threadIdx.x == 0) fr = f;
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    publish_frame(w, fr);
+  if (bx == 0 && threadIdx.x == 0) {
+    publish_frame(w, fr, bx);
     if (info_dev) *info_dev = w.h->info;
   }
   if (st != HAV_OK) return;
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < w.n;
-       i += static_cast<int64_t>(gridDim.x) * kThreads)
+  for (int64_t i = bx * static_cast<int64_t>(kThreads) + threadIdx.x; i < w.n;
+       i += static_cast<int64_t>(gx) * kThreads)
     idx[i] = static_cast<int32_t>(i);
 }
 
 // ----------------------------------------------------------------------------- binning
 
-__global__ void __launch_bounds__(kThreads) k_bin_count(const float* __restrict__ xyz, Ws w,
-                                                        Plan P) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKBin, bx, gx);
+  const Ws& w = cd.w;
+  const Plan& P = cd.P;
+  if (P.identity) return;
+  const float* __restrict__ xyz = w.xyz;
   __shared__ Frame fr;
   __shared__ uint32_t hist[kBins];
   Frame f;
@@ -620,10 +706,10 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(const float* __restrict_
   if (threadIdx.x == 0) fr = f;
   for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0;
   __syncthreads();
-  publish_frame(w, fr);
+  publish_frame(w, fr, bx);
   if (st != HAV_OK) return;
   const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
-  const int64_t beg = blockIdx.x * chunk, end = min(w.n, beg + chunk);
+  const int64_t beg = bx * chunk, end = min(w.n, beg + chunk);
   for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) {
     const float rx = xyz[3 * i] - fr.mn[0];
     const float ry = xyz[3 * i + 1] - fr.mn[1];
@@ -632,21 +718,27 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(const float* __restrict_
   }
   __syncthreads();
   for (int b = threadIdx.x; b < kBins; b += kThreads)
-    w.bh[static_cast<size_t>(blockIdx.x) * kBins + b] = hist[b];
+    w.bh[static_cast<size_t>(bx) * kBins + b] = hist[b];
 }
 
 // Offsets of every (block, cell) run of the counting sort. Block c of this kernel owns
 // cells [16c, 16c+16): sixteen threads per cell scan its counts over the binning
 // blocks (a sixteenth of them each), then the block scans its cells' totals; the
 // last block scans the chunk totals and starts layer 1.
-__global__ void __launch_bounds__(kThreads) k_bin_scan(Ws w, Plan P) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_bin_scan(Src src) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKBScan, bx, gx);
+  const Ws& w = cd.w;
+  const Plan& P = cd.P;
+  if (P.identity) return;
   if (w.h->frame.status != HAV_OK) return;
   constexpr int kParts = kThreads / kBinChunk;  // 16
   __shared__ uint32_t s_tmp[kThreads / 64];
   __shared__ uint32_t s_q[kParts][kBinChunk];
   __shared__ uint32_t s_tot[kBinChunk];
   const int lb = threadIdx.x & (kBinChunk - 1);
-  const int bin = blockIdx.x * kBinChunk + lb;
+  const int bin = bx * kBinChunk + lb;
   const int q = threadIdx.x / kBinChunk;
   const int nq = (w.nbb + kParts - 1) / kParts;
   const int b0 = q * nq, b1 = min(w.nbb, b0 + nq);
@@ -671,13 +763,13 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Ws w, Plan P) {
   const uint32_t x = threadIdx.x < kBinChunk ? s_tot[threadIdx.x] : 0u;
   uint32_t ex;
   const uint32_t chunk_total = block_exclusive_scan<kThreads>(x, &ex, s_tmp);
-  if (threadIdx.x < kBinChunk) w.binpre[blockIdx.x * kBinChunk + threadIdx.x] = ex;
-  if (threadIdx.x == 0) atomicExch(&w.bsum[blockIdx.x], chunk_total);
-  if (!arrive_last(w.h, gridDim.x)) return;
-  const uint32_t y = threadIdx.x < static_cast<int>(gridDim.x) ? peek(&w.bsum[threadIdx.x]) : 0u;
+  if (threadIdx.x < kBinChunk) w.binpre[bx * kBinChunk + threadIdx.x] = ex;
+  if (threadIdx.x == 0) atomicExch(&w.bsum[bx], chunk_total);
+  if (!arrive_last(w.h, bx, gx)) return;
+  const uint32_t y = threadIdx.x < static_cast<int>(gx) ? peek(&w.bsum[threadIdx.x]) : 0u;
   uint32_t ey;
   block_exclusive_scan<kThreads>(y, &ey, s_tmp);
-  if (threadIdx.x < static_cast<int>(gridDim.x)) w.bsum[threadIdx.x] = ey;
+  if (threadIdx.x < static_cast<int>(gx)) w.bsum[threadIdx.x] = ey;
   if (threadIdx.x == 0) {
     Ctrl* c = &w.h->ctrl;
     c->set = 0;
@@ -688,16 +780,22 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Ws w, Plan P) {
   }
 }
 
-__global__ void __launch_bounds__(kThreads) k_bin_scatter(const float* __restrict__ xyz, Ws w) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKBin, bx, gx);
+  const Ws& w = cd.w;
+  if (cd.P.identity) return;
+  const float* __restrict__ xyz = w.xyz;
   if (w.h->frame.status != HAV_OK) return;
   __shared__ Frame fr;
   __shared__ uint32_t off[kBins];
   if (threadIdx.x == 0) fr = w.h->frame;
   for (int b = threadIdx.x; b < kBins; b += kThreads)
-    off[b] = w.bh[static_cast<size_t>(blockIdx.x) * kBins + b] + w.binpre[b] + w.bsum[b / kBinChunk];
+    off[b] = w.bh[static_cast<size_t>(bx) * kBins + b] + w.binpre[b] + w.bsum[b / kBinChunk];
   __syncthreads();
   const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
-  const int64_t beg = blockIdx.x * chunk, end = min(w.n, beg + chunk);
+  const int64_t beg = bx * chunk, end = min(w.n, beg + chunk);
   for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) {
     const float rx = xyz[3 * i] - fr.mn[0];
     const float ry = xyz[3 * i + 1] - fr.mn[1];
@@ -751,10 +849,15 @@ __device__ void clear_claims(const Ws& w, int set, int nc, uint32_t hashed, int 
   __syncthreads();
 }
 
-// The claims of the search's last pass, for this block's tile.
-__device__ void clear_pending(const Ws& w, const Ctrl* c) {
+// The claims of the search's last pass, for one tile.
+__device__ void clear_pending(const Ws& w, const Ctrl* c, int tile) {
   __shared__ int s_cn[kMaxCand + 1];
-  clear_claims(w, c->pend_set, c->pend_nc, c->pend_hashed, blockIdx.x, s_cn);
+  clear_claims(w, c->pend_set, c->pend_nc, c->pend_hashed, tile, s_cn);
+}
+
+// Whether a cloud has work in layer L (batched grids skip the others).
+__device__ __forceinline__ bool layer_due(const Cloud& cd, int L) {
+  return !cd.P.identity && L < cd.P.nlayers && cd.w.h->frame.status == HAV_OK;
 }
 
 // LDS insert of one (key, bits) run into a candidate's hash table, at most
@@ -1071,146 +1174,182 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
   if (threadIdx.x < nc) st_agent(claim_n(w, set, threadIdx.x, tile), static_cast<int32_t>(sh.ncl[threadIdx.x]));
 }
 
-// The adaptive voxel search of a layer (Sec. 3.3) in one launch. The passes' work
-// is a queue of tickets: ticket t is tile t % ntile of pass t / ntile. A block takes
-// a ticket, waits until that pass's candidates are published, counts the tile's
-// voxels at every candidate scale and adds them to the pass's counts; the block that
-// completes the pass's last tile runs the bisection step and publishes the next
-// pass (or the end). A block only ever waits for tiles that running blocks hold, so
-// the launch needs no co-resident grid and no kernel boundary per pass.
-__global__ void __launch_bounds__(kThreads) k_search(Ws w, Plan P) {
+// Block-shared state of the search kernels.
+struct SearchShared {
+  SState st;
+  EvalShared sh;
+  uint32_t cnt[kMaxCand];
+  int cn[kMaxCand + 1];
+  int cloud, pass, tile, go, last;
+};
+
+enum TicketResult : int { kTicketDone = 0, kTicketPublished = 1, kTicketFinished = 2 };
+
+// One ticket of a cloud's search: tile `tile` of pass `p`, whose state S.st holds and
+// whose loads are in flight in pt/tg. Clears the tile's claims of the previous pass,
+// counts the tile at the pass's candidates and adds the counts; the block that
+// completes the pass runs the bisection step and publishes the next pass
+// (kTicketPublished; S.st is then that pass's state) or the end of the search
+// (kTicketFinished; the controller and report are written for the following kernels).
+__device__ __forceinline__ int run_ticket(const Ws& w, const Plan& P, SearchShared& S,
+                                          uint64_t* lvals, uint64_t* lkeys,
+                                          float4 (&pt)[kPerThread], const uint32_t (&tg)[kPerThread],
+                                          int p, int tile) {
   Header* h = w.h;
-  if (h->frame.status != HAV_OK) return;
+  SState& st = S.st;
+  const int nc = st.nc;
+  const int ntile = w.ntile;
+  clear_claims(w, st.prev_set, st.prev_nc, st.prev_hashed, tile, S.cn);
+  if (threadIdx.x < nc) S.sh.fresh[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t live;
+  finish_tile(pt, tg, live, S.sh);
+  eval_loaded(w, tile, st, S.sh, lvals, lkeys, pt, live);
+  __syncthreads();
+  if (threadIdx.x < nc && S.sh.fresh[threadIdx.x])
+    atomicAdd(&h->sacc[p & 1][threadIdx.x][tile & (kGroups - 1)][0], S.sh.fresh[threadIdx.x]);
+  // this tile's clears, table updates and counts are complete before it counts as done
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // two-level completion count: a pass's tiles of group g = tile % kGroups, then the
+    // groups (every pass adds exactly gsize and ngroups)
+    const int g = tile & (kGroups - 1);
+    const uint32_t gsize = static_cast<uint32_t>((ntile - g + kGroups - 1) / kGroups);
+    const uint32_t ngroups = static_cast<uint32_t>(ntile < kGroups ? ntile : kGroups);
+    int last = 0;
+    const uint32_t d = atomicAdd(&h->sq_dgrp[g][0], 1u);
+    if (d % gsize == gsize - 1) {
+      const uint32_t e = atomicAdd(&h->sq_done[0], 1u);
+      last = (e % ngroups) == ngroups - 1;
+    }
+    S.last = last;
+  }
+  __syncthreads();
+  if (!S.last) return kTicketDone;
+  // ---- last tile of pass p: bisection step, then publish pass p + 1 or the end
+  if (threadIdx.x < nc) S.cnt[threadIdx.x] = 0;
+  __syncthreads();
+  if (threadIdx.x < nc * kGroups) {
+    const uint32_t v = atomicExch(&h->sacc[p & 1][threadIdx.x / kGroups][threadIdx.x % kGroups][0], 0u);
+    if (v) atomicAdd(&S.cnt[threadIdx.x / kGroups], v);
+  }
+  __syncthreads();
   Ctrl* c = &h->ctrl;
-  if (c->done) return;  // fixed voxel size: no search
-  extern __shared__ uint64_t lds[];
-  __shared__ SState st;
-  __shared__ EvalShared sh;
-  __shared__ uint32_t s_cnt[kMaxCand];
-  __shared__ int s_cn[kMaxCand + 1];
-  __shared__ int s_tile, s_pass, s_go, s_last;
-  const int ncap = (1 << P.depth) - 1;
-  uint64_t* lvals = lds;
-  uint64_t* lkeys = lds + static_cast<size_t>(ncap) * kBrickCap;
+  if (threadIdx.x == 0) search_step(&st, S.cnt, P, h->frame, c->m, c->upper);
+  __syncthreads();
+  if (st.done) {
+    if (threadIdx.x == 0) {
+      c->evals = st.evals;
+      c->accepted = st.accepted;
+      c->lo = st.lo;
+      c->hi = st.hi;
+      c->done = 1;
+      c->set = st.set;
+      c->pend_set = st.prev_set;
+      c->pend_nc = st.prev_nc;
+      c->pend_hashed = st.prev_hashed;
+      set_final(c, st.s_final, P, h->frame);
+      const int Lc = c->layer;
+      h->info.evals[Lc] = st.evals;
+      h->info.accepted[Lc] = st.accepted;
+      h->info.s[Lc] = st.s_final;
+      atomicExch(&h->sq_fin[0], 1u);
+    }
+    __syncthreads();
+    return kTicketFinished;
+  }
+  if (threadIdx.x < kPubWords)
+    st_agent(&h->pub[threadIdx.x], reinterpret_cast<const uint32_t*>(&st)[threadIdx.x]);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicExch(&h->sq_gen[0], static_cast<uint32_t>(p + 1));
+  return kTicketPublished;
+}
+
+// Wait (thread 0) until pass p of the cloud behind `h` is published. 1: go on; 0: the
+// cloud's search has ended (drop the ticket); -1: a wait gave up (error flag raised).
+__device__ int wait_pass(Header* h, int p, uint32_t* err) {
+  uint32_t spins = 0;
+  while (ld_agent(&h->sq_gen[0]) < static_cast<uint32_t>(p)) {
+    if (ld_agent(&h->sq_fin[0])) return 0;
+    if (ld_agent(&h->sq_err[0]) || (err && ld_agent(err))) return -1;
+    if (++spins > kSpinLimit) {
+      atomicOr(&h->sq_err[0], 1u);
+      if (err) atomicOr(err, 1u);
+      return -1;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return 1;
+}
+
+__device__ __forceinline__ void search_lds_init(uint64_t* lds, int depth, uint64_t*& lvals,
+                                                uint64_t*& lkeys) {
+  const int ncap = (1 << depth) - 1;
+  lvals = lds;
+  lkeys = lds + static_cast<size_t>(ncap) * kBrickCap;
   for (int e = threadIdx.x; e < ncap * kBrickCap; e += kThreads) {
     lvals[e] = 0ull;
     lkeys[e] = kEmptyKey;
   }
-  const uint32_t m = c->m, upper = c->upper;
-  const Frame fr = h->frame;
+}
+
+// A wait gave up: tables may hold claims nobody cleared, so the workspace needs
+// hav_workspace_init again.
+__device__ void mark_search_failed(Header* h) {
+  h->frame.status = HAV_ERR_HIP;
+  h->info.status = HAV_ERR_HIP;
+  h->magic = 0;
+}
+
+// The adaptive voxel search of a layer (Sec. 3.3) in one launch. The passes' work is
+// a queue of tickets: ticket t is tile t % ntile of pass t / ntile. A block takes a
+// ticket, waits until that pass's candidates are published and runs it (run_ticket).
+// A block only ever waits for tiles that running blocks hold, so the launch needs no
+// co-resident grid and no kernel boundary per pass.
+__global__ void __launch_bounds__(kThreads) k_search(One src, int L) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKTile, bx, gx);
+  if (!layer_due(cd, L)) return;
+  const Ws& w = cd.w;
+  const Plan& P = cd.P;
+  Header* h = w.h;
+  if (h->ctrl.done) return;  // fixed voxel size: no search
+  extern __shared__ uint64_t lds[];
+  __shared__ SearchShared S;
+  uint64_t *lvals, *lkeys;
+  search_lds_init(lds, P.depth, lvals, lkeys);
   const int ntile = w.ntile;
-  int cur = -1;  // pass whose state st holds
+  int cur = -1;  // pass whose state S.st holds
   float4 pt[kPerThread];
-  uint32_t live;
   while (true) {
+    __syncthreads();  // every thread has read the previous ticket's shared fields
     if (threadIdx.x == 0) {
       const uint32_t t = atomicAdd(&h->sq_ticket[0], 1u);
       const int p = static_cast<int>(t / static_cast<uint32_t>(ntile));
-      int go = p < P.t_max;  // every pass makes at least one evaluation
-      if (go && p != cur) {
-        uint32_t spins = 0;
-        while (ld_agent(&h->sq_gen[0]) < static_cast<uint32_t>(p)) {
-          if (ld_agent(&h->sq_fin[0]) || ld_agent(&h->sq_err[0])) {
-            go = 0;
-            break;
-          }
-          if (++spins > kSpinLimit) {
-            atomicOr(&h->sq_err[0], 1u);
-            go = 0;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
-        }
-      }
-      s_pass = p;
-      s_tile = static_cast<int>(t - static_cast<uint32_t>(p) * static_cast<uint32_t>(ntile));
-      s_go = go;
+      S.pass = p;
+      S.tile = static_cast<int>(t - static_cast<uint32_t>(p) * static_cast<uint32_t>(ntile));
     }
     __syncthreads();
-    if (!s_go) break;
-    const int p = s_pass, tile = s_tile;
+    const int p = S.pass, tile = S.tile;
+    if (p >= P.t_max) break;  // every pass makes at least one evaluation
     uint32_t tg[kPerThread];
-    issue_tile(w, tile, pt, tg);  // in flight while the state and claims are read
+    issue_tile(w, tile, pt, tg);  // in flight during the wait and the state and claim reads
     if (p != cur) {
-      if (threadIdx.x < kPubWords)
-        reinterpret_cast<uint32_t*>(&st)[threadIdx.x] = ld_agent(&h->pub[threadIdx.x]);
+      if (threadIdx.x == 0) S.go = wait_pass(h, p, nullptr);
       __syncthreads();
-      if (st.done) break;  // the search ended with the previous pass
+      if (S.go <= 0) break;
+      if (threadIdx.x < kPubWords)
+        reinterpret_cast<uint32_t*>(&S.st)[threadIdx.x] = ld_agent(&h->pub[threadIdx.x]);
+      __syncthreads();
       cur = p;
     }
-    const int nc = st.nc;
-    // empty the words this tile claimed in the previous pass (the other table set)
-    clear_claims(w, st.prev_set, st.prev_nc, st.prev_hashed, tile, s_cn);
-    if (threadIdx.x < nc) sh.fresh[threadIdx.x] = 0;
-    __syncthreads();
-    finish_tile(pt, tg, live, sh);
-    eval_loaded(w, tile, st, sh, lvals, lkeys, pt, live);
-    __syncthreads();
-    if (threadIdx.x < nc && sh.fresh[threadIdx.x])
-      atomicAdd(&h->sacc[p & 1][threadIdx.x][tile & (kGroups - 1)][0], sh.fresh[threadIdx.x]);
-    // this tile's clears, table updates and counts are complete before it counts as done
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      // two-level completion count: a pass's tiles of group g = tile % kGroups,
-      // then the groups (every pass adds exactly gsize and ngroups)
-      const int g = tile & (kGroups - 1);
-      const uint32_t gsize = static_cast<uint32_t>((ntile - g + kGroups - 1) / kGroups);
-      const uint32_t ngroups = static_cast<uint32_t>(ntile < kGroups ? ntile : kGroups);
-      int last = 0;
-      const uint32_t d = atomicAdd(&h->sq_dgrp[g][0], 1u);
-      if (d % gsize == gsize - 1) {
-        const uint32_t e = atomicAdd(&h->sq_done[0], 1u);
-        last = (e % ngroups) == ngroups - 1;
-      }
-      s_last = last;
-    }
-    __syncthreads();
-    if (!s_last) continue;
-    // ---- last tile of pass p: bisection step, then publish pass p + 1 or the end
-    if (threadIdx.x < nc) s_cnt[threadIdx.x] = 0;
-    __syncthreads();
-    if (threadIdx.x < nc * kGroups) {
-      const uint32_t v = atomicExch(&h->sacc[p & 1][threadIdx.x / kGroups][threadIdx.x % kGroups][0], 0u);
-      if (v) atomicAdd(&s_cnt[threadIdx.x / kGroups], v);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) search_step(&st, s_cnt, P, fr, m, upper);
-    __syncthreads();
-    if (st.done) {
-      if (threadIdx.x == 0) {
-        c->evals = st.evals;
-        c->accepted = st.accepted;
-        c->lo = st.lo;
-        c->hi = st.hi;
-        c->done = 1;
-        c->set = st.set;
-        c->pend_set = st.prev_set;
-        c->pend_nc = st.prev_nc;
-        c->pend_hashed = st.prev_hashed;
-        set_final(c, st.s_final, P, fr);
-        const int L = c->layer;
-        h->info.evals[L] = st.evals;
-        h->info.accepted[L] = st.accepted;
-        h->info.s[L] = st.s_final;
-        atomicExch(&h->sq_fin[0], 1u);
-      }
-      break;
-    }
-    if (threadIdx.x < kPubWords)
-      st_agent(&h->pub[threadIdx.x], reinterpret_cast<const uint32_t*>(&st)[threadIdx.x]);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) atomicExch(&h->sq_gen[0], static_cast<uint32_t>(p + 1));
-    cur = p + 1;
+    const int r = run_ticket(w, P, S, lvals, lkeys, pt, tg, p, tile);
+    if (r == kTicketFinished) break;
+    if (r == kTicketPublished) cur = p + 1;
   }
-  if (threadIdx.x == 0 && ld_agent(&h->sq_err[0])) {
-    // a wait gave up: tables may hold claims nobody cleared, so the workspace needs
-    // hav_workspace_init again
-    h->frame.status = HAV_ERR_HIP;
-    h->info.status = HAV_ERR_HIP;
-    h->magic = 0;
-  }
+  if (threadIdx.x == 0 && ld_agent(&h->sq_err[0])) mark_search_failed(h);
 }
 
 // ----------------------------------------------------------------------------- select
@@ -1274,12 +1413,16 @@ __device__ __forceinline__ void select_global(const Ws& w, int dense, uint64_t k
 // Centre-closest point of every occupied voxel at the chosen size (Sec. 3.2): the
 // tile's minimum of (bits(d^2) << 32 | index) per voxel in LDS (a dense box array
 // when the tile's voxels fit one), then one global atomicMin per voxel of the tile.
-__global__ void __launch_bounds__(kThreads) k_select(Ws w) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKTile, bx, gx);
+  if (!layer_due(cd, L)) return;
+  const Ws& w = cd.w;
   Header* h = w.h;
-  if (h->frame.status != HAV_OK) return;
   Ctrl* c = &h->ctrl;
-  const int tile = blockIdx.x;
-  clear_pending(w, c);
+  const int tile = bx;
+  clear_pending(w, c, tile);
   extern __shared__ uint64_t lds[];
   uint64_t* lvals = lds;
   uint64_t* lkeys = lds + kLdsCap;
@@ -1399,7 +1542,7 @@ __global__ void __launch_bounds__(kThreads) k_select(Ws w) {
     w.scn[tile] = s_ncl;
     if (s_ncl) atomicAdd(&h->acc[0][tile & (kGroups - 1)][0], static_cast<uint32_t>(s_ncl));
   }
-  if (!arrive_last(h, gridDim.x)) return;
+  if (!arrive_last(h, bx, gx)) return;
   __shared__ uint32_t s_nvox;
   if (threadIdx.x == 0) s_nvox = 0;
   __syncthreads();
@@ -1417,11 +1560,11 @@ __global__ void __launch_bounds__(kThreads) k_select(Ws w) {
   c->prefix = 0;
   c->rank = c->m - 1;
   c->rounds_done = 0;
-  const int L = c->layer;
-  h->info.count[L] = static_cast<int32_t>(nvox);
-  h->info.trimmed[L] = nvox > c->m ? static_cast<int32_t>(nvox - c->m) : 0;
-  h->info.padded[L] = static_cast<int32_t>(c->need);
-  h->info.s[L] = c->s_final;
+  const int Lc = c->layer;
+  h->info.count[Lc] = static_cast<int32_t>(nvox);
+  h->info.trimmed[Lc] = nvox > c->m ? static_cast<int32_t>(nvox - c->m) : 0;
+  h->info.padded[Lc] = static_cast<int32_t>(c->need);
+  h->info.s[Lc] = c->s_final;
 }
 
 // ----------------------------------------------------------------------------- trim
@@ -1449,15 +1592,19 @@ __device__ void find_digit(const uint32_t* hist, uint32_t rank, int* digit, uint
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kThreads) k_trim_hist(Ws w, int round) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_trim_hist(Src src, int L, int round) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKTile, bx, gx);
+  if (!layer_due(cd, L) || round >= cd.P.rounds) return;
+  const Ws& w = cd.w;
   Header* h = w.h;
-  if (h->frame.status != HAV_OK) return;
   Ctrl* c = &h->ctrl;
   if (!c->trim) return;
   __shared__ uint32_t lh[256];
   for (int i = threadIdx.x; i < 256; i += kThreads) lh[i] = 0;
   __syncthreads();
-  const int tile = blockIdx.x;
+  const int tile = bx;
   const int n = w.scn[tile];
   const int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
   const int dshift = 56 - 8 * round;
@@ -1471,7 +1618,7 @@ __global__ void __launch_bounds__(kThreads) k_trim_hist(Ws w, int round) {
   const int g = tile & (kGroups - 1);
   for (int i = threadIdx.x; i < 256; i += kThreads)
     if (lh[i]) atomicAdd(&h->hist[g][i], lh[i]);
-  if (!arrive_last(h, gridDim.x)) return;
+  if (!arrive_last(h, bx, gx)) return;
   // last block: total histogram, pick the digit holding rank
   __shared__ uint32_t tot[256];
   for (int i = threadIdx.x; i < 256; i += kThreads) {
@@ -1492,11 +1639,15 @@ __global__ void __launch_bounds__(kThreads) k_trim_hist(Ws w, int round) {
 
 // Keep the representatives below the prefix bucket, queue the bucket's members for
 // k_ties, and empty the selection table.
-__global__ void __launch_bounds__(kThreads) k_mark(Ws w) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKTile, bx, gx);
+  if (!layer_due(cd, L)) return;
+  const Ws& w = cd.w;
   Header* h = w.h;
-  if (h->frame.status != HAV_OK) return;
   const Ctrl* c = &h->ctrl;
-  const int tile = blockIdx.x;
+  const int tile = bx;
   const int n = w.scn[tile];
   const int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
   const int trim = c->trim;
@@ -1562,9 +1713,13 @@ __global__ void __launch_bounds__(kThreads) k_mark(Ws w) {
 // staged in LDS when it fits (it normally holds a handful of voxels).
 constexpr int kTieLds = 4096;
 
-__global__ void __launch_bounds__(kThreads) k_ties(Ws w) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_ties(Src src, int L) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKOne, bx, gx);
+  if (!layer_due(cd, L)) return;
+  const Ws& w = cd.w;
   Header* h = w.h;
-  if (h->frame.status != HAV_OK) return;
   Ctrl* c = &h->ctrl;
   __shared__ uint32_t cnt_g[kGroups + 1];  // exclusive prefix over groups
   __shared__ uint32_t hst[256];
@@ -1641,12 +1796,16 @@ __global__ void __launch_bounds__(kThreads) k_ties(Ws w) {
 // ----------------------------------------------------------------------------- scans over tag_o
 
 // mode 0: pad (count tag_o == 0), only when the layer is short; mode 1: output.
-__global__ void __launch_bounds__(kThreads) k_scan_count(Ws w, int mode) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_scan_count(Src src, int L, int mode) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKScan, bx, gx);
+  const Ws& w = cd.w;
   Header* h = w.h;
-  if (h->frame.status != HAV_OK) return;
-  if (mode == 0 && h->ctrl.need == 0) return;
+  if (cd.P.identity || h->frame.status != HAV_OK) return;
+  if (mode == 0 && (L >= cd.P.nlayers || h->ctrl.need == 0)) return;
   __shared__ uint32_t s_tmp[kThreads / 64];
-  const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
+  const int64_t base = bx * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
   uint32_t cnt = 0;
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
@@ -1656,32 +1815,37 @@ __global__ void __launch_bounds__(kThreads) k_scan_count(Ws w, int mode) {
     }
   }
   const uint32_t tot = block_sum_u32<kThreads>(cnt, s_tmp);
-  if (threadIdx.x == 0) atomicExch(&w.tcnt[blockIdx.x], tot);
-  if (!arrive_last(h, gridDim.x)) return;
+  if (threadIdx.x == 0) atomicExch(&w.tcnt[bx], tot);
+  if (!arrive_last(h, bx, gx)) return;
   // last block: exclusive scan of the tile counts
   uint32_t carry = 0;
-  for (int b0 = 0; b0 < static_cast<int>(gridDim.x); b0 += kThreads) {
+  for (int b0 = 0; b0 < static_cast<int>(gx); b0 += kThreads) {
     const int b = b0 + threadIdx.x;
-    const uint32_t v = b < static_cast<int>(gridDim.x) ? peek(&w.tcnt[b]) : 0u;
+    const uint32_t v = b < static_cast<int>(gx) ? peek(&w.tcnt[b]) : 0u;
     uint32_t ex;
     const uint32_t t = block_exclusive_scan<kThreads>(v, &ex, s_tmp);
-    if (b < static_cast<int>(gridDim.x)) w.tcnt[b] = carry + ex;
+    if (b < static_cast<int>(gx)) w.tcnt[b] = carry + ex;
     carry += t;
     __syncthreads();
   }
 }
 
 // Pad: mark the lowest-index unsampled points; then start the next layer.
-__global__ void __launch_bounds__(kThreads) k_pad_mark(Ws w, Plan P) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_pad_mark(Src src, int Lc) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKScan, bx, gx);
+  if (!layer_due(cd, Lc)) return;
+  const Ws& w = cd.w;
+  const Plan& P = cd.P;
   Header* h = w.h;
-  if (h->frame.status != HAV_OK) return;
   Ctrl* c = &h->ctrl;
   const uint32_t need = c->need;
   const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
   const int L = c->layer;
   if (need > 0) {
     __shared__ uint32_t s_tmp[kThreads / 64];
-    const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
+    const int64_t base = bx * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
     uint8_t t[kScanPer];
     uint32_t cnt = 0;
 #pragma unroll
@@ -1691,7 +1855,7 @@ __global__ void __launch_bounds__(kThreads) k_pad_mark(Ws w, Plan P) {
     }
     uint32_t ex;
     block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
-    uint32_t r = w.tcnt[blockIdx.x] + ex;
+    uint32_t r = w.tcnt[bx] + ex;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       if (t[k] == 0) {
@@ -1703,17 +1867,23 @@ __global__ void __launch_bounds__(kThreads) k_pad_mark(Ws w, Plan P) {
       }
     }
   }
-  if (!arrive_last(h, gridDim.x)) return;
+  if (!arrive_last(h, bx, gx)) return;
   if (threadIdx.x == 0 && L + 1 < P.nlayers) layer_init(h, P, L + 1);
 }
 
-__global__ void __launch_bounds__(kThreads) k_out_write(Ws w, int32_t* idx, int64_t M,
-                                                        hav_info_t* info_dev) {
+template <class Src>
+__global__ void __launch_bounds__(kThreads) k_out_write(Src src) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKScan, bx, gx);
+  const Ws& w = cd.w;
+  if (cd.P.identity) return;
   Header* h = w.h;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && info_dev) *info_dev = h->info;
+  int32_t* idx = w.idx;
+  const int64_t M = w.M;
+  if (bx == 0 && threadIdx.x == 0 && w.info_dev) *w.info_dev = h->info;
   if (h->frame.status != HAV_OK) return;
   __shared__ uint32_t s_tmp[kThreads / 64];
-  const int64_t base = blockIdx.x * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
+  const int64_t base = bx * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
   uint8_t t[kScanPer];
   uint32_t cnt = 0;
 #pragma unroll
@@ -1723,7 +1893,7 @@ __global__ void __launch_bounds__(kThreads) k_out_write(Ws w, int32_t* idx, int6
   }
   uint32_t ex;
   block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
-  uint32_t r = w.tcnt[blockIdx.x] + ex;
+  uint32_t r = w.tcnt[bx] + ex;
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
     if (t[k]) {
@@ -1785,23 +1955,16 @@ __global__ void __launch_bounds__(kThreads) k_compose(const int32_t* __restrict_
 // ============================================================================ host side
 
 constexpr size_t kAlign = 256;
-size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+__host__ __device__ inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 int depth_of(const hav_params_t* p) {
   return p->spec_depth == 0 ? kDefaultDepth : p->spec_depth;
 }
 
-uint32_t table_cap(int64_t n) {
+__host__ __device__ inline uint32_t table_cap(int64_t n) {
   uint64_t cap = 1024;
   while (cap < 2 * static_cast<uint64_t>(n)) cap <<= 1;
   return static_cast<uint32_t>(cap);
-}
-
-int bbox_blocks(int64_t n) {
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kMaxBBoxBlocks, (n + 2047) / 2048)));
-}
-int bin_blocks(int64_t n) {
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kMaxBinBlocks, (n + 4095) / 4096)));
 }
 
 struct Layout {
@@ -1813,7 +1976,7 @@ struct Layout {
   int64_t tie_seg;
 };
 
-Layout make_layout(int64_t n, int depth) {
+__host__ __device__ inline Layout make_layout(int64_t n, int depth) {
   Layout L;
   L.n_ws = n;
   L.cap_ws = table_cap(n);
@@ -1850,12 +2013,12 @@ Layout make_layout(int64_t n, int depth) {
   return L;
 }
 
-uint64_t magic_of(const Layout& L) {
+__host__ __device__ inline uint64_t magic_of(const Layout& L) {
   return kMagic ^ (static_cast<uint64_t>(L.n_ws) << 8) ^ (static_cast<uint64_t>(L.ncmax) << 56);
 }
 
 // Device view of the workspace for a stage of n points (n <= the workspace's size).
-Ws make_ws(char* base, const Layout& L, int64_t n) {
+__host__ __device__ inline Ws make_ws(char* base, const Layout& L, int64_t n) {
   Ws w;
   w.h = reinterpret_cast<Header*>(base + L.hdr);
   w.pts = reinterpret_cast<float4*>(base + L.pts);
@@ -1882,14 +2045,18 @@ Ws make_ws(char* base, const Layout& L, int64_t n) {
   w.ntile = static_cast<int32_t>((n + kTile - 1) / kTile);
   w.npad = static_cast<int64_t>(w.ntile) * kTile;
   w.nscan = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
-  w.nbb = bin_blocks(n);
-  w.nbbox = bbox_blocks(n);
+  w.nbb = static_cast<int32_t>(blocks_of(kKBin, n));
+  w.nbbox = static_cast<int32_t>(blocks_of(kKBBox, n));
   w.cap = table_cap(n);
   w.cmask = w.cap - 1;
   w.cap_ws = L.cap_ws;
   w.ntile_ws = L.ntile_ws;
   w.ncmax = L.ncmax;
   w.tie_seg = L.tie_seg;
+  w.xyz = nullptr;
+  w.idx = nullptr;
+  w.info_dev = nullptr;
+  w.M = 0;
   return w;
 }
 
@@ -1913,7 +2080,7 @@ bool params_ok(const hav_params_t* p) {
 }
 
 // m_l = M r^(l-1) (r-1) / (r^k - 1), floored for l < k; the last layer takes the rest.
-void layer_sizes(int64_t M, int k, int r, int64_t* m) {
+__host__ __device__ inline void layer_sizes(int64_t M, int k, int r, int64_t* m) {
   uint64_t rk = 1;
   for (int l = 0; l < k; ++l) rk *= static_cast<uint64_t>(r);
   uint64_t rl = 1;
@@ -1926,38 +2093,300 @@ void layer_sizes(int64_t M, int k, int r, int64_t* m) {
   m[k - 1] = M - used;
 }
 
-int grid_for(int64_t work) {
-  const int64_t g = (work + kThreads - 1) / kThreads;
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, 4096)));
-}
-
 // Radix rounds over the top priority bits before one block settles the bucket:
 // enough that the expected bucket (n / 256^R) stays small.
-int trim_rounds(int64_t n) {
+__host__ __device__ inline int trim_rounds(int64_t n) {
   int R = 1;
   while (R < 7 && (n >> (8 * R)) > 2048) ++R;
   return R;
 }
 
-// Blocks of the search launch: one per tile, at most as many as the device holds at
-// once (more would only wait for tickets). The limit is cached per device and depth.
-int search_grid(int ntile, int depth) {
-  static std::atomic<int> cache[kMaxDevices][kMaxDepth + 1];
+// The sampling parameters a plan needs (plain values, so a kernel can take them).
+struct ParamLite {
+  int32_t layers, ratio, t_max, depth, fixed;
+  double sigma;
+  float aspect[3], fixed_v[3];
+};
+
+ParamLite lite_of(const hav_params_t* p) {
+  ParamLite q;
+  q.layers = p->layers;
+  q.ratio = p->layer_ratio;
+  q.t_max = p->t_max;
+  q.depth = depth_of(p);
+  q.fixed = (p->flags & HAV_FIXED_VOXEL) ? 1 : 0;
+  q.sigma = p->sigma;
+  for (int a = 0; a < 3; ++a) {
+    q.aspect[a] = p->aspect[a];
+    q.fixed_v[a] = p->fixed_voxel[a];
+  }
+  return q;
+}
+
+// One cloud of a call: input, output, report and its workspace segment (laid out for
+// n_cap >= n points).
+struct CloudSpec {
+  const float* xyz;
+  int32_t* idx;
+  hav_info_t* info;
+  char* seg;
+  int64_t n, m, n_cap;
+};
+
+__host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite& q) {
+  Cloud cd;
+  const Layout L = make_layout(c.n_cap, q.depth);
+  cd.w = make_ws(c.seg, L, c.n);
+  cd.w.xyz = c.xyz;
+  cd.w.idx = c.idx;
+  cd.w.info_dev = c.info;
+  cd.w.M = c.m;
+  Plan& P = cd.P;
+  P.t_max = q.t_max;
+  P.depth = q.depth;
+  P.fixed = q.fixed;
+  P.magic = magic_of(L);
+  P.cap = cd.w.cap;
+  P.sel_cap = cd.w.cap * static_cast<uint32_t>(kSelDense);
+  P.spec_mult = kSpecMult;
+  P.identity = c.m == c.n ? 1 : 0;
+  P.rounds = trim_rounds(c.n);
+  for (int a = 0; a < 3; ++a) {
+    P.aspect[a] = q.aspect[a];
+    P.fixed_v[a] = q.fixed_v[a];
+  }
+  int64_t m[HAV_MAX_LAYERS];
+  layer_sizes(c.m, q.layers, q.ratio, m);
+  int nl = 0;
+  for (int l = 0; l < HAV_MAX_LAYERS; ++l) {
+    P.m[l] = 0;
+    P.upper[l] = 0;
+  }
+  for (int l = 0; l < q.layers; ++l) {
+    if (m[l] == 0) continue;
+    const double up = floor(static_cast<double>(m[l]) * (1.0 + q.sigma));
+    P.m[nl] = static_cast<uint32_t>(m[l]);
+    P.upper[nl] = up >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(up);
+    ++nl;
+  }
+  P.nlayers = nl;
+  return cd;
+}
+
+// ----------------------------------------------------------------------------- batched calls
+
+// Kernel arguments of k_setup: up to kSetupChunk clouds of a call.
+constexpr int kSetupChunk = 32;
+struct SetupArgs {
+  BatchDev* bd;
+  Cloud* clouds;
+  BlockRef* bmap;
+  int32_t* act;
+  ParamLite q;
+  int32_t B, first, count;
+  int32_t kind_off[kKinds], kind_total[kKinds];
+  CloudSpec cl[kSetupChunk];
+};
+
+// Every cloud's device view, and (first chunk) the batch header.
+__global__ void __launch_bounds__(64) k_setup(SetupArgs a) {
+  const int i = threadIdx.x;
+  if (i < a.count) a.clouds[a.first + i] = make_cloud(a.cl[i], a.q);
+  if (a.first == 0 && i == 0) {
+    BatchDev* bd = a.bd;
+    bd->B = a.B;
+    bd->depth = a.q.depth;
+    for (int k = 0; k < kKinds; ++k) {
+      bd->kind_off[k] = a.kind_off[k];
+      bd->kind_total[k] = a.kind_total[k];
+    }
+    bd->nact = 0;
+    bd->clouds = a.clouds;
+    bd->bmap = a.bmap;
+    bd->act = a.act;
+    bd->nfin[0] = 0;
+    bd->err[0] = 0;
+  }
+}
+
+// Block map of every grid kind (block k of this kernel builds kind k): for each cloud
+// in order, its blocks (cloud, block within the cloud, the cloud's block count).
+__global__ void __launch_bounds__(kThreads) k_map(BatchDev* bd) {
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  const int kind = blockIdx.x;
+  const int B = bd->B;
+  BlockRef* out = bd->bmap + bd->kind_off[kind];
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < B; c0 += kThreads) {
+    const int c = c0 + threadIdx.x;
+    const uint32_t nb = c < B ? static_cast<uint32_t>(blocks_of(kind, bd->clouds[c].w.n)) : 0u;
+    uint32_t ex;
+    const uint32_t tot = block_exclusive_scan<kThreads>(nb, &ex, s_tmp);
+    for (uint32_t b = 0; b < nb; ++b) {
+      BlockRef r;
+      r.c = c;
+      r.b = static_cast<int32_t>(b);
+      r.nb = static_cast<int32_t>(nb);
+      r.pad = 0;
+      out[carry + ex + b] = r;
+    }
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+// The clouds that search in layer L (in cloud order), and the batch's search counters.
+__global__ void __launch_bounds__(kThreads) k_search_prep(Many src, int L) {
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  BatchDev* bd = src.bd;
+  const int B = bd->B;
+  uint32_t carry = 0;
+  for (int c0 = 0; c0 < B; c0 += kThreads) {
+    const int c = c0 + threadIdx.x;
+    uint32_t on = 0;
+    if (c < B) {
+      const Cloud& cd = bd->clouds[c];
+      on = layer_due(cd, L) && !cd.P.fixed ? 1u : 0u;
+    }
+    uint32_t ex;
+    const uint32_t tot = block_exclusive_scan<kThreads>(on, &ex, s_tmp);
+    if (on) bd->act[carry + ex] = c;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    bd->nact = static_cast<int32_t>(carry);
+    bd->nfin[0] = 0;
+    bd->err[0] = 0;
+  }
+}
+
+// The voxel searches of every cloud of a batch in one launch. Each cloud keeps its
+// own ticket queue and controller (as in k_search). A block picks, among the searching
+// clouds (starting from a rotating position), one whose current pass still has tiles
+// to hand out, takes a ticket there and runs it. Waits are only for tiles that running
+// blocks hold, so any grid size makes progress.
+__global__ void __launch_bounds__(kThreads) k_search_many(Many src, int L) {
+  BatchDev* bd = src.bd;
+  const int nact = bd->nact;
+  if (nact == 0) return;
+  extern __shared__ uint64_t lds[];
+  __shared__ SearchShared S;
+  uint64_t *lvals, *lkeys;
+  search_lds_init(lds, bd->depth, lvals, lkeys);
+  int cur_c = -1, cur_p = -1;  // cloud and pass whose state S.st holds
+  int start = static_cast<int>(blockIdx.x) % nact;
+  float4 pt[kPerThread];
+  while (true) {
+    __syncthreads();  // every thread has read the previous ticket's shared fields
+    if (threadIdx.x < 64) {
+      // wave 0: lane k looks at searching cloud start + k (+ 64 j)
+      const int lane = threadIdx.x;
+      uint32_t spins = 0;
+      while (true) {
+        int pick = -1;
+        for (int base = 0; base < nact && pick < 0; base += 64) {
+          const int k = base + lane;
+          int c = -1;
+          bool avail = false;
+          if (k < nact) {
+            c = bd->act[(start + k) % nact];
+            Header* hc = bd->clouds[c].w.h;
+            const uint32_t nt = static_cast<uint32_t>(bd->clouds[c].w.ntile);
+            const uint32_t gen = ld_agent(&hc->sq_gen[0]);
+            const uint32_t tk = ld_agent(&hc->sq_ticket[0]);
+            const uint32_t fin = ld_agent(&hc->sq_fin[0]);
+            avail = !fin && tk < (gen + 1) * nt;
+          }
+          const uint64_t bal = __ballot(avail);
+          if (bal) pick = __shfl(c, static_cast<int>(__ffsll(static_cast<long long>(bal)) - 1), 64);
+        }
+        if (pick >= 0) {
+          if (lane == 0) {
+            Header* hc = bd->clouds[pick].w.h;
+            const uint32_t nt = static_cast<uint32_t>(bd->clouds[pick].w.ntile);
+            const uint32_t t = atomicAdd(&hc->sq_ticket[0], 1u);
+            S.cloud = pick;
+            S.pass = static_cast<int>(t / nt);
+            S.tile = static_cast<int>(t % nt);
+            S.go = 1;
+          }
+          break;
+        }
+        if (ld_agent(&bd->nfin[0]) >= static_cast<uint32_t>(nact) || ld_agent(&bd->err[0])) {
+          if (lane == 0) S.go = 0;
+          break;
+        }
+        if (++spins > kSpinLimit) {
+          if (lane == 0) {
+            atomicOr(&bd->err[0], 1u);
+            S.go = 0;
+          }
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __syncthreads();
+    if (!S.go) break;
+    const int c = S.cloud, p = S.pass, tile = S.tile;
+    start = (start + 1) % nact;
+    const Cloud& cd = bd->clouds[c];
+    const Ws& w = cd.w;
+    const Plan& P = cd.P;
+    Header* h = w.h;
+    if (p >= P.t_max) continue;  // a ticket past the last possible pass
+    uint32_t tg[kPerThread];
+    issue_tile(w, tile, pt, tg);
+    if (c != cur_c || p != cur_p) {
+      if (threadIdx.x == 0) S.go = wait_pass(h, p, &bd->err[0]);
+      __syncthreads();
+      if (S.go < 0) break;
+      if (S.go == 0) continue;  // that cloud's search has ended: drop the ticket
+      if (threadIdx.x < kPubWords)
+        reinterpret_cast<uint32_t*>(&S.st)[threadIdx.x] = ld_agent(&h->pub[threadIdx.x]);
+      __syncthreads();
+      cur_c = c;
+      cur_p = p;
+    }
+    const int r = run_ticket(w, P, S, lvals, lkeys, pt, tg, p, tile);
+    if (r == kTicketPublished) cur_p = p + 1;
+    if (r == kTicketFinished) {
+      if (threadIdx.x == 0) atomicAdd(&bd->nfin[0], 1u);
+      cur_c = -1;
+    }
+  }
+  if (threadIdx.x == 0 && ld_agent(&bd->err[0]))
+    for (int k = 0; k < nact; ++k) mark_search_failed(bd->clouds[bd->act[k]].w.h);
+}
+
+int grid_for(int64_t work) {
+  const int64_t g = (work + kThreads - 1) / kThreads;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, 4096)));
+}
+
+
+// Blocks of a search launch: one per tile, at most as many as the device holds at
+// once (more would only wait for tickets). The limit is cached per device, kernel
+// (single or batched) and depth.
+int search_grid(int ntile, int depth, bool many) {
+  static std::atomic<int> cache[kMaxDevices][2][kMaxDepth + 1];
   int dev = 0;
   int cap = 1024;
   if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) {
-    int c = cache[dev][depth].load(std::memory_order_relaxed);
+    int c = cache[dev][many][depth].load(std::memory_order_relaxed);
     if (c == 0) {
       const size_t lds = 2 * static_cast<size_t>((1 << depth) - 1) * kBrickCap * sizeof(uint64_t);
       int per_cu = 0, cus = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-              &per_cu, reinterpret_cast<const void*>(&k_search), kThreads, lds) == hipSuccess &&
+      const void* fn = many ? reinterpret_cast<const void*>(&k_search_many)
+                            : reinterpret_cast<const void*>(&k_search);
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) == hipSuccess &&
           hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
           per_cu > 0 && cus > 0)
         c = per_cu * cus;
       else
         c = cap;
-      cache[dev][depth].store(c, std::memory_order_relaxed);
+      cache[dev][many][depth].store(c, std::memory_order_relaxed);
     }
     cap = c;
   }
@@ -2008,55 +2437,33 @@ void timing_keep(const char* name, hipEvent_t e0, hipEvent_t e1) {
 
 hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_t* p, int32_t* idx,
                        char* ws, const Layout& L, hav_info_t* info_dev, hipStream_t st) {
-  Ws w = make_ws(ws, L, N);
-  Plan P;
-  std::memset(&P, 0, sizeof(P));
-  P.t_max = p->t_max;
-  P.depth = depth_of(p);
-  P.fixed = (p->flags & HAV_FIXED_VOXEL) ? 1 : 0;
-  P.magic = magic_of(L);
-  P.cap = w.cap;
-  P.sel_cap = w.cap * static_cast<uint32_t>(kSelDense);
-  P.spec_mult = kSpecMult;
-  for (int a = 0; a < 3; ++a) {
-    P.aspect[a] = p->aspect[a];
-    P.fixed_v[a] = p->fixed_voxel[a];
-  }
-  int64_t m[HAV_MAX_LAYERS];
-  layer_sizes(M, p->layers, p->layer_ratio, m);
-  int nl = 0;
-  for (int l = 0; l < p->layers; ++l) {
-    if (m[l] == 0) continue;
-    const double up = std::floor(static_cast<double>(m[l]) * (1.0 + p->sigma));
-    P.m[nl] = static_cast<uint32_t>(m[l]);
-    P.upper[nl] = up >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(up);
-    ++nl;
-  }
-  P.nlayers = nl;
-
-  HAV_LAUNCH(k_bbox, dim3(w.nbbox), dim3(kThreads), 0, st, xyz, w);
-  if (M == N) {
-    HAV_LAUNCH(k_identity, dim3(grid_for(N)), dim3(kThreads), 0, st, w, P, idx, info_dev);
+  const CloudSpec spec{xyz, idx, info_dev, ws, N, M, L.n_ws};
+  const One one{make_cloud(spec, lite_of(p))};
+  const Ws& w = one.c.w;
+  const Plan& P = one.c.P;
+  HAV_LAUNCH(k_bbox<One>, dim3(w.nbbox), dim3(kThreads), 0, st, one);
+  if (P.identity) {
+    HAV_LAUNCH(k_identity<One>, dim3(w.nscan), dim3(kThreads), 0, st, one);
     return HAV_OK;
   }
-  HAV_LAUNCH(k_bin_count, dim3(w.nbb), dim3(kThreads), 0, st, xyz, w, P);
-  HAV_LAUNCH(k_bin_scan, dim3(kBinChunks), dim3(kThreads), 0, st, w, P);
-  HAV_LAUNCH(k_bin_scatter, dim3(w.nbb), dim3(kThreads), 0, st, xyz, w);
-  const int sgrid = search_grid(w.ntile, P.depth);
-  const int R = trim_rounds(N);
+  HAV_LAUNCH(k_bin_count<One>, dim3(w.nbb), dim3(kThreads), 0, st, one);
+  HAV_LAUNCH(k_bin_scan<One>, dim3(kBinChunks), dim3(kThreads), 0, st, one);
+  HAV_LAUNCH(k_bin_scatter<One>, dim3(w.nbb), dim3(kThreads), 0, st, one);
+  const int sgrid = search_grid(w.ntile, P.depth, false);
   const size_t eval_lds = 2 * static_cast<size_t>((1 << P.depth) - 1) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
-  for (int l = 0; l < nl; ++l) {
-    if (!P.fixed) HAV_LAUNCH(k_search, dim3(sgrid), dim3(kThreads), eval_lds, st, w, P);
-    HAV_LAUNCH(k_select, dim3(w.ntile), dim3(kThreads), sel_lds, st, w);
-    for (int r = 0; r < R; ++r) HAV_LAUNCH(k_trim_hist, dim3(w.ntile), dim3(kThreads), 0, st, w, r);
-    HAV_LAUNCH(k_mark, dim3(w.ntile), dim3(kThreads), 0, st, w);
-    HAV_LAUNCH(k_ties, dim3(1), dim3(kThreads), 0, st, w);
-    HAV_LAUNCH(k_scan_count, dim3(w.nscan), dim3(kThreads), 0, st, w, 0);
-    HAV_LAUNCH(k_pad_mark, dim3(w.nscan), dim3(kThreads), 0, st, w, P);
+  for (int l = 0; l < P.nlayers; ++l) {
+    if (!P.fixed) HAV_LAUNCH(k_search, dim3(sgrid), dim3(kThreads), eval_lds, st, one, l);
+    HAV_LAUNCH(k_select<One>, dim3(w.ntile), dim3(kThreads), sel_lds, st, one, l);
+    for (int r = 0; r < P.rounds; ++r)
+      HAV_LAUNCH(k_trim_hist<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l, r);
+    HAV_LAUNCH(k_mark<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l);
+    HAV_LAUNCH(k_ties<One>, dim3(1), dim3(kThreads), 0, st, one, l);
+    HAV_LAUNCH(k_scan_count<One>, dim3(w.nscan), dim3(kThreads), 0, st, one, l, 0);
+    HAV_LAUNCH(k_pad_mark<One>, dim3(w.nscan), dim3(kThreads), 0, st, one, l);
   }
-  HAV_LAUNCH(k_scan_count, dim3(w.nscan), dim3(kThreads), 0, st, w, 1);
-  HAV_LAUNCH(k_out_write, dim3(w.nscan), dim3(kThreads), 0, st, w, idx, M, info_dev);
+  HAV_LAUNCH(k_scan_count<One>, dim3(w.nscan), dim3(kThreads), 0, st, one, -1, 1);
+  HAV_LAUNCH(k_out_write<One>, dim3(w.nscan), dim3(kThreads), 0, st, one);
   return HAV_OK;
 }
 
@@ -2096,6 +2503,135 @@ hav_status_t init_ws(char* base, const Layout& L, hipStream_t st) {
              2 * static_cast<size_t>(L.ncmax) * kReps * kHotCap);
   HAV_LAUNCH(k_ws_seal, dim3(1), dim3(64), 0, st, w.h, magic_of(L));
   return HAV_OK;
+}
+
+// ----------------------------------------------------------------------------- batched host side
+
+constexpr int32_t kMaxBatch = 4096;
+static_assert(sizeof(SetupArgs) <= 3072, "k_setup arguments");
+
+// A batched call's region: header, cloud views, block maps, searching-cloud list.
+struct BatchLayout {
+  size_t bd = 0, clouds = 0, bmap = 0, act = 0, total = 0;
+  int32_t kind_off[kKinds] = {}, kind_total[kKinds] = {};
+};
+
+BatchLayout make_batch_layout(int32_t B, const int64_t* n) {
+  BatchLayout BL;
+  int64_t off = 0;
+  for (int k = 0; k < kKinds; ++k) {
+    int64_t t = 0;
+    for (int32_t i = 0; i < B; ++i) t += blocks_of(k, n[i]);
+    BL.kind_off[k] = static_cast<int32_t>(off);
+    BL.kind_total[k] = static_cast<int32_t>(t);
+    off += t;
+  }
+  size_t o = 0;
+  BL.bd = o;     o = align_up(o + sizeof(BatchDev));
+  BL.clouds = o; o = align_up(o + static_cast<size_t>(B) * sizeof(Cloud));
+  BL.bmap = o;   o = align_up(o + static_cast<size_t>(off) * sizeof(BlockRef));
+  BL.act = o;    o = align_up(o + static_cast<size_t>(B) * 4);
+  BL.total = o;
+  return BL;
+}
+
+// All kernels of one stage for B clouds at once. `region` holds the BatchLayout;
+// every spec has its own initialised segment.
+hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p, char* region,
+                       const BatchLayout& BL, hipStream_t st) {
+  const ParamLite q = lite_of(p);
+  BatchDev* bd = reinterpret_cast<BatchDev*>(region + BL.bd);
+  Cloud* clouds = reinterpret_cast<Cloud*>(region + BL.clouds);
+  BlockRef* bmap = reinterpret_cast<BlockRef*>(region + BL.bmap);
+  int32_t* act = reinterpret_cast<int32_t*>(region + BL.act);
+  int max_layers = 0, max_rounds = 0;
+  bool any_identity = false, any_work = false, any_search = false;
+  for (int32_t i = 0; i < B; ++i) {
+    const Cloud cd = make_cloud(specs[i], q);
+    if (cd.P.identity) {
+      any_identity = true;
+      continue;
+    }
+    any_work = true;
+    any_search |= !cd.P.fixed;
+    max_layers = std::max(max_layers, cd.P.nlayers);
+    max_rounds = std::max(max_rounds, cd.P.rounds);
+  }
+  for (int32_t first = 0; first < B; first += kSetupChunk) {
+    SetupArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.bd = bd;
+    a.clouds = clouds;
+    a.bmap = bmap;
+    a.act = act;
+    a.q = q;
+    a.B = B;
+    a.first = first;
+    a.count = std::min<int32_t>(kSetupChunk, B - first);
+    for (int k = 0; k < kKinds; ++k) {
+      a.kind_off[k] = BL.kind_off[k];
+      a.kind_total[k] = BL.kind_total[k];
+    }
+    for (int32_t i = 0; i < a.count; ++i) a.cl[i] = specs[first + i];
+    HAV_LAUNCH(k_setup, dim3(1), dim3(64), 0, st, a);
+  }
+  HAV_LAUNCH(k_map, dim3(kKinds), dim3(kThreads), 0, st, bd);
+  const Many many{bd};
+  const int* T = BL.kind_total;
+  HAV_LAUNCH(k_bbox<Many>, dim3(T[kKBBox]), dim3(kThreads), 0, st, many);
+  if (any_identity) HAV_LAUNCH(k_identity<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many);
+  if (!any_work) return HAV_OK;
+  HAV_LAUNCH(k_bin_count<Many>, dim3(T[kKBin]), dim3(kThreads), 0, st, many);
+  HAV_LAUNCH(k_bin_scan<Many>, dim3(T[kKBScan]), dim3(kThreads), 0, st, many);
+  HAV_LAUNCH(k_bin_scatter<Many>, dim3(T[kKBin]), dim3(kThreads), 0, st, many);
+  const int sgrid = search_grid(T[kKTile], q.depth, true);
+  const size_t eval_lds = 2 * static_cast<size_t>((1 << q.depth) - 1) * kBrickCap * sizeof(uint64_t);
+  const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
+  for (int l = 0; l < max_layers; ++l) {
+    if (any_search) {
+      HAV_LAUNCH(k_search_prep, dim3(1), dim3(kThreads), 0, st, many, l);
+      HAV_LAUNCH(k_search_many, dim3(sgrid), dim3(kThreads), eval_lds, st, many, l);
+    }
+    HAV_LAUNCH(k_select<Many>, dim3(T[kKTile]), dim3(kThreads), sel_lds, st, many, l);
+    for (int r = 0; r < max_rounds; ++r)
+      HAV_LAUNCH(k_trim_hist<Many>, dim3(T[kKTile]), dim3(kThreads), 0, st, many, l, r);
+    HAV_LAUNCH(k_mark<Many>, dim3(T[kKTile]), dim3(kThreads), 0, st, many, l);
+    HAV_LAUNCH(k_ties<Many>, dim3(T[kKOne]), dim3(kThreads), 0, st, many, l);
+    HAV_LAUNCH(k_scan_count<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many, l, 0);
+    HAV_LAUNCH(k_pad_mark<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many, l);
+  }
+  HAV_LAUNCH(k_scan_count<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many, -1, 1);
+  HAV_LAUNCH(k_out_write<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many);
+  return HAV_OK;
+}
+
+// Workspace of hav_sample_batch: the batch region, then one segment per cloud.
+struct BatchWsLayout {
+  BatchLayout BL;
+  std::vector<size_t> seg;
+  size_t total = 0;
+};
+
+bool batch_args_ok(int32_t B, const int64_t* N, const int64_t* M) {
+  if (B < 1 || B > kMaxBatch || !N) return false;
+  for (int32_t i = 0; i < B; ++i) {
+    if (N[i] < 1 || N[i] > kMaxPoints) return false;
+    if (M && (M[i] < 1 || M[i] > N[i])) return false;
+  }
+  return true;
+}
+
+BatchWsLayout make_batch_ws_layout(int32_t B, const int64_t* N, int depth) {
+  BatchWsLayout W;
+  W.BL = make_batch_layout(B, N);
+  size_t o = align_up(W.BL.total);
+  W.seg.resize(static_cast<size_t>(B));
+  for (int32_t i = 0; i < B; ++i) {
+    W.seg[i] = o;
+    o = align_up(o + make_layout(N[i], depth).total);
+  }
+  W.total = o;
+  return W;
 }
 
 }  // namespace
@@ -2163,6 +2699,68 @@ hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params
                    static_cast<hipStream_t>(stream));
 }
 
+}  // extern "C"
+
+namespace {
+// A kept launch name ("k_select<One>") matches the plain kernel name.
+bool same_kernel(const char* kept, const char* name) {
+  size_t i = 0;
+  for (; name[i] && kept[i] == name[i]; ++i) {
+  }
+  return name[i] == 0 && (kept[i] == 0 || kept[i] == '<');
+}
+}  // namespace
+
+extern "C" {
+
+size_t hav_batch_workspace_size(int32_t B, const int64_t* N_host, const int64_t* M_host,
+                                const hav_params_t* params) {
+  if (!batch_args_ok(B, N_host, M_host) || !params_ok(params)) return 0;
+  return make_batch_ws_layout(B, N_host, depth_of(params)).total;
+}
+
+hav_status_t hav_batch_workspace_init(int32_t B, const int64_t* N_host, const hav_params_t* params,
+                                      void* ws, size_t ws_bytes, void* stream) {
+  if (!ws || !batch_args_ok(B, N_host, nullptr) || !params_ok(params)) return HAV_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
+  const int depth = depth_of(params);
+  const BatchWsLayout W = make_batch_ws_layout(B, N_host, depth);
+  if (ws_bytes < W.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
+  char* base = static_cast<char*>(ws);
+  for (int32_t i = 0; i < B; ++i) {
+    const hav_status_t s = init_ws(base + W.seg[i], make_layout(N_host[i], depth),
+                                   static_cast<hipStream_t>(stream));
+    if (s != HAV_OK) return s;
+  }
+  return HAV_OK;
+}
+
+hav_status_t hav_sample_batch(const float* xyz_concat, const int64_t* offsets_host,
+                              const int64_t* M_host, int32_t B, const hav_params_t* params,
+                              int32_t* idx_concat, void* ws, size_t ws_bytes, hav_info_t* info_dev,
+                              void* stream) {
+  if (!xyz_concat || !offsets_host || !M_host || !idx_concat || !ws || B < 1 || B > kMaxBatch ||
+      !params_ok(params))
+    return HAV_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
+  if (offsets_host[0] != 0) return HAV_ERR_INVALID_ARG;
+  std::vector<int64_t> N(static_cast<size_t>(B));
+  for (int32_t i = 0; i < B; ++i) N[i] = offsets_host[i + 1] - offsets_host[i];
+  if (!batch_args_ok(B, N.data(), M_host)) return HAV_ERR_INVALID_ARG;
+  const int depth = depth_of(params);
+  const BatchWsLayout W = make_batch_ws_layout(B, N.data(), depth);
+  if (ws_bytes < W.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
+  char* base = static_cast<char*>(ws);
+  std::vector<CloudSpec> specs(static_cast<size_t>(B));
+  int64_t mo = 0;
+  for (int32_t i = 0; i < B; ++i) {
+    specs[i] = CloudSpec{xyz_concat + 3 * offsets_host[i], idx_concat + mo,
+                         info_dev ? info_dev + i : nullptr, base + W.seg[i], N[i], M_host[i], N[i]};
+    mo += M_host[i];
+  }
+  return run_batch(specs.data(), B, params, base, W.BL, static_cast<hipStream_t>(stream));
+}
+
 hav_status_t hav_timing_enable(int32_t on) {
   g_timing_on.store(on ? 1 : 0, std::memory_order_relaxed);
   return HAV_OK;
@@ -2176,7 +2774,7 @@ hav_status_t hav_timing_collect(const char* kernel, int32_t* launches, double* t
   hav_status_t status = HAV_OK;
   std::vector<TimedLaunch> rest;
   for (const TimedLaunch& t : g_timed) {
-    if (std::strcmp(t.name, kernel) != 0) {
+    if (!same_kernel(t.name, kernel)) {
       rest.push_back(t);
       continue;
     }

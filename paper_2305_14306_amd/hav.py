@@ -101,6 +101,13 @@ def lib():
         L.hav_sample_chain.restype = C.c_int
         L.hav_sample_chain.argtypes = [vp, C.c_int64, i64p, C.c_int32, C.POINTER(Params), i32p, vp,
                                        C.c_size_t, vp, vp]
+        L.hav_batch_workspace_size.restype = C.c_size_t
+        L.hav_batch_workspace_size.argtypes = [C.c_int32, i64p, i64p, C.POINTER(Params)]
+        L.hav_batch_workspace_init.restype = C.c_int
+        L.hav_batch_workspace_init.argtypes = [C.c_int32, i64p, C.POINTER(Params), vp, C.c_size_t, vp]
+        L.hav_sample_batch.restype = C.c_int
+        L.hav_sample_batch.argtypes = [vp, i64p, i64p, C.c_int32, C.POINTER(Params), i32p, vp,
+                                       C.c_size_t, vp, vp]
         L.hav_timing_enable.restype = C.c_int
         L.hav_timing_enable.argtypes = [C.c_int32]
         L.hav_timing_collect.restype = C.c_int
@@ -153,6 +160,17 @@ def chain_workspace_size(N: int, Ms, p: Params | None = None) -> int:
     return int(lib().hav_chain_workspace_size(int(N), arr, len(Ms), C.byref(p)))
 
 
+def _i64(values):
+    vals = [int(v) for v in values]
+    return (C.c_int64 * len(vals))(*vals)
+
+
+def batch_workspace_size(Ns, Ms=None, p: Params | None = None) -> int:
+    p = p if p is not None else params()
+    return int(lib().hav_batch_workspace_size(len(Ns), _i64(Ns), _i64(Ms) if Ms is not None else None,
+                                              C.byref(p)))
+
+
 def _torch():
     import torch
     return torch
@@ -189,17 +207,23 @@ class Sampler:
         self.ws_key = None
         self.info = None
 
-    def _workspace(self, nbytes: int, N: int, p: Params, stream=None):
+    def _workspace(self, nbytes: int, N, p: Params, stream=None):
+        """N: a point count (single clouds and chains) or a tuple of counts (batches)."""
         torch = _torch()
         if self.ws is None or self.ws.numel() < nbytes:
             self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
             self.ws_key = None
-        key = (int(N), int(p.spec_depth))
+        key = (N if isinstance(N, tuple) else int(N), int(p.spec_depth))
         if self.ws_key != key:
-            st = lib().hav_workspace_init(int(N), C.byref(p), C.c_void_p(self.ws.data_ptr()),
-                                          self.ws.numel(), _stream_ptr(stream))
+            if isinstance(N, tuple):
+                st = lib().hav_batch_workspace_init(len(N), _i64(N), C.byref(p),
+                                                    C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                                    _stream_ptr(stream))
+            else:
+                st = lib().hav_workspace_init(int(N), C.byref(p), C.c_void_p(self.ws.data_ptr()),
+                                              self.ws.numel(), _stream_ptr(stream))
             if st != OK:
-                raise HavError(st, "hav_workspace_init")
+                raise HavError(st, "workspace init")
             self.ws_key = key
         return self.ws
 
@@ -262,6 +286,42 @@ class Sampler:
             off += int(m)
         if with_info:
             return parts, read_info(info[:len(Ms) * C.sizeof(Info)], len(Ms))
+        return parts
+
+
+    def sample_batch(self, xyz_concat, offsets, Ms, p: Params | None = None, out=None,
+                     with_info: bool = False, stream=None):
+        """hav_sample_batch: cloud i is xyz_concat[offsets[i]:offsets[i+1]]; returns one
+        tensor of local indices (ascending) per cloud."""
+        torch = _torch()
+        _check_xyz(xyz_concat)
+        p = p if p is not None else params()
+        offsets = [int(o) for o in offsets]
+        Ms = [int(m) for m in Ms]
+        B = len(Ms)
+        if len(offsets) != B + 1 or offsets[-1] != xyz_concat.shape[0]:
+            raise ValueError("offsets must have B+1 entries ending at the number of points")
+        Ns = tuple(offsets[i + 1] - offsets[i] for i in range(B))
+        nbytes = batch_workspace_size(Ns, Ms, p)
+        if nbytes == 0:
+            raise HavError(ERR_INVALID_ARG, "hav_batch_workspace_size")
+        ws = self._workspace(nbytes, Ns, p, stream)
+        total = sum(Ms)
+        idx = out if out is not None else torch.empty(total, dtype=torch.int32, device=xyz_concat.device)
+        info = self._info(B) if with_info else None
+        st = lib().hav_sample_batch(C.c_void_p(xyz_concat.data_ptr()), _i64(offsets), _i64(Ms), B,
+                                    C.byref(p), C.c_void_p(idx.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                    ws.numel(),
+                                    C.c_void_p(info.data_ptr()) if info is not None else None,
+                                    _stream_ptr(stream))
+        if st != OK:
+            raise HavError(st, "hav_sample_batch")
+        parts, off = [], 0
+        for m in Ms:
+            parts.append(idx[off:off + m])
+            off += m
+        if with_info:
+            return parts, read_info(info[:B * C.sizeof(Info)], B)
         return parts
 
 

@@ -145,3 +145,34 @@ def test_binding_refuses_cpu_tensors(hav):
     import torch
     with pytest.raises(ValueError):
         hav.sample(torch.zeros(10, 3), 5)
+
+
+def test_batch_workspace_size(hav):
+    p = hav.params()
+    one = hav.workspace_size(10000, 100, p)
+    both = hav.batch_workspace_size([10000, 20000], [100, 200], p)
+    assert both > one + hav.workspace_size(20000, 200, p)
+    assert hav.batch_workspace_size([10000], None, p) > 0
+    assert hav.batch_workspace_size([10000, 0], None, p) == 0
+    assert hav.batch_workspace_size([10000, 5], [100, 6], p) == 0  # M > N
+    assert hav.batch_workspace_size([], None, p) == 0
+    assert hav.batch_workspace_size([1 << 30], None, p) == 0
+
+
+def test_batch_host_rejects_bad_arguments(hav):
+    p = hav.params()
+    L = hav.lib()
+    E = hav.ERR_INVALID_ARG
+
+    def call(offs, Ms, ws_bytes=1 << 30, ws=0x30000):
+        o = (C.c_int64 * len(offs))(*offs)
+        m = (C.c_int64 * len(Ms))(*Ms)
+        return L.hav_sample_batch(C.c_void_p(0x10000), o, m, len(Ms), C.byref(p), C.c_void_p(0x20000),
+                                  C.c_void_p(ws), ws_bytes, None, None)
+
+    assert call([1, 10, 20], [5, 5]) == E          # offsets must start at 0
+    assert call([0, 10, 5], [5, 5]) == E           # a negative cloud size
+    assert call([0, 10, 20], [5, 11]) == E         # M > N
+    assert call([0, 10, 20], [0, 5]) == E          # M = 0
+    assert call([0, 10, 20], [5, 5], ws=0x30010) == E
+    assert call([0, 10, 20], [5, 5], ws_bytes=100) == hav.ERR_WORKSPACE_TOO_SMALL
