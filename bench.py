@@ -77,6 +77,129 @@ def measured_traffic():
         return None
 
 
+def batch_leg(torch, hav, synth, steps: int) -> dict:
+    """64 uneven LiDAR-shaped clouds (N_i ~ U{20k..200k}, M_i = N_i / 4): one batched
+    call against 64 sequential single-cloud calls on the same stream, each with its own
+    initialised workspace. Both produce the same indices (checked)."""
+    import numpy as np
+    clouds, Ms = synth.batch_lidar_clouds()
+    offs = np.concatenate([[0], np.cumsum([c.shape[0] for c in clouds])]).astype(np.int64)
+    xyz = torch.from_numpy(np.concatenate(clouds)).cuda()
+    total_n = int(offs[-1])
+    bs = hav.Sampler()
+    out = torch.empty(sum(Ms), dtype=torch.int32, device="cuda")
+    singles = [hav.Sampler() for _ in clouds]
+    views = [xyz[int(offs[i]):int(offs[i + 1])] for i in range(len(clouds))]
+    outs = [torch.empty(m, dtype=torch.int32, device="cuda") for m in Ms]
+    p = hav.params()
+
+    def batched():
+        bs.sample_batch(xyz, offs, Ms, p, out=out)
+
+    def per_cloud():
+        for i in range(len(clouds)):
+            singles[i].sample(views[i], Ms[i], p, out=outs[i])
+
+    for _ in range(2):
+        batched()
+        per_cloud()
+    torch.cuda.synchronize()
+    assert torch.equal(out, torch.cat(outs)), "batched and per-cloud results differ"
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    t_b = timed(batched)
+    t_s = timed(per_cloud)
+    return {"workload": "64 LiDAR-shaped clouds, N_i ~ U{20k..200k} (sum %d), M_i = N_i/4" % total_n,
+            "batched_ms": round(t_b, 4), "per_cloud_ms": round(t_s, 4),
+            "speedup": round(t_s / t_b, 3), "batched_Mpoints_per_s": round(total_n / t_b / 1e3, 1)}
+
+
+def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
+    """Poisson arrivals at 2,000 clouds/s (seed 7), N lognormal (median 1e5, sigma_ln 1,
+    clamped to [1,024, 2,097,152]), LiDAR- or scene-shaped with probability 1/2, M = N/4
+    or N/16. Each request's cloud is a window of N consecutive points of a 2,097,152-point
+    base cloud of its kind held in pinned host memory (the LiDAR sweep is azimuth-ordered,
+    so a window is a sector; the scene cloud is shuffled). The trace is replayed in real
+    time against the continuous-batching server and against the same server limited to
+    one request at a time on one stream (FIFO). Latency: submit to completion, host clock,
+    the first `warm` requests discarded."""
+    import time
+    import numpy as np
+    tr = synth.serving_trace(n_requests)
+    nmax = 1 << 21
+    scene = synth.scene_planes_blobs(nmax, seed=31)
+    lidar = synth.lidar_scan(seed=32, n_azimuth=int(np.ceil(nmax / (64 * 0.85))) + 2048)[:nmax]
+    bases = [torch.from_numpy(np.ascontiguousarray(lidar)).pin_memory(),
+             torch.from_numpy(np.ascontiguousarray(scene)).pin_memory()]
+    rng = np.random.default_rng(8)
+    views = []
+    for i in range(n_requests):
+        b = bases[int(tr["kind"][i])]
+        n = int(tr["n"][i])
+        o = int(rng.integers(0, b.shape[0] - n + 1))
+        views.append(b[o:o + n])
+
+    def replay(max_batch, streams):
+        srv = hav.Server(48 << 30, max_batch=max_batch, streams=streams)
+        lat = np.zeros(n_requests)
+        t_sub = np.zeros(n_requests)
+        outstanding = []
+        t0 = time.perf_counter() + 0.05
+        try:
+            def drain(block):
+                while outstanding:
+                    i, t = outstanding[0]
+                    r = srv.wait(t) if block else srv.poll(t)
+                    if r is None:
+                        return
+                    assert r[0] == 0, r[0]
+                    lat[i] = r[3]
+                    outstanding.pop(0)
+            for i in range(n_requests):
+                target = t0 + float(tr["t_arrival"][i])
+                while True:
+                    now = time.perf_counter()
+                    if now >= target:
+                        break
+                    drain(False)
+                    if target - now > 2e-4:
+                        time.sleep(1e-4)
+                t_sub[i] = time.perf_counter()
+                outstanding.append((i, srv.submit(views[i], int(tr["m"][i]))))
+                if len(outstanding) > 64:
+                    drain(False)
+            drain(True)
+            stats = srv.stats()
+        finally:
+            srv.close()
+        sel = slice(warm, n_requests)
+        done = t_sub + lat * 1e-3
+        pts = float(tr["n"][sel].sum())
+        span = float(done[sel].max() - t_sub[warm])
+        return {"p50_ms": round(float(np.percentile(lat[sel], 50)), 3),
+                "p99_ms": round(float(np.percentile(lat[sel], 99)), 3),
+                "mean_ms": round(float(lat[sel].mean()), 3),
+                "Mpoints_per_s": round(pts / span / 1e6, 1),
+                "batches": int(stats["batches"]), "max_batch": int(stats["max_batch_seen"]),
+                "slots": int(stats["slots"]), "hbm_GiB": round(stats["hbm_used"] / 2 ** 30, 2)}
+
+    cont = replay(64, 2)
+    fifo = replay(1, 1)
+    return {"workload": "Poisson 2000/s, N lognormal median 1e5 (sigma_ln 1, <= 2^21), "
+                        "LiDAR/scene mix, M = N/4 or N/16, %d requests (first %d discarded)"
+                        % (n_requests, warm),
+            "continuous": cont, "fifo": fifo,
+            "p99_speedup": round(fifo["p99_ms"] / cont["p99_ms"], 3)}
+
+
 def cpu_baseline(x, M: int, budget_s: float) -> dict:
     import oracle
     reps, t0 = 0, time.perf_counter()
@@ -99,6 +222,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batched leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter "
                          "calibration for profiling runs)")
@@ -188,6 +314,13 @@ def main() -> int:
                    "N": N, "M": M, "evals": info["evals"], "count": info["count"]},
         "roofline": roofline,
     }
+    if not args.no_batch:
+        result["batch"] = batch_leg(torch, hav, synth, max(3, min(args.steps, 10)))
+        print(f"bench: batch {result['batch']}", file=sys.stderr, flush=True)
+    if not args.no_serve:
+        result["serve"] = serve_leg(torch, hav, synth, args.serve_requests,
+                                    min(500, args.serve_requests // 10))
+        print(f"bench: serve {result['serve']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(x, M, args.cpu_seconds)
     print(json.dumps(result), flush=True)

@@ -46,8 +46,9 @@ typedef enum {
                                       for 21-bit voxel coordinates */
   HAV_ERR_NONFINITE = 5,           /* device: a coordinate is NaN or infinite */
   HAV_ERR_HIP = 6,                 /* a HIP launch failed */
-  HAV_ERR_WORKSPACE_NOT_INIT = 7   /* device: workspace not initialised for this call's
+  HAV_ERR_WORKSPACE_NOT_INIT = 7,  /* device: workspace not initialised for this call's
                                       size and depth (see hav_workspace_init) */
+  HAV_NOT_READY = 8                /* serving: the request has not finished yet */
 } hav_status_t;
 
 /* flags */
@@ -165,6 +166,47 @@ hav_status_t hav_sample_batch(const float* xyz_concat, const int64_t* offsets_ho
                               const int64_t* M_host, int32_t B, const hav_params_t* params,
                               int32_t* idx_concat, void* ws, size_t ws_bytes, hav_info_t* info_dev,
                               void* stream);
+
+/* ---- Serving loop (continuous batching).
+ * A server owns device memory within an HBM budget: per-request slots in capacity
+ * classes of 2^k points (4,096 .. 16,777,216), each keeping its workspace initialised on
+ * the device for its life, and one batch region per stream. A worker thread admits
+ * submitted requests in arrival order as slots become free (a request that does not fit
+ * yet lets smaller ones behind it pass; idle slots of other classes are released when
+ * the budget needs the room), and launches every admitted request in the next batch on
+ * a free stream, so up to `streams` batches overlap on the device. Each result equals
+ * what hav_sample gives the same cloud alone. Latency is measured from submit to the
+ * worker seeing the batch complete (host steady clock). */
+typedef struct hav_server hav_server_t;
+
+typedef struct {
+  int64_t submitted, completed, batches, max_batch_seen;
+  int64_t slots, slots_created, evictions, points_done;
+  uint64_t hbm_used; /* bytes of device memory the server holds */
+} hav_server_stats_t;
+
+/* Create a server on the current device. max_batch 1..1024 requests per launch,
+ * streams 1..8 batches in flight. NULL on invalid arguments or if the batch regions
+ * cannot be allocated (this entry point allocates device and pinned host memory). */
+hav_server_t* hav_server_create(size_t hbm_budget_bytes, int32_t max_batch, int32_t streams,
+                                const hav_params_t* params);
+
+/* Queue a request: N points at xyz_host_pinned ([N][3] float32 in pinned host memory that
+ * stays valid and unchanged until the request completes), sample M. Writes a ticket.
+ * HAV_ERR_OUT_OF_MEMORY if one slot of its class cannot fit the budget. */
+hav_status_t hav_server_submit(hav_server_t* server, const float* xyz_host_pinned, int64_t N,
+                               int64_t M, uint64_t* ticket);
+
+/* HAV_NOT_READY while the request runs. Once it has finished: copies the M ascending
+ * indices to idx_host (if not NULL and the request succeeded), its report to info_host
+ * and its latency in milliseconds, forgets the ticket and returns the request's status. */
+hav_status_t hav_server_poll(hav_server_t* server, uint64_t ticket, int32_t* idx_host,
+                             hav_info_t* info_host, double* latency_ms);
+
+hav_status_t hav_server_stats(hav_server_t* server, hav_server_stats_t* out);
+
+/* Finish the batches in flight, drop requests not yet admitted, free everything. */
+void hav_server_destroy(hav_server_t* server);
 
 /* Measurement support. While enabled (on != 0), every kernel launch the library makes
  * is bracketed by a pair of HIP events recorded on the call's stream; the events are

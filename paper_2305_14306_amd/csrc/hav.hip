@@ -45,7 +45,13 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
 #include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 #include <cmath>
 #include <cstring>
@@ -1994,7 +2000,7 @@ __host__ __device__ inline Layout make_layout(int64_t n, int depth) {
   L.tag_s = o;  o = align_up(o + NP);
   L.tag_o = o;  o = align_up(o + N);
   L.part = o;   o = align_up(o + static_cast<size_t>(kMaxBBoxBlocks) * 8 * 4);
-  L.bh = o;     o = align_up(o + static_cast<size_t>(kBins) * kMaxBinBlocks * 4);
+  L.bh = o;     o = align_up(o + static_cast<size_t>(kBins) * blocks_of(kKBin, n) * 4);
   L.binpre = o; o = align_up(o + static_cast<size_t>(kBins) * 4);
   L.bsum = o;   o = align_up(o + static_cast<size_t>(kBinChunks) * 4);
   L.ckeys = o;  o = align_up(o + tabs * L.cap_ws * 8);
@@ -2668,6 +2674,7 @@ const char* hav_status_string(hav_status_t s) {
     case HAV_ERR_NONFINITE: return "non-finite coordinate";
     case HAV_ERR_HIP: return "HIP error";
     case HAV_ERR_WORKSPACE_NOT_INIT: return "workspace not initialised for this size";
+    case HAV_NOT_READY: return "not ready";
   }
   return "unknown status";
 }
@@ -2839,3 +2846,5 @@ hav_status_t hav_sample_chain(const float* xyz, int64_t N, const int64_t* M_host
 }
 
 }  // extern "C"
+
+#include "hav_server.inc"

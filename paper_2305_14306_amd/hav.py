@@ -17,7 +17,7 @@ MAX_LAYERS = 8
 FIXED_VOXEL = 1
 
 OK, ERR_INVALID_ARG, ERR_WORKSPACE_TOO_SMALL, ERR_OUT_OF_MEMORY, ERR_UNSUPPORTED, \
-    ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE_NOT_INIT = range(8)
+    ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE_NOT_INIT, NOT_READY = range(9)
 
 
 class Params(C.Structure):
@@ -67,6 +67,15 @@ class Info(C.Structure):
         }
 
 
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "completed", "batches", "max_batch_seen", "slots",
+                                         "slots_created", "evictions", "points_done")] + \
+               [("hbm_used", C.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class HavError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
@@ -108,6 +117,16 @@ def lib():
         L.hav_sample_batch.restype = C.c_int
         L.hav_sample_batch.argtypes = [vp, i64p, i64p, C.c_int32, C.POINTER(Params), i32p, vp,
                                        C.c_size_t, vp, vp]
+        L.hav_server_create.restype = C.c_void_p
+        L.hav_server_create.argtypes = [C.c_size_t, C.c_int32, C.c_int32, C.POINTER(Params)]
+        L.hav_server_submit.restype = C.c_int
+        L.hav_server_submit.argtypes = [vp, vp, C.c_int64, C.c_int64, C.POINTER(C.c_uint64)]
+        L.hav_server_poll.restype = C.c_int
+        L.hav_server_poll.argtypes = [vp, C.c_uint64, vp, C.POINTER(Info), C.POINTER(C.c_double)]
+        L.hav_server_stats.restype = C.c_int
+        L.hav_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.hav_server_destroy.restype = None
+        L.hav_server_destroy.argtypes = [vp]
         L.hav_timing_enable.restype = C.c_int
         L.hav_timing_enable.argtypes = [C.c_int32]
         L.hav_timing_collect.restype = C.c_int
@@ -333,3 +352,74 @@ def sample(xyz, M: int, p: Params | None = None, with_info: bool = False):
 def chain(xyz, Ms, p: Params | None = None, with_info: bool = False):
     """One-shot hav_sample_chain: returns one original-index tensor per stage."""
     return Sampler(xyz.device).chain(xyz, Ms, p, with_info=with_info)
+
+
+class Server:
+    """Serving loop of the library (hav_server_*): continuous batching of requests whose
+    clouds sit in pinned host memory, within an HBM budget. The caller keeps each cloud's
+    tensor alive until its request has been polled to completion."""
+
+    def __init__(self, hbm_budget_bytes: int, max_batch: int = 64, streams: int = 2,
+                 p: Params | None = None):
+        self.p = p if p is not None else params()
+        self.h = lib().hav_server_create(int(hbm_budget_bytes), int(max_batch), int(streams),
+                                         C.byref(self.p))
+        if not self.h:
+            raise HavError(ERR_INVALID_ARG, "hav_server_create")
+        self._m = {}
+
+    def submit(self, xyz_pinned, M: int) -> int:
+        torch = _torch()
+        if not (isinstance(xyz_pinned, torch.Tensor) and not xyz_pinned.is_cuda
+                and xyz_pinned.is_pinned() and xyz_pinned.dtype == torch.float32
+                and xyz_pinned.dim() == 2 and xyz_pinned.shape[1] == 3 and xyz_pinned.is_contiguous()):
+            raise ValueError("xyz must be a contiguous pinned float32 CPU tensor of shape [N, 3]")
+        t = C.c_uint64(0)
+        st = lib().hav_server_submit(C.c_void_p(self.h), C.c_void_p(xyz_pinned.data_ptr()),
+                                     xyz_pinned.shape[0], int(M), C.byref(t))
+        if st != OK:
+            raise HavError(st, "hav_server_submit")
+        self._m[t.value] = int(M)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while running; else (status, idx int32 numpy array or None, info dict,
+        latency in ms)."""
+        import numpy as np
+        M = self._m[ticket]
+        out = np.empty(M, dtype=np.int32)
+        info = Info()
+        lat = C.c_double(0.0)
+        st = lib().hav_server_poll(C.c_void_p(self.h), ticket, C.c_void_p(out.ctypes.data),
+                                   C.byref(info), C.byref(lat))
+        if st == NOT_READY:
+            return None
+        del self._m[ticket]
+        return st, (out if st == OK else None), info.as_dict(), lat.value
+
+    def wait(self, ticket: int, timeout_s: float = 60.0):
+        import time
+        t0 = time.perf_counter()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"request {ticket} not done after {timeout_s} s")
+            time.sleep(50e-6)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        lib().hav_server_stats(C.c_void_p(self.h), C.byref(s))
+        return s.as_dict()
+
+    def close(self):
+        if self.h:
+            lib().hav_server_destroy(C.c_void_p(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -71,7 +71,7 @@ def test_params_default(hav):
 
 
 def test_status_strings(hav):
-    for s in range(8):
+    for s in range(9):
         assert isinstance(hav.status_string(s), str) and hav.status_string(s)
     assert hav.status_string(99) == "unknown status"
 
@@ -176,3 +176,18 @@ def test_batch_host_rejects_bad_arguments(hav):
     assert call([0, 10, 20], [0, 5]) == E          # M = 0
     assert call([0, 10, 20], [5, 5], ws=0x30010) == E
     assert call([0, 10, 20], [5, 5], ws_bytes=100) == hav.ERR_WORKSPACE_TOO_SMALL
+
+
+def test_server_create_rejects_bad_arguments(hav):
+    # rejected before any device call
+    L = hav.lib()
+    p = hav.params()
+    assert not L.hav_server_create(1 << 30, 0, 2, C.byref(p))
+    assert not L.hav_server_create(1 << 30, 2000, 2, C.byref(p))
+    assert not L.hav_server_create(1 << 30, 16, 0, C.byref(p))
+    assert not L.hav_server_create(1 << 30, 16, 9, C.byref(p))
+    bad = hav.params(layers=0)
+    assert not L.hav_server_create(1 << 30, 16, 2, C.byref(bad))
+    t = C.c_uint64(0)
+    assert L.hav_server_submit(None, C.c_void_p(0x1000), 10, 5, C.byref(t)) == hav.ERR_INVALID_ARG
+    assert L.hav_server_poll(None, 1, None, None, None) == hav.ERR_INVALID_ARG
