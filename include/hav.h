@@ -69,8 +69,13 @@ typedef struct {
   uint32_t flags;      /* HAV_FIXED_VOXEL or 0 */
   float fixed_voxel[3];/* used iff HAV_FIXED_VOXEL; each in [2^-100, 2^100] */
   int32_t spec_depth;  /* tuning only: bisection levels the device evaluates per pass of
-                          the voxel search, 1..4; 0 = library default. Results do not
+                          the voxel search, 1..3; 0 = library default (2). Results do not
                           depend on it; workspace size does. */
+  int32_t spec_budget; /* tuning only: a pass drops its finest speculative levels while
+                          their estimated voxel count exceeds this many times the window
+                          top; 0 = default (16), else 1..1024 */
+  int32_t search_blocks; /* tuning only: blocks of the voxel-search launch; 0 = as many as
+                            the device holds at once (at most one per tile), else 1..65536 */
 } hav_params_t;
 
 /* Per-call report, written by the device into caller memory (info_dev). */
@@ -207,6 +212,20 @@ hav_status_t hav_server_stats(hav_server_t* server, hav_server_stats_t* out);
 
 /* Finish the batches in flight, drop requests not yet admitted, free everything. */
 void hav_server_destroy(hav_server_t* server);
+
+/* ---- HIP graphs of library calls.
+ * Library calls only enqueue kernels (no host synchronisation, allocation or memset on
+ * the stream), so a sequence of calls can be recorded once and replayed: begin capture
+ * on a stream that is not the null stream, make the calls on it (they are recorded,
+ * not run), end the capture to get an instantiated graph, and launch it any number of
+ * times. A replay reads and writes exactly the buffers the recorded calls named, and
+ * gives the same results as the calls. The workspaces involved must be initialised
+ * before the capture. */
+typedef struct hav_graph hav_graph_t;
+hav_status_t hav_graph_capture_begin(void* stream);
+hav_status_t hav_graph_capture_end(void* stream, hav_graph_t** graph);
+hav_status_t hav_graph_launch(hav_graph_t* graph, void* stream);
+void hav_graph_destroy(hav_graph_t* graph);
 
 /* Measurement support. While enabled (on != 0), every kernel launch the library makes
  * is bracketed by a pair of HIP events recorded on the call's stream; the events are

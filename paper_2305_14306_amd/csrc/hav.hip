@@ -2074,6 +2074,8 @@ bool params_ok(const hav_params_t* p) {
   if (!std::isfinite(p->sigma) || p->sigma < 0.0 || p->sigma > 16.0) return false;
   if (p->flags & ~HAV_FIXED_VOXEL) return false;
   if (p->spec_depth < 0 || p->spec_depth > kMaxDepth) return false;
+  if (p->spec_budget < 0 || p->spec_budget > 1024) return false;
+  if (p->search_blocks < 0 || p->search_blocks > 65536) return false;
   for (int a = 0; a < 3; ++a) {
     const float as = p->aspect[a];
     if (!std::isfinite(as) || as < 0x1p-16f || as > 0x1p16f) return false;
@@ -2109,7 +2111,7 @@ __host__ __device__ inline int trim_rounds(int64_t n) {
 
 // The sampling parameters a plan needs (plain values, so a kernel can take them).
 struct ParamLite {
-  int32_t layers, ratio, t_max, depth, fixed;
+  int32_t layers, ratio, t_max, depth, fixed, spec_budget;
   double sigma;
   float aspect[3], fixed_v[3];
 };
@@ -2121,6 +2123,7 @@ ParamLite lite_of(const hav_params_t* p) {
   q.t_max = p->t_max;
   q.depth = depth_of(p);
   q.fixed = (p->flags & HAV_FIXED_VOXEL) ? 1 : 0;
+  q.spec_budget = p->spec_budget;
   q.sigma = p->sigma;
   for (int a = 0; a < 3; ++a) {
     q.aspect[a] = p->aspect[a];
@@ -2154,7 +2157,7 @@ __host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite&
   P.magic = magic_of(L);
   P.cap = cd.w.cap;
   P.sel_cap = cd.w.cap * static_cast<uint32_t>(kSelDense);
-  P.spec_mult = kSpecMult;
+  P.spec_mult = q.spec_budget ? static_cast<float>(q.spec_budget) : kSpecMult;
   P.identity = c.m == c.n ? 1 : 0;
   P.rounds = trim_rounds(c.n);
   for (int a = 0; a < 3; ++a) {
@@ -2375,7 +2378,8 @@ int grid_for(int64_t work) {
 // Blocks of a search launch: one per tile, at most as many as the device holds at
 // once (more would only wait for tickets). The limit is cached per device, kernel
 // (single or batched) and depth.
-int search_grid(int ntile, int depth, bool many) {
+int search_grid(int ntile, int depth, bool many, int requested) {
+  if (requested > 0) return std::min(requested, std::max(1, ntile));
   static std::atomic<int> cache[kMaxDevices][2][kMaxDepth + 1];
   int dev = 0;
   int cap = 1024;
@@ -2410,6 +2414,9 @@ std::atomic<int> g_timing_on{0};
 std::vector<TimedLaunch> g_timed;
 
 hipEvent_t timing_mark(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+    return nullptr;  // nothing is timed while a stream records a graph
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   if (hipEventRecord(e, st) != hipSuccess) {
@@ -2455,7 +2462,7 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
   HAV_LAUNCH(k_bin_count<One>, dim3(w.nbb), dim3(kThreads), 0, st, one);
   HAV_LAUNCH(k_bin_scan<One>, dim3(kBinChunks), dim3(kThreads), 0, st, one);
   HAV_LAUNCH(k_bin_scatter<One>, dim3(w.nbb), dim3(kThreads), 0, st, one);
-  const int sgrid = search_grid(w.ntile, P.depth, false);
+  const int sgrid = search_grid(w.ntile, P.depth, false, p->search_blocks);
   const size_t eval_lds = 2 * static_cast<size_t>((1 << P.depth) - 1) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
   for (int l = 0; l < P.nlayers; ++l) {
@@ -2590,7 +2597,7 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
   HAV_LAUNCH(k_bin_count<Many>, dim3(T[kKBin]), dim3(kThreads), 0, st, many);
   HAV_LAUNCH(k_bin_scan<Many>, dim3(T[kKBScan]), dim3(kThreads), 0, st, many);
   HAV_LAUNCH(k_bin_scatter<Many>, dim3(T[kKBin]), dim3(kThreads), 0, st, many);
-  const int sgrid = search_grid(T[kKTile], q.depth, true);
+  const int sgrid = search_grid(T[kKTile], q.depth, true, p->search_blocks);
   const size_t eval_lds = 2 * static_cast<size_t>((1 << q.depth) - 1) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
   for (int l = 0; l < max_layers; ++l) {
@@ -2661,6 +2668,8 @@ hav_params_t hav_params_default(void) {
   }
   p.flags = 0;
   p.spec_depth = 0;
+  p.spec_budget = 0;
+  p.search_blocks = 0;
   return p;
 }
 
@@ -2766,6 +2775,53 @@ hav_status_t hav_sample_batch(const float* xyz_concat, const int64_t* offsets_ho
     mo += M_host[i];
   }
   return run_batch(specs.data(), B, params, base, W.BL, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+struct hav_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+hav_status_t hav_graph_capture_begin(void* stream) {
+  if (!stream) return HAV_ERR_INVALID_ARG;
+  return hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal) ==
+                 hipSuccess
+             ? HAV_OK
+             : HAV_ERR_HIP;
+}
+
+hav_status_t hav_graph_capture_end(void* stream, hav_graph_t** out) {
+  if (!stream || !out) return HAV_ERR_INVALID_ARG;
+  *out = nullptr;
+  auto g = new hav_graph();
+  if (hipStreamEndCapture(static_cast<hipStream_t>(stream), &g->graph) != hipSuccess || !g->graph) {
+    delete g;
+    return HAV_ERR_HIP;
+  }
+  if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+    return HAV_ERR_HIP;
+  }
+  *out = g;
+  return HAV_OK;
+}
+
+hav_status_t hav_graph_launch(hav_graph_t* g, void* stream) {
+  if (!g) return HAV_ERR_INVALID_ARG;
+  return hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? HAV_OK
+                                                                                : HAV_ERR_HIP;
+}
+
+void hav_graph_destroy(hav_graph_t* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 hav_status_t hav_timing_enable(int32_t on) {

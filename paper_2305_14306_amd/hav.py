@@ -31,6 +31,8 @@ class Params(C.Structure):
         ("flags", C.c_uint32),
         ("fixed_voxel", C.c_float * 3),
         ("spec_depth", C.c_int32),
+        ("spec_budget", C.c_int32),
+        ("search_blocks", C.c_int32),
     ]
 
 
@@ -127,6 +129,14 @@ def lib():
         L.hav_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.hav_server_destroy.restype = None
         L.hav_server_destroy.argtypes = [vp]
+        L.hav_graph_capture_begin.restype = C.c_int
+        L.hav_graph_capture_begin.argtypes = [vp]
+        L.hav_graph_capture_end.restype = C.c_int
+        L.hav_graph_capture_end.argtypes = [vp, C.POINTER(C.c_void_p)]
+        L.hav_graph_launch.restype = C.c_int
+        L.hav_graph_launch.argtypes = [vp, vp]
+        L.hav_graph_destroy.restype = None
+        L.hav_graph_destroy.argtypes = [vp]
         L.hav_timing_enable.restype = C.c_int
         L.hav_timing_enable.argtypes = [C.c_int32]
         L.hav_timing_collect.restype = C.c_int
@@ -154,10 +164,10 @@ def status_string(status: int) -> str:
 
 
 def params(layers=2, layer_ratio=4, t_max=20, sigma=0.05, aspect=(1.0, 1.0, 1.0),
-           fixed_voxel=None, spec_depth=0) -> Params:
+           fixed_voxel=None, spec_depth=0, spec_budget=0, search_blocks=0) -> Params:
     p = lib().hav_params_default()
     p.layers, p.layer_ratio, p.t_max, p.sigma = layers, layer_ratio, t_max, sigma
-    p.spec_depth = spec_depth
+    p.spec_depth, p.spec_budget, p.search_blocks = spec_depth, spec_budget, search_blocks
     for a in range(3):
         p.aspect[a] = aspect[a]
     if fixed_voxel is not None:
@@ -416,6 +426,50 @@ class Server:
     def close(self):
         if self.h:
             lib().hav_server_destroy(C.c_void_p(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A recorded sequence of library calls (hav_graph_*), replayed with launch().
+
+        g = Graph.capture(stream, lambda: sampler.chain(xyz, Ms, out=out, stream=stream))
+        g.launch(stream)
+
+    The stream must not be the null stream; workspaces must be initialised first (make
+    the same calls once eagerly)."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    @classmethod
+    def capture(cls, stream, fn):
+        sp = _stream_ptr(stream)
+        st = lib().hav_graph_capture_begin(sp)
+        if st != OK:
+            raise HavError(st, "hav_graph_capture_begin")
+        g = C.c_void_p(0)
+        try:
+            fn()
+        finally:
+            st = lib().hav_graph_capture_end(sp, C.byref(g))
+        if st != OK:
+            raise HavError(st, "hav_graph_capture_end")
+        return cls(g.value)
+
+    def launch(self, stream=None):
+        st = lib().hav_graph_launch(C.c_void_p(self.h), _stream_ptr(stream))
+        if st != OK:
+            raise HavError(st, "hav_graph_launch")
+
+    def close(self):
+        if self.h:
+            lib().hav_graph_destroy(C.c_void_p(self.h))
             self.h = None
 
     def __del__(self):

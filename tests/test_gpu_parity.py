@@ -233,3 +233,11 @@ def test_spec_depth_does_not_change_results(gpu, orc, depth):
     for M in (25000, 6000):
         _check(gpu, orc, x, M, gpu.params(spec_depth=depth), f"depth {depth}")
     _check(gpu, orc, synth.lattice(8), 60, gpu.params(spec_depth=depth), f"lattice depth {depth}")
+
+
+@pytest.mark.parametrize("kw", [dict(spec_budget=1), dict(spec_budget=1024), dict(search_blocks=1),
+                                dict(search_blocks=7), dict(search_blocks=5000),
+                                dict(spec_depth=3, spec_budget=1, search_blocks=64)])
+def test_tuning_fields_do_not_change_results(gpu, orc, kw):
+    x = synth.scene_planes_blobs(60000, seed=23)
+    _check(gpu, orc, x, 15000, gpu.params(**kw), f"tuning {kw}")
