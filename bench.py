@@ -223,6 +223,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batched leg")
+    ap.add_argument("--spec-depth", type=int, default=0,
+                    help="tuning: voxel sizes per search pass (0 = library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--copy-calib", action="store_true",
@@ -246,7 +248,7 @@ def main() -> int:
     xd = torch.from_numpy(x).to(dev)
     sampler = hav.Sampler(dev)
     out = torch.empty(M, dtype=torch.int32, device=dev)
-    p = hav.params()
+    p = hav.params(spec_depth=args.spec_depth)
     print(f"bench: N={N} M={M} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
 
     _, info = sampler.sample(xd, M, p, out=out, with_info=True)

@@ -68,12 +68,12 @@ typedef struct {
                           each in [2^-16, 2^16]; default {1,1,1} */
   uint32_t flags;      /* HAV_FIXED_VOXEL or 0 */
   float fixed_voxel[3];/* used iff HAV_FIXED_VOXEL; each in [2^-100, 2^100] */
-  int32_t spec_depth;  /* tuning only: bisection levels the device evaluates per pass of
-                          the voxel search, 1..3; 0 = library default (2). Results do not
-                          depend on it; workspace size does. */
-  int32_t spec_budget; /* tuning only: a pass drops its finest speculative levels while
-                          their estimated voxel count exceeds this many times the window
-                          top; 0 = default (16), else 1..1024 */
+  int32_t spec_depth;  /* tuning only: voxel sizes one pass of the search evaluates, along
+                          the bisection path a count model predicts, 1..7; 0 = library
+                          default (4). Results do not depend on it; workspace size does. */
+  int32_t spec_budget; /* tuning only: a pass stops its chain before a size whose predicted
+                          voxel count exceeds this many times the window top; 0 = default
+                          (16), else 1..1024 */
   int32_t search_blocks; /* tuning only: blocks of the voxel-search launch; 0 = as many as
                             the device holds at once (at most one per tile), else 1..65536 */
 } hav_params_t;

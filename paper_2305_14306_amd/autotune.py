@@ -19,7 +19,7 @@ import os
 
 from . import hav
 
-DEPTHS = (1, 2, 3)
+DEPTHS = (2, 4, 6)
 BUDGETS = (4, 16, 64)
 GRIDS = (0, 256)
 

@@ -68,9 +68,9 @@ constexpr int kPerThread = kTile / kThreads;    // 8
 constexpr int kLdsCap = 4096;                   // select: LDS voxel map entries (2x tile)
 constexpr int kBrickCap = 1024;                 // search: LDS brick table per candidate
 constexpr int kBrickProbe = 64;                 // LDS probes before a point goes global
-constexpr int kMaxDepth = 3;
-constexpr int kMaxCand = (1 << kMaxDepth) - 1;  // 7
-constexpr int kDefaultDepth = 2;
+constexpr int kMaxCand = 7;                     // candidate scales per search pass
+constexpr int kMaxDepth = kMaxCand;
+constexpr int kDefaultDepth = 4;
 constexpr int kGroups = 16;
 constexpr int kStride = 32;                     // uint32 spacing of hot counters (128 B)
 constexpr int kBinBits = 12;
@@ -84,6 +84,10 @@ constexpr int kScanPer = kScanTile / kThreads;
 constexpr int kSelDense = 4;                    // voxel value slots per brick-table slot
 constexpr uint64_t kMagic = 0x4841565F57533031ull;
 constexpr int kMaxDevices = 64;
+constexpr int kTieLds = 4096;                   // tie bucket staged (and sorted) in LDS
+constexpr int kTieRank = 128;                   // tie buckets up to this size: rank directly
+constexpr int kTrimBits = 8;                    // priority digit of one trim round
+constexpr int kTrimBins = 1 << kTrimBits;
 constexpr int kHotCap = 4096;                   // brick grids this small use replicas
 constexpr int kReps = 16;                       // replicas of a hot brick table
 constexpr int kClaimCap = 2 * kTile;            // claims per tile and candidate
@@ -124,6 +128,8 @@ struct Ctrl {
 struct SState {
   float lo, hi;
   uint32_t c_hi;  // count at hi (0: hi is the initial bracket, never evaluated)
+  uint32_t c_lo;  // count at lo (0: lo is 0, never evaluated)
+  int32_t pdir[kMaxCand];  // predicted step after candidate k: 0 down (hi = s), 1 up (lo = s)
   int32_t evals, done, accepted;
   int32_t nc, set, prev_set, prev_nc;
   uint32_t prev_hashed;  // bit k: candidate k of the previous pass used a hashed table
@@ -148,7 +154,7 @@ struct Plan {  // per-call constants (kernel argument)
   uint32_t sel_cap;   // voxel value slots: dense voxel grids up to this size
   float spec_mult;    // speculation budget of the search, in multiples of the window top
   int32_t identity;   // M == N: output 0..N-1, nothing else runs
-  int32_t rounds;     // radix rounds of the trim before the bucket is settled
+  int32_t rounds[HAV_MAX_LAYERS];  // radix rounds of each layer's trim before k_ties
 };
 
 constexpr int kPubWords = static_cast<int>(sizeof(SState) / 4);
@@ -163,7 +169,7 @@ struct alignas(256) Header {
   alignas(256) uint32_t sync_top[kStride];
   uint32_t sync_grp[kGroups][kStride];
   uint32_t acc[kMaxCand][kGroups][kStride];
-  uint32_t hist[kGroups][256];
+  uint32_t hist[kGroups][kTrimBins];  // trim: priority digit histograms
   uint32_t tie_cur[kGroups][kStride];
   // voxel search: double-buffered per-pass counts, tile tickets, completed tiles,
   // the pass whose candidates are published, finish and failure flags
@@ -347,35 +353,38 @@ __device__ __forceinline__ void max_coords(const Frame& fr, const float* inv, ui
   for (int ax = 0; ax < 3; ++ax) mk[ax] = axis_coord(fr.mx[ax] - fr.mn[ax], inv[ax]);
 }
 
-// Candidates of the next pass: the bisection subtree of up to P.depth levels below
-// the bracket [lo, hi], in heap order. Node k with bracket [a, b] evaluates
-// s = (a+b)/2; its child 2k+1 ([a, s]) is taken when the count is below m, 2k+2
-// ([s, b]) when above the window -- the same arithmetic as one bisection step at a
-// time. The depth is lowered while the finest candidate would be much finer than a
-// scale whose count is known (the count grows at most with the cube of the scale
-// ratio), since such candidates cost the most and are rarely the ones taken.
-__device__ void plan_search(SState* st, const Plan& P, const Frame& fr, uint32_t upper) {
+// Candidates of the next pass: the next P.depth steps of the bisection as a model
+// predicts them. Candidate 0 is the midpoint of the bracket [lo, hi]; candidate k+1
+// is the midpoint of the half the model expects step k to keep (down, to [lo, s], when
+// the count at s looks below m; up otherwise), computed with the same arithmetic as
+// bisection itself. A candidate counts as an evaluation only if every step before it
+// went the predicted way (search_step), so results are those of plain bisection; a
+// good model just gets several steps out of one pass. The model is a power law
+// Cnt(s) = c_ref (s_ref / s)^D through the counts known at the bracket ends (D fitted
+// when both are known, else 2); the chain stops early where it predicts acceptance.
+__device__ void plan_search(SState* st, const Plan& P, const Frame& fr, uint32_t m, uint32_t upper) {
   const int left = P.t_max - st->evals;
-  int D = left < P.depth ? left : P.depth;
-  const float cref = st->c_hi ? static_cast<float>(st->c_hi) : 1.0f;
-  const float budget = P.spec_mult * static_cast<float>(upper) + 64.0f;
-  while (D > 1) {
-    const float smin = st->lo + (st->hi - st->lo) / static_cast<float>(1 << D);
-    const float ratio = st->hi / smin;
-    if (cref * ratio * ratio * ratio <= budget) break;
-    --D;
+  const int D = left < P.depth ? left : P.depth;
+  float sref = st->hi, cref = st->c_hi ? static_cast<float>(st->c_hi) : 1.0f, dim = 2.0f;
+  if (st->c_lo && st->c_hi && st->lo > 0.0f && st->c_lo > st->c_hi) {
+    dim = __logf(static_cast<float>(st->c_lo) / static_cast<float>(st->c_hi)) / __logf(st->hi / st->lo);
+  } else if (st->c_lo && !st->c_hi) {
+    sref = st->lo;
+    cref = static_cast<float>(st->c_lo);
   }
-  const int nc = (1 << D) - 1;
-  float a[kMaxCand], b[kMaxCand];
-  a[0] = st->lo;
-  b[0] = st->hi;
-  for (int k = 0; k < nc; ++k) {
-    const float s = (a[k] + b[k]) * 0.5f;
+  float lo = st->lo, hi = st->hi;
+  int nc = 0;
+  for (int k = 0; k < D; ++k) {
+    const float s = (lo + hi) * 0.5f;
     st->cand_s[k] = s;
     for (int ax = 0; ax < 3; ++ax) {
       const float v = s * P.aspect[ax];
       st->cand_inv[k][ax] = 1.0f / v;
     }
+    const float pred = cref * __expf(dim * __logf(sref / s));
+    // a speculative candidate predicted far finer than the window's scale would cost
+    // a lot (its count, and so its table work, is large): end the chain before it
+    if (k > 0 && pred > P.spec_mult * static_cast<float>(upper)) break;
     uint32_t mk[3];
     max_coords(fr, st->cand_inv[k], mk);
     const uint64_t nbx = (mk[0] >> kBrickShift) + 1, nby = (mk[1] >> kBrickShift) + 1,
@@ -385,18 +394,20 @@ __device__ void plan_search(SState* st, const Plan& P, const Frame& fr, uint32_t
     st->cand_hot[k] = nb <= static_cast<uint64_t>(kHotCap) ? 1 : 0;
     st->cand_nb[k][0] = static_cast<uint32_t>(nbx);
     st->cand_nb[k][1] = static_cast<uint32_t>(nby);
-    if (2 * k + 2 < nc) {
-      a[2 * k + 1] = a[k];
-      b[2 * k + 1] = s;
-      a[2 * k + 2] = s;
-      b[2 * k + 2] = b[k];
-    }
+    nc = k + 1;
+    if (pred >= static_cast<float>(m) && pred <= static_cast<float>(upper)) break;
+    st->pdir[k] = pred < static_cast<float>(m) ? 0 : 1;
+    if (st->pdir[k] == 0)
+      hi = s;
+    else
+      lo = s;
   }
   st->nc = nc;
 }
 
-// One bisection step per evaluated candidate on a pass's counts, walking the
-// pass's subtree; then the next pass's candidates, or the final scale.
+// The bisection steps of a pass, on its counts: candidate k is used only while the
+// steps before it went the predicted way; then the next pass's candidates, or the
+// final scale.
 __device__ void search_step(SState* st, const uint32_t* cnt, const Plan& P, const Frame& fr,
                             uint32_t m, uint32_t upper) {
   st->prev_set = st->set;
@@ -405,8 +416,7 @@ __device__ void search_step(SState* st, const uint32_t* cnt, const Plan& P, cons
   for (int k = 0; k < st->nc; ++k) hm |= static_cast<uint32_t>(st->cand_dense[k] == 0) << k;
   st->prev_hashed = hm;
   st->set ^= 1;
-  int k = 0;
-  while (k < st->nc) {
+  for (int k = 0; k < st->nc; ++k) {
     const uint32_t cc = cnt[k];
     const float s = st->cand_s[k];
     st->evals += 1;
@@ -416,14 +426,16 @@ __device__ void search_step(SState* st, const uint32_t* cnt, const Plan& P, cons
       st->s_final = s;
       return;
     }
-    if (cc < m) {
+    const int dir = cc < m ? 0 : 1;
+    if (dir == 0) {
       st->hi = s;
       st->c_hi = cc;
-      k = 2 * k + 1;
     } else {
       st->lo = s;
-      k = 2 * k + 2;
+      st->c_lo = cc;
     }
+    if (st->evals >= P.t_max) break;
+    if (k + 1 < st->nc && dir != st->pdir[k]) break;  // the rest of the chain is off the path
   }
   if (st->evals >= P.t_max) {
     // no size in the window: the finest size with too many voxels if there was one
@@ -432,7 +444,7 @@ __device__ void search_step(SState* st, const uint32_t* cnt, const Plan& P, cons
     st->s_final = st->lo > 0.0f ? st->lo : st->hi;
     return;
   }
-  plan_search(st, P, fr, upper);
+  plan_search(st, P, fr, m, upper);
 }
 
 __device__ void set_select_grid(Ctrl* c, const Plan& P, const Frame& fr) {
@@ -494,6 +506,7 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
     s0->lo = 0.0f;
     s0->hi = h->frame.hi0;
     s0->c_hi = 0;
+    s0->c_lo = 0;
     s0->evals = 0;
     s0->done = 0;
     s0->accepted = 0;
@@ -502,7 +515,7 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
     s0->prev_nc = 0;
     s0->prev_hashed = 0;
     s0->s_final = 0.0f;
-    plan_search(s0, P, h->frame, c->upper);
+    plan_search(s0, P, h->frame, c->m, c->upper);
   }
 }
 
@@ -1292,7 +1305,7 @@ __device__ int wait_pass(Header* h, int p, uint32_t* err) {
 
 __device__ __forceinline__ void search_lds_init(uint64_t* lds, int depth, uint64_t*& lvals,
                                                 uint64_t*& lkeys) {
-  const int ncap = (1 << depth) - 1;
+  const int ncap = depth;
   lvals = lds;
   lkeys = lds + static_cast<size_t>(ncap) * kBrickCap;
   for (int e = threadIdx.x; e < ncap * kBrickCap; e += kThreads) {
@@ -1384,36 +1397,51 @@ __device__ __forceinline__ bool lds_try_min(uint64_t* tk, uint64_t* tv, uint64_t
 }
 
 // Global selection-table update of voxel `key` (dense: slot index) with `val`.
-__device__ __forceinline__ void select_global(const Ws& w, int dense, uint64_t key, uint64_t val,
+// Hashed selection-table update of voxel `key` (packed coordinate) with `val`; true
+// if this call claimed the voxel's slot (and recorded it).
+__device__ __forceinline__ bool select_hashed(const Ws& w, uint64_t key, uint64_t val,
                                               int32_t* list, int* s_ncl) {
-  if (dense) {
-    // a plain read can only be stale by being too large: skip when ours is not
-    // smaller; the tile whose atomic finds the slot empty records it
-    const uint32_t sl = static_cast<uint32_t>(key);
-    if (val < w.svals[sl]) {
-      const unsigned long long old = atomicMin(&w.svals[sl], static_cast<unsigned long long>(val));
-      if (old == ~0ull) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(sl);
-    }
-    return;
-  }
   uint32_t sl = table_hash(key) & w.cmask;
   while (true) {
     const unsigned long long k = w.skeys[sl];
     const unsigned long long cur = w.svals[sl];
     if (k == key) {
       if (val < cur) atomicMin(&w.svals[sl], static_cast<unsigned long long>(val));
-      return;
+      return false;
     }
     if (k == kEmptyKey) {
       const unsigned long long prev = atomicCAS(&w.skeys[sl], kEmptyKey, key);
       if (prev == kEmptyKey || prev == key) {
         if (prev == kEmptyKey) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(sl);
         atomicMin(&w.svals[sl], static_cast<unsigned long long>(val));
-        return;
+        return prev == kEmptyKey;
       }
     }
     sl = (sl + 1) & w.cmask;
   }
+}
+
+// The digit whose bucket holds rank (0-based) in a 256-bin histogram, and the rank
+// inside that bucket: one bin per thread and a block scan. Every thread gets both.
+__device__ void find_digit(const uint32_t* hist, uint32_t rank, int* digit, uint32_t* rest) {
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  __shared__ int s_d;
+  __shared__ uint32_t s_r;
+  const uint32_t v = threadIdx.x < 256 ? hist[threadIdx.x] : 0u;
+  if (threadIdx.x == 0) {
+    s_d = 255;
+    s_r = 0;
+  }
+  uint32_t ex;
+  block_exclusive_scan<kThreads>(v, &ex, s_tmp);
+  if (threadIdx.x < 256 && rank >= ex && rank < ex + v) {
+    s_d = threadIdx.x;
+    s_r = rank - ex;
+  }
+  __syncthreads();
+  *digit = s_d;
+  *rest = s_r;
+  __syncthreads();
 }
 
 // Centre-closest point of every occupied voxel at the chosen size (Sec. 3.2): the
@@ -1528,20 +1556,45 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   }
   __syncthreads();
   int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
-  for (int e = threadIdx.x; e < kLdsCap; e += kThreads) {
-    const uint64_t val = lvals[e];
-    if (val == ~0ull) continue;
-    uint64_t key;
-    if (vol) {
-      if (e >= static_cast<int>(vol)) continue;
-      const uint32_t gx = bl0 + static_cast<uint32_t>(e) % bdx;
-      const uint32_t t2 = static_cast<uint32_t>(e) / bdx;
-      const uint32_t gy = bl1 + t2 % bdy, gz = bl2 + t2 / bdy;
-      key = dense ? gx + nx * (gy + ny * gz) : pack_key(gx, gy, gz);
-    } else {
-      key = lkeys[e];
+  // thread t owns entries t + j*kThreads; a dense table's minima are issued four at a
+  // time so that their round trips overlap (the atomic's old value says whether this
+  // tile is the voxel's first, which then records the slot)
+  for (int e0 = 0; e0 < kLdsCap; e0 += 4 * kThreads) {
+    uint64_t key[4], val[4];
+    uint32_t has = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = e0 + j * kThreads + static_cast<int>(threadIdx.x);
+      key[j] = 0ull;
+      val[j] = lvals[e];
+      if (val[j] == ~0ull) continue;
+      if (vol) {
+        if (e >= static_cast<int>(vol)) continue;
+        const uint32_t gx = bl0 + static_cast<uint32_t>(e) % bdx;
+        const uint32_t t2 = static_cast<uint32_t>(e) / bdx;
+        const uint32_t gy = bl1 + t2 % bdy, gz = bl2 + t2 / bdy;
+        key[j] = dense ? gx + nx * (gy + ny * gz) : pack_key(gx, gy, gz);
+      } else {
+        key[j] = lkeys[e];
+      }
+      has |= 1u << j;
     }
-    select_global(w, dense, key, val, list, &s_ncl);
+    if (!has) continue;
+    if (!dense) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if ((has >> j) & 1u) select_hashed(w, key[j], val[j], list, &s_ncl);
+      continue;
+    }
+    uint64_t old[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      old[j] = ((has >> j) & 1u) ? atomicMin(&w.svals[static_cast<uint32_t>(key[j])],
+                                             static_cast<unsigned long long>(val[j]))
+                                 : 0ull;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (((has >> j) & 1u) && old[j] == ~0ull) list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(key[j]);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1575,67 +1628,46 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
 
 // ----------------------------------------------------------------------------- trim
 
-// The digit whose bucket holds rank (0-based) in a 256-bin histogram, and the rank
-// inside that bucket: one bin per thread and a block scan. Every thread gets both.
-__device__ void find_digit(const uint32_t* hist, uint32_t rank, int* digit, uint32_t* rest) {
-  __shared__ uint32_t s_tmp[kThreads / 64];
-  __shared__ int s_d;
-  __shared__ uint32_t s_r;
-  const uint32_t v = threadIdx.x < 256 ? hist[threadIdx.x] : 0u;
-  if (threadIdx.x == 0) {
-    s_d = 255;
-    s_r = 0;
-  }
-  uint32_t ex;
-  block_exclusive_scan<kThreads>(v, &ex, s_tmp);
-  if (threadIdx.x < 256 && rank >= ex && rank < ex + v) {
-    s_d = threadIdx.x;
-    s_r = rank - ex;
-  }
-  __syncthreads();
-  *digit = s_d;
-  *rest = s_r;
-  __syncthreads();
-}
-
+// One radix round of the trim (keep the m voxels of smallest priority): histogram of
+// the next 8 priority bits of the voxels still in the bucket, then the last block
+// fixes the digit holding the rank.
 template <class Src>
 __global__ void __launch_bounds__(kThreads) k_trim_hist(Src src, int L, int round) {
   int bx, gx;
   const Cloud& cd = cloud_of(src, kKTile, bx, gx);
-  if (!layer_due(cd, L) || round >= cd.P.rounds) return;
+  if (!layer_due(cd, L) || round >= cd.P.rounds[L]) return;
   const Ws& w = cd.w;
   Header* h = w.h;
   Ctrl* c = &h->ctrl;
   if (!c->trim) return;
-  __shared__ uint32_t lh[256];
-  for (int i = threadIdx.x; i < 256; i += kThreads) lh[i] = 0;
+  __shared__ uint32_t lh[kTrimBins];
+  for (int i = threadIdx.x; i < kTrimBins; i += kThreads) lh[i] = 0;
   __syncthreads();
   const int tile = bx;
   const int n = w.scn[tile];
   const int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
-  const int dshift = 56 - 8 * round;
+  const int dshift = 64 - kTrimBits * (round + 1);
   const uint64_t pref = c->prefix;
   for (int i = threadIdx.x; i < n; i += kThreads) {
     const uint64_t p = voxel_priority(sel_key(w, c, list[i]));
-    if (round > 0 && (p >> (dshift + 8)) != (pref >> (dshift + 8))) continue;
-    atomicAdd(&lh[(p >> dshift) & 255u], 1u);
+    if (round > 0 && (p >> (dshift + kTrimBits)) != (pref >> (dshift + kTrimBits))) continue;
+    atomicAdd(&lh[(p >> dshift) & (kTrimBins - 1)], 1u);
   }
   __syncthreads();
   const int g = tile & (kGroups - 1);
-  for (int i = threadIdx.x; i < 256; i += kThreads)
+  for (int i = threadIdx.x; i < kTrimBins; i += kThreads)
     if (lh[i]) atomicAdd(&h->hist[g][i], lh[i]);
   if (!arrive_last(h, bx, gx)) return;
-  // last block: total histogram, pick the digit holding rank
-  __shared__ uint32_t tot[256];
-  for (int i = threadIdx.x; i < 256; i += kThreads) {
-    uint32_t s = 0;
-    for (int q = 0; q < kGroups; ++q) s += take(&h->hist[q][i]);
-    tot[i] = s;
+  // last block: the total histogram (emptied as read), then the digit holding rank
+  for (int i = threadIdx.x; i < kTrimBins; i += kThreads) {
+    uint32_t t = 0;
+    for (int q = 0; q < kGroups; ++q) t += take(&h->hist[q][i]);
+    lh[i] = t;
   }
   __syncthreads();
   int b;
   uint32_t rest;
-  find_digit(tot, c->rank, &b, &rest);
+  find_digit(lh, c->rank, &b, &rest);
   if (threadIdx.x == 0) {
     c->rank = rest;
     c->prefix |= static_cast<uint64_t>(b) << dshift;
@@ -1658,7 +1690,7 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
   const int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
   const int trim = c->trim;
   const int dense = c->sel_dense;
-  const int shift = 64 - 8 * c->rounds_done;  // bits below the decided prefix
+  const int shift = 64 - kTrimBits * c->rounds_done;  // bits below the decided prefix
   const uint64_t pref_hi = shift >= 64 ? 0ull : (c->prefix >> shift);
   const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
   const int g = tile & (kGroups - 1);
@@ -1714,11 +1746,9 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
   if (threadIdx.x == 0) w.scn[tile] = 0;
 }
 
-// One block: the rank-th smallest priority inside the bucket (radix select over the
-// bits below the prefix), then mark every queued voxel up to it. The bucket is
-// staged in LDS when it fits (it normally holds a handful of voxels).
-constexpr int kTieLds = 4096;
-
+// One block: the rank-th smallest priority inside the bucket, then mark every queued
+// voxel up to it. A bucket that fits LDS is sorted there; a larger one (possible only
+// when a search fell back to a scale with far too many voxels) is radix-selected.
 template <class Src>
 __global__ void __launch_bounds__(kThreads) k_ties(Src src, int L) {
   int bx, gx;
@@ -1732,6 +1762,7 @@ __global__ void __launch_bounds__(kThreads) k_ties(Src src, int L) {
   __shared__ uint64_t s_pref;
   __shared__ uint32_t s_rank;
   __shared__ uint64_t lp[kTieLds];
+  __shared__ uint64_t ls[kTieLds];
   __shared__ int32_t lo[kTieLds];
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
@@ -1763,26 +1794,69 @@ __global__ void __launch_bounds__(kThreads) k_ties(Src src, int L) {
     }
     __syncthreads();
   }
-  const int shift = 64 - 8 * c->rounds_done;
+  const int shift = 64 - kTrimBits * c->rounds_done;  // bits below the bucket's prefix
   const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
-  for (int sh = shift - 8; sh >= 0; sh -= 8) {
-    for (int i = threadIdx.x; i < 256; i += kThreads) hst[i] = 0;
-    __syncthreads();
-    const uint64_t pref = s_pref;
+  if (staged && total <= static_cast<uint32_t>(kTieRank)) {
+    // small bucket: the member whose rank is s_rank (priorities are distinct)
+    const uint32_t want = s_rank;
     for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
-      const uint64_t p = staged ? lp[j] : w.tie_p[locate(j)];
-      if (sh + 8 < 64 && (p >> (sh + 8)) != (pref >> (sh + 8))) continue;
-      atomicAdd(&hst[(p >> sh) & 255u], 1u);
+      const uint64_t pj = lp[j];
+      uint32_t r = 0;
+      for (uint32_t i = 0; i < total; ++i) r += lp[i] < pj ? 1u : 0u;
+      if (r == want) ls[0] = pj;
     }
     __syncthreads();
-    int b;
-    uint32_t rest;
-    find_digit(hst, s_rank, &b, &rest);
-    if (threadIdx.x == 0) {
-      s_rank = rest;
-      s_pref = pref | (static_cast<uint64_t>(b) << sh);
-    }
+    if (threadIdx.x == 0) s_pref = ls[0];
     __syncthreads();
+  } else if (staged) {
+    // the bucket sorted in LDS (bitonic, padded with the largest key); the rank-th
+    // entry is the threshold
+    uint32_t np2 = 1;
+    while (np2 < total) np2 <<= 1;
+    for (uint32_t j = threadIdx.x; j < np2; j += kThreads) ls[j] = j < total ? lp[j] : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= np2; k <<= 1) {
+      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+        for (uint32_t i = threadIdx.x; i < np2; i += kThreads) {
+          const uint32_t l = i ^ jj;
+          if (l > i) {
+            const uint64_t a = ls[i], bb = ls[l];
+            const bool up = (i & k) == 0;
+            if ((a > bb) == up) {
+              ls[i] = bb;
+              ls[l] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (threadIdx.x == 0) s_pref = ls[s_rank];
+    __syncthreads();
+  } else {
+    // radix select over the remaining bits, at most 8 at a time
+    for (int hi = shift; hi > 0;) {
+      const int wdt = hi >= 8 ? 8 : hi;
+      const int sh = hi - wdt;
+      for (int i = threadIdx.x; i < 256; i += kThreads) hst[i] = 0;
+      __syncthreads();
+      const uint64_t pref = s_pref;
+      for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
+        const uint64_t p = staged ? lp[j] : w.tie_p[locate(j)];
+        if (hi < 64 && (p >> hi) != (pref >> hi)) continue;
+        atomicAdd(&hst[(p >> sh) & ((1u << wdt) - 1u)], 1u);
+      }
+      __syncthreads();
+      int b;
+      uint32_t rest;
+      find_digit(hst, s_rank, &b, &rest);
+      if (threadIdx.x == 0) {
+        s_rank = rest;
+        s_pref = pref | (static_cast<uint64_t>(b) << sh);
+      }
+      __syncthreads();
+      hi = sh;
+    }
   }
   const uint64_t thr = s_pref;  // the rank-th smallest priority of the bucket
   for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
@@ -1988,7 +2062,7 @@ __host__ __device__ inline Layout make_layout(int64_t n, int depth) {
   L.cap_ws = table_cap(n);
   L.ntile_ws = static_cast<int32_t>((n + kTile - 1) / kTile);
   L.nscan_ws = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
-  L.ncmax = (1 << depth) - 1;
+  L.ncmax = depth;
   L.tie_seg = static_cast<int64_t>((L.ntile_ws + kGroups - 1) / kGroups) * kTile;
   const size_t N = static_cast<size_t>(n);
   const size_t NP = static_cast<size_t>(L.ntile_ws) * kTile;
@@ -2103,9 +2177,11 @@ __host__ __device__ inline void layer_sizes(int64_t M, int k, int r, int64_t* m)
 
 // Radix rounds over the top priority bits before one block settles the bucket:
 // enough that the expected bucket (n / 256^R) stays small.
-__host__ __device__ inline int trim_rounds(int64_t n) {
+// Radix rounds of a trim over about v voxels: enough that the expected bucket left
+// for k_ties (v / 256^R) is small enough to rank directly.
+__host__ __device__ inline int trim_rounds(int64_t v) {
   int R = 1;
-  while (R < 7 && (n >> (8 * R)) > 2048) ++R;
+  while (R < 7 && (v >> (kTrimBits * R)) > kTieRank / 2) ++R;
   return R;
 }
 
@@ -2159,7 +2235,6 @@ __host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite&
   P.sel_cap = cd.w.cap * static_cast<uint32_t>(kSelDense);
   P.spec_mult = q.spec_budget ? static_cast<float>(q.spec_budget) : kSpecMult;
   P.identity = c.m == c.n ? 1 : 0;
-  P.rounds = trim_rounds(c.n);
   for (int a = 0; a < 3; ++a) {
     P.aspect[a] = q.aspect[a];
     P.fixed_v[a] = q.fixed_v[a];
@@ -2170,12 +2245,14 @@ __host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite&
   for (int l = 0; l < HAV_MAX_LAYERS; ++l) {
     P.m[l] = 0;
     P.upper[l] = 0;
+    P.rounds[l] = 0;
   }
   for (int l = 0; l < q.layers; ++l) {
     if (m[l] == 0) continue;
     const double up = floor(static_cast<double>(m[l]) * (1.0 + q.sigma));
     P.m[nl] = static_cast<uint32_t>(m[l]);
     P.upper[nl] = up >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(up);
+    P.rounds[nl] = trim_rounds(static_cast<int64_t>(P.upper[nl]));
     ++nl;
   }
   P.nlayers = nl;
@@ -2386,7 +2463,7 @@ int search_grid(int ntile, int depth, bool many, int requested) {
   if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) {
     int c = cache[dev][many][depth].load(std::memory_order_relaxed);
     if (c == 0) {
-      const size_t lds = 2 * static_cast<size_t>((1 << depth) - 1) * kBrickCap * sizeof(uint64_t);
+      const size_t lds = 2 * static_cast<size_t>(depth) * kBrickCap * sizeof(uint64_t);
       int per_cu = 0, cus = 0;
       const void* fn = many ? reinterpret_cast<const void*>(&k_search_many)
                             : reinterpret_cast<const void*>(&k_search);
@@ -2463,12 +2540,12 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
   HAV_LAUNCH(k_bin_scan<One>, dim3(kBinChunks), dim3(kThreads), 0, st, one);
   HAV_LAUNCH(k_bin_scatter<One>, dim3(w.nbb), dim3(kThreads), 0, st, one);
   const int sgrid = search_grid(w.ntile, P.depth, false, p->search_blocks);
-  const size_t eval_lds = 2 * static_cast<size_t>((1 << P.depth) - 1) * kBrickCap * sizeof(uint64_t);
+  const size_t eval_lds = 2 * static_cast<size_t>(P.depth) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
   for (int l = 0; l < P.nlayers; ++l) {
     if (!P.fixed) HAV_LAUNCH(k_search, dim3(sgrid), dim3(kThreads), eval_lds, st, one, l);
     HAV_LAUNCH(k_select<One>, dim3(w.ntile), dim3(kThreads), sel_lds, st, one, l);
-    for (int r = 0; r < P.rounds; ++r)
+    for (int r = 0; r < P.rounds[l]; ++r)
       HAV_LAUNCH(k_trim_hist<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l, r);
     HAV_LAUNCH(k_mark<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l);
     HAV_LAUNCH(k_ties<One>, dim3(1), dim3(kThreads), 0, st, one, l);
@@ -2568,7 +2645,7 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
     any_work = true;
     any_search |= !cd.P.fixed;
     max_layers = std::max(max_layers, cd.P.nlayers);
-    max_rounds = std::max(max_rounds, cd.P.rounds);
+    for (int l = 0; l < cd.P.nlayers; ++l) max_rounds = std::max(max_rounds, cd.P.rounds[l]);
   }
   for (int32_t first = 0; first < B; first += kSetupChunk) {
     SetupArgs a;
@@ -2598,7 +2675,7 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
   HAV_LAUNCH(k_bin_scan<Many>, dim3(T[kKBScan]), dim3(kThreads), 0, st, many);
   HAV_LAUNCH(k_bin_scatter<Many>, dim3(T[kKBin]), dim3(kThreads), 0, st, many);
   const int sgrid = search_grid(T[kKTile], q.depth, true, p->search_blocks);
-  const size_t eval_lds = 2 * static_cast<size_t>((1 << q.depth) - 1) * kBrickCap * sizeof(uint64_t);
+  const size_t eval_lds = 2 * static_cast<size_t>(q.depth) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
   for (int l = 0; l < max_layers; ++l) {
     if (any_search) {

@@ -36,7 +36,7 @@ def source_digest() -> str:
 
 
 def short_name(name: str) -> str:
-    m = re.search(r"\b(k_\w+)\(", name)
+    m = re.search(r"\b(k_\w+)\s*[<(]", name)
     if m:
         return m.group(1)
     if "neg_kernel" in name:

@@ -114,7 +114,7 @@ def test_host_rejects_bad_arguments(hav):
     for kw in (dict(layers=0), dict(layers=9), dict(layer_ratio=1), dict(layer_ratio=17),
                dict(t_max=0), dict(t_max=21), dict(sigma=-1.0), dict(sigma=float("nan")),
                dict(aspect=(1.0, 0.0, 1.0)), dict(aspect=(1.0, float("inf"), 1.0)),
-               dict(fixed_voxel=0.0), dict(fixed_voxel=float("nan")), dict(spec_depth=4),
+               dict(fixed_voxel=0.0), dict(fixed_voxel=float("nan")), dict(spec_depth=8),
                dict(spec_depth=-1), dict(spec_budget=-1), dict(spec_budget=1025),
                dict(search_blocks=-1), dict(search_blocks=65537)):
         assert _call(hav, p=hav.params(**kw)) == E, kw

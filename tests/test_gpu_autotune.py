@@ -20,7 +20,7 @@ def test_autotune_single_and_batch(tmp_path):
     offs = np.concatenate([[0], np.cumsum([c.shape[0] for c in clouds])])
     xb = torch.from_numpy(np.concatenate(clouds)).cuda()
     bbest, btable = autotune.tune_batch(xb, offs, Ms, reps=1,
-                                        cands=list(autotune.candidates(depths=(1, 2), budgets=(16,))))
+                                        cands=list(autotune.candidates(depths=(1, 4), budgets=(16,))))
     assert bbest in [c for c, _ in btable]
     path = str(tmp_path / "tune.json")
     got = autotune.cached_or_tune(path, x, 20000)

@@ -227,7 +227,7 @@ def test_workspace_reuse_across_sizes(gpu, orc):
                 assert np.array_equal(idx.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("depth", [1, 2, 3, 4, 7])
 def test_spec_depth_does_not_change_results(gpu, orc, depth):
     x = synth.scene_planes_blobs(100000, seed=21)
     for M in (25000, 6000):
