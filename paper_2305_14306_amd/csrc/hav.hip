@@ -67,7 +67,7 @@ constexpr int kTile = 2048;                     // points per search/select tile
 constexpr int kPerThread = kTile / kThreads;    // 8
 constexpr int kLdsCap = 4096;                   // select: LDS voxel map entries (2x tile)
 constexpr int kBrickCap = 1024;                 // search: LDS brick table per candidate
-constexpr int kBrickProbe = 64;                 // LDS probes before a point goes global
+constexpr int kBrickProbe = 64;                 // LDS probes before a run goes to the global table
 constexpr int kMaxCand = 7;                     // candidate scales per search pass
 constexpr int kMaxDepth = kMaxCand;
 constexpr int kDefaultDepth = 4;
@@ -84,7 +84,7 @@ constexpr int kScanPer = kScanTile / kThreads;
 constexpr int kSelDense = 4;                    // voxel value slots per brick-table slot
 constexpr uint64_t kMagic = 0x4841565F57533031ull;
 constexpr int kMaxDevices = 64;
-constexpr int kTieLds = 4096;                   // tie bucket staged (and sorted) in LDS
+constexpr int kTieLds = 1024;                   // tie bucket staged (and sorted) in LDS
 constexpr int kTieRank = 128;                   // tie buckets up to this size: rank directly
 constexpr int kTrimBits = 8;                    // priority digit of one trim round
 constexpr int kTrimBins = 1 << kTrimBits;
@@ -171,6 +171,8 @@ struct alignas(256) Header {
   uint32_t acc[kMaxCand][kGroups][kStride];
   uint32_t hist[kGroups][kTrimBins];  // trim: priority digit histograms
   uint32_t tie_cur[kGroups][kStride];
+  uint32_t ord[kStride];          // dispatch-order block ids of the tag scans
+  uint32_t scan_bad[kStride];     // a tag-scan wait gave up
   // voxel search: double-buffered per-pass counts, tile tickets, completed tiles,
   // the pass whose candidates are published, finish and failure flags
   uint32_t sacc[2][kMaxCand][kGroups][kStride];
@@ -1675,8 +1677,130 @@ __global__ void __launch_bounds__(kThreads) k_trim_hist(Src src, int L, int roun
   }
 }
 
-// Keep the representatives below the prefix bucket, queue the bucket's members for
-// k_ties, and empty the selection table.
+// The last block of k_mark: the rank-th smallest priority inside the bucket, then
+// mark every queued voxel up to it. A bucket that fits LDS is ranked or sorted there; a
+// larger one (possible only when a search fell back to a size with far too many
+// voxels) is radix-selected from global memory. The queue was written in the same
+// launch, so it is read with agent-scope atomic loads.
+__device__ void settle_ties(const Ws& w, Header* h) {
+  Ctrl* c = &h->ctrl;
+  __shared__ uint32_t cnt_g[kGroups + 1];  // exclusive prefix over groups
+  __shared__ uint32_t hst[256];
+  __shared__ uint64_t s_pref;
+  __shared__ uint32_t s_rank;
+  __shared__ uint64_t lp[kTieLds];
+  __shared__ uint64_t ls[kTieLds];
+  __shared__ int32_t lo[kTieLds];
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int q = 0; q < kGroups; ++q) {
+      const uint32_t t = take(&h->tie_cur[q][0]);
+      cnt_g[q] = acc;
+      acc += t < w.tie_seg ? t : static_cast<uint32_t>(w.tie_seg);
+    }
+    cnt_g[kGroups] = acc;
+    s_pref = c->prefix;
+    s_rank = c->rank;
+  }
+  __syncthreads();
+  if (!c->trim) return;
+  const uint32_t total = cnt_g[kGroups];
+  const bool staged = total <= static_cast<uint32_t>(kTieLds);
+  // item j of the bucket: group q with cnt_g[q] <= j < cnt_g[q+1]
+  auto locate = [&](uint32_t j) -> int64_t {
+    int q = 0;
+    while (j >= cnt_g[q + 1]) ++q;
+    return static_cast<int64_t>(q) * w.tie_seg + (j - cnt_g[q]);
+  };
+  if (staged) {
+    for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
+      const int64_t at = locate(j);
+      lp[j] = ld_agent(&w.tie_p[at]);
+      lo[j] = ld_agent(&w.tie_o[at]);
+    }
+    __syncthreads();
+  }
+  const int shift = 64 - kTrimBits * c->rounds_done;  // bits below the bucket's prefix
+  const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
+  if (staged && total <= static_cast<uint32_t>(kTieRank)) {
+    // small bucket: the member whose rank is s_rank (priorities are distinct)
+    const uint32_t want = s_rank;
+    for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
+      const uint64_t pj = lp[j];
+      uint32_t r = 0;
+      for (uint32_t i = 0; i < total; ++i) r += lp[i] < pj ? 1u : 0u;
+      if (r == want) ls[0] = pj;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_pref = ls[0];
+    __syncthreads();
+  } else if (staged) {
+    // the bucket sorted in LDS (bitonic, padded with the largest key); the rank-th
+    // entry is the threshold
+    uint32_t np2 = 1;
+    while (np2 < total) np2 <<= 1;
+    for (uint32_t j = threadIdx.x; j < np2; j += kThreads) ls[j] = j < total ? lp[j] : ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= np2; k <<= 1) {
+      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+        for (uint32_t i = threadIdx.x; i < np2; i += kThreads) {
+          const uint32_t l = i ^ jj;
+          if (l > i) {
+            const uint64_t a = ls[i], bb = ls[l];
+            const bool up = (i & k) == 0;
+            if ((a > bb) == up) {
+              ls[i] = bb;
+              ls[l] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (threadIdx.x == 0) s_pref = ls[s_rank];
+    __syncthreads();
+  } else {
+    // radix select over the remaining bits, at most 8 at a time
+    for (int hi = shift; hi > 0;) {
+      const int wdt = hi >= 8 ? 8 : hi;
+      const int sh = hi - wdt;
+      for (int i = threadIdx.x; i < 256; i += kThreads) hst[i] = 0;
+      __syncthreads();
+      const uint64_t pref = s_pref;
+      for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
+        const uint64_t p = staged ? lp[j] : ld_agent(&w.tie_p[locate(j)]);
+        if (hi < 64 && (p >> hi) != (pref >> hi)) continue;
+        atomicAdd(&hst[(p >> sh) & ((1u << wdt) - 1u)], 1u);
+      }
+      __syncthreads();
+      int b;
+      uint32_t rest;
+      find_digit(hst, s_rank, &b, &rest);
+      if (threadIdx.x == 0) {
+        s_rank = rest;
+        s_pref = pref | (static_cast<uint64_t>(b) << sh);
+      }
+      __syncthreads();
+      hi = sh;
+    }
+  }
+  const uint64_t thr = s_pref;  // the rank-th smallest priority of the bucket
+  for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
+    int64_t at = 0;
+    if (!staged) at = locate(j);
+    const uint64_t p = staged ? lp[j] : ld_agent(&w.tie_p[at]);
+    if (p <= thr) {
+      const int32_t orig = staged ? lo[j] : ld_agent(&w.tie_o[at]);
+      if (orig >= 0 && orig < w.n) {
+        w.tag_o[orig] = lt;
+        w.tag_s[w.invp[orig]] = lt;
+      }
+    }
+  }
+}
+
+// Keep the representatives below the prefix bucket, queue the bucket's members (the
+// last block then settles the bucket), and empty the selection table.
 template <class Src>
 __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
   int bx, gx;
@@ -1737,182 +1861,66 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
       const uint32_t pos =
           s_base + s_wbase[wv] + static_cast<uint32_t>(__popcll(bal & ((1ull << lane) - 1ull)));
       if (pos < w.tie_seg) {
-        w.tie_p[g * w.tie_seg + pos] = p;
-        w.tie_o[g * w.tie_seg + pos] = orig;
+        st_agent(&w.tie_p[g * w.tie_seg + pos], p);
+        st_agent(&w.tie_o[g * w.tie_seg + pos], orig);
       }
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) w.scn[tile] = 0;
-}
-
-// One block: the rank-th smallest priority inside the bucket, then mark every queued
-// voxel up to it. A bucket that fits LDS is sorted there; a larger one (possible only
-// when a search fell back to a scale with far too many voxels) is radix-selected.
-template <class Src>
-__global__ void __launch_bounds__(kThreads) k_ties(Src src, int L) {
-  int bx, gx;
-  const Cloud& cd = cloud_of(src, kKOne, bx, gx);
-  if (!layer_due(cd, L)) return;
-  const Ws& w = cd.w;
-  Header* h = w.h;
-  Ctrl* c = &h->ctrl;
-  __shared__ uint32_t cnt_g[kGroups + 1];  // exclusive prefix over groups
-  __shared__ uint32_t hst[256];
-  __shared__ uint64_t s_pref;
-  __shared__ uint32_t s_rank;
-  __shared__ uint64_t lp[kTieLds];
-  __shared__ uint64_t ls[kTieLds];
-  __shared__ int32_t lo[kTieLds];
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int q = 0; q < kGroups; ++q) {
-      const uint32_t t = h->tie_cur[q][0];
-      cnt_g[q] = acc;
-      acc += t < w.tie_seg ? t : static_cast<uint32_t>(w.tie_seg);
-    }
-    cnt_g[kGroups] = acc;
-    s_pref = c->prefix;
-    s_rank = c->rank;
-  }
-  __syncthreads();
-  if (threadIdx.x < kGroups) h->tie_cur[threadIdx.x][0] = 0;
-  if (!c->trim) return;
-  const uint32_t total = cnt_g[kGroups];
-  const bool staged = total <= static_cast<uint32_t>(kTieLds);
-  // item j of the bucket: group q with cnt_g[q] <= j < cnt_g[q+1]
-  auto locate = [&](uint32_t j) -> int64_t {
-    int q = 0;
-    while (j >= cnt_g[q + 1]) ++q;
-    return static_cast<int64_t>(q) * w.tie_seg + (j - cnt_g[q]);
-  };
-  if (staged) {
-    for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
-      const int64_t at = locate(j);
-      lp[j] = w.tie_p[at];
-      lo[j] = w.tie_o[at];
-    }
-    __syncthreads();
-  }
-  const int shift = 64 - kTrimBits * c->rounds_done;  // bits below the bucket's prefix
-  const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
-  if (staged && total <= static_cast<uint32_t>(kTieRank)) {
-    // small bucket: the member whose rank is s_rank (priorities are distinct)
-    const uint32_t want = s_rank;
-    for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
-      const uint64_t pj = lp[j];
-      uint32_t r = 0;
-      for (uint32_t i = 0; i < total; ++i) r += lp[i] < pj ? 1u : 0u;
-      if (r == want) ls[0] = pj;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) s_pref = ls[0];
-    __syncthreads();
-  } else if (staged) {
-    // the bucket sorted in LDS (bitonic, padded with the largest key); the rank-th
-    // entry is the threshold
-    uint32_t np2 = 1;
-    while (np2 < total) np2 <<= 1;
-    for (uint32_t j = threadIdx.x; j < np2; j += kThreads) ls[j] = j < total ? lp[j] : ~0ull;
-    __syncthreads();
-    for (uint32_t k = 2; k <= np2; k <<= 1) {
-      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-        for (uint32_t i = threadIdx.x; i < np2; i += kThreads) {
-          const uint32_t l = i ^ jj;
-          if (l > i) {
-            const uint64_t a = ls[i], bb = ls[l];
-            const bool up = (i & k) == 0;
-            if ((a > bb) == up) {
-              ls[i] = bb;
-              ls[l] = a;
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
-    if (threadIdx.x == 0) s_pref = ls[s_rank];
-    __syncthreads();
-  } else {
-    // radix select over the remaining bits, at most 8 at a time
-    for (int hi = shift; hi > 0;) {
-      const int wdt = hi >= 8 ? 8 : hi;
-      const int sh = hi - wdt;
-      for (int i = threadIdx.x; i < 256; i += kThreads) hst[i] = 0;
-      __syncthreads();
-      const uint64_t pref = s_pref;
-      for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
-        const uint64_t p = staged ? lp[j] : w.tie_p[locate(j)];
-        if (hi < 64 && (p >> hi) != (pref >> hi)) continue;
-        atomicAdd(&hst[(p >> sh) & ((1u << wdt) - 1u)], 1u);
-      }
-      __syncthreads();
-      int b;
-      uint32_t rest;
-      find_digit(hst, s_rank, &b, &rest);
-      if (threadIdx.x == 0) {
-        s_rank = rest;
-        s_pref = pref | (static_cast<uint64_t>(b) << sh);
-      }
-      __syncthreads();
-      hi = sh;
-    }
-  }
-  const uint64_t thr = s_pref;  // the rank-th smallest priority of the bucket
-  for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
-    int64_t at = 0;
-    if (!staged) at = locate(j);
-    const uint64_t p = staged ? lp[j] : w.tie_p[at];
-    if (p <= thr) {
-      const int32_t orig = staged ? lo[j] : w.tie_o[at];
-      if (orig >= 0 && orig < w.n) {
-        w.tag_o[orig] = lt;
-        w.tag_s[w.invp[orig]] = lt;
-      }
-    }
-  }
+  if (!arrive_last(h, bx, gx)) return;
+  settle_ties(w, h);
 }
 
 // ----------------------------------------------------------------------------- scans over tag_o
 
-// mode 0: pad (count tag_o == 0), only when the layer is short; mode 1: output.
-template <class Src>
-__global__ void __launch_bounds__(kThreads) k_scan_count(Src src, int L, int mode) {
-  int bx, gx;
-  const Cloud& cd = cloud_of(src, kKScan, bx, gx);
-  const Ws& w = cd.w;
-  Header* h = w.h;
-  if (cd.P.identity || h->frame.status != HAV_OK) return;
-  if (mode == 0 && (L >= cd.P.nlayers || h->ctrl.need == 0)) return;
+// Tag scans in one pass: a block takes its scan tile in dispatch order (an atomic
+// ticket), counts its tile, publishes the count (slot = count + 1, agent-scope atomic
+// store) and adds up the slots of the tiles before it, which belong to blocks that
+// started earlier, so every wait ends; the wait is still bounded. The last block
+// empties the slots and the ticket for the next scan. Returns the exclusive prefix
+// (all threads), or ~0u if a wait gave up.
+__device__ uint32_t scan_prefix(const Ws& w, uint32_t mine, int lb) {
   __shared__ uint32_t s_tmp[kThreads / 64];
-  const int64_t base = bx * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
-  uint32_t cnt = 0;
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    if (base + k < w.n) {
-      const uint8_t t = w.tag_o[base + k];
-      cnt += mode ? (t != 0) : (t == 0);
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) {
+    st_agent(&w.tcnt[lb], mine + 1u);
+    s_bad = 0;
+  }
+  __syncthreads();
+  uint32_t sum = 0;
+  for (int i = threadIdx.x; i < lb; i += kThreads) {
+    uint32_t v, spins = 0;
+    while ((v = ld_agent(&w.tcnt[i])) == 0u) {
+      if (++spins > kSpinLimit) {
+        s_bad = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
     }
+    if (v) sum += v - 1u;
   }
-  const uint32_t tot = block_sum_u32<kThreads>(cnt, s_tmp);
-  if (threadIdx.x == 0) atomicExch(&w.tcnt[bx], tot);
-  if (!arrive_last(h, bx, gx)) return;
-  // last block: exclusive scan of the tile counts
-  uint32_t carry = 0;
-  for (int b0 = 0; b0 < static_cast<int>(gx); b0 += kThreads) {
-    const int b = b0 + threadIdx.x;
-    const uint32_t v = b < static_cast<int>(gx) ? peek(&w.tcnt[b]) : 0u;
-    uint32_t ex;
-    const uint32_t t = block_exclusive_scan<kThreads>(v, &ex, s_tmp);
-    if (b < static_cast<int>(gx)) w.tcnt[b] = carry + ex;
-    carry += t;
-    __syncthreads();
-  }
+  const uint32_t tot = block_sum_u32<kThreads>(sum, s_tmp);
+  return s_bad ? ~0u : tot;
 }
 
-// Pad: mark the lowest-index unsampled points; then start the next layer.
+__device__ __forceinline__ int scan_ticket(Header* h) {
+  __shared__ int s_lb;
+  if (threadIdx.x == 0) s_lb = static_cast<int>(atomicAdd(&h->ord[0], 1u));
+  __syncthreads();
+  return s_lb;
+}
+
+// The last block of a scan: empty the slots and the ticket.
+__device__ void scan_reset(const Ws& w, Header* h, int nb) {
+  for (int i = threadIdx.x; i < nb; i += kThreads) st_agent(&w.tcnt[i], 0u);
+  if (threadIdx.x == 0) atomicExch(&h->ord[0], 0u);
+}
+
+// Pad (when the layer found fewer voxels than m): mark the lowest-index unsampled
+// points; then start the next layer.
 template <class Src>
-__global__ void __launch_bounds__(kThreads) k_pad_mark(Src src, int Lc) {
+__global__ void __launch_bounds__(kThreads) k_pad(Src src, int Lc) {
   int bx, gx;
   const Cloud& cd = cloud_of(src, kKScan, bx, gx);
   if (!layer_due(cd, Lc)) return;
@@ -1925,7 +1933,8 @@ __global__ void __launch_bounds__(kThreads) k_pad_mark(Src src, int Lc) {
   const int L = c->layer;
   if (need > 0) {
     __shared__ uint32_t s_tmp[kThreads / 64];
-    const int64_t base = bx * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
+    const int lb = scan_ticket(h);
+    const int64_t base = lb * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
     uint8_t t[kScanPer];
     uint32_t cnt = 0;
 #pragma unroll
@@ -1934,25 +1943,32 @@ __global__ void __launch_bounds__(kThreads) k_pad_mark(Src src, int Lc) {
       cnt += (t[k] == 0);
     }
     uint32_t ex;
-    block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
-    uint32_t r = w.tcnt[bx] + ex;
+    const uint32_t tot = block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
+    const uint32_t before = scan_prefix(w, tot, lb);
+    if (before == ~0u) {
+      if (threadIdx.x == 0) h->frame.status = HAV_ERR_HIP;
+    } else {
+      uint32_t r = before + ex;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      if (t[k] == 0) {
-        if (r < need) {
-          w.tag_o[base + k] = lt;
-          w.tag_s[w.invp[base + k]] = lt;
+      for (int k = 0; k < kScanPer; ++k) {
+        if (t[k] == 0) {
+          if (r < need) {
+            w.tag_o[base + k] = lt;
+            w.tag_s[w.invp[base + k]] = lt;
+          }
+          ++r;
         }
-        ++r;
       }
     }
   }
   if (!arrive_last(h, bx, gx)) return;
+  if (need > 0) scan_reset(w, h, gx);
   if (threadIdx.x == 0 && L + 1 < P.nlayers) layer_init(h, P, L + 1);
 }
 
+// Ascending output: every picked point's index, in index order.
 template <class Src>
-__global__ void __launch_bounds__(kThreads) k_out_write(Src src) {
+__global__ void __launch_bounds__(kThreads) k_out(Src src) {
   int bx, gx;
   const Cloud& cd = cloud_of(src, kKScan, bx, gx);
   const Ws& w = cd.w;
@@ -1960,10 +1976,13 @@ __global__ void __launch_bounds__(kThreads) k_out_write(Src src) {
   Header* h = w.h;
   int32_t* idx = w.idx;
   const int64_t M = w.M;
-  if (bx == 0 && threadIdx.x == 0 && w.info_dev) *w.info_dev = h->info;
-  if (h->frame.status != HAV_OK) return;
+  if (h->frame.status != HAV_OK) {
+    if (bx == 0 && threadIdx.x == 0 && w.info_dev) *w.info_dev = h->info;
+    return;
+  }
   __shared__ uint32_t s_tmp[kThreads / 64];
-  const int64_t base = bx * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
+  const int lb = scan_ticket(h);
+  const int64_t base = lb * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
   uint8_t t[kScanPer];
   uint32_t cnt = 0;
 #pragma unroll
@@ -1972,21 +1991,32 @@ __global__ void __launch_bounds__(kThreads) k_out_write(Src src) {
     cnt += (t[k] != 0);
   }
   uint32_t ex;
-  block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
-  uint32_t r = w.tcnt[bx] + ex;
+  const uint32_t tot = block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
+  const uint32_t before = scan_prefix(w, tot, lb);
+  if (before != ~0u) {
+    uint32_t r = before + ex;
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    if (t[k]) {
-      if (r < M) idx[r] = static_cast<int32_t>(base + k);
-      ++r;
+    for (int k = 0; k < kScanPer; ++k) {
+      if (t[k]) {
+        if (r < M) idx[r] = static_cast<int32_t>(base + k);
+        ++r;
+      }
     }
+  } else if (threadIdx.x == 0) {
+    atomicOr(&h->scan_bad[0], 1u);
+  }
+  if (!arrive_last(h, bx, gx)) return;
+  scan_reset(w, h, gx);
+  if (threadIdx.x == 0) {
+    if (take(&h->scan_bad[0])) h->info.status = HAV_ERR_HIP;
+    if (w.info_dev) *w.info_dev = h->info;
   }
 }
 
 // ----------------------------------------------------------------------------- workspace init
 
 __global__ void __launch_bounds__(kThreads) k_ws_init(Ws w, size_t nct, size_t ncn, size_t nst,
-                                                      size_t nsv, size_t nsn, size_t nhr) {
+                                                      size_t nsv, size_t nsn, size_t nhr, size_t nsc) {
   const size_t stride = static_cast<size_t>(gridDim.x) * kThreads;
   const size_t t0 = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
   for (size_t i = t0; i < nct; i += stride) {
@@ -1995,6 +2025,7 @@ __global__ void __launch_bounds__(kThreads) k_ws_init(Ws w, size_t nct, size_t n
   }
   for (size_t i = t0; i < ncn; i += stride) w.ccn[i] = 0;
   for (size_t i = t0; i < nhr; i += stride) w.hrep[i] = 0ull;
+  for (size_t i = t0; i < nsc; i += stride) w.tcnt[i] = 0u;
   for (size_t i = t0; i < nst; i += stride) w.skeys[i] = kEmptyKey;
   for (size_t i = t0; i < nsv; i += stride) w.svals[i] = ~0ull;
   for (size_t i = t0; i < nsn; i += stride) w.scn[i] = 0;
@@ -2548,12 +2579,9 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
     for (int r = 0; r < P.rounds[l]; ++r)
       HAV_LAUNCH(k_trim_hist<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l, r);
     HAV_LAUNCH(k_mark<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l);
-    HAV_LAUNCH(k_ties<One>, dim3(1), dim3(kThreads), 0, st, one, l);
-    HAV_LAUNCH(k_scan_count<One>, dim3(w.nscan), dim3(kThreads), 0, st, one, l, 0);
-    HAV_LAUNCH(k_pad_mark<One>, dim3(w.nscan), dim3(kThreads), 0, st, one, l);
+    HAV_LAUNCH(k_pad<One>, dim3(w.nscan), dim3(kThreads), 0, st, one, l);
   }
-  HAV_LAUNCH(k_scan_count<One>, dim3(w.nscan), dim3(kThreads), 0, st, one, -1, 1);
-  HAV_LAUNCH(k_out_write<One>, dim3(w.nscan), dim3(kThreads), 0, st, one);
+  HAV_LAUNCH(k_out<One>, dim3(w.nscan), dim3(kThreads), 0, st, one);
   return HAV_OK;
 }
 
@@ -2590,7 +2618,7 @@ hav_status_t init_ws(char* base, const Layout& L, hipStream_t st) {
   HAV_LAUNCH(k_ws_init, dim3(2048), dim3(kThreads), 0, st, w, nct, ncn,
              static_cast<size_t>(L.cap_ws), static_cast<size_t>(L.cap_ws) * kSelDense,
              static_cast<size_t>(L.ntile_ws),
-             2 * static_cast<size_t>(L.ncmax) * kReps * kHotCap);
+             2 * static_cast<size_t>(L.ncmax) * kReps * kHotCap, static_cast<size_t>(L.nscan_ws));
   HAV_LAUNCH(k_ws_seal, dim3(1), dim3(64), 0, st, w.h, magic_of(L));
   return HAV_OK;
 }
@@ -2686,12 +2714,9 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
     for (int r = 0; r < max_rounds; ++r)
       HAV_LAUNCH(k_trim_hist<Many>, dim3(T[kKTile]), dim3(kThreads), 0, st, many, l, r);
     HAV_LAUNCH(k_mark<Many>, dim3(T[kKTile]), dim3(kThreads), 0, st, many, l);
-    HAV_LAUNCH(k_ties<Many>, dim3(T[kKOne]), dim3(kThreads), 0, st, many, l);
-    HAV_LAUNCH(k_scan_count<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many, l, 0);
-    HAV_LAUNCH(k_pad_mark<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many, l);
+    HAV_LAUNCH(k_pad<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many, l);
   }
-  HAV_LAUNCH(k_scan_count<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many, -1, 1);
-  HAV_LAUNCH(k_out_write<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many);
+  HAV_LAUNCH(k_out<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many);
   return HAV_OK;
 }
 
