@@ -364,10 +364,32 @@ __device__ __forceinline__ void max_coords(const Frame& fr, const float* inv, ui
 // good model just gets several steps out of one pass. The model is a power law
 // Cnt(s) = c_ref (s_ref / s)^D through the counts known at the bracket ends (D fitted
 // when both are known, else 2); the chain stops early where it predicts acceptance.
+//
+// Steps whose outcome is certain are taken without a count: at size s no point has a
+// voxel coordinate above that of the max corner, so Cnt(s) is at most the number of
+// grid cells up to it, and when that is below m the step goes down. Such a step still
+// counts as an evaluation (the bisection is the same); the last step of the budget
+// is always counted.
 __device__ void plan_search(SState* st, const Plan& P, const Frame& fr, uint32_t m, uint32_t upper) {
+  while (st->evals + 1 < P.t_max) {
+    const float s = (st->lo + st->hi) * 0.5f;
+    float inv[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      const float v = s * P.aspect[ax];
+      inv[ax] = 1.0f / v;
+    }
+    uint32_t mk[3];
+    max_coords(fr, inv, mk);
+    const double cells = (double(mk[0]) + 1.0) * (double(mk[1]) + 1.0) * (double(mk[2]) + 1.0);
+    if (!(cells < static_cast<double>(m))) break;
+    st->hi = s;
+    st->evals += 1;
+  }
   const int left = P.t_max - st->evals;
   const int D = left < P.depth ? left : P.depth;
-  float sref = st->hi, cref = st->c_hi ? static_cast<float>(st->c_hi) : 1.0f, dim = 2.0f;
+  // with no count at hi, the model starts from one voxel at hi0
+  float sref = st->c_hi ? st->hi : fr.hi0, cref = st->c_hi ? static_cast<float>(st->c_hi) : 1.0f;
+  float dim = 2.0f;
   if (st->c_lo && st->c_hi && st->lo > 0.0f && st->c_lo > st->c_hi) {
     dim = __logf(static_cast<float>(st->c_lo) / static_cast<float>(st->c_hi)) / __logf(st->hi / st->lo);
   } else if (st->c_lo && !st->c_hi) {
