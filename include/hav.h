@@ -76,6 +76,10 @@ typedef struct {
                           (16), else 1..1024 */
   int32_t search_blocks; /* tuning only: blocks of the voxel-search launch; 0 = as many as
                             the device holds at once (at most one per tile), else 1..65536 */
+  float trim_window;   /* tuning only: half-width, in standard deviations of its expected
+                          position, of the priority window the trim first tries as the bucket
+                          holding its threshold; 0 = default (6), negative = no window (the
+                          bucket is every voxel), else at most 64. Results do not depend on it. */
 } hav_params_t;
 
 /* Per-call report, written by the device into caller memory (info_dev). */

@@ -84,8 +84,9 @@ constexpr int kScanPer = kScanTile / kThreads;
 constexpr int kSelDense = 4;                    // voxel value slots per brick-table slot
 constexpr uint64_t kMagic = 0x4841565F57533031ull;
 constexpr int kMaxDevices = 64;
-constexpr int kTieLds = 1024;                   // tie bucket staged (and sorted) in LDS
-constexpr int kTieRank = 128;                   // tie buckets up to this size: rank directly
+constexpr int kTieLds = 1024;                   // trim bucket staged in LDS up to this size
+constexpr float kWinSigma = 6.0f;                // default trim window half-width (std devs)
+constexpr int kTieRank = 128;                   // bucket members ranked directly up to this many
 constexpr int kTrimBits = 8;                    // priority digit of one trim round
 constexpr int kTrimBins = 1 << kTrimBits;
 constexpr int kHotCap = 4096;                   // brick grids this small use replicas
@@ -118,9 +119,14 @@ struct Ctrl {
   uint32_t ncand;       // occupied voxels at the chosen size
   int32_t trim;
   uint32_t need;        // pad count
-  uint32_t rank;        // radix select: rank sought inside the prefix bucket
-  uint64_t prefix;
+  uint32_t rank;        // rank sought inside the trim bucket
+  uint64_t prefix;      // radix rounds: decided top bits of the threshold
   int32_t rounds_done;
+  // trim bucket: 0 the radix prefix, 1 the priority window [blo, bhi], 2 every voxel
+  int32_t trim_mode;
+  uint32_t c_final;     // voxels the search counted at s_final (0: no search)
+  int32_t win;          // a window was set for the selection kernel to test
+  uint64_t blo, bhi;
 };
 
 // State of the voxel search between passes (Sec. 3.3): the bracket, the outcome so
@@ -129,6 +135,7 @@ struct SState {
   float lo, hi;
   uint32_t c_hi;  // count at hi (0: hi is the initial bracket, never evaluated)
   uint32_t c_lo;  // count at lo (0: lo is 0, never evaluated)
+  uint32_t c_final;  // count at s_final once done
   int32_t pdir[kMaxCand];  // predicted step after candidate k: 0 down (hi = s), 1 up (lo = s)
   int32_t evals, done, accepted;
   int32_t nc, set, prev_set, prev_nc;
@@ -153,8 +160,9 @@ struct Plan {  // per-call constants (kernel argument)
   uint32_t cap;       // brick table slots: dense brick grids up to this size
   uint32_t sel_cap;   // voxel value slots: dense voxel grids up to this size
   float spec_mult;    // speculation budget of the search, in multiples of the window top
+  float win_sigma;    // trim window half-width in standard deviations (<= 0: none)
   int32_t identity;   // M == N: output 0..N-1, nothing else runs
-  int32_t rounds[HAV_MAX_LAYERS];  // radix rounds of each layer's trim before k_ties
+  int32_t rounds[HAV_MAX_LAYERS];  // radix rounds of each layer's trim (fixed size only)
 };
 
 constexpr int kPubWords = static_cast<int>(sizeof(SState) / 4);
@@ -448,6 +456,7 @@ __device__ void search_step(SState* st, const uint32_t* cnt, const Plan& P, cons
       st->accepted = 1;
       st->done = 1;
       st->s_final = s;
+      st->c_final = cc;
       return;
     }
     const int dir = cc < m ? 0 : 1;
@@ -466,6 +475,8 @@ __device__ void search_step(SState* st, const uint32_t* cnt, const Plan& P, cons
     // (then trim), else the smallest size evaluated (then pad)
     st->done = 1;
     st->s_final = st->lo > 0.0f ? st->lo : st->hi;
+    // lo is always evaluated; hi is too when lo is 0 (the budget's last step is)
+    st->c_final = st->lo > 0.0f ? st->c_lo : st->c_hi;
     return;
   }
   plan_search(st, P, fr, m, upper);
@@ -489,6 +500,26 @@ __device__ void set_final(Ctrl* c, float s, const Plan& P, const Frame& fr) {
   set_select_grid(c, P, fr);
 }
 
+// Trim window: with c voxels of which the m of smallest priority stay, the threshold
+// is the m-th smallest of c priorities. SplitMix64 spreads keys evenly over 64 bits,
+// so that order statistic lies near the fraction m / (c + 1) of the range, with
+// standard deviation sqrt(x (1 - x) / (c + 2)). The window spans `sig` of them (by
+// default kWinSigma) on each side; the selection kernel counts the voxels below and
+// inside it and uses it as the trim bucket only if the threshold is proven to lie
+// inside (any input stays exact: otherwise the bucket is every voxel).
+__device__ void set_window(Ctrl* c, float sig) {
+  c->win = 0;
+  const uint32_t cf = c->c_final, m = c->m;
+  if (cf <= m || m == 0 || !(sig > 0.0f)) return;
+  const double kWin = sig;
+  const double x = static_cast<double>(m) / (static_cast<double>(cf) + 1.0);
+  const double sd = sqrt(x * (1.0 - x) / (static_cast<double>(cf) + 2.0));
+  const double lo = (x - kWin * sd) * 0x1p64, hi = (x + kWin * sd) * 0x1p64;
+  c->blo = lo <= 0.0 ? 0ull : (lo >= 0x1p64 ? ~0ull : static_cast<uint64_t>(lo));
+  c->bhi = hi >= 0x1p64 ? ~0ull : (hi <= 0.0 ? 0ull : static_cast<uint64_t>(hi));
+  c->win = 1;
+}
+
 __device__ void layer_init(Header* h, const Plan& P, int L) {
   Ctrl* c = &h->ctrl;
   c->layer = L;
@@ -504,6 +535,9 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
   c->rank = 0;
   c->prefix = 0;
   c->rounds_done = 0;
+  c->trim_mode = 0;
+  c->c_final = 0;
+  c->win = 0;
   h->info.m[L] = static_cast<int32_t>(P.m[L]);
   h->info.layers = L + 1;
   for (int b = 0; b < 2; ++b)
@@ -539,6 +573,7 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
     s0->prev_nc = 0;
     s0->prev_hashed = 0;
     s0->s_final = 0.0f;
+    s0->c_final = 0;
     plan_search(s0, P, h->frame, c->m, c->upper);
   }
 }
@@ -1293,6 +1328,8 @@ __device__ __forceinline__ int run_ticket(const Ws& w, const Plan& P, SearchShar
       c->pend_nc = st.prev_nc;
       c->pend_hashed = st.prev_hashed;
       set_final(c, st.s_final, P, h->frame);
+      c->c_final = st.c_final;
+      set_window(c, P.win_sigma);
       const int Lc = c->layer;
       h->info.evals[Lc] = st.evals;
       h->info.accepted[Lc] = st.accepted;
@@ -1487,6 +1524,7 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   __shared__ int s_ncl;
   __shared__ uint32_t s_red[kThreads / 64][6];
   __shared__ uint32_t s_box[6];
+  __shared__ uint32_t s_below, s_inwin;
   const float vx = c->v_final[0], vy = c->v_final[1], vz = c->v_final[2];
   const float ix = c->inv_final[0], iy = c->inv_final[1], iz = c->inv_final[2];
   const int dense = c->sel_dense;
@@ -1495,7 +1533,25 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
     lkeys[e] = kEmptyKey;
     lvals[e] = ~0ull;
   }
-  if (threadIdx.x == 0) s_ncl = 0;
+  if (threadIdx.x == 0) {
+    s_ncl = 0;
+    s_below = 0;
+    s_inwin = 0;
+  }
+  // trim window test of a voxel this tile claimed first (every voxel has one such tile)
+  const int win = c->win;
+  const uint64_t blo = c->blo, bhi = c->bhi;
+  auto wcount = [&](uint64_t pk) {
+    const uint64_t p = voxel_priority(pk);
+    if (p < blo) atomicAdd(&s_below, 1u);
+    else if (p <= bhi) atomicAdd(&s_inwin, 1u);
+  };
+  auto unpack = [&](uint64_t key) -> uint64_t {
+    if (!dense) return key;
+    const uint32_t u = static_cast<uint32_t>(key);
+    const uint32_t t = u / static_cast<uint32_t>(nx);
+    return pack_key(u % static_cast<uint32_t>(nx), t % static_cast<uint32_t>(ny), t / static_cast<uint32_t>(ny));
+  };
   const int64_t base = static_cast<int64_t>(tile) * kTile + threadIdx.x;
   float4 pt[kPerThread];
   uint32_t live = 0;
@@ -1607,7 +1663,7 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
     if (!dense) {
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if ((has >> j) & 1u) select_hashed(w, key[j], val[j], list, &s_ncl);
+        if (((has >> j) & 1u) && select_hashed(w, key[j], val[j], list, &s_ncl) && win) wcount(key[j]);
       continue;
     }
     uint64_t old[4];
@@ -1617,25 +1673,32 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
                                              static_cast<unsigned long long>(val[j]))
                                  : 0ull;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (((has >> j) & 1u) && old[j] == ~0ull) list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(key[j]);
+    for (int j = 0; j < 4; ++j) {
+      if (((has >> j) & 1u) && old[j] == ~0ull) {
+        list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(key[j]);
+        if (win) wcount(unpack(key[j]));
+      }
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    const int g = tile & (kGroups - 1);
     w.scn[tile] = s_ncl;
-    if (s_ncl) atomicAdd(&h->acc[0][tile & (kGroups - 1)][0], static_cast<uint32_t>(s_ncl));
+    if (s_ncl) atomicAdd(&h->acc[0][g][0], static_cast<uint32_t>(s_ncl));
+    if (s_below) atomicAdd(&h->acc[1][g][0], s_below);
+    if (s_inwin) atomicAdd(&h->acc[2][g][0], s_inwin);
   }
   if (!arrive_last(h, bx, gx)) return;
-  __shared__ uint32_t s_nvox;
-  if (threadIdx.x == 0) s_nvox = 0;
+  __shared__ uint32_t s_sum[3];
+  if (threadIdx.x < 3) s_sum[threadIdx.x] = 0;
   __syncthreads();
-  if (threadIdx.x < kGroups) {
-    const uint32_t v = take(&h->acc[0][threadIdx.x][0]);
-    if (v) atomicAdd(&s_nvox, v);
+  if (threadIdx.x < 3 * kGroups) {
+    const uint32_t v = take(&h->acc[threadIdx.x / kGroups][threadIdx.x % kGroups][0]);
+    if (v) atomicAdd(&s_sum[threadIdx.x / kGroups], v);
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const uint32_t nvox = s_nvox;
+  const uint32_t nvox = s_sum[0], below = s_sum[1], inwin = s_sum[2];
   c->pend_nc = 0;
   c->ncand = nvox;
   c->trim = nvox > c->m ? 1 : 0;
@@ -1643,6 +1706,17 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   c->prefix = 0;
   c->rank = c->m - 1;
   c->rounds_done = 0;
+  c->trim_mode = 0;
+  if (c->trim && !cd.P.fixed) {
+    // the window holds the threshold iff fewer than m voxels lie below it and at
+    // least m lie below or inside it
+    if (win && nvox == c->c_final && below < c->m && c->m <= below + inwin) {
+      c->trim_mode = 1;
+      c->rank = c->m - 1 - below;
+    } else {
+      c->trim_mode = 2;
+    }
+  }
   const int Lc = c->layer;
   h->info.count[Lc] = static_cast<int32_t>(nvox);
   h->info.trimmed[Lc] = nvox > c->m ? static_cast<int32_t>(nvox - c->m) : 0;
@@ -1663,7 +1737,7 @@ __global__ void __launch_bounds__(kThreads) k_trim_hist(Src src, int L, int roun
   const Ws& w = cd.w;
   Header* h = w.h;
   Ctrl* c = &h->ctrl;
-  if (!c->trim) return;
+  if (!c->trim || c->trim_mode != 0) return;
   __shared__ uint32_t lh[kTrimBins];
   for (int i = threadIdx.x; i < kTrimBins; i += kThreads) lh[i] = 0;
   __syncthreads();
@@ -1700,19 +1774,20 @@ __global__ void __launch_bounds__(kThreads) k_trim_hist(Src src, int L, int roun
 }
 
 // The last block of k_mark: the rank-th smallest priority inside the bucket, then
-// mark every queued voxel up to it. A bucket that fits LDS is ranked or sorted there; a
-// larger one (possible only when a search fell back to a size with far too many
-// voxels) is radix-selected from global memory. The queue was written in the same
+// mark every queued voxel up to it. The bucket's members, less the bucket's base, fit
+// in its bit width; radix rounds of 8 bits narrow them (from LDS when the bucket fits
+// there, else from the queue in global memory) until at most kTieRank remain, which
+// are ranked directly (priorities are distinct). The queue was written in the same
 // launch, so it is read with agent-scope atomic loads.
 __device__ void settle_ties(const Ws& w, Header* h) {
   Ctrl* c = &h->ctrl;
   __shared__ uint32_t cnt_g[kGroups + 1];  // exclusive prefix over groups
   __shared__ uint32_t hst[256];
-  __shared__ uint64_t s_pref;
-  __shared__ uint32_t s_rank;
+  __shared__ uint64_t s_pfx, s_thr;
+  __shared__ uint32_t s_rank, s_remain, s_nm;
   __shared__ uint64_t lp[kTieLds];
-  __shared__ uint64_t ls[kTieLds];
   __shared__ int32_t lo[kTieLds];
+  __shared__ uint64_t ls[kTieRank];
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
     for (int q = 0; q < kGroups; ++q) {
@@ -1721,8 +1796,11 @@ __device__ void settle_ties(const Ws& w, Header* h) {
       acc += t < w.tie_seg ? t : static_cast<uint32_t>(w.tie_seg);
     }
     cnt_g[kGroups] = acc;
-    s_pref = c->prefix;
     s_rank = c->rank;
+    s_pfx = 0;
+    s_thr = 0;
+    s_remain = acc;
+    s_nm = 0;
   }
   __syncthreads();
   if (!c->trim) return;
@@ -1742,71 +1820,63 @@ __device__ void settle_ties(const Ws& w, Header* h) {
     }
     __syncthreads();
   }
-  const int shift = 64 - kTrimBits * c->rounds_done;  // bits below the bucket's prefix
-  const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
-  if (staged && total <= static_cast<uint32_t>(kTieRank)) {
-    // small bucket: the member whose rank is s_rank (priorities are distinct)
-    const uint32_t want = s_rank;
+  auto prio = [&](uint32_t j) -> uint64_t { return staged ? lp[j] : ld_agent(&w.tie_p[locate(j)]); };
+  uint64_t base = 0;
+  int hi = 64;
+  if (c->trim_mode == 0) {
+    hi = 64 - kTrimBits * c->rounds_done;  // bits below the decided prefix
+    base = c->prefix;
+  } else if (c->trim_mode == 1) {
+    base = c->blo;
+    const uint64_t width = c->bhi - c->blo;
+    hi = width ? 64 - __clzll(static_cast<long long>(width)) : 0;
+  }
+  while (s_remain > static_cast<uint32_t>(kTieRank) && hi > 0) {
+    const int wdt = hi >= 8 ? 8 : hi;
+    const int sh = hi - wdt;
+    for (int i = threadIdx.x; i < 256; i += kThreads) hst[i] = 0;
+    __syncthreads();
+    const uint64_t pfx = s_pfx;
     for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
-      const uint64_t pj = lp[j];
-      uint32_t r = 0;
-      for (uint32_t i = 0; i < total; ++i) r += lp[i] < pj ? 1u : 0u;
-      if (r == want) ls[0] = pj;
+      const uint64_t r = prio(j) - base;
+      if (hi < 64 && (r >> hi) != (pfx >> hi)) continue;
+      atomicAdd(&hst[(r >> sh) & ((1u << wdt) - 1u)], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) s_pref = ls[0];
-    __syncthreads();
-  } else if (staged) {
-    // the bucket sorted in LDS (bitonic, padded with the largest key); the rank-th
-    // entry is the threshold
-    uint32_t np2 = 1;
-    while (np2 < total) np2 <<= 1;
-    for (uint32_t j = threadIdx.x; j < np2; j += kThreads) ls[j] = j < total ? lp[j] : ~0ull;
-    __syncthreads();
-    for (uint32_t k = 2; k <= np2; k <<= 1) {
-      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-        for (uint32_t i = threadIdx.x; i < np2; i += kThreads) {
-          const uint32_t l = i ^ jj;
-          if (l > i) {
-            const uint64_t a = ls[i], bb = ls[l];
-            const bool up = (i & k) == 0;
-            if ((a > bb) == up) {
-              ls[i] = bb;
-              ls[l] = a;
-            }
-          }
-        }
-        __syncthreads();
-      }
+    int b;
+    uint32_t rest;
+    find_digit(hst, s_rank, &b, &rest);
+    if (threadIdx.x == 0) {
+      s_rank = rest;
+      s_pfx = pfx | (static_cast<uint64_t>(b) << sh);
+      s_remain = hst[b];
     }
-    if (threadIdx.x == 0) s_pref = ls[s_rank];
     __syncthreads();
-  } else {
-    // radix select over the remaining bits, at most 8 at a time
-    for (int hi = shift; hi > 0;) {
-      const int wdt = hi >= 8 ? 8 : hi;
-      const int sh = hi - wdt;
-      for (int i = threadIdx.x; i < 256; i += kThreads) hst[i] = 0;
-      __syncthreads();
-      const uint64_t pref = s_pref;
-      for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
-        const uint64_t p = staged ? lp[j] : ld_agent(&w.tie_p[locate(j)]);
-        if (hi < 64 && (p >> hi) != (pref >> hi)) continue;
-        atomicAdd(&hst[(p >> sh) & ((1u << wdt) - 1u)], 1u);
+    hi = sh;
+  }
+  // the members left: gathered, then the one of rank s_rank among them
+  {
+    const uint64_t pfx = s_pfx;
+    for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
+      const uint64_t p = prio(j);
+      const uint64_t r = p - base;
+      if (hi >= 64 || (r >> hi) == (pfx >> hi)) {
+        const uint32_t k = atomicAdd(&s_nm, 1u);
+        if (k < static_cast<uint32_t>(kTieRank)) ls[k] = p;
       }
-      __syncthreads();
-      int b;
-      uint32_t rest;
-      find_digit(hst, s_rank, &b, &rest);
-      if (threadIdx.x == 0) {
-        s_rank = rest;
-        s_pref = pref | (static_cast<uint64_t>(b) << sh);
-      }
-      __syncthreads();
-      hi = sh;
     }
   }
-  const uint64_t thr = s_pref;  // the rank-th smallest priority of the bucket
+  __syncthreads();
+  const uint32_t nm = s_nm < static_cast<uint32_t>(kTieRank) ? s_nm : static_cast<uint32_t>(kTieRank);
+  for (uint32_t j = threadIdx.x; j < nm; j += kThreads) {
+    const uint64_t pj = ls[j];
+    uint32_t r = 0;
+    for (uint32_t i = 0; i < nm; ++i) r += ls[i] < pj ? 1u : 0u;
+    if (r == s_rank) s_thr = pj;
+  }
+  __syncthreads();
+  const uint64_t thr = s_thr;  // the rank-th smallest priority of the bucket
+  const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
   for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
     int64_t at = 0;
     if (!staged) at = locate(j);
@@ -1835,6 +1905,8 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
   const int n = w.scn[tile];
   const int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
   const int trim = c->trim;
+  const int mode = c->trim_mode;
+  const uint64_t blo = c->blo, bhi = c->bhi;
   const int dense = c->sel_dense;
   const int shift = 64 - kTrimBits * c->rounds_done;  // bits below the decided prefix
   const uint64_t pref_hi = shift >= 64 ? 0ull : (c->prefix >> shift);
@@ -1856,9 +1928,17 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
       bool keep = true;
       if (trim) {
         p = voxel_priority(key);
-        const uint64_t hi = shift >= 64 ? 0ull : (p >> shift);
-        keep = hi < pref_hi;
-        tie = hi == pref_hi;
+        if (mode == 0) {
+          const uint64_t hi = shift >= 64 ? 0ull : (p >> shift);
+          keep = hi < pref_hi;
+          tie = hi == pref_hi;
+        } else if (mode == 1) {
+          keep = p < blo;
+          tie = !keep && p <= bhi;
+        } else {
+          keep = false;
+          tie = true;
+        }
       }
       if (keep && orig >= 0 && orig < w.n) {
         w.tag_o[orig] = lt;
@@ -2203,6 +2283,7 @@ bool params_ok(const hav_params_t* p) {
   if (p->spec_depth < 0 || p->spec_depth > kMaxDepth) return false;
   if (p->spec_budget < 0 || p->spec_budget > 1024) return false;
   if (p->search_blocks < 0 || p->search_blocks > 65536) return false;
+  if (!std::isfinite(p->trim_window) || p->trim_window > 64.0f) return false;
   for (int a = 0; a < 3; ++a) {
     const float as = p->aspect[a];
     if (!std::isfinite(as) || as < 0x1p-16f || as > 0x1p16f) return false;
@@ -2242,6 +2323,7 @@ __host__ __device__ inline int trim_rounds(int64_t v) {
 struct ParamLite {
   int32_t layers, ratio, t_max, depth, fixed, spec_budget;
   double sigma;
+  float trim_window;
   float aspect[3], fixed_v[3];
 };
 
@@ -2254,6 +2336,7 @@ ParamLite lite_of(const hav_params_t* p) {
   q.fixed = (p->flags & HAV_FIXED_VOXEL) ? 1 : 0;
   q.spec_budget = p->spec_budget;
   q.sigma = p->sigma;
+  q.trim_window = p->trim_window;
   for (int a = 0; a < 3; ++a) {
     q.aspect[a] = p->aspect[a];
     q.fixed_v[a] = p->fixed_voxel[a];
@@ -2287,6 +2370,7 @@ __host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite&
   P.cap = cd.w.cap;
   P.sel_cap = cd.w.cap * static_cast<uint32_t>(kSelDense);
   P.spec_mult = q.spec_budget ? static_cast<float>(q.spec_budget) : kSpecMult;
+  P.win_sigma = q.trim_window == 0.0f ? kWinSigma : q.trim_window;
   P.identity = c.m == c.n ? 1 : 0;
   for (int a = 0; a < 3; ++a) {
     P.aspect[a] = q.aspect[a];
@@ -2305,7 +2389,7 @@ __host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite&
     const double up = floor(static_cast<double>(m[l]) * (1.0 + q.sigma));
     P.m[nl] = static_cast<uint32_t>(m[l]);
     P.upper[nl] = up >= 4294967295.0 ? 0xFFFFFFFFu : static_cast<uint32_t>(up);
-    P.rounds[nl] = trim_rounds(static_cast<int64_t>(P.upper[nl]));
+    P.rounds[nl] = P.fixed ? trim_rounds(static_cast<int64_t>(P.upper[nl])) : 0;
     ++nl;
   }
   P.nlayers = nl;
@@ -2794,6 +2878,7 @@ hav_params_t hav_params_default(void) {
   p.spec_depth = 0;
   p.spec_budget = 0;
   p.search_blocks = 0;
+  p.trim_window = 0.0f;
   return p;
 }
 

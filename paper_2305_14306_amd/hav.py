@@ -33,6 +33,7 @@ class Params(C.Structure):
         ("spec_depth", C.c_int32),
         ("spec_budget", C.c_int32),
         ("search_blocks", C.c_int32),
+        ("trim_window", C.c_float),
     ]
 
 
@@ -164,10 +165,12 @@ def status_string(status: int) -> str:
 
 
 def params(layers=2, layer_ratio=4, t_max=20, sigma=0.05, aspect=(1.0, 1.0, 1.0),
-           fixed_voxel=None, spec_depth=0, spec_budget=0, search_blocks=0) -> Params:
+           fixed_voxel=None, spec_depth=0, spec_budget=0, search_blocks=0,
+           trim_window=0.0) -> Params:
     p = lib().hav_params_default()
     p.layers, p.layer_ratio, p.t_max, p.sigma = layers, layer_ratio, t_max, sigma
     p.spec_depth, p.spec_budget, p.search_blocks = spec_depth, spec_budget, search_blocks
+    p.trim_window = trim_window
     for a in range(3):
         p.aspect[a] = aspect[a]
     if fixed_voxel is not None:

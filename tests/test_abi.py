@@ -116,7 +116,8 @@ def test_host_rejects_bad_arguments(hav):
                dict(aspect=(1.0, 0.0, 1.0)), dict(aspect=(1.0, float("inf"), 1.0)),
                dict(fixed_voxel=0.0), dict(fixed_voxel=float("nan")), dict(spec_depth=8),
                dict(spec_depth=-1), dict(spec_budget=-1), dict(spec_budget=1025),
-               dict(search_blocks=-1), dict(search_blocks=65537)):
+               dict(search_blocks=-1), dict(search_blocks=65537),
+               dict(trim_window=64.5), dict(trim_window=float("nan")), dict(trim_window=float("inf"))):
         assert _call(hav, p=hav.params(**kw)) == E, kw
     p = hav.params()
     p.abi_version = 2

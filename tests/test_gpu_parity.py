@@ -241,3 +241,14 @@ def test_spec_depth_does_not_change_results(gpu, orc, depth):
 def test_tuning_fields_do_not_change_results(gpu, orc, kw):
     x = synth.scene_planes_blobs(60000, seed=23)
     _check(gpu, orc, x, 15000, gpu.params(**kw), f"tuning {kw}")
+
+
+@pytest.mark.parametrize("tw", [-1.0, 0.02, 0.5, 64.0])
+def test_trim_window_does_not_change_results(gpu, orc, tw):
+    # a window too narrow to hold the threshold, or none at all, takes the every-voxel
+    # bucket; a wide one a large bucket: the picks never change
+    x = synth.scene_planes_blobs(60000, seed=29)
+    _check(gpu, orc, x, 15000, gpu.params(trim_window=tw), f"trim window {tw}")
+    _check(gpu, orc, x, 9000, gpu.params(trim_window=tw, sigma=0.6), f"trim window {tw} wide tolerance")
+    _check(gpu, orc, x, 7000, gpu.params(trim_window=tw, t_max=4), f"trim window {tw} fallback")
+    _check(gpu, orc, synth.lattice(8), 12, gpu.params(trim_window=tw, layers=1), f"lattice window {tw}")
