@@ -242,6 +242,49 @@ hav_status_t hav_timing_enable(int32_t on);
  * not be read (its duration then counts as 0). */
 hav_status_t hav_timing_collect(const char* kernel, int32_t* launches, double* total_ms);
 
+/* ---------------------------------------------------------------------------------
+ * The samplers of the latency comparison (Sec. 4.2, Fig. 7). Same conventions as
+ * above: device pointers, asynchronous on `stream`, nothing allocated.
+ * --------------------------------------------------------------------------------- */
+
+#define HAV_FPS_MAX_POINTS 1048576     /* 256 blocks x 1024 threads x 4 points */
+#define HAV_RPS_MAX_POINTS 1073741823  /* 2^30 - 1 */
+
+/* Farthest point sampling (Sec. 3.1, Eq. 1): idx[0] = start, then idx[j] is the
+ * point whose squared distance to the nearest of idx[0..j-1] is largest, ties to
+ * the lowest index. Squared distances are computed in double as
+ * ((dx*dx + dy*dy) + dz*dz) with dx = (double)x_i - (double)x_c and no fused
+ * multiply-add, so results are reproducible bit for bit. idx holds M indices in
+ * selection order (not sorted). Coordinates must be finite.
+ *   xyz [N][3] float32 device; 1 <= M <= N <= HAV_FPS_MAX_POINTS; 0 <= start < N.
+ *   blocks: 0 = automatic; else 1..256 blocks share the cloud (cooperative launch when
+ *   more than one; N must fit 4 points per thread of 1024-thread blocks).
+ *   ws: hav_fps_workspace_size(N) bytes of device memory, no initialisation needed;
+ *   one call at a time per workspace.
+ * Returns HAV_ERR_INVALID_ARG / HAV_ERR_WORKSPACE_TOO_SMALL / HAV_ERR_HIP at once. A
+ * multi-block call whose blocks could not all run at once gives up after a bounded
+ * wait and raises the flag hav_fps_error reads (idx is then incomplete). */
+size_t hav_fps_workspace_size(int64_t N);
+hav_status_t hav_fps(const float* xyz, int64_t N, int64_t M, int64_t start, int32_t* idx, void* ws,
+                     size_t ws_bytes, int32_t blocks, void* stream);
+/* Synchronous read of the flag above (0 = the last call on ws completed). */
+hav_status_t hav_fps_error(const void* ws, uint32_t* flag_host);
+
+/* Random point sampling: point i gets the key mix(seed + (i + 1) * 0x9E3779B97F4A7C15)
+ * (output i + 1 of the SplitMix64 generator seeded with `seed`; mix as in the trim
+ * priority), and the M points of smallest key are returned in ascending index order.
+ *   1 <= M <= N <= HAV_RPS_MAX_POINTS; idx [M] int32 device.
+ *   window: tuning only, the half-width in standard deviations of the key window a
+ *   first pass tries around the expected threshold; 0 = default (6), negative = none
+ *   (select over all keys), at most 64. Results do not depend on it.
+ *   ws: hav_rps_workspace_size(N) bytes, initialised once with hav_rps_workspace_init
+ *   for that N (or any larger N); every call leaves it initialised. One call at a time
+ *   per workspace. */
+size_t hav_rps_workspace_size(int64_t N);
+hav_status_t hav_rps_workspace_init(void* ws, size_t ws_bytes, int64_t N, void* stream);
+hav_status_t hav_rps(int64_t N, int64_t M, uint64_t seed, float window, int32_t* idx, void* ws,
+                     size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -109,6 +109,8 @@ def lib():
         L.oracle_layer_budgets.restype = None
         L.oracle_fps.argtypes = [f32p, C.c_int64, C.c_int64, C.c_int64, i32p]
         L.oracle_fps.restype = C.c_int32
+        L.oracle_rps.argtypes = [C.c_int64, C.c_int64, C.c_uint64, i32p]
+        L.oracle_rps.restype = C.c_int32
         L.oracle_covering_radius.argtypes = [f32p, C.c_int64, i32p, C.c_int64]
         L.oracle_covering_radius.restype = C.c_double
         _lib = L
@@ -226,6 +228,16 @@ def fps(xyz, m: int, start: int = 0) -> np.ndarray:
     st = lib().oracle_fps(_ptr(a, C.c_float), a.shape[0], int(m), int(start), _ptr(out, C.c_int32))
     if st != 0:
         raise ValueError("fps: bad arguments")
+    return out
+
+
+def rps(N: int, m: int, seed: int) -> np.ndarray:
+    """Random point sampling: the m points of smallest SplitMix64 key (output i+1 of
+    the generator seeded with `seed` keys point i), ascending."""
+    out = np.zeros(int(m), dtype=np.int32)
+    st = lib().oracle_rps(int(N), int(m), C.c_uint64(int(seed) & ((1 << 64) - 1)), _ptr(out, C.c_int32))
+    if st != 0:
+        raise ValueError("rps: bad arguments")
     return out
 
 

@@ -1,10 +1,13 @@
 // Sampling-quality context tools — TEST INFRASTRUCTURE ONLY (CPU).
 //
-// Farthest point sampling (arXiv 2305.14306, Sec. 3.1, Eq. 1) and the covering
-// radius of a sample (largest distance from any cloud point to its nearest sampled
-// point). The paper motivates the voxel sampler by the wide, even coverage of FPS
-// (Sec. 3.1, Fig. 3); these give that comparison on synthetic clouds. They are not
-// part of the sampler and the GPU library does not have them.
+// Farthest point sampling (arXiv 2305.14306, Sec. 3.1, Eq. 1), random point
+// sampling, and the covering radius of a sample (largest distance from any cloud
+// point to its nearest sampled point). The paper motivates the voxel sampler by the
+// wide, even coverage of FPS (Sec. 3.1, Fig. 3) and times it against FPS and RPS
+// (Sec. 4.2, Fig. 7); FPS and RPS here are the definitions the GPU comparators are
+// checked against, bit for bit. Pins: FPS by a closed form on a line of equally
+// spaced points and by its factor-2 bound on the k-centre optimum (brute force on
+// tiny clouds); RPS by published SplitMix64 outputs.
 
 #include <algorithm>
 #include <cmath>
@@ -37,6 +40,31 @@ int32_t oracle_fps(const float* xyz, int64_t N, int64_t m, int64_t start, int32_
     }
     cur = arg;
   }
+  return 0;
+}
+
+// Random point sampling, the fast baseline of the latency comparison (Sec. 4.2,
+// Fig. 7): point i gets the key splitmix64(seed + (i + 1) * golden gamma), output
+// i + 1 of the SplitMix64 generator (Steele, Lea and Flood 2014) seeded with `seed`;
+// the m points of smallest key are returned in ascending index order. Keys are
+// distinct (the finaliser is a bijection of seed + (i+1) gamma, itself distinct for
+// i < 2^64), so the set is unique.
+static uint64_t sm64_finalise(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+int32_t oracle_rps(int64_t N, int64_t m, uint64_t seed, int32_t* out) {
+  if (!out || N < 1 || m < 1 || m > N) return 1;
+  std::vector<std::pair<uint64_t, int64_t>> key(static_cast<size_t>(N));
+  for (int64_t i = 0; i < N; ++i)
+    key[i] = {sm64_finalise(seed + static_cast<uint64_t>(i + 1) * 0x9E3779B97F4A7C15ull), i};
+  std::sort(key.begin(), key.end());
+  std::vector<int64_t> pick;
+  for (int64_t j = 0; j < m; ++j) pick.push_back(key[j].second);
+  std::sort(pick.begin(), pick.end());
+  for (int64_t j = 0; j < m; ++j) out[j] = static_cast<int32_t>(pick[j]);
   return 0;
 }
 

@@ -138,6 +138,18 @@ def lib():
         L.hav_graph_launch.argtypes = [vp, vp]
         L.hav_graph_destroy.restype = None
         L.hav_graph_destroy.argtypes = [vp]
+        L.hav_fps_workspace_size.restype = C.c_size_t
+        L.hav_fps_workspace_size.argtypes = [C.c_int64]
+        L.hav_fps.restype = C.c_int
+        L.hav_fps.argtypes = [vp, C.c_int64, C.c_int64, C.c_int64, i32p, vp, C.c_size_t, C.c_int32, vp]
+        L.hav_fps_error.restype = C.c_int
+        L.hav_fps_error.argtypes = [vp, C.POINTER(C.c_uint32)]
+        L.hav_rps_workspace_size.restype = C.c_size_t
+        L.hav_rps_workspace_size.argtypes = [C.c_int64]
+        L.hav_rps_workspace_init.restype = C.c_int
+        L.hav_rps_workspace_init.argtypes = [vp, C.c_size_t, C.c_int64, vp]
+        L.hav_rps.restype = C.c_int
+        L.hav_rps.argtypes = [C.c_int64, C.c_int64, C.c_uint64, C.c_float, i32p, vp, C.c_size_t, vp]
         L.hav_timing_enable.restype = C.c_int
         L.hav_timing_enable.argtypes = [C.c_int32]
         L.hav_timing_collect.restype = C.c_int
@@ -480,3 +492,63 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------- comparators (Fig. 7)
+
+class FPS:
+    """Farthest point sampling on the GPU (hav_fps): the comparator of the latency
+    study. Keeps its (small) workspace; calls run on the current stream."""
+
+    def __init__(self, device=None):
+        torch = _torch()
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self._ws = torch.empty(int(lib().hav_fps_workspace_size(1)), dtype=torch.uint8, device=self.device)
+
+    def sample(self, xyz, M: int, start: int = 0, blocks: int = 0, out=None, stream=None):
+        """idx [M] int32 in selection order."""
+        torch = _torch()
+        _check_xyz(xyz)
+        N = xyz.shape[0]
+        out = out if out is not None else torch.empty(int(M), dtype=torch.int32, device=xyz.device)
+        st = lib().hav_fps(xyz.data_ptr(), N, int(M), int(start), out.data_ptr(), self._ws.data_ptr(),
+                           self._ws.numel(), int(blocks), _stream_ptr(stream))
+        if st != 0:
+            raise HavError(st)
+        return out
+
+    def error_flag(self) -> int:
+        f = C.c_uint32(0)
+        st = lib().hav_fps_error(self._ws.data_ptr(), C.byref(f))
+        if st != 0:
+            raise HavError(st)
+        return int(f.value)
+
+
+class RPS:
+    """Random point sampling on the GPU (hav_rps): the m points of smallest SplitMix64
+    key, ascending. Keeps a workspace sized for the largest N seen."""
+
+    def __init__(self, device=None):
+        torch = _torch()
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self._ws = None
+        self._n = 0
+
+    def sample(self, N: int, M: int, seed: int = 0, window: float = 0.0, out=None, stream=None):
+        torch = _torch()
+        if N > self._n:
+            nbytes = int(lib().hav_rps_workspace_size(int(N)))
+            if nbytes == 0:
+                raise HavError(1)
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            st = lib().hav_rps_workspace_init(self._ws.data_ptr(), nbytes, int(N), _stream_ptr(stream))
+            if st != 0:
+                raise HavError(st)
+            self._n = int(N)
+        out = out if out is not None else torch.empty(int(M), dtype=torch.int32, device=self.device)
+        st = lib().hav_rps(int(N), int(M), int(seed) & ((1 << 64) - 1), float(window), out.data_ptr(),
+                           self._ws.data_ptr(), self._ws.numel(), _stream_ptr(stream))
+        if st != 0:
+            raise HavError(st)
+        return out

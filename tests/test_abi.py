@@ -194,3 +194,29 @@ def test_server_create_rejects_bad_arguments(hav):
     t = C.c_uint64(0)
     assert L.hav_server_submit(None, C.c_void_p(0x1000), 10, 5, C.byref(t)) == hav.ERR_INVALID_ARG
     assert L.hav_server_poll(None, 1, None, None, None) == hav.ERR_INVALID_ARG
+
+
+def test_comparators_reject_bad_arguments(hav):
+    L = hav.lib()
+    buf = C.create_string_buffer(1 << 16)
+    ptr = C.addressof(buf)
+    assert L.hav_fps_workspace_size(0) == 0
+    assert L.hav_fps_workspace_size(hav.lib().hav_fps_workspace_size(1)) > 0
+    ws = L.hav_fps_workspace_size(100)
+    for args in [(0, 100, 10, 0, ptr, ptr, ws, 0),          # no xyz
+                 (ptr, 100, 0, 0, ptr, ptr, ws, 0),         # M < 1
+                 (ptr, 100, 101, 0, ptr, ptr, ws, 0),       # M > N
+                 (ptr, 100, 10, 100, ptr, ptr, ws, 0),      # start out of range
+                 (ptr, 100, 10, 0, ptr, ptr, ws, 257),      # too many blocks
+                 (ptr, 1 << 21, 10, 0, ptr, ptr, ws, 0),    # above HAV_FPS_MAX_POINTS
+                 (ptr, 20000, 10, 0, ptr, ptr, ws, 1)]:     # one block cannot hold it
+        assert L.hav_fps(*args, None) == 1, args
+    assert L.hav_fps(ptr, 100, 10, 0, ptr, ptr, 8, 0, None) == 2
+    assert L.hav_rps_workspace_size(0) == 0
+    rw = L.hav_rps_workspace_size(1000)
+    assert rw > 0
+    for args in [(1000, 0, 1, 0.0, ptr, ptr, rw), (1000, 1001, 1, 0.0, ptr, ptr, rw),
+                 (1000, 10, 1, float("nan"), ptr, ptr, rw), (1000, 10, 1, 65.0, ptr, ptr, rw),
+                 (1000, 10, 1, 0.0, 0, ptr, rw)]:
+        assert L.hav_rps(*args, None) == 1, args
+    assert L.hav_rps(1000, 10, 1, 0.0, ptr, ptr, 16, None) == 2

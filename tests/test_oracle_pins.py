@@ -396,3 +396,65 @@ def test_linear_time(orc):
         work = n * sum(ev + 1 for ev in info["evals"])
         rates.append(dt / work)
     assert max(rates) / min(rates) < 4.0, rates
+
+
+# ---------------------------------------------------------------- comparators (Fig. 7)
+
+def test_rps_keys_are_published_splitmix64_outputs(orc):
+    # point i is keyed by output i+1 of the generator seeded with 1234567 (the golden
+    # file): the m smallest of those five published numbers, in index order
+    vals = [int(r[0]) for r in _golden_lines("splitmix64_seed1234567.txt")]
+    order = sorted(range(len(vals)), key=lambda i: vals[i])
+    for m in range(1, len(vals) + 1):
+        assert list(orc.rps(len(vals), m, 1234567)) == sorted(order[:m])
+
+
+def test_rps_invariants(orc):
+    for N, m, seed in [(1, 1, 0), (10, 10, 5), (1000, 1, 9), (1000, 999, 9), (4097, 1234, 77)]:
+        got = orc.rps(N, m, seed)
+        assert len(got) == m and len(set(got.tolist())) == m
+        assert np.all(np.diff(got) > 0) and got[0] >= 0 and got[-1] < N
+    assert list(orc.rps(10, 10, 5)) == list(range(10))
+    # nested: the m smallest keys contain the m-1 smallest
+    a, b = set(orc.rps(5000, 700, 3).tolist()), set(orc.rps(5000, 701, 3).tolist())
+    assert a < b and len(b - a) == 1
+    # even spread: about m/N of every tenth of the index range is kept
+    got = orc.rps(100000, 20000, 11)
+    hist = np.bincount(got // 10000, minlength=10)
+    assert np.all(np.abs(hist - 2000) < 6 * np.sqrt(2000 * 0.8))
+
+
+def test_fps_line_closed_form(orc):
+    # nine equally spaced points on a line, start 0: the far end, then the middle, then
+    # the quarter points (2 before 6: ties go to the lower index), then the odd points
+    # (all at distance 1) in index order
+    x = np.zeros((9, 3), dtype=np.float32)
+    x[:, 0] = np.arange(9)
+    assert list(orc.fps(x, 9, 0)) == [0, 8, 4, 2, 6, 1, 3, 5, 7]
+    assert list(orc.fps(x, 3, 4)) == [4, 0, 8]
+
+
+def test_fps_ties_lowest_index(orc):
+    # from the centre all four are at 1; after each pick the others stay at 1 from the
+    # centre (and farther from the picks), so every step is a tie won by the lowest index
+    x = np.array([[0, 0, 0], [0, 1, 0], [1, 0, 0], [0, -1, 0], [-1, 0, 0]], dtype=np.float32)
+    assert list(orc.fps(x, 5, 0)) == [0, 1, 2, 3, 4]
+    # from the middle of the line -1, 0, 1 (indices 1, 2, 0) both ends are at 1: index 0 first
+    y = np.array([[1, 0, 0], [-1, 0, 0], [0, 0, 0]], dtype=np.float32)
+    assert list(orc.fps(y, 3, 2)) == [2, 0, 1]
+
+
+def test_fps_within_twice_the_k_centre_optimum(orc):
+    # Gonzalez: the covering radius of the first k FPS picks is at most twice that of
+    # the best k-subset (found here by brute force over every subset)
+    import itertools
+    rng = np.random.default_rng(5)
+    for trial in range(6):
+        x = rng.uniform(-3, 3, size=(9, 3)).astype(np.float32)
+        D = np.sqrt(((x[:, None, :].astype(np.float64) - x[None, :, :]) ** 2).sum(-1))
+        for k in (1, 2, 3, 4):
+            picks = orc.fps(x, k, trial % 9)
+            r_fps = D[:, picks].min(1).max()
+            r_opt = min(D[:, list(c)].min(1).max() for c in itertools.combinations(range(9), k))
+            assert r_fps <= 2 * r_opt + 1e-12
+            assert orc.covering_radius(x, picks) == pytest.approx(r_fps, rel=1e-6)
