@@ -27,8 +27,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 DOMINANT = "k_search"
 KERNELS = ("k_bbox", "k_identity", "k_bin_count", "k_bin_scan", "k_bin_scatter", "k_search",
-           "k_select", "k_trim_hist", "k_mark", "k_ties", "k_scan_count", "k_pad_mark",
-           "k_out_write", "k_ws_init", "k_ws_seal", "k_compose", "k_gather")
+           "k_select", "k_trim_hist", "k_mark", "k_pad", "k_out", "k_ws_init", "k_ws_seal",
+           "k_compose", "k_gather")
 PMC_FILE = os.path.join(ROOT, "profiles", "k_search_scene1M_pmc.txt")
 
 
@@ -120,6 +120,57 @@ def batch_leg(torch, hav, synth, steps: int) -> dict:
     return {"workload": "64 LiDAR-shaped clouds, N_i ~ U{20k..200k} (sum %d), M_i = N_i/4" % total_n,
             "batched_ms": round(t_b, 4), "per_cloud_ms": round(t_s, 4),
             "speedup": round(t_s / t_b, 3), "batched_Mpoints_per_s": round(total_n / t_b / 1e3, 1)}
+
+
+def fig7_leg(torch, hav, synth, reps: int) -> dict:
+    """The latency study of Sec. 4.2 (Fig. 7): LiDAR-shaped clouds of 2^14, 2^16 and
+    2^18 points, each downsampled in 3 steps of ratio 2 by HAVSampler, farthest point
+    sampling and random point sampling, all on the GPU. Each method chains on its own
+    output. A step's latency is its sampler call alone (median of `reps`, CUDA events on
+    the current stream, after one untimed call); the gather of the next step's cloud is
+    not counted."""
+    import numpy as np
+
+    def median_ms(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    scales = {}
+    for e in (14, 16, 18):
+        N = 1 << e
+        x = torch.from_numpy(synth.lidar_points(N, seed=700 + e)).cuda()
+        row = {}
+        for name in ("hav", "fps", "rps"):
+            cur, times = x, []
+            for step in range(3):
+                n = cur.shape[0]
+                m = n // 2
+                out = torch.empty(m, dtype=torch.int32, device="cuda")
+                if name == "hav":
+                    s = hav.Sampler()
+                    fn = lambda s=s, cur=cur, m=m, out=out: s.sample(cur, m, out=out)
+                elif name == "fps":
+                    f = hav.FPS()
+                    fn = lambda f=f, cur=cur, m=m, out=out: f.sample(cur, m, 0, 0, out=out)
+                else:
+                    r = hav.RPS()
+                    fn = lambda r=r, n=n, m=m, out=out: r.sample(n, m, 12345 + step, out=out)
+                times.append(round(median_ms(fn), 4))
+                cur = cur.index_select(0, out.long()).contiguous()
+            row[name + "_ms"] = times
+            print(f"bench: fig7 2^{e} {name} {times}", file=sys.stderr, flush=True)
+        row["fps_over_hav"] = round(sum(row["fps_ms"]) / sum(row["hav_ms"]), 1)
+        scales[f"2^{e}"] = row
+    return {"workload": "LiDAR-shaped clouds of 2^14, 2^16, 2^18 points, 3 chained steps of ratio 2 "
+                        "(per-step sampler latency, ms)", "scales": scales}
 
 
 def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
@@ -226,6 +277,8 @@ def main() -> int:
     ap.add_argument("--spec-depth", type=int, default=0,
                     help="tuning: voxel sizes per search pass (0 = library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-fig7", action="store_true",
+                    help="skip the latency comparison with FPS and RPS (Fig. 7 of the paper)")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter "
@@ -323,6 +376,8 @@ def main() -> int:
         result["serve"] = serve_leg(torch, hav, synth, args.serve_requests,
                                     min(500, args.serve_requests // 10))
         print(f"bench: serve {result['serve']}", file=sys.stderr, flush=True)
+    if not args.no_fig7:
+        result["fig7"] = fig7_leg(torch, hav, synth, 3)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(x, M, args.cpu_seconds)
     print(json.dumps(result), flush=True)

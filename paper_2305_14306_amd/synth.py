@@ -162,10 +162,31 @@ def batch_lidar_clouds(n_clouds: int = 64, seed0: int = 1000, n_min: int = 20000
             pts = _cast_rays(rng, az, 64, boxes, 1.8, 120.0, 0.02)
             if pts.shape[0] >= n_i:
                 break
-            az = int(math.ceil(az * 1.25))
+            if pts.shape[0] < az * 64 // 4:
+                boxes = _lidar_boxes(rng, 30)  # a box encloses the sensor
+            else:
+                az = int(math.ceil(az * 1.25))
         clouds.append(_f32(pts[:n_i]))
         ms.append(n_i // ratio)
     return clouds, ms
+
+
+def lidar_points(n: int, seed: int = 0, beams: int = 64):
+    """A LiDAR-shaped sweep (as lidar_scan: ground, 30 boxes, 64 beams) with exactly n
+    points: ceil(n / (beams * 0.85)) azimuth steps (more if the sweep has fewer hits),
+    the first n hits kept (azimuth-major order). Boxes are drawn again if one encloses
+    the sensor (then no ray leaves it)."""
+    rng = np.random.default_rng(seed)
+    az = int(math.ceil(n / (beams * 0.85)))
+    boxes = _lidar_boxes(rng, 30)
+    while True:
+        pts = _cast_rays(rng, az, beams, boxes, 1.8, 120.0, 0.02)
+        if pts.shape[0] >= n:
+            return _f32(pts[:n])
+        if pts.shape[0] < az * beams // 4:
+            boxes = _lidar_boxes(rng, 30)  # a box encloses the sensor: every ray is lost
+        else:
+            az = int(math.ceil(az * 1.25))
 
 
 def serving_trace(n_requests: int = 10000, rate_hz: float = 2000.0, seed: int = 7,
