@@ -12,24 +12,29 @@
 //                  is exactly what Eq. 2 consumes, and the original index), so each
 //                  2048-point tile is spatially compact
 //   per layer (Sec. 3.4, Eq. 3):
-//     k_eval x P   adaptive voxel search (Sec. 3.3). A pass evaluates the voxel
-//                  counter Cnt for the next `depth` levels of the bisection tree at
-//                  once; the decisions, and so the scales, are exactly those of one
-//                  bisection step at a time. A tile dedups its voxels in LDS as 4x4x4
-//                  bricks with 64-bit occupancy masks, then makes one find-or-claim
-//                  and at most one atomicOr per distinct brick in a global table; the
-//                  newly set bits are newly seen voxels. The last block to finish
-//                  walks the tree and plans the next pass.
+//     k_search     adaptive voxel search (Sec. 3.3), one launch: a queue of (pass,
+//                  tile) tickets. A pass evaluates the voxel counter Cnt at up to
+//                  `depth` sizes along the bisection path a count model predicts;
+//                  steps whose count is provably below m (more voxels than grid cells
+//                  is impossible) are taken without evaluation. Decisions, and so the
+//                  chosen size, are exactly those of one bisection step at a time. A
+//                  tile dedups its voxels in LDS as 4x4x4 bricks with 64-bit occupancy
+//                  masks, then makes one find-or-claim and at most one atomicOr per
+//                  distinct brick in a global table; the newly set bits are newly seen
+//                  voxels. The block that completes a pass runs the bisection step and
+//                  publishes the next pass.
 //     k_select     centre-closest point per occupied voxel at the chosen size
 //                  (Sec. 3.2): LDS min of (bits(d^2) << 32 | index), then at most one
-//                  global atomicMin per tile-distinct voxel; ties go to the lowest index
-//     k_trim_hist  radix select (8-bit digits) of the m-th smallest SplitMix64 voxel
-//                  priority when there are more voxels than m
-//     k_mark       keep the voxels below the selected bucket, queue the bucket
-//     k_ties       one block settles the exact rank inside the bucket
-//     k_scan_count / k_pad_mark   pad with the lowest-index unsampled points when
-//                  there are fewer voxels than m
-//   k_scan_count / k_out_write    ascending output indices by a two-level scan
+//                  global atomicMin per tile-distinct voxel; ties go to the lowest
+//                  index. Also counts voxel priorities below / inside a window around
+//                  the expected trim threshold
+//     k_trim_hist  (fixed voxel size only) radix rounds of the trim threshold
+//     k_mark       keep the voxels below the trim bucket, queue the bucket; the last
+//                  block ranks the bucket and marks up to the exact threshold
+//     k_pad        pad with the lowest-index unsampled points when there are fewer
+//                  voxels than m (one pass, tiles chained in dispatch order); starts
+//                  the next layer
+//   k_out          ascending output indices (one pass, same chaining)
 //
 // Table hygiene: a workspace is initialised once (hav_workspace_init). Each kernel
 // that fills a table records the slots it claimed and a later kernel of the same call

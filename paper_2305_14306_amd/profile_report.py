@@ -27,11 +27,22 @@ SOURCES = (os.path.join(ROOT, "paper_2305_14306_amd", "csrc", "hav.hip"),
 CALIB_KIB = 256 * 1024  # the calibration kernel reads and writes 256 MiB
 
 
+def _code_only(text: str) -> str:
+    """The source with // comments and blank lines removed (comments do not change
+    what the counters measured)."""
+    out = []
+    for line in text.splitlines():
+        code = line.split("//", 1)[0].rstrip() if "//" in line and '"' not in line else line.rstrip()
+        if code:
+            out.append(code)
+    return "\n".join(out)
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     for f in SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
