@@ -55,6 +55,13 @@ typedef enum {
 #define HAV_FIXED_VOXEL 1u /* use fixed_voxel[] instead of the adaptive search
                               (the "Fix" setting of the ablation, Sec. 4.5 Table 6) */
 
+/* representative of an occupied voxel (hav_params_t.select) */
+#define HAV_SELECT_CENTRE_CLOSEST 0 /* the point closest to the voxel centre, ties to the
+                                       lowest index (Sec. 3.2; "CC" of Table 6) */
+#define HAV_SELECT_RANDOM 1         /* a random member: the point with the smallest top 32
+                                       bits of SplitMix64 output i+1 for select_seed (point
+                                       i), ties to the lowest index ("RA" of Table 6) */
+
 /* Sampling parameters. Start from hav_params_default(). */
 typedef struct {
   int32_t abi_version; /* must be HAV_ABI_VERSION */
@@ -80,6 +87,8 @@ typedef struct {
                           position, of the priority window the trim first tries as the bucket
                           holding its threshold; 0 = default (6), negative = no window (the
                           bucket is every voxel), else at most 64. Results do not depend on it. */
+  int32_t select;      /* HAV_SELECT_CENTRE_CLOSEST (default) or HAV_SELECT_RANDOM */
+  uint32_t select_seed;/* generator seed of HAV_SELECT_RANDOM */
 } hav_params_t;
 
 /* Per-call report, written by the device into caller memory (info_dev). */

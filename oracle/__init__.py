@@ -33,6 +33,8 @@ class Params(C.Structure):
         ("sigma", C.c_double),
         ("aspect", C.c_float * 3),
         ("fixed_voxel", C.c_float * 3),
+        ("select", C.c_int32),
+        ("seed", C.c_uint32),
     ]
 
 
@@ -129,9 +131,10 @@ def _xyz(xyz) -> np.ndarray:
 
 
 def params(layers=2, layer_ratio=4, t_max=20, sigma=0.05, aspect=(1.0, 1.0, 1.0),
-           fixed_voxel=None) -> Params:
+           fixed_voxel=None, select=0, seed=0) -> Params:
     p = lib().oracle_params_default()
     p.layers, p.layer_ratio, p.t_max, p.sigma = layers, layer_ratio, t_max, sigma
+    p.select, p.seed = select, seed
     for a in range(3):
         p.aspect[a] = aspect[a]
     if fixed_voxel is not None:

@@ -70,6 +70,8 @@ typedef struct {
   double sigma;
   float aspect[3];
   float fixed_voxel[3];
+  int32_t select;   // 0: centre-closest (Sec. 3.2); 1: random member (Table 6, RA)
+  uint32_t seed;    // random member: generator seed
 } OracleParams;
 
 typedef struct {
@@ -188,6 +190,7 @@ bool params_valid(const OracleParams* p) {
     }
   }
   if (p->flags & ~OR_FIXED_VOXEL) return false;
+  if (p->select != 0 && p->select != 1) return false;
   return true;
 }
 
@@ -333,14 +336,21 @@ int32_t sample_stage(const float* xyz, int64_t N, int64_t M, const OracleParams*
       inf.accepted[L] = accepted ? 1 : 0;
     }
 
-    // Centre-closest representative per voxel, ties to the lowest index.
+    // Centre-closest representative per voxel, ties to the lowest index. The random
+    // variant (the "RA" selection of Table 6) ranks a voxel's points instead by the top
+    // 32 bits of output i+1 of a SplitMix64 generator seeded with p->seed, ties again
+    // to the lowest index.
     std::unordered_map<uint64_t, std::pair<uint32_t, int64_t>> best;
     best.reserve(R.size() * 2 + 16);
     for (int64_t i : R) {
       int32_t g[3];
       float r[3];
       const uint64_t key = voxel_key(xyz + 3 * i, mn, inv, g, r);
-      const uint32_t d2 = float_bits(centre_dist2(r, g, v));  // d2 >= 0: bits order = value order
+      const uint32_t d2 =
+          p->select == 1
+              ? static_cast<uint32_t>(voxel_priority(static_cast<uint64_t>(p->seed) +
+                                                     static_cast<uint64_t>(i) * 0x9E3779B97F4A7C15ull) >> 32)
+              : float_bits(centre_dist2(r, g, v));  // d2 >= 0: bits order = value order
       auto it = best.find(key);
       if (it == best.end()) {
         best.emplace(key, std::make_pair(d2, i));
@@ -408,6 +418,8 @@ OracleParams oracle_params_default(void) {
     p.aspect[a] = 1.0f;
     p.fixed_voxel[a] = 1.0f;
   }
+  p.select = 0;
+  p.seed = 0;
   return p;
 }
 

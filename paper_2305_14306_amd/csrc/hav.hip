@@ -166,6 +166,8 @@ struct Plan {  // per-call constants (kernel argument)
   uint32_t sel_cap;   // voxel value slots: dense voxel grids up to this size
   float spec_mult;    // speculation budget of the search, in multiples of the window top
   float win_sigma;    // trim window half-width in standard deviations (<= 0: none)
+  int32_t select;     // HAV_SELECT_CENTRE_CLOSEST or HAV_SELECT_RANDOM
+  uint32_t seed;      // random member: generator seed
   int32_t identity;   // M == N: output 0..N-1, nothing else runs
   int32_t rounds[HAV_MAX_LAYERS];  // radix rounds of each layer's trim (fixed size only)
 };
@@ -1534,6 +1536,8 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   const float ix = c->inv_final[0], iy = c->inv_final[1], iz = c->inv_final[2];
   const int dense = c->sel_dense;
   const uint64_t nx = c->sel_nv[0], ny = c->sel_nv[1];
+  const bool rnd = cd.P.select == HAV_SELECT_RANDOM;
+  const uint64_t seed = cd.P.seed;
   for (int e = threadIdx.x; e < kLdsCap; e += kThreads) {
     lkeys[e] = kEmptyKey;
     lvals[e] = ~0ull;
@@ -1619,9 +1623,16 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
         if (!(live & (1u << k))) continue;
         const float4 p = pt[k];
         const uint32_t gx = axis_coord(p.x, ix), gy = axis_coord(p.y, iy), gz = axis_coord(p.z, iz);
-        const float d2 = centre_dist2(p.x, p.y, p.z, gx, gy, gz, vx, vy, vz);
-        val = (static_cast<uint64_t>(__float_as_uint(d2)) << 32) |
-              static_cast<uint32_t>(__float_as_int(p.w));
+        const uint32_t orig = static_cast<uint32_t>(__float_as_int(p.w));
+        uint32_t rank;
+        if (rnd) {
+          // random member: top half of SplitMix64 output orig + 1 for the seed
+          rank = static_cast<uint32_t>(
+              voxel_priority(seed + static_cast<uint64_t>(orig) * 0x9E3779B97F4A7C15ull) >> 32);
+        } else {
+          rank = __float_as_uint(centre_dist2(p.x, p.y, p.z, gx, gy, gz, vx, vy, vz));
+        }
+        val = (static_cast<uint64_t>(rank) << 32) | orig;
         key = vol ? static_cast<uint64_t>((gx - bl0) + bdx * ((gy - bl1) + bdy * (gz - bl2)))
                   : (dense ? gx + nx * (gy + ny * gz) : pack_key(gx, gy, gz));
         if (key == cur) {
@@ -2289,6 +2300,7 @@ bool params_ok(const hav_params_t* p) {
   if (p->spec_budget < 0 || p->spec_budget > 1024) return false;
   if (p->search_blocks < 0 || p->search_blocks > 65536) return false;
   if (!std::isfinite(p->trim_window) || p->trim_window > 64.0f) return false;
+  if (p->select != HAV_SELECT_CENTRE_CLOSEST && p->select != HAV_SELECT_RANDOM) return false;
   for (int a = 0; a < 3; ++a) {
     const float as = p->aspect[a];
     if (!std::isfinite(as) || as < 0x1p-16f || as > 0x1p16f) return false;
@@ -2330,6 +2342,8 @@ struct ParamLite {
   double sigma;
   float trim_window;
   float aspect[3], fixed_v[3];
+  int32_t select;
+  uint32_t seed;
 };
 
 ParamLite lite_of(const hav_params_t* p) {
@@ -2342,6 +2356,8 @@ ParamLite lite_of(const hav_params_t* p) {
   q.spec_budget = p->spec_budget;
   q.sigma = p->sigma;
   q.trim_window = p->trim_window;
+  q.select = p->select;
+  q.seed = p->select_seed;
   for (int a = 0; a < 3; ++a) {
     q.aspect[a] = p->aspect[a];
     q.fixed_v[a] = p->fixed_voxel[a];
@@ -2376,6 +2392,8 @@ __host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite&
   P.sel_cap = cd.w.cap * static_cast<uint32_t>(kSelDense);
   P.spec_mult = q.spec_budget ? static_cast<float>(q.spec_budget) : kSpecMult;
   P.win_sigma = q.trim_window == 0.0f ? kWinSigma : q.trim_window;
+  P.select = q.select;
+  P.seed = q.seed;
   P.identity = c.m == c.n ? 1 : 0;
   for (int a = 0; a < 3; ++a) {
     P.aspect[a] = q.aspect[a];
@@ -2884,6 +2902,8 @@ hav_params_t hav_params_default(void) {
   p.spec_budget = 0;
   p.search_blocks = 0;
   p.trim_window = 0.0f;
+  p.select = HAV_SELECT_CENTRE_CLOSEST;
+  p.select_seed = 0;
   return p;
 }
 

@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(HERE, "libhav.so")
 ABI_VERSION = 1
 MAX_LAYERS = 8
 FIXED_VOXEL = 1
+SELECT_CENTRE_CLOSEST = 0
+SELECT_RANDOM = 1
 
 OK, ERR_INVALID_ARG, ERR_WORKSPACE_TOO_SMALL, ERR_OUT_OF_MEMORY, ERR_UNSUPPORTED, \
     ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE_NOT_INIT, NOT_READY = range(9)
@@ -34,6 +36,8 @@ class Params(C.Structure):
         ("spec_budget", C.c_int32),
         ("search_blocks", C.c_int32),
         ("trim_window", C.c_float),
+        ("select", C.c_int32),
+        ("select_seed", C.c_uint32),
     ]
 
 
@@ -178,11 +182,12 @@ def status_string(status: int) -> str:
 
 def params(layers=2, layer_ratio=4, t_max=20, sigma=0.05, aspect=(1.0, 1.0, 1.0),
            fixed_voxel=None, spec_depth=0, spec_budget=0, search_blocks=0,
-           trim_window=0.0) -> Params:
+           trim_window=0.0, select=0, select_seed=0) -> Params:
     p = lib().hav_params_default()
     p.layers, p.layer_ratio, p.t_max, p.sigma = layers, layer_ratio, t_max, sigma
     p.spec_depth, p.spec_budget, p.search_blocks = spec_depth, spec_budget, search_blocks
     p.trim_window = trim_window
+    p.select, p.select_seed = select, select_seed
     for a in range(3):
         p.aspect[a] = aspect[a]
     if fixed_voxel is not None:

@@ -117,7 +117,8 @@ def test_host_rejects_bad_arguments(hav):
                dict(fixed_voxel=0.0), dict(fixed_voxel=float("nan")), dict(spec_depth=8),
                dict(spec_depth=-1), dict(spec_budget=-1), dict(spec_budget=1025),
                dict(search_blocks=-1), dict(search_blocks=65537),
-               dict(trim_window=64.5), dict(trim_window=float("nan")), dict(trim_window=float("inf"))):
+               dict(trim_window=64.5), dict(trim_window=float("nan")), dict(trim_window=float("inf")),
+               dict(select=2), dict(select=-1)):
         assert _call(hav, p=hav.params(**kw)) == E, kw
     p = hav.params()
     p.abi_version = 2

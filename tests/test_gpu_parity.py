@@ -38,7 +38,7 @@ def _to_dev(x):
 def _oracle_params(orc, p):
     fv = tuple(p.fixed_voxel) if p.flags & 1 else None
     return orc.params(layers=p.layers, layer_ratio=p.layer_ratio, t_max=p.t_max, sigma=p.sigma,
-                      aspect=tuple(p.aspect), fixed_voxel=fv)
+                      aspect=tuple(p.aspect), fixed_voxel=fv, select=p.select, seed=p.select_seed)
 
 
 def _check(gpu, orc, x, M, p=None, label=""):
@@ -252,3 +252,17 @@ def test_trim_window_does_not_change_results(gpu, orc, tw):
     _check(gpu, orc, x, 9000, gpu.params(trim_window=tw, sigma=0.6), f"trim window {tw} wide tolerance")
     _check(gpu, orc, x, 7000, gpu.params(trim_window=tw, t_max=4), f"trim window {tw} fallback")
     _check(gpu, orc, synth.lattice(8), 12, gpu.params(trim_window=tw, layers=1), f"lattice window {tw}")
+
+
+@pytest.mark.parametrize("seed", [0, 99, 0xFFFFFFFF])
+def test_random_member_selection(gpu, orc, seed):
+    # the "RA" strategy of Table 6: a random member per voxel instead of the
+    # centre-closest one; the search, trim and pad are unchanged
+    x = synth.scene_planes_blobs(80000, seed=31)
+    p = gpu.params(select=gpu.SELECT_RANDOM, select_seed=seed)
+    got, _ = _check(gpu, orc, x, 20000, p, f"random member seed {seed}")
+    cc, _ = _check(gpu, orc, x, 20000, gpu.params(), "centre-closest")
+    assert not np.array_equal(got, cc)
+    _check(gpu, orc, x, 5000, gpu.params(select=gpu.SELECT_RANDOM, select_seed=seed, fixed_voxel=0.7),
+           "random member fixed voxel (RVS-like)")
+    _check(gpu, orc, synth.lattice(8), 60, p, "random member lattice")

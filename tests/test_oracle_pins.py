@@ -458,3 +458,34 @@ def test_fps_within_twice_the_k_centre_optimum(orc):
             r_opt = min(D[:, list(c)].min(1).max() for c in itertools.combinations(range(9), k))
             assert r_fps <= 2 * r_opt + 1e-12
             assert orc.covering_radius(x, picks) == pytest.approx(r_fps, rel=1e-6)
+
+
+def test_random_member_uses_published_splitmix64(orc):
+    # five points in one voxel (fixed size 10), one layer, M = 1: the member with the
+    # smallest top 32 bits of the generator's outputs for seed 1234567 (the golden file:
+    # output j+1 keys point j) is kept
+    vals = [int(r[0]) for r in _golden_lines("splitmix64_seed1234567.txt")]
+    x = np.array([[0.1 * j, 0.2, 0.3] for j in range(5)], dtype=np.float32)
+    p = orc.params(layers=1, fixed_voxel=10.0, select=1, seed=1234567)
+    st, idx, info = orc.sample(x, 1, p)
+    assert st == 0 and info["count"] == [1]
+    assert list(idx) == [min(range(5), key=lambda j: (vals[j] >> 32, j))]
+    # centre-closest on the same points keeps the one nearest (5, 5, 5): the last
+    st, idx, _ = orc.sample(x, 1, orc.params(layers=1, fixed_voxel=10.0))
+    assert list(idx) == [4]
+
+
+def test_random_member_sort_route(orc):
+    # with a fixed voxel size and no trim, the picks are the first point of each voxel
+    # after sorting by (packed key, top 32 bits of the point's key, index)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0, 3, size=(400, 3)).astype(np.float32)
+    seed = 77
+    g, key, _ = orc.keys(x, x.min(0), np.array([0.5, 0.5, 0.5], dtype=np.float32))
+    rk = [orc.priority((seed + i * GOLDEN_GAMMA) & MASK64) >> 32 for i in range(400)]
+    order = sorted(range(400), key=lambda i: (int(key[i]), rk[i], i))
+    firsts = sorted({int(key[i]): i for i in reversed(order)}.values())
+    M = len(firsts)
+    st, idx, info = orc.sample(x, M, orc.params(layers=1, fixed_voxel=0.5, select=1, seed=seed))
+    assert st == 0 and info["trimmed"] == [0] and info["padded"] == [0]
+    assert list(idx) == firsts
