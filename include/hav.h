@@ -61,6 +61,9 @@ typedef enum {
 #define HAV_SELECT_RANDOM 1         /* a random member: the point with the smallest top 32
                                        bits of SplitMix64 output i+1 for select_seed (point
                                        i), ties to the lowest index ("RA" of Table 6) */
+#define HAV_SELECT_CENTRE 2         /* the voxel's centre ("CE"), hav_sample_points only */
+#define HAV_SELECT_MEAN 3           /* the mean of the voxel's points ("ME"), hav_sample_points
+                                       only */
 
 /* Sampling parameters. Start from hav_params_default(). */
 typedef struct {
@@ -87,7 +90,9 @@ typedef struct {
                           position, of the priority window the trim first tries as the bucket
                           holding its threshold; 0 = default (6), negative = no window (the
                           bucket is every voxel), else at most 64. Results do not depend on it. */
-  int32_t select;      /* HAV_SELECT_CENTRE_CLOSEST (default) or HAV_SELECT_RANDOM */
+  int32_t select;      /* HAV_SELECT_CENTRE_CLOSEST (default) or HAV_SELECT_RANDOM; CENTRE and
+                          MEAN with hav_sample_points and its workspace only (the workspace size
+                          depends on it) */
   uint32_t select_seed;/* generator seed of HAV_SELECT_RANDOM */
 } hav_params_t;
 
@@ -250,6 +255,26 @@ hav_status_t hav_timing_enable(int32_t on);
  * of launches and their summed duration in milliseconds. HAV_ERR_HIP if an event could
  * not be read (its duration then counts as 0). */
 hav_status_t hav_timing_collect(const char* kernel, int32_t* launches, double* total_ms);
+
+/* Voxel representatives as points: the "CE" (centre) and "ME" (mean) selections of the
+ * ablation (Sec. 4.5, Table 6), whose representative of a voxel is not a cloud point.
+ * The call samples exactly like hav_sample with centre-closest selection (same search,
+ * trim, pad, layers and idx: the kept voxels' centre-closest points, ascending), and
+ * xyz_out[j] is the point that stands for idx[j]:
+ *   params->select == HAV_SELECT_CENTRE: the voxel centre mn + v * (g + 0.5), in float32
+ *     as ((g + 0.5) * v) + mn, mn the cloud's min corner (the grid origin);
+ *   params->select == HAV_SELECT_MEAN: the mean of the voxel's points (those not taken by
+ *     an earlier layer), summed exactly in fixed point: along axis a,
+ *     q = floor(r * 2^32 / H_a) with r = x - mn_a and H_a the smallest power of two >=
+ *     the extent, and mean = (float)(mn_a + (sum q / n) * H_a * 2^-32) in double;
+ *   CENTRE_CLOSEST / RANDOM: the point itself;
+ *   a padded point (a layer with fewer voxels than m_l) stands for itself.
+ *   xyz_out [M][3] float32 device. ws: hav_workspace_size(N, M, params) bytes initialised
+ *   with hav_workspace_init(N, params, ...) (the points modes need more workspace). Errors
+ *   as hav_sample. */
+hav_status_t hav_sample_points(const float* xyz, int64_t N, int64_t M, const hav_params_t* params,
+                               int32_t* idx, float* xyz_out, void* ws, size_t ws_bytes,
+                               hav_info_t* info_dev, void* stream);
 
 /* ---------------------------------------------------------------------------------
  * The samplers of the latency comparison (Sec. 4.2, Fig. 7). Same conventions as

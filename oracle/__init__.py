@@ -97,6 +97,9 @@ def lib():
         L.oracle_sample_tags.argtypes = [f32p, C.c_int64, C.c_int64, C.POINTER(Params), i32p,
                                          C.POINTER(Info), C.POINTER(C.c_uint8)]
         L.oracle_sample_tags.restype = C.c_int32
+        L.oracle_sample_points.argtypes = [f32p, C.c_int64, C.c_int64, C.POINTER(Params), i32p, f32p,
+                                           C.POINTER(Info)]
+        L.oracle_sample_points.restype = C.c_int32
         L.oracle_chain.argtypes = [f32p, C.c_int64, i64p, C.c_int32, C.POINTER(Params), i32p, C.POINTER(Info)]
         L.oracle_chain.restype = C.c_int32
         L.oracle_count.argtypes = [f32p, C.c_int64, f32p, f32p, C.POINTER(C.c_uint8)]
@@ -167,6 +170,19 @@ def sample_tags(xyz, M: int, p: Params | None = None):
     st = lib().oracle_sample_tags(_ptr(a, C.c_float), a.shape[0], int(M), C.byref(p),
                                   _ptr(idx, C.c_int32), C.byref(info), _ptr(tag, C.c_uint8))
     return st, idx[: int(M)] if M > 0 else idx[:0], info.as_dict(), tag
+
+
+def sample_points(xyz, M: int, p: Params | None = None):
+    """Returns (status, idx[M], pts[M, 3] float32, info): pts[j] stands for idx[j] (the
+    voxel centre / mean with select 2 / 3, else the point itself)."""
+    a = _xyz(xyz)
+    p = p if p is not None else params()
+    idx = np.zeros(max(int(M), 1), dtype=np.int32)
+    pts = np.zeros((max(int(M), 1), 3), dtype=np.float32)
+    info = Info()
+    st = lib().oracle_sample_points(_ptr(a, C.c_float), a.shape[0], int(M), C.byref(p),
+                                    _ptr(idx, C.c_int32), _ptr(pts, C.c_float), C.byref(info))
+    return st, idx[: int(M)], pts[: int(M)], info.as_dict()
 
 
 def chain(xyz, Ms, p: Params | None = None):

@@ -35,6 +35,7 @@
 // sort-and-unique second route, the covering bound and published SplitMix64 values).
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -70,7 +71,8 @@ typedef struct {
   double sigma;
   float aspect[3];
   float fixed_voxel[3];
-  int32_t select;   // 0: centre-closest (Sec. 3.2); 1: random member (Table 6, RA)
+  int32_t select;   // 0: centre-closest (Sec. 3.2); 1: random member (Table 6, RA);
+                    // 2: voxel centre, 3: voxel mean (CE, ME; points, not indices)
   uint32_t seed;    // random member: generator seed
 } OracleParams;
 
@@ -190,7 +192,7 @@ bool params_valid(const OracleParams* p) {
     }
   }
   if (p->flags & ~OR_FIXED_VOXEL) return false;
-  if (p->select != 0 && p->select != 1) return false;
+  if (p->select < 0 || p->select > 3) return false;
   return true;
 }
 
@@ -210,9 +212,12 @@ void layer_budgets(int64_t M, int k, int r, int64_t* m) {
   m[k - 1] = M - used;
 }
 
-// One stage: sample exactly M of the N points. idx gets M ascending indices.
+// One stage: sample exactly M of the N points. idx gets M ascending indices. pt_out
+// (optional, [N][3]) gets, for every voxel representative, the point that stands for
+// its voxel: the representative itself, or with select 2 / 3 the voxel's centre /
+// the mean of its points; a padded point stands for itself.
 int32_t sample_stage(const float* xyz, int64_t N, int64_t M, const OracleParams* p,
-                     int32_t* idx, OracleInfo* info, uint8_t* tag_out) {
+                     int32_t* idx, OracleInfo* info, uint8_t* tag_out, float* pt_out = nullptr) {
   OracleInfo local{};
   OracleInfo& inf = info ? *info : local;
   std::memset(&inf, 0, sizeof(inf));
@@ -238,6 +243,7 @@ int32_t sample_stage(const float* xyz, int64_t N, int64_t M, const OracleParams*
   std::memcpy(inf.mx, mx, sizeof(mx));
   if (M == N) {  // every point is kept
     for (int64_t i = 0; i < N; ++i) idx[i] = static_cast<int32_t>(i);
+    if (pt_out) std::memcpy(pt_out, xyz, static_cast<size_t>(N) * 3 * sizeof(float));
     if (tag_out) std::memset(tag_out, 1, static_cast<size_t>(N));
     return OR_OK;
   }
@@ -266,6 +272,19 @@ int32_t sample_stage(const float* xyz, int64_t N, int64_t M, const OracleParams*
         return inf.status;
       }
     }
+  }
+
+  // Voxel mean (select 3) in fixed point, so that the sum does not depend on the
+  // order of the points: along axis a, q = floor(r_a * 2^32 / H_a) with H_a the
+  // smallest power of two >= the extent (r_a <= H_a, so q <= 2^32 and a sum over up
+  // to 2^30 points fits 64 bits); mean = mn + (sum_q / n) * H_a * 2^-32 in double,
+  // rounded to float once.
+  float qscale[3];
+  double qback[3];
+  for (int a = 0; a < 3; ++a) {
+    const float H = pow2_ceil(std::max(mx[a] - mn[a], std::ldexp(1.0f, -64)));
+    qscale[a] = 4294967296.0f / H;
+    qback[a] = static_cast<double>(H) / 4294967296.0;
   }
 
   int64_t budget[kMaxLayers];
@@ -359,6 +378,38 @@ int32_t sample_stage(const float* xyz, int64_t N, int64_t M, const OracleParams*
       }
     }
     const int64_t c = static_cast<int64_t>(best.size());
+    if (pt_out) {
+      // what stands for each voxel (only the kept voxels' entries are read)
+      std::unordered_map<uint64_t, std::array<uint64_t, 4>> sums;
+      if (p->select == 3) {
+        for (int64_t i : R) {
+          int32_t g[3];
+          float r[3];
+          const uint64_t key = voxel_key(xyz + 3 * i, mn, inv, g, r);
+          auto& acc = sums[key];
+          for (int a = 0; a < 3; ++a) acc[a] += static_cast<uint64_t>(r[a] * qscale[a]);
+          acc[3] += 1;
+        }
+      }
+      for (const auto& kv : best) {
+        const int64_t i = kv.second.second;
+        float* o = pt_out + 3 * i;
+        if (p->select == 2) {
+          for (int a = 0; a < 3; ++a) {
+            const float ga = static_cast<float>((kv.first >> (21 * a)) & 0x1FFFFF);
+            o[a] = mn[a] + v[a] * (ga + 0.5f);
+          }
+        } else if (p->select == 3) {
+          const auto& acc = sums[kv.first];
+          for (int a = 0; a < 3; ++a) {
+            const double mean = static_cast<double>(acc[a]) / static_cast<double>(acc[3]);
+            o[a] = static_cast<float>(static_cast<double>(mn[a]) + mean * qback[a]);
+          }
+        } else {
+          for (int a = 0; a < 3; ++a) o[a] = xyz[3 * i + a];
+        }
+      }
+    }
     if (c != c_final) {  // the search and the selection must see the same voxels
       inf.status = OR_INVALID_ARG;
       return inf.status;
@@ -385,6 +436,8 @@ int32_t sample_stage(const float* xyz, int64_t N, int64_t M, const OracleParams*
         if (need == 0) break;
         if (!taken[i]) {
           taken[i] = static_cast<uint8_t>(L + 1);
+          if (pt_out)
+            for (int a = 0; a < 3; ++a) pt_out[3 * i + a] = xyz[3 * i + a];
           --need;
         }
       }
@@ -433,6 +486,19 @@ int32_t oracle_sample(const float* xyz, int64_t N, int64_t M, const OracleParams
 int32_t oracle_sample_tags(const float* xyz, int64_t N, int64_t M, const OracleParams* p,
                            int32_t* idx, OracleInfo* info, uint8_t* tag) {
   return sample_stage(xyz, N, M, p, idx, info, tag);
+}
+
+// The stage's picks as points: xyz_out[j] stands for idx[j] (the voxel centre or mean
+// with select 2 / 3, else the point itself).
+int32_t oracle_sample_points(const float* xyz, int64_t N, int64_t M, const OracleParams* p,
+                             int32_t* idx, float* xyz_out, OracleInfo* info) {
+  if (!xyz_out || N < 1) return OR_INVALID_ARG;
+  std::vector<float> pt(static_cast<size_t>(N) * 3, 0.0f);
+  const int32_t st = sample_stage(xyz, N, M, p, idx, info, nullptr, pt.data());
+  if (st != OR_OK) return st;
+  for (int64_t j = 0; j < M; ++j)
+    for (int a = 0; a < 3; ++a) xyz_out[3 * j + a] = pt[3 * static_cast<int64_t>(idx[j]) + a];
+  return OR_OK;
 }
 
 // Chained stages: stage j samples Ms[j] points of the cloud stage j-1 produced

@@ -223,6 +223,11 @@ struct Ws {
   uint64_t* tie_p;               // [kGroups][tie_seg]
   int32_t* tie_o;
   uint32_t* tcnt;                // scan tile counts [nscan_ws]
+  float* pt_out;                 // points modes: what stands for each kept point [n_ws][3]
+  unsigned long long* msum;      // mean mode: per voxel slot fixed-point sums [slots][3]
+  uint32_t* mcnt;                // mean mode: per voxel slot point counts [slots]
+  float* xyz_out;                // points modes: output [M][3] (null: indices only)
+  int32_t pmode;                 // 0 indices, 1 voxel centres, 2 voxel means
   int64_t n;
   int64_t npad;                  // slots of the sorted arrays: ntile * kTile
   int32_t ntile, nscan, nbb, nbbox;
@@ -770,8 +775,11 @@ __global__ void __launch_bounds__(kThreads) k_identity(Src src) {
   }
   if (st != HAV_OK) return;
   for (int64_t i = bx * static_cast<int64_t>(kThreads) + threadIdx.x; i < w.n;
-       i += static_cast<int64_t>(gx) * kThreads)
+       i += static_cast<int64_t>(gx) * kThreads) {
     idx[i] = static_cast<int32_t>(i);
+    if (w.xyz_out)
+      for (int a = 0; a < 3; ++a) w.xyz_out[3 * i + a] = w.xyz[3 * i + a];
+  }
 }
 
 // ----------------------------------------------------------------------------- binning
@@ -1789,6 +1797,84 @@ __global__ void __launch_bounds__(kThreads) k_trim_hist(Src src, int L, int roun
   }
 }
 
+// ----------------------------------------------------------------------------- points modes
+
+// Fixed-point scale of the voxel mean along each axis: q = floor(r * 2^32 / H) with H
+// the smallest power of two >= the cloud's extent (r <= H, so q <= 2^32 and a sum over
+// 2^30 points fits 64 bits); sums are exact, so the mean does not depend on the order
+// the points arrive in.
+__device__ __forceinline__ float mean_extent(float ext) {
+  const float e = ext < 0x1p-64f ? 0x1p-64f : ext;
+  const uint32_t bits = __float_as_uint(e);
+  return (bits & 0x7FFFFFu) ? __uint_as_float((bits & 0x7F800000u) + 0x00800000u) : e;
+}
+
+// The slot of voxel (gx, gy, gz) in the selection table at the chosen size (it exists:
+// the selection inserted every voxel of R); -1 if the probe runs out.
+__device__ __forceinline__ int64_t sel_slot(const Ws& w, const Ctrl* c, uint32_t gx, uint32_t gy,
+                                            uint32_t gz) {
+  if (c->sel_dense)
+    return static_cast<int64_t>(gx) + static_cast<int64_t>(c->sel_nv[0]) *
+                                          (gy + static_cast<int64_t>(c->sel_nv[1]) * gz);
+  const uint64_t key = pack_key(gx, gy, gz);
+  uint32_t sl = table_hash(key) & w.cmask;
+  for (uint32_t pr = 0; pr <= w.cmask; ++pr) {
+    if (w.skeys[sl] == key) return sl;
+    sl = (sl + 1) & w.cmask;
+  }
+  return -1;
+}
+
+// Voxel means ("ME" of Table 6): every unsampled point adds its fixed-point
+// coordinates and a count to its voxel's slot.
+__global__ void __launch_bounds__(kThreads) k_mean(One src, int L) {
+  int bx, gx;
+  const Cloud& cd = cloud_of(src, kKTile, bx, gx);
+  if (!layer_due(cd, L)) return;
+  const Ws& w = cd.w;
+  const Ctrl* c = &w.h->ctrl;
+  const Frame& fr = w.h->frame;
+  float qs[3];
+  for (int a = 0; a < 3; ++a) qs[a] = 4294967296.0f / mean_extent(fr.mx[a] - fr.mn[a]);
+  const float ix = c->inv_final[0], iy = c->inv_final[1], iz = c->inv_final[2];
+  const int64_t base = static_cast<int64_t>(bx) * kTile + threadIdx.x;
+  for (int k = 0; k < kPerThread; ++k) {
+    const int64_t S = base + k * kThreads;
+    if (w.tag_s[S] != 0) continue;
+    const float4 p = w.pts[S];
+    const int64_t sl = sel_slot(w, c, axis_coord(p.x, ix), axis_coord(p.y, iy), axis_coord(p.z, iz));
+    if (sl < 0) continue;
+    atomicAdd(&w.msum[3 * sl], static_cast<unsigned long long>(p.x * qs[0]));
+    atomicAdd(&w.msum[3 * sl + 1], static_cast<unsigned long long>(p.y * qs[1]));
+    atomicAdd(&w.msum[3 * sl + 2], static_cast<unsigned long long>(p.z * qs[2]));
+    atomicAdd(&w.mcnt[sl], 1u);
+  }
+}
+
+// What stands for voxel `key` (selection slot s) whose representative is point orig:
+// its centre mn + v (g + 0.5) ("CE" of Table 6) or the mean of its points ("ME"), in
+// the cloud's coordinates; the mean's sums are emptied as read.
+__device__ void stand_in(const Ws& w, const Ctrl* c, const Frame& fr, int32_t s, uint64_t key,
+                         int32_t orig) {
+  float o[3];
+  if (w.pmode == 1) {
+    for (int a = 0; a < 3; ++a) {
+      const float ga = static_cast<float>((key >> (kKeyBits * a)) & ((1ull << kKeyBits) - 1ull));
+      o[a] = fr.mn[a] + c->v_final[a] * (ga + 0.5f);
+    }
+  } else {
+    const double n = static_cast<double>(w.mcnt[s]);
+    for (int a = 0; a < 3; ++a) {
+      const double back = static_cast<double>(mean_extent(fr.mx[a] - fr.mn[a])) / 4294967296.0;
+      const double mean = static_cast<double>(w.msum[3 * static_cast<int64_t>(s) + a]) / n;
+      o[a] = static_cast<float>(static_cast<double>(fr.mn[a]) + mean * back);
+      w.msum[3 * static_cast<int64_t>(s) + a] = 0ull;
+    }
+    w.mcnt[s] = 0u;
+  }
+  for (int a = 0; a < 3; ++a) w.pt_out[3 * static_cast<int64_t>(orig) + a] = o[a];
+}
+
 // The last block of k_mark: the rank-th smallest priority inside the bucket, then
 // mark every queued voxel up to it. The bucket's members, less the bucket's base, fit
 // in its bit width; radix rounds of 8 bits narrow them (from LDS when the bucket fits
@@ -1941,6 +2027,7 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
       orig = static_cast<int32_t>(w.svals[s] & 0xFFFFFFFFull);
       if (!dense) w.skeys[s] = kEmptyKey;
       w.svals[s] = ~0ull;
+      if (w.pmode && orig >= 0 && orig < w.n) stand_in(w, c, h->frame, s, key, orig);
       bool keep = true;
       if (trim) {
         p = voxel_priority(key);
@@ -2073,6 +2160,8 @@ __global__ void __launch_bounds__(kThreads) k_pad(Src src, int Lc) {
           if (r < need) {
             w.tag_o[base + k] = lt;
             w.tag_s[w.invp[base + k]] = lt;
+            if (w.pmode)
+              for (int a = 0; a < 3; ++a) w.pt_out[3 * (base + k) + a] = w.xyz[3 * (base + k) + a];
           }
           ++r;
         }
@@ -2116,7 +2205,11 @@ __global__ void __launch_bounds__(kThreads) k_out(Src src) {
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       if (t[k]) {
-        if (r < M) idx[r] = static_cast<int32_t>(base + k);
+        if (r < M) {
+          idx[r] = static_cast<int32_t>(base + k);
+          if (w.xyz_out)
+            for (int a = 0; a < 3; ++a) w.xyz_out[3 * r + a] = w.pt_out[3 * (base + k) + a];
+        }
         ++r;
       }
     }
@@ -2134,7 +2227,8 @@ __global__ void __launch_bounds__(kThreads) k_out(Src src) {
 // ----------------------------------------------------------------------------- workspace init
 
 __global__ void __launch_bounds__(kThreads) k_ws_init(Ws w, size_t nct, size_t ncn, size_t nst,
-                                                      size_t nsv, size_t nsn, size_t nhr, size_t nsc) {
+                                                      size_t nsv, size_t nsn, size_t nhr, size_t nsc,
+                                                      size_t nms) {
   const size_t stride = static_cast<size_t>(gridDim.x) * kThreads;
   const size_t t0 = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
   for (size_t i = t0; i < nct; i += stride) {
@@ -2144,6 +2238,12 @@ __global__ void __launch_bounds__(kThreads) k_ws_init(Ws w, size_t nct, size_t n
   for (size_t i = t0; i < ncn; i += stride) w.ccn[i] = 0;
   for (size_t i = t0; i < nhr; i += stride) w.hrep[i] = 0ull;
   for (size_t i = t0; i < nsc; i += stride) w.tcnt[i] = 0u;
+  for (size_t i = t0; i < nms; i += stride) {
+    w.msum[3 * i] = 0ull;
+    w.msum[3 * i + 1] = 0ull;
+    w.msum[3 * i + 2] = 0ull;
+    w.mcnt[i] = 0u;
+  }
   for (size_t i = t0; i < nst; i += stride) w.skeys[i] = kEmptyKey;
   for (size_t i = t0; i < nsv; i += stride) w.svals[i] = ~0ull;
   for (size_t i = t0; i < nsn; i += stride) w.scn[i] = 0;
@@ -2198,16 +2298,18 @@ __host__ __device__ inline uint32_t table_cap(int64_t n) {
 
 struct Layout {
   size_t hdr, pts, invp, tag_s, tag_o, part, bh, binpre, bsum, ckeys, cmasks, ccl, hrep, ccn, skeys, svals, scl,
-      scn, tie_p, tie_o, tcnt, total;
+      scn, tie_p, tie_o, tcnt, pto, msum, mcnt, total;
   int64_t n_ws;
+  int32_t pmode;
   uint32_t cap_ws;
   int32_t ntile_ws, nscan_ws, ncmax;
   int64_t tie_seg;
 };
 
-__host__ __device__ inline Layout make_layout(int64_t n, int depth) {
+__host__ __device__ inline Layout make_layout(int64_t n, int depth, int pmode = 0) {
   Layout L;
   L.n_ws = n;
+  L.pmode = pmode;
   L.cap_ws = table_cap(n);
   L.ntile_ws = static_cast<int32_t>((n + kTile - 1) / kTile);
   L.nscan_ws = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
@@ -2238,12 +2340,17 @@ __host__ __device__ inline Layout make_layout(int64_t n, int depth) {
   L.tie_p = o;  o = align_up(o + static_cast<size_t>(kGroups) * L.tie_seg * 8);
   L.tie_o = o;  o = align_up(o + static_cast<size_t>(kGroups) * L.tie_seg * 4);
   L.tcnt = o;   o = align_up(o + static_cast<size_t>(L.nscan_ws) * 4);
+  const size_t slots = pmode == 2 ? static_cast<size_t>(L.cap_ws) * kSelDense : 0;
+  L.pto = o;    o = align_up(o + (pmode ? N * 12 : 0));
+  L.msum = o;   o = align_up(o + slots * 24);
+  L.mcnt = o;   o = align_up(o + slots * 4);
   L.total = o;
   return L;
 }
 
 __host__ __device__ inline uint64_t magic_of(const Layout& L) {
-  return kMagic ^ (static_cast<uint64_t>(L.n_ws) << 8) ^ (static_cast<uint64_t>(L.ncmax) << 56);
+  return kMagic ^ (static_cast<uint64_t>(L.n_ws) << 8) ^ (static_cast<uint64_t>(L.ncmax) << 56) ^
+         (static_cast<uint64_t>(L.pmode) << 48);
 }
 
 // Device view of the workspace for a stage of n points (n <= the workspace's size).
@@ -2270,6 +2377,11 @@ __host__ __device__ inline Ws make_ws(char* base, const Layout& L, int64_t n) {
   w.tie_p = reinterpret_cast<uint64_t*>(base + L.tie_p);
   w.tie_o = reinterpret_cast<int32_t*>(base + L.tie_o);
   w.tcnt = reinterpret_cast<uint32_t*>(base + L.tcnt);
+  w.pmode = L.pmode;
+  w.pt_out = L.pmode ? reinterpret_cast<float*>(base + L.pto) : nullptr;
+  w.msum = L.pmode == 2 ? reinterpret_cast<unsigned long long*>(base + L.msum) : nullptr;
+  w.mcnt = L.pmode == 2 ? reinterpret_cast<uint32_t*>(base + L.mcnt) : nullptr;
+  w.xyz_out = nullptr;
   w.n = n;
   w.ntile = static_cast<int32_t>((n + kTile - 1) / kTile);
   w.npad = static_cast<int64_t>(w.ntile) * kTile;
@@ -2289,7 +2401,16 @@ __host__ __device__ inline Ws make_ws(char* base, const Layout& L, int64_t n) {
   return w;
 }
 
+// Parameters of any entry point; the selections whose representatives are not cloud
+// points (centre, mean) only through hav_sample_points.
+bool params_any_ok(const hav_params_t* p);
 bool params_ok(const hav_params_t* p) {
+  return params_any_ok(p) && (p->select == HAV_SELECT_CENTRE_CLOSEST || p->select == HAV_SELECT_RANDOM);
+}
+int points_mode(const hav_params_t* p) {
+  return p->select == HAV_SELECT_CENTRE ? 1 : (p->select == HAV_SELECT_MEAN ? 2 : 0);
+}
+bool params_any_ok(const hav_params_t* p) {
   if (!p || p->abi_version != HAV_ABI_VERSION) return false;
   if (p->layers < 1 || p->layers > HAV_MAX_LAYERS) return false;
   if (p->layer_ratio < 2 || p->layer_ratio > 16) return false;
@@ -2300,7 +2421,7 @@ bool params_ok(const hav_params_t* p) {
   if (p->spec_budget < 0 || p->spec_budget > 1024) return false;
   if (p->search_blocks < 0 || p->search_blocks > 65536) return false;
   if (!std::isfinite(p->trim_window) || p->trim_window > 64.0f) return false;
-  if (p->select != HAV_SELECT_CENTRE_CLOSEST && p->select != HAV_SELECT_RANDOM) return false;
+  if (p->select < HAV_SELECT_CENTRE_CLOSEST || p->select > HAV_SELECT_MEAN) return false;
   for (int a = 0; a < 3; ++a) {
     const float as = p->aspect[a];
     if (!std::isfinite(as) || as < 0x1p-16f || as > 0x1p16f) return false;
@@ -2373,13 +2494,16 @@ struct CloudSpec {
   hav_info_t* info;
   char* seg;
   int64_t n, m, n_cap;
+  float* xyz_out;  // points modes only (else null)
 };
 
 __host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite& q) {
   Cloud cd;
-  const Layout L = make_layout(c.n_cap, q.depth);
+  const int pmode = q.select == HAV_SELECT_CENTRE ? 1 : (q.select == HAV_SELECT_MEAN ? 2 : 0);
+  const Layout L = make_layout(c.n_cap, q.depth, pmode);
   cd.w = make_ws(c.seg, L, c.n);
   cd.w.xyz = c.xyz;
+  cd.w.xyz_out = c.xyz_out;
   cd.w.idx = c.idx;
   cd.w.info_dev = c.info;
   cd.w.M = c.m;
@@ -2686,8 +2810,9 @@ void timing_keep(const char* name, hipEvent_t e0, hipEvent_t e1) {
   } while (0)
 
 hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_t* p, int32_t* idx,
-                       char* ws, const Layout& L, hav_info_t* info_dev, hipStream_t st) {
-  const CloudSpec spec{xyz, idx, info_dev, ws, N, M, L.n_ws};
+                       char* ws, const Layout& L, hav_info_t* info_dev, hipStream_t st,
+                       float* xyz_out = nullptr) {
+  const CloudSpec spec{xyz, idx, info_dev, ws, N, M, L.n_ws, xyz_out};
   const One one{make_cloud(spec, lite_of(p))};
   const Ws& w = one.c.w;
   const Plan& P = one.c.P;
@@ -2705,6 +2830,7 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
   for (int l = 0; l < P.nlayers; ++l) {
     if (!P.fixed) HAV_LAUNCH(k_search, dim3(sgrid), dim3(kThreads), eval_lds, st, one, l);
     HAV_LAUNCH(k_select<One>, dim3(w.ntile), dim3(kThreads), sel_lds, st, one, l);
+    if (w.pmode == 2) HAV_LAUNCH(k_mean, dim3(w.ntile), dim3(kThreads), 0, st, one, l);
     for (int r = 0; r < P.rounds[l]; ++r)
       HAV_LAUNCH(k_trim_hist<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l, r);
     HAV_LAUNCH(k_mark<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l);
@@ -2747,7 +2873,8 @@ hav_status_t init_ws(char* base, const Layout& L, hipStream_t st) {
   HAV_LAUNCH(k_ws_init, dim3(2048), dim3(kThreads), 0, st, w, nct, ncn,
              static_cast<size_t>(L.cap_ws), static_cast<size_t>(L.cap_ws) * kSelDense,
              static_cast<size_t>(L.ntile_ws),
-             2 * static_cast<size_t>(L.ncmax) * kReps * kHotCap, static_cast<size_t>(L.nscan_ws));
+             2 * static_cast<size_t>(L.ncmax) * kReps * kHotCap, static_cast<size_t>(L.nscan_ws),
+             L.pmode == 2 ? static_cast<size_t>(L.cap_ws) * kSelDense : size_t(0));
   HAV_LAUNCH(k_ws_seal, dim3(1), dim3(64), 0, st, w.h, magic_of(L));
   return HAV_OK;
 }
@@ -2923,15 +3050,15 @@ const char* hav_status_string(hav_status_t s) {
 }
 
 size_t hav_workspace_size(int64_t N, int64_t M, const hav_params_t* params) {
-  if (N < 1 || M < 1 || M > N || N > kMaxPoints || !params_ok(params)) return 0;
-  return make_layout(N, depth_of(params)).total;
+  if (N < 1 || M < 1 || M > N || N > kMaxPoints || !params_any_ok(params)) return 0;
+  return make_layout(N, depth_of(params), points_mode(params)).total;
 }
 
 hav_status_t hav_workspace_init(int64_t N, const hav_params_t* params, void* ws, size_t ws_bytes,
                                 void* stream) {
-  if (!ws || N < 1 || N > kMaxPoints || !params_ok(params)) return HAV_ERR_INVALID_ARG;
+  if (!ws || N < 1 || N > kMaxPoints || !params_any_ok(params)) return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
-  const Layout L = make_layout(N, depth_of(params));
+  const Layout L = make_layout(N, depth_of(params), points_mode(params));
   if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   return init_ws(static_cast<char*>(ws), L, static_cast<hipStream_t>(stream));
 }
@@ -2947,6 +3074,19 @@ hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params
   if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   return run_stage(xyz, N, M, params, idx, static_cast<char*>(ws), L, info_dev,
                    static_cast<hipStream_t>(stream));
+}
+
+hav_status_t hav_sample_points(const float* xyz, int64_t N, int64_t M, const hav_params_t* params,
+                               int32_t* idx, float* xyz_out, void* ws, size_t ws_bytes,
+                               hav_info_t* info_dev, void* stream) {
+  if (!xyz || !idx || !xyz_out || !ws || N < 1 || M < 1 || M > N || N > kMaxPoints ||
+      !params_any_ok(params))
+    return HAV_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
+  const Layout L = make_layout(N, depth_of(params), points_mode(params));
+  if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
+  return run_stage(xyz, N, M, params, idx, static_cast<char*>(ws), L, info_dev,
+                   static_cast<hipStream_t>(stream), xyz_out);
 }
 
 }  // extern "C"

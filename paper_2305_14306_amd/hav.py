@@ -17,6 +17,8 @@ MAX_LAYERS = 8
 FIXED_VOXEL = 1
 SELECT_CENTRE_CLOSEST = 0
 SELECT_RANDOM = 1
+SELECT_CENTRE = 2
+SELECT_MEAN = 3
 
 OK, ERR_INVALID_ARG, ERR_WORKSPACE_TOO_SMALL, ERR_OUT_OF_MEMORY, ERR_UNSUPPORTED, \
     ERR_NONFINITE, ERR_HIP, ERR_WORKSPACE_NOT_INIT, NOT_READY = range(9)
@@ -112,6 +114,9 @@ def lib():
         L.hav_sample.restype = C.c_int
         L.hav_sample.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(Params), i32p, vp, C.c_size_t,
                                  vp, vp]
+        L.hav_sample_points.restype = C.c_int
+        L.hav_sample_points.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(Params), i32p, vp, vp,
+                                        C.c_size_t, vp, vp]
         L.hav_chain_workspace_size.restype = C.c_size_t
         L.hav_chain_workspace_size.argtypes = [C.c_int64, i64p, C.c_int32, C.POINTER(Params)]
         L.hav_sample_chain.restype = C.c_int
@@ -262,7 +267,8 @@ class Sampler:
         if self.ws is None or self.ws.numel() < nbytes:
             self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
             self.ws_key = None
-        key = (N if isinstance(N, tuple) else int(N), int(p.spec_depth))
+        pmode = int(p.select) if int(p.select) >= SELECT_CENTRE else 0  # layout differs
+        key = (N if isinstance(N, tuple) else int(N), int(p.spec_depth), pmode)
         if self.ws_key != key:
             if isinstance(N, tuple):
                 st = lib().hav_batch_workspace_init(len(N), _i64(N), C.byref(p),
@@ -307,6 +313,30 @@ class Sampler:
         if with_info:
             return idx, read_info(info[:C.sizeof(Info)])[0]
         return idx
+
+    def sample_points(self, xyz, M: int, p: Params, with_info: bool = False, stream=None):
+        """hav_sample_points: (idx [M] int32, pts [M, 3] float32), pts[j] standing for
+        idx[j] (voxel centre / mean with select SELECT_CENTRE / SELECT_MEAN)."""
+        torch = _torch()
+        _check_xyz(xyz)
+        N = xyz.shape[0]
+        nbytes = workspace_size(N, M, p)
+        if nbytes == 0:
+            raise HavError(ERR_INVALID_ARG, "hav_workspace_size")
+        ws = self._workspace(nbytes, N, p, stream)
+        idx = torch.empty(int(M), dtype=torch.int32, device=xyz.device)
+        pts = torch.empty((int(M), 3), dtype=torch.float32, device=xyz.device)
+        info = self._info(1) if with_info else None
+        st = lib().hav_sample_points(C.c_void_p(xyz.data_ptr()), N, int(M), C.byref(p),
+                                     C.c_void_p(idx.data_ptr()), C.c_void_p(pts.data_ptr()),
+                                     C.c_void_p(ws.data_ptr()), ws.numel(),
+                                     C.c_void_p(info.data_ptr()) if info is not None else None,
+                                     _stream_ptr(stream))
+        if st != OK:
+            raise HavError(st, "hav_sample_points")
+        if with_info:
+            return idx, pts, read_info(info[:C.sizeof(Info)])[0]
+        return idx, pts
 
     def chain(self, xyz, Ms, p: Params | None = None, out=None, with_info: bool = False,
               stream=None):

@@ -266,3 +266,37 @@ def test_random_member_selection(gpu, orc, seed):
     _check(gpu, orc, x, 5000, gpu.params(select=gpu.SELECT_RANDOM, select_seed=seed, fixed_voxel=0.7),
            "random member fixed voxel (RVS-like)")
     _check(gpu, orc, synth.lattice(8), 60, p, "random member lattice")
+
+
+def _check_points(gpu, orc, x, M, p, label):
+    _note(f"case points {label} N={x.shape[0]} M={M} select={p.select}")
+    st, want_idx, want_pts, winfo = orc.sample_points(x, M, _oracle_params(orc, p))
+    assert st == 0
+    idx, pts, info = gpu.Sampler().sample_points(_to_dev(x), M, p, with_info=True)
+    assert info == winfo, (info, winfo)
+    assert np.array_equal(idx.cpu().numpy(), want_idx)
+    got = pts.cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), want_pts.view(np.uint32))  # bit for bit
+    return got
+
+
+@pytest.mark.parametrize("sel", [2, 3])
+def test_centre_and_mean_points(gpu, orc, sel):
+    x = synth.scene_planes_blobs(70000, seed=41)
+    _check_points(gpu, orc, x, 17500, gpu.params(select=sel), "scene")
+    _check_points(gpu, orc, x, 3000, gpu.params(select=sel, layers=3), "scene 3 layers")
+    _check_points(gpu, orc, x, 6000, gpu.params(select=sel, t_max=3), "fallback (trim or pad)")
+    _check_points(gpu, orc, x, 2000, gpu.params(select=sel, fixed_voxel=0.6), "fixed voxel")
+    lat = synth.lattice(8) + np.float32(10.25)
+    got = _check_points(gpu, orc, lat, 64, gpu.params(select=sel, layers=1, fixed_voxel=2.0), "lattice")
+    assert np.all(np.mod(got - (11.25 if sel == 2 else 10.75), 2.0) == 0.0)
+    q = synth.random_cloud(20000, 5, kind="quantised")
+    _check_points(gpu, orc, q, 9000, gpu.params(select=sel), "quantised (duplicates, pad)")
+    _check_points(gpu, orc, q, 20000, gpu.params(select=sel), "identity")
+
+
+def test_points_modes_rejected_elsewhere(gpu):
+    import torch
+    x = _to_dev(synth.random_cloud(1000, 1))
+    with pytest.raises(gpu.HavError):
+        gpu.Sampler().sample(x, 100, gpu.params(select=gpu.SELECT_MEAN))

@@ -489,3 +489,44 @@ def test_random_member_sort_route(orc):
     st, idx, info = orc.sample(x, M, orc.params(layers=1, fixed_voxel=0.5, select=1, seed=seed))
     assert st == 0 and info["trimmed"] == [0] and info["padded"] == [0]
     assert list(idx) == firsts
+
+
+def test_centre_and_mean_closed_forms(orc):
+    # the 8^3 lattice shifted by 10.25, fixed voxel 2 (origin = the min corner): voxel
+    # (a, b, c) holds the 8 points at 10.25 + {2a, 2a+1}; its centre is 11.25 + 2a and the
+    # mean of its points 10.75 + 2a along each axis; its centre-closest point, the
+    # representative index, is the one at 11.25 + 2a (d = 0)
+    x = synth.lattice(8) + np.float32(10.25)
+    for sel, off in ((2, 11.25), (3, 10.75)):
+        st, idx, pts, info = orc.sample_points(x, 64, orc.params(layers=1, fixed_voxel=2.0, select=sel))
+        assert st == 0 and info["count"] == [64] and info["padded"] == [0]
+        want_idx, want_pts = [], []
+        for cz in range(4):
+            for cy in range(4):
+                for cx in range(4):
+                    want_idx.append((2 * cx + 1) + 8 * (2 * cy + 1) + 64 * (2 * cz + 1))
+                    want_pts.append((off + 2 * cx, off + 2 * cy, off + 2 * cz))
+        order = np.argsort(want_idx)
+        assert list(idx) == sorted(want_idx)
+        assert np.array_equal(pts, np.array(want_pts, dtype=np.float32)[order])
+    # centre-closest / random selections stand for themselves
+    st, idx, pts, _ = orc.sample_points(x, 64, orc.params(layers=1, fixed_voxel=2.0))
+    assert np.array_equal(pts, x[idx])
+
+
+def test_mean_is_within_voxel_and_exact_for_dyadic_points(orc):
+    # points whose offsets from the origin are multiples of 2^-8 (exact in the fixed
+    # point): the mean equals the plain average; every mean lies inside its voxel
+    rng = np.random.default_rng(12)
+    x = (rng.integers(0, 2048, size=(3000, 3)) / 256.0).astype(np.float32)
+    x[0] = 0.0  # the origin
+    x[1] = 2047 / 256.0
+    st, idx, pts, info = orc.sample_points(x, 400, orc.params(layers=1, select=3))
+    assert st == 0 and info["trimmed"][0] >= 0
+    s = info["s"][0]
+    g, key, _ = orc.keys(x, x.min(0), np.array([s, s, s], dtype=np.float32))
+    for j, i in enumerate(idx[:60]):
+        members = np.nonzero(key == key[i])[0]
+        assert np.allclose(pts[j], x[members].astype(np.float64).mean(0), rtol=0, atol=1e-6)
+        lo = g[i] * np.float32(s)
+        assert np.all(pts[j] >= lo - 1e-6) and np.all(pts[j] <= lo + s + 1e-6)
