@@ -173,6 +173,59 @@ def fig7_leg(torch, hav, synth, reps: int) -> dict:
                         "(per-step sampler latency, ms)", "scales": scales}
 
 
+def variants_leg(torch, hav, synth) -> dict:
+    """Selection strategies of the ablation (Sec. 4.5, Table 6) on the 16,384-point
+    KITTI-like cloud -> 4,096: centre-closest (CC), random member (RA), voxel centre (CE)
+    and voxel mean (ME) with the adaptive voxel size, RVS (ME at a fixed size, one layer),
+    and FPS / RPS for reference. Coverage context (computed with scipy's k-d tree on the
+    host): the covering radius (largest distance from a cloud point to its nearest
+    sample) and the mean nearest-neighbour spacing of the samples; plus GPU time per call."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    x = synth.uniform_box_with_ground(16384, seed=1)
+    M = 4096
+    xd = torch.from_numpy(x).cuda()
+    tree = cKDTree(x.astype(np.float64))
+
+    def metrics(pts):
+        pts = np.asarray(pts, dtype=np.float64)
+        cover = float(cKDTree(pts).query(x.astype(np.float64))[0].max())
+        d, _ = cKDTree(pts).query(pts, k=2)
+        return {"covering_radius": round(cover, 4), "mean_spacing": round(float(d[:, 1].mean()), 4)}
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / reps
+
+    s = hav.Sampler()
+    out = {}
+    _, info0 = s.sample(xd, M, hav.params(layers=1), with_info=True)
+    s_fix = float(info0["s"][0])
+    cases = [("CC", hav.params()), ("RA", hav.params(select=hav.SELECT_RANDOM, select_seed=1)),
+             ("CE", hav.params(select=hav.SELECT_CENTRE)), ("ME", hav.params(select=hav.SELECT_MEAN)),
+             ("RVS (ME, fixed voxel, 1 layer)",
+              hav.params(select=hav.SELECT_MEAN, layers=1, fixed_voxel=s_fix))]
+    for name, p in cases:
+        (idx, pts), ms = timed(lambda p=p: s.sample_points(xd, M, p))
+        out[name] = dict(metrics(pts.cpu().numpy()), ms=round(ms, 4))
+    f = hav.FPS()
+    idx, ms = timed(lambda: f.sample(xd, M), reps=3)
+    out["FPS"] = dict(metrics(x[idx.cpu().numpy()]), ms=round(ms, 4))
+    r = hav.RPS()
+    idx, ms = timed(lambda: r.sample(x.shape[0], M, 1))
+    out["RPS"] = dict(metrics(x[idx.cpu().numpy()]), ms=round(ms, 4))
+    del tree
+    return {"workload": "KITTI-like 16,384 -> 4,096 (half box, half ground plane); fixed voxel for "
+                        "RVS = the 1-layer adaptive size %.4f" % s_fix, "strategies": out}
+
+
 def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
     """Poisson arrivals at 2,000 clouds/s (seed 7), N lognormal (median 1e5, sigma_ln 1,
     clamped to [1,024, 2,097,152]), LiDAR- or scene-shaped with probability 1/2, M = N/4
@@ -277,6 +330,8 @@ def main() -> int:
     ap.add_argument("--spec-depth", type=int, default=0,
                     help="tuning: voxel sizes per search pass (0 = library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the selection-strategy comparison (Table 6 of the paper)")
     ap.add_argument("--no-fig7", action="store_true",
                     help="skip the latency comparison with FPS and RPS (Fig. 7 of the paper)")
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -378,6 +433,9 @@ def main() -> int:
         print(f"bench: serve {result['serve']}", file=sys.stderr, flush=True)
     if not args.no_fig7:
         result["fig7"] = fig7_leg(torch, hav, synth, 3)
+    if not args.no_variants:
+        result["variants"] = variants_leg(torch, hav, synth)
+        print(f"bench: variants {result['variants']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(x, M, args.cpu_seconds)
     print(json.dumps(result), flush=True)

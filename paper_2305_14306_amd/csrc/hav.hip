@@ -2207,8 +2207,11 @@ __global__ void __launch_bounds__(kThreads) k_out(Src src) {
       if (t[k]) {
         if (r < M) {
           idx[r] = static_cast<int32_t>(base + k);
-          if (w.xyz_out)
-            for (int a = 0; a < 3; ++a) w.xyz_out[3 * r + a] = w.pt_out[3 * (base + k) + a];
+          if (w.xyz_out) {
+            // centre / mean modes: what stands for the point; else the point itself
+            const float* src = (w.pmode ? w.pt_out : w.xyz) + 3 * (base + k);
+            for (int a = 0; a < 3; ++a) w.xyz_out[3 * r + a] = src[a];
+          }
         }
         ++r;
       }

@@ -300,3 +300,12 @@ def test_points_modes_rejected_elsewhere(gpu):
     x = _to_dev(synth.random_cloud(1000, 1))
     with pytest.raises(gpu.HavError):
         gpu.Sampler().sample(x, 100, gpu.params(select=gpu.SELECT_MEAN))
+
+
+@pytest.mark.parametrize("sel", [0, 1])
+def test_points_of_point_selections(gpu, orc, sel):
+    # centre-closest and random members stand for themselves
+    x = synth.scene_planes_blobs(30000, seed=43)
+    got = _check_points(gpu, orc, x, 7000, gpu.params(select=sel, select_seed=5), "self")
+    st, idx, _ = orc.sample(x, 7000, orc.params(select=sel, seed=5))
+    assert np.array_equal(got, x[idx])
