@@ -319,6 +319,28 @@ hav_status_t hav_rps_workspace_init(void* ws, size_t ws_bytes, int64_t N, void* 
 hav_status_t hav_rps(int64_t N, int64_t M, uint64_t seed, float window, int32_t* idx, void* ws,
                      size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------------
+ * Coverage and spacing of a sample (Sec. 3.1, Fig. 3): nearest-sample distances.
+ * --------------------------------------------------------------------------------- */
+
+#define HAV_NN_MAX_SAMPLES 1073741823  /* 2^30 - 1, also the query limit */
+
+/* For every query q_j the squared distance to its nearest sample, in double as
+ * ((ex*ex + ey*ey) + ez*ez) with ex = (double)sample_x - (double)query_x (no fused
+ * multiply-add): exact, so results are reproducible bit for bit. With exclude_self the
+ * queries must be the samples themselves (Q == M >= 2) and query j skips sample j: the
+ * values are then each sample's spacing to its nearest other sample (the distribution
+ * Fig. 3 plots). *max_d2 gets the largest value (with the cloud as queries: the squared
+ * covering radius of the sample), or -1 if an internal bounded wait gave up.
+ *   samples [M][3], queries [Q][3] float32 device; d2_out [Q] double device or NULL;
+ *   max_d2 one double, device. 1 <= M, Q <= HAV_NN_MAX_SAMPLES; finite coordinates.
+ *   ws: hav_nn_workspace_size(M) bytes initialised once with hav_nn_workspace_init (for
+ *   that M or a larger one); every call leaves it initialised; one call at a time. */
+size_t hav_nn_workspace_size(int64_t M);
+hav_status_t hav_nn_workspace_init(void* ws, size_t ws_bytes, int64_t M, void* stream);
+hav_status_t hav_nn(const float* samples, int64_t M, const float* queries, int64_t Q, int32_t exclude_self,
+                    double* d2_out, double* max_d2, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,6 +116,8 @@ def lib():
         L.oracle_fps.restype = C.c_int32
         L.oracle_rps.argtypes = [C.c_int64, C.c_int64, C.c_uint64, i32p]
         L.oracle_rps.restype = C.c_int32
+        L.oracle_nn_d2.argtypes = [f32p, C.c_int64, f32p, C.c_int64, C.c_int32, C.POINTER(C.c_double)]
+        L.oracle_nn_d2.restype = C.c_int32
         L.oracle_covering_radius.argtypes = [f32p, C.c_int64, i32p, C.c_int64]
         L.oracle_covering_radius.restype = C.c_double
         _lib = L
@@ -257,6 +259,18 @@ def rps(N: int, m: int, seed: int) -> np.ndarray:
     st = lib().oracle_rps(int(N), int(m), C.c_uint64(int(seed) & ((1 << 64) - 1)), _ptr(out, C.c_int32))
     if st != 0:
         raise ValueError("rps: bad arguments")
+    return out
+
+
+def nn_d2(samples, queries, exclude_self: bool = False) -> np.ndarray:
+    """Squared distance (double) from every query to its nearest sample; with
+    exclude_self the queries are the samples and skip themselves (the spacing)."""
+    s, q = _xyz(samples), _xyz(queries)
+    out = np.zeros(q.shape[0], dtype=np.float64)
+    st = lib().oracle_nn_d2(_ptr(s, C.c_float), s.shape[0], _ptr(q, C.c_float), q.shape[0],
+                            1 if exclude_self else 0, _ptr(out, C.c_double))
+    if st != 0:
+        raise ValueError("nn_d2: bad arguments")
     return out
 
 

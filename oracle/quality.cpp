@@ -68,66 +68,42 @@ int32_t oracle_rps(int64_t N, int64_t m, uint64_t seed, int32_t* out) {
   return 0;
 }
 
-// Covering radius: max over all points of the distance to the nearest point of idx.
-// Exact nearest-neighbour search on a uniform grid of the sampled points, searched
-// in growing shells of cells until no closer cell can remain.
+// Squared distance from every query to its nearest sample, in double as
+// ((ex*ex + ey*ey) + ez*ez) with ex = sample - query: brute force over all pairs.
+// exclude_self: query j is sample j and does not count as its own neighbour.
+void nn_d2(const float* smp, int64_t M, const float* qry, int64_t Q, int exclude_self, double* out) {
+  for (int64_t i = 0; i < Q; ++i) {
+    const double px = qry[3 * i], py = qry[3 * i + 1], pz = qry[3 * i + 2];
+    double best = std::numeric_limits<double>::infinity();
+    for (int64_t q = 0; q < M; ++q) {
+      if (exclude_self && q == i) continue;
+      const double ex = static_cast<double>(smp[3 * q]) - px;
+      const double ey = static_cast<double>(smp[3 * q + 1]) - py;
+      const double ez = static_cast<double>(smp[3 * q + 2]) - pz;
+      best = std::min(best, ex * ex + ey * ey + ez * ez);
+    }
+    out[i] = best;
+  }
+}
+
+int32_t oracle_nn_d2(const float* samples, int64_t M, const float* queries, int64_t Q,
+                     int32_t exclude_self, double* out) {
+  if (!samples || !queries || !out || M < 1 || Q < 1 || (exclude_self && (Q != M || M < 2))) return 1;
+  nn_d2(samples, M, queries, Q, exclude_self, out);
+  return 0;
+}
+
+// Covering radius: max over all points of the distance to the nearest point of idx
+// (brute force: O(N m)).
 double oracle_covering_radius(const float* xyz, int64_t N, const int32_t* idx, int64_t m) {
   if (!xyz || !idx || N < 1 || m < 1) return -1.0;
-  double mn[3], mx[3];
-  for (int a = 0; a < 3; ++a) {
-    mn[a] = std::numeric_limits<double>::infinity();
-    mx[a] = -std::numeric_limits<double>::infinity();
-  }
-  for (int64_t i = 0; i < N; ++i)
-    for (int a = 0; a < 3; ++a) {
-      mn[a] = std::min(mn[a], static_cast<double>(xyz[3 * i + a]));
-      mx[a] = std::max(mx[a], static_cast<double>(xyz[3 * i + a]));
-    }
-  double vol = 1.0;
-  for (int a = 0; a < 3; ++a) vol *= std::max(mx[a] - mn[a], 1e-9);
-  const double h = std::max(std::cbrt(vol / static_cast<double>(m)) * 1.5, 1e-9);
-  auto cell = [&](const float* p, int a) {
-    return static_cast<int64_t>(std::floor((p[a] - mn[a]) / h));
-  };
-  auto pack = [](int64_t x, int64_t y, int64_t z) {
-    return (static_cast<uint64_t>(x) & 0x1FFFFF) | ((static_cast<uint64_t>(y) & 0x1FFFFF) << 21) |
-           ((static_cast<uint64_t>(z) & 0x1FFFFF) << 42);
-  };
-  std::unordered_map<uint64_t, std::vector<int32_t>> grid;
-  int64_t cmax[3] = {0, 0, 0};
-  for (int a = 0; a < 3; ++a) cmax[a] = static_cast<int64_t>(std::floor((mx[a] - mn[a]) / h));
-  for (int64_t j = 0; j < m; ++j) {
-    const float* p = xyz + 3 * static_cast<int64_t>(idx[j]);
-    grid[pack(cell(p, 0), cell(p, 1), cell(p, 2))].push_back(idx[j]);
-  }
-  const int64_t rmax = std::max({cmax[0], cmax[1], cmax[2]}) + 1;
+  std::vector<float> smp(static_cast<size_t>(m) * 3);
+  for (int64_t j = 0; j < m; ++j)
+    for (int a = 0; a < 3; ++a) smp[3 * j + a] = xyz[3 * static_cast<int64_t>(idx[j]) + a];
+  std::vector<double> d(static_cast<size_t>(N));
+  nn_d2(smp.data(), m, xyz, N, 0, d.data());
   double worst = 0.0;
-  for (int64_t i = 0; i < N; ++i) {
-    const float* p = xyz + 3 * i;
-    const int64_t c0 = cell(p, 0), c1 = cell(p, 1), c2 = cell(p, 2);
-    double best = std::numeric_limits<double>::infinity();
-    for (int64_t r = 0; r <= rmax; ++r) {
-      for (int64_t dx = -r; dx <= r; ++dx)
-        for (int64_t dy = -r; dy <= r; ++dy)
-          for (int64_t dz = -r; dz <= r; ++dz) {
-            if (std::max({std::llabs(dx), std::llabs(dy), std::llabs(dz)}) != r) continue;
-            const int64_t x = c0 + dx, y = c1 + dy, z = c2 + dz;
-            if (x < 0 || y < 0 || z < 0 || x > cmax[0] || y > cmax[1] || z > cmax[2]) continue;
-            auto it = grid.find(pack(x, y, z));
-            if (it == grid.end()) continue;
-            for (int32_t q : it->second) {
-              const double ex = static_cast<double>(xyz[3 * q]) - p[0];
-              const double ey = static_cast<double>(xyz[3 * q + 1]) - p[1];
-              const double ez = static_cast<double>(xyz[3 * q + 2]) - p[2];
-              best = std::min(best, ex * ex + ey * ey + ez * ez);
-            }
-          }
-      // every sample in a ring beyond r is at least r*h away
-      const double bound = static_cast<double>(r) * h;
-      if (best <= bound * bound) break;
-    }
-    worst = std::max(worst, best);
-  }
+  for (double v : d) worst = std::max(worst, v);
   return std::sqrt(worst);
 }
 

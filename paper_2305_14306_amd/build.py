@@ -14,7 +14,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "hav.hip"), os.path.join(HERE, "csrc", "compare.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "hav.hip"), os.path.join(HERE, "csrc", "compare.hip"),
+           os.path.join(HERE, "csrc", "metrics.hip")]
 DEPS = [os.path.join(HERE, "csrc", "hav_device.hpp"), os.path.join(ROOT, "include", "hav.h")]
 LIB = os.path.join(HERE, "libhav.so")
 ARCH = os.environ.get("HAV_OFFLOAD_ARCH", "gfx950")

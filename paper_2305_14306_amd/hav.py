@@ -159,6 +159,12 @@ def lib():
         L.hav_rps_workspace_init.argtypes = [vp, C.c_size_t, C.c_int64, vp]
         L.hav_rps.restype = C.c_int
         L.hav_rps.argtypes = [C.c_int64, C.c_int64, C.c_uint64, C.c_float, i32p, vp, C.c_size_t, vp]
+        L.hav_nn_workspace_size.restype = C.c_size_t
+        L.hav_nn_workspace_size.argtypes = [C.c_int64]
+        L.hav_nn_workspace_init.restype = C.c_int
+        L.hav_nn_workspace_init.argtypes = [vp, C.c_size_t, C.c_int64, vp]
+        L.hav_nn.restype = C.c_int
+        L.hav_nn.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_int32, vp, vp, vp, C.c_size_t, vp]
         L.hav_timing_enable.restype = C.c_int
         L.hav_timing_enable.argtypes = [C.c_int32]
         L.hav_timing_collect.restype = C.c_int
@@ -587,3 +593,40 @@ class RPS:
         if st != 0:
             raise HavError(st)
         return out
+
+
+class NearestSample:
+    """Nearest-sample distances on the GPU (hav_nn): coverage and spacing of a sample."""
+
+    def __init__(self, device=None):
+        torch = _torch()
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self._ws = None
+        self._m = 0
+
+    def d2(self, samples, queries=None, stream=None):
+        """(d2 [Q] float64, max_d2 float64 tensor of one element). queries None: the
+        samples' spacing (each skips itself)."""
+        torch = _torch()
+        _check_xyz(samples)
+        M = samples.shape[0]
+        if M > self._m:
+            nbytes = int(lib().hav_nn_workspace_size(M))
+            if nbytes == 0:
+                raise HavError(ERR_INVALID_ARG, "hav_nn_workspace_size")
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            st = lib().hav_nn_workspace_init(self._ws.data_ptr(), nbytes, M, _stream_ptr(stream))
+            if st != OK:
+                raise HavError(st, "hav_nn_workspace_init")
+            self._m = M
+        self_q = queries is None
+        q = samples if self_q else queries
+        _check_xyz(q)
+        out = torch.empty(q.shape[0], dtype=torch.float64, device=self.device)
+        mx = torch.empty(1, dtype=torch.float64, device=self.device)
+        st = lib().hav_nn(samples.data_ptr(), M, q.data_ptr(), q.shape[0], 1 if self_q else 0,
+                          out.data_ptr(), mx.data_ptr(), self._ws.data_ptr(), self._ws.numel(),
+                          _stream_ptr(stream))
+        if st != OK:
+            raise HavError(st, "hav_nn")
+        return out, mx

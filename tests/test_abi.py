@@ -221,3 +221,20 @@ def test_comparators_reject_bad_arguments(hav):
                  (1000, 10, 1, 0.0, 0, ptr, rw)]:
         assert L.hav_rps(*args, None) == 1, args
     assert L.hav_rps(1000, 10, 1, 0.0, ptr, ptr, 16, None) == 2
+
+
+def test_nearest_sample_rejects_bad_arguments(hav):
+    L = hav.lib()
+    buf = C.create_string_buffer(1 << 16)
+    ptr = C.addressof(buf)
+    assert L.hav_nn_workspace_size(0) == 0
+    ws = L.hav_nn_workspace_size(100)
+    assert ws > 0
+    for args in [(0, 100, ptr, 10, 0, ptr, ptr, ptr, ws),      # no samples
+                 (ptr, 0, ptr, 10, 0, ptr, ptr, ptr, ws),      # M < 1
+                 (ptr, 100, ptr, 0, 0, ptr, ptr, ptr, ws),     # Q < 1
+                 (ptr, 100, ptr, 99, 1, ptr, ptr, ptr, ws),    # self needs Q == M
+                 (ptr, 1, ptr, 1, 1, ptr, ptr, ptr, ws),       # self needs M >= 2
+                 (ptr, 100, ptr, 10, 0, ptr, 0, ptr, ws)]:     # no max output
+        assert L.hav_nn(*args, None) == 1, args
+    assert L.hav_nn(ptr, 100, ptr, 10, 0, ptr, ptr, ptr, 64, None) == 2

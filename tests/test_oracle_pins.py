@@ -530,3 +530,31 @@ def test_mean_is_within_voxel_and_exact_for_dyadic_points(orc):
         assert np.allclose(pts[j], x[members].astype(np.float64).mean(0), rtol=0, atol=1e-6)
         lo = g[i] * np.float32(s)
         assert np.all(pts[j] >= lo - 1e-6) and np.all(pts[j] <= lo + s + 1e-6)
+
+
+def _brute_nn_d2(s, q, exclude_self=False):
+    d = s[None, :, :].astype(np.float64) - q[:, None, :].astype(np.float64)
+    d2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+    if exclude_self:
+        np.fill_diagonal(d2, np.inf)
+    return d2.min(1)
+
+
+@pytest.mark.parametrize("shape", ["box", "plane", "line", "dups", "one"])
+def test_nearest_sample_matches_brute_force(orc, shape):
+    rng = np.random.default_rng(hash(shape) % 1000)
+    if shape == "box":
+        s = rng.uniform(0, 5, (400, 3))
+    elif shape == "plane":
+        s = np.c_[rng.uniform(0, 5, (400, 2)), np.zeros(400)]
+    elif shape == "line":
+        s = np.c_[rng.uniform(-3, 3, 400), np.zeros((400, 2))]
+    elif shape == "dups":
+        s = np.repeat(rng.uniform(0, 2, (100, 3)), 4, axis=0)
+    else:
+        s = rng.uniform(0, 1, (1, 3))
+    s = s.astype(np.float32)
+    q = rng.uniform(-2, 7, (600, 3)).astype(np.float32)  # also outside the samples' box
+    assert np.array_equal(orc.nn_d2(s, q), _brute_nn_d2(s, q))
+    if s.shape[0] > 1:
+        assert np.array_equal(orc.nn_d2(s, s, True), _brute_nn_d2(s, s, True))
