@@ -177,21 +177,26 @@ def variants_leg(torch, hav, synth) -> dict:
     """Selection strategies of the ablation (Sec. 4.5, Table 6) on the 16,384-point
     KITTI-like cloud -> 4,096: centre-closest (CC), random member (RA), voxel centre (CE)
     and voxel mean (ME) with the adaptive voxel size, RVS (ME at a fixed size, one layer),
-    and FPS / RPS for reference. Coverage context (computed with scipy's k-d tree on the
-    host): the covering radius (largest distance from a cloud point to its nearest
-    sample) and the mean nearest-neighbour spacing of the samples; plus GPU time per call."""
+    and FPS / RPS for reference. Coverage and spacing (Sec. 3.1, Fig. 3) on the GPU
+    (hav_nn): the covering radius (largest distance from a cloud point to its nearest
+    sample) and the spacing distribution (each sample's distance to its nearest other
+    sample: minimum, 5th percentile, median, mean); plus GPU time per sampler call."""
     import numpy as np
-    from scipy.spatial import cKDTree
     x = synth.uniform_box_with_ground(16384, seed=1)
     M = 4096
     xd = torch.from_numpy(x).cuda()
-    tree = cKDTree(x.astype(np.float64))
+    nn = hav.NearestSample()
 
     def metrics(pts):
-        pts = np.asarray(pts, dtype=np.float64)
-        cover = float(cKDTree(pts).query(x.astype(np.float64))[0].max())
-        d, _ = cKDTree(pts).query(pts, k=2)
-        return {"covering_radius": round(cover, 4), "mean_spacing": round(float(d[:, 1].mean()), 4)}
+        pts = pts.contiguous()
+        _, cover = nn.d2(pts, xd)
+        sp, _ = nn.d2(pts)
+        sp = torch.sqrt(sp).cpu().numpy()
+        return {"covering_radius": round(float(torch.sqrt(cover).cpu()[0]), 4),
+                "spacing_min": round(float(sp.min()), 4),
+                "spacing_p5": round(float(np.percentile(sp, 5)), 4),
+                "spacing_median": round(float(np.median(sp)), 4),
+                "spacing_mean": round(float(sp.mean()), 4)}
 
     def timed(fn, reps=10):
         fn()
@@ -214,16 +219,22 @@ def variants_leg(torch, hav, synth) -> dict:
               hav.params(select=hav.SELECT_MEAN, layers=1, fixed_voxel=s_fix))]
     for name, p in cases:
         (idx, pts), ms = timed(lambda p=p: s.sample_points(xd, M, p))
-        out[name] = dict(metrics(pts.cpu().numpy()), ms=round(ms, 4))
+        out[name] = dict(metrics(pts), ms=round(ms, 4))
     f = hav.FPS()
     idx, ms = timed(lambda: f.sample(xd, M), reps=3)
-    out["FPS"] = dict(metrics(x[idx.cpu().numpy()]), ms=round(ms, 4))
+    out["FPS"] = dict(metrics(xd[idx.long()]), ms=round(ms, 4))
     r = hav.RPS()
     idx, ms = timed(lambda: r.sample(x.shape[0], M, 1))
-    out["RPS"] = dict(metrics(x[idx.cpu().numpy()]), ms=round(ms, 4))
-    del tree
+    out["RPS"] = dict(metrics(xd[idx.long()]), ms=round(ms, 4))
+    # cost of the metric itself at the headline scale: covering radius of 262,144 samples
+    # over 1,048,576 points
+    big = torch.from_numpy(synth.scene_planes_blobs(1 << 20, seed=3)).cuda()
+    bidx = hav.Sampler().sample(big, 1 << 18)
+    bs = big[bidx.long()].contiguous()
+    (_, cov), ms_cov = timed(lambda: nn.d2(bs, big), reps=5)
     return {"workload": "KITTI-like 16,384 -> 4,096 (half box, half ground plane); fixed voxel for "
-                        "RVS = the 1-layer adaptive size %.4f" % s_fix, "strategies": out}
+                        "RVS = the 1-layer adaptive size %.4f" % s_fix, "strategies": out,
+            "covering_1M_262k": {"radius": round(float(torch.sqrt(cov).cpu()[0]), 4), "ms": round(ms_cov, 3)}}
 
 
 def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
