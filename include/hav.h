@@ -341,6 +341,23 @@ hav_status_t hav_nn_workspace_init(void* ws, size_t ws_bytes, int64_t M, void* s
 hav_status_t hav_nn(const float* samples, int64_t M, const float* queries, int64_t Q, int32_t exclude_self,
                     double* d2_out, double* max_d2, void* ws, size_t ws_bytes, void* stream);
 
+/* Ball query: the grouping step that follows sampling in a set-abstraction block (the
+ * sampled points become centres; Sec. 3.1 places the sampler in front of grouping).
+ * For centre j, idx[j][0..n-1] are the n = min(K, count[j]) lowest indices i with
+ * d2 < radius^2 (strict), ascending, d2 in float32 as ((dx*dx + dy*dy) + dz*dz),
+ * dx = x_i - c_j, no fused multiply-add, radius^2 = fl(radius * radius); the rest of the
+ * row repeats idx[j][0], or is -1 when the ball is empty. count[j] (optional) is the
+ * number of points inside the ball.
+ *   xyz [N][3], centres [Q][3] float32 device; idx [Q][K] int32 device; count [Q] int32
+ *   device or NULL. 1 <= N, Q <= HAV_NN_MAX_SAMPLES; 1 <= K <= 64; radius > 0 finite.
+ *   ws: hav_ball_workspace_size(N) bytes initialised once with hav_ball_workspace_init
+ *   (for that N or a larger one); one call at a time. */
+size_t hav_ball_workspace_size(int64_t N);
+hav_status_t hav_ball_workspace_init(void* ws, size_t ws_bytes, int64_t N, void* stream);
+hav_status_t hav_ball_query(const float* xyz, int64_t N, const float* centres, int64_t Q, float radius,
+                            int32_t K, int32_t* idx, int32_t* count, void* ws, size_t ws_bytes,
+                            void* stream);
+
 #ifdef __cplusplus
 }
 #endif

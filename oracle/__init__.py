@@ -118,6 +118,8 @@ def lib():
         L.oracle_rps.restype = C.c_int32
         L.oracle_nn_d2.argtypes = [f32p, C.c_int64, f32p, C.c_int64, C.c_int32, C.POINTER(C.c_double)]
         L.oracle_nn_d2.restype = C.c_int32
+        L.oracle_ball_query.argtypes = [f32p, C.c_int64, f32p, C.c_int64, C.c_float, C.c_int32, i32p, i32p]
+        L.oracle_ball_query.restype = C.c_int32
         L.oracle_covering_radius.argtypes = [f32p, C.c_int64, i32p, C.c_int64]
         L.oracle_covering_radius.restype = C.c_double
         _lib = L
@@ -272,6 +274,19 @@ def nn_d2(samples, queries, exclude_self: bool = False) -> np.ndarray:
     if st != 0:
         raise ValueError("nn_d2: bad arguments")
     return out
+
+
+def ball_query(xyz, centres, radius: float, K: int):
+    """(idx [Q, K] int32, count [Q] int32): the K lowest-index points strictly inside
+    the radius of each centre."""
+    a, c = _xyz(xyz), _xyz(centres)
+    idx = np.zeros((c.shape[0], int(K)), dtype=np.int32)
+    cnt = np.zeros(c.shape[0], dtype=np.int32)
+    st = lib().oracle_ball_query(_ptr(a, C.c_float), a.shape[0], _ptr(c, C.c_float), c.shape[0],
+                                 C.c_float(radius), int(K), _ptr(idx, C.c_int32), _ptr(cnt, C.c_int32))
+    if st != 0:
+        raise ValueError("ball_query: bad arguments")
+    return idx, cnt
 
 
 def covering_radius(xyz, idx) -> float:

@@ -93,6 +93,33 @@ int32_t oracle_nn_d2(const float* samples, int64_t M, const float* queries, int6
   return 0;
 }
 
+// Ball query, the grouping step after sampling: for centre j the lowest-index points
+// with d2 < r2 (float32, ((dx*dx + dy*dy) + dz*dz), dx = x_i - c_j), up to K in index
+// order; the row's rest repeats its first entry, or is -1 for an empty ball; count[j]
+// is the number of points inside. Brute force in index order.
+int32_t oracle_ball_query(const float* xyz, int64_t N, const float* ctr, int64_t Q, float radius,
+                          int32_t K, int32_t* idx, int32_t* count) {
+  if (!xyz || !ctr || !idx || N < 1 || Q < 1 || K < 1 || !(radius > 0.0f)) return 1;
+  const float r2 = radius * radius;
+  for (int64_t j = 0; j < Q; ++j) {
+    int32_t* row = idx + j * K;
+    int32_t n = 0;
+    int64_t total = 0;
+    for (int64_t i = 0; i < N; ++i) {
+      const float dx = xyz[3 * i] - ctr[3 * j];
+      const float dy = xyz[3 * i + 1] - ctr[3 * j + 1];
+      const float dz = xyz[3 * i + 2] - ctr[3 * j + 2];
+      const float d2 = dx * dx + dy * dy + dz * dz;
+      if (!(d2 < r2)) continue;
+      ++total;
+      if (n < K) row[n++] = static_cast<int32_t>(i);
+    }
+    for (int32_t t = n; t < K; ++t) row[t] = n > 0 ? row[0] : -1;
+    if (count) count[j] = static_cast<int32_t>(total);
+  }
+  return 0;
+}
+
 // Covering radius: max over all points of the distance to the nearest point of idx
 // (brute force: O(N m)).
 double oracle_covering_radius(const float* xyz, int64_t N, const int32_t* idx, int64_t m) {

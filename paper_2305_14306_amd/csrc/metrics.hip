@@ -9,6 +9,11 @@
 // samples' bounding box, so no host round trip). A query scans rings of cells around
 // its own cell (Chebyshev distance 0, 1, 2, ...) and stops once its best distance is
 // below the gap to the next ring, so the minimum is exact.
+//
+// The same grid, built over the cloud with cells at least the radius wide, serves the
+// ball query that groups points around the sampled centres (the grouping that follows
+// sampling in a set-abstraction block, Sec. 3.1): each centre scans its 27 cells and
+// keeps the K lowest-index points strictly inside the radius.
 
 #include <hip/hip_runtime.h>
 
@@ -311,6 +316,64 @@ __global__ void __launch_bounds__(kNnThreads) k_nn_query(NnWs w, const float* __
   if (bmax) atomicMax(&w.h->max_d2, bmax);
 }
 
+constexpr int kBallMaxK = 64;
+
+// Ball query: for centre j the lowest-index points i with d2 < r2 (d2 in float32 as
+// ((dx*dx + dy*dy) + dz*dz), dx = x_i - c_j, no fused multiply-add), up to K of them in
+// ascending index order; the rest of the row repeats the first, or is -1 when the ball
+// is empty. count[j] = the number of points inside. Cells are at least the radius wide,
+// so the 27 cells around the centre's cell hold every candidate. Each thread keeps its
+// K smallest indices sorted in its own LDS row.
+__global__ void __launch_bounds__(kNnThreads) k_ball(NnWs w, const float* __restrict__ xyz,
+                                                    const float* __restrict__ ctr, int64_t Q, float r2,
+                                                    int32_t K, int32_t* __restrict__ out,
+                                                    int32_t* __restrict__ count) {
+  const NnHdr& h = *w.h;
+  __shared__ int32_t kb[kNnThreads * kBallMaxK];
+  int32_t* row = kb + threadIdx.x * kBallMaxK;
+  for (int64_t j = static_cast<int64_t>(blockIdx.x) * kNnThreads + threadIdx.x; j < Q;
+       j += static_cast<int64_t>(gridDim.x) * kNnThreads) {
+    const float cxf = ctr[3 * j], cyf = ctr[3 * j + 1], czf = ctr[3 * j + 2];
+    const int64_t cx = nn_cell_axis(cxf, h, 0), cy = nn_cell_axis(cyf, h, 1), cz = nn_cell_axis(czf, h, 2);
+    int n = 0;
+    int64_t total = 0;
+    for (int64_t z = cz - 1; z <= cz + 1; ++z) {
+      if (z < 0 || z >= h.dims[2]) continue;
+      for (int64_t y = cy - 1; y <= cy + 1; ++y) {
+        if (y < 0 || y >= h.dims[1]) continue;
+        for (int64_t x = cx - 1; x <= cx + 1; ++x) {
+          if (x < 0 || x >= h.dims[0]) continue;
+          const int64_t c = x + h.dims[0] * (y + h.dims[1] * z);
+          const uint32_t e = w.off[c + 1];
+          for (uint32_t k = w.off[c]; k < e; ++k) {
+            const float dx = w.sorted[3 * static_cast<int64_t>(k)] - cxf;
+            const float dy = w.sorted[3 * static_cast<int64_t>(k) + 1] - cyf;
+            const float dz = w.sorted[3 * static_cast<int64_t>(k) + 2] - czf;
+            float d2 = dx * dx;
+            d2 = d2 + dy * dy;
+            d2 = d2 + dz * dz;
+            if (!(d2 < r2)) continue;
+            ++total;
+            const int32_t id = w.sorted_id[k];
+            if (n == K && id >= row[K - 1]) continue;
+            // insert id into the sorted row (the largest drops out when full)
+            int t = n < K ? n : K - 1;
+            while (t > 0 && row[t - 1] > id) {
+              row[t] = row[t - 1];
+              --t;
+            }
+            row[t] = id;
+            if (n < K) ++n;
+          }
+        }
+      }
+    }
+    int32_t* o = out + j * static_cast<int64_t>(K);
+    for (int t = 0; t < K; ++t) o[t] = t < n ? row[t] : (n > 0 ? row[0] : -1);
+    if (count) count[j] = static_cast<int32_t>(total < 0x7FFFFFFF ? total : 0x7FFFFFFF);
+  }
+}
+
 __global__ void k_nn_init(NnWs w, int64_t ncell_cap) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -402,6 +465,37 @@ hav_status_t hav_nn(const float* samples, int64_t M, const float* queries, int64
   hipLaunchKernelGGL(k_nn_query, dim3(gq), dim3(kNnThreads), 0, st, w, queries, Q, exclude_self, d2_out);
   hipLaunchKernelGGL(k_nn_clear, dim3(1024), dim3(256), 0, st, w);
   hipLaunchKernelGGL(k_nn_result, dim3(1), dim3(64), 0, st, w, max_d2);
+  return hipGetLastError() == hipSuccess ? HAV_OK : HAV_ERR_HIP;
+}
+
+size_t hav_ball_workspace_size(int64_t N) { return hav_nn_workspace_size(N); }
+
+hav_status_t hav_ball_workspace_init(void* ws, size_t ws_bytes, int64_t N, void* stream) {
+  return hav_nn_workspace_init(ws, ws_bytes, N, stream);
+}
+
+hav_status_t hav_ball_query(const float* xyz, int64_t N, const float* centres, int64_t Q, float radius,
+                            int32_t K, int32_t* idx, int32_t* count, void* ws, size_t ws_bytes,
+                            void* stream) {
+  if (!xyz || !centres || !idx || !ws || N < 1 || N > HAV_NN_MAX_SAMPLES || Q < 1 ||
+      Q > HAV_NN_MAX_SAMPLES || K < 1 || K > kBallMaxK || !(radius > 0.0f) || !std::isfinite(radius))
+    return HAV_ERR_INVALID_ARG;
+  const NnLayout L = nn_layout(N);
+  if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const NnWs w = nn_ws(ws, L);
+  const float r2 = radius * radius;
+  // cells a little wider than the radius, so one ring of cells holds the whole ball
+  const double min_h = static_cast<double>(radius) * 1.001;
+  const unsigned gb = static_cast<unsigned>(std::min<int64_t>(kNnBoxBlocks, (N + kNnThreads - 1) / kNnThreads));
+  hipLaunchKernelGGL(k_nn_box, dim3(gb), dim3(kNnThreads), 0, st, w, xyz, N, min_h);
+  const unsigned gs = static_cast<unsigned>(std::min<int64_t>(4096, (N + kNnThreads - 1) / kNnThreads));
+  hipLaunchKernelGGL(k_nn_count, dim3(gs), dim3(kNnThreads), 0, st, w, xyz, N);
+  hipLaunchKernelGGL(k_nn_scan, dim3(static_cast<unsigned>(kNnCells / kNnScanTile)), dim3(kNnThreads), 0, st, w, N);
+  hipLaunchKernelGGL(k_nn_scatter, dim3(gs), dim3(kNnThreads), 0, st, w, xyz, N);
+  const unsigned gq = static_cast<unsigned>(std::min<int64_t>(65536, (Q + kNnThreads - 1) / kNnThreads));
+  hipLaunchKernelGGL(k_ball, dim3(gq), dim3(kNnThreads), 0, st, w, xyz, centres, Q, r2, K, idx, count);
+  hipLaunchKernelGGL(k_nn_clear, dim3(1024), dim3(256), 0, st, w);
   return hipGetLastError() == hipSuccess ? HAV_OK : HAV_ERR_HIP;
 }
 

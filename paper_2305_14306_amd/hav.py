@@ -165,6 +165,13 @@ def lib():
         L.hav_nn_workspace_init.argtypes = [vp, C.c_size_t, C.c_int64, vp]
         L.hav_nn.restype = C.c_int
         L.hav_nn.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_int32, vp, vp, vp, C.c_size_t, vp]
+        L.hav_ball_workspace_size.restype = C.c_size_t
+        L.hav_ball_workspace_size.argtypes = [C.c_int64]
+        L.hav_ball_workspace_init.restype = C.c_int
+        L.hav_ball_workspace_init.argtypes = [vp, C.c_size_t, C.c_int64, vp]
+        L.hav_ball_query.restype = C.c_int
+        L.hav_ball_query.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_float, C.c_int32, vp, vp, vp,
+                                     C.c_size_t, vp]
         L.hav_timing_enable.restype = C.c_int
         L.hav_timing_enable.argtypes = [C.c_int32]
         L.hav_timing_collect.restype = C.c_int
@@ -630,3 +637,39 @@ class NearestSample:
         if st != OK:
             raise HavError(st, "hav_nn")
         return out, mx
+
+
+class BallQuery:
+    """Ball-query grouping on the GPU (hav_ball_query): for each centre the K lowest-index
+    points strictly inside the radius."""
+
+    def __init__(self, device=None):
+        torch = _torch()
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        self._ws = None
+        self._n = 0
+
+    def query(self, xyz, centres, radius: float, K: int, stream=None):
+        """(idx [Q, K] int32, count [Q] int32)."""
+        torch = _torch()
+        _check_xyz(xyz)
+        _check_xyz(centres)
+        N = xyz.shape[0]
+        if N > self._n:
+            nbytes = int(lib().hav_ball_workspace_size(N))
+            if nbytes == 0:
+                raise HavError(ERR_INVALID_ARG, "hav_ball_workspace_size")
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            st = lib().hav_ball_workspace_init(self._ws.data_ptr(), nbytes, N, _stream_ptr(stream))
+            if st != OK:
+                raise HavError(st, "hav_ball_workspace_init")
+            self._n = N
+        Q = centres.shape[0]
+        idx = torch.empty((Q, int(K)), dtype=torch.int32, device=self.device)
+        cnt = torch.empty(Q, dtype=torch.int32, device=self.device)
+        st = lib().hav_ball_query(xyz.data_ptr(), N, centres.data_ptr(), Q, float(radius), int(K),
+                                  idx.data_ptr(), cnt.data_ptr(), self._ws.data_ptr(), self._ws.numel(),
+                                  _stream_ptr(stream))
+        if st != OK:
+            raise HavError(st, "hav_ball_query")
+        return idx, cnt

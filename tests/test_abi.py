@@ -238,3 +238,19 @@ def test_nearest_sample_rejects_bad_arguments(hav):
                  (ptr, 100, ptr, 10, 0, ptr, 0, ptr, ws)]:     # no max output
         assert L.hav_nn(*args, None) == 1, args
     assert L.hav_nn(ptr, 100, ptr, 10, 0, ptr, ptr, ptr, 64, None) == 2
+
+
+def test_ball_query_rejects_bad_arguments(hav):
+    L = hav.lib()
+    buf = C.create_string_buffer(1 << 16)
+    ptr = C.addressof(buf)
+    ws = L.hav_ball_workspace_size(100)
+    assert ws > 0 and L.hav_ball_workspace_size(0) == 0
+    for args in [(0, 100, ptr, 10, 1.0, 8, ptr, ptr, ptr, ws),              # no points
+                 (ptr, 100, ptr, 0, 1.0, 8, ptr, ptr, ptr, ws),             # Q < 1
+                 (ptr, 100, ptr, 10, 0.0, 8, ptr, ptr, ptr, ws),            # radius 0
+                 (ptr, 100, ptr, 10, float("nan"), 8, ptr, ptr, ptr, ws),   # radius NaN
+                 (ptr, 100, ptr, 10, 1.0, 0, ptr, ptr, ptr, ws),            # K < 1
+                 (ptr, 100, ptr, 10, 1.0, 65, ptr, ptr, ptr, ws)]:          # K > 64
+        assert L.hav_ball_query(*args, None) == 1, args
+    assert L.hav_ball_query(ptr, 100, ptr, 10, 1.0, 8, ptr, ptr, ptr, 64, None) == 2

@@ -74,3 +74,33 @@ def test_nn_covering_of_sampler_output(gpu, orc):
     assert np.sqrt(d.max()) == pytest.approx(orc.covering_radius(x, idx), rel=0, abs=0)
     _check(gpu, orc, s, None, "spacing 15k", nn)
     _check(gpu, orc, s[:7000], x[:30000], "reuse smaller", nn)
+
+
+def _check_ball(gpu, orc, x, c, radius, K, label, bq=None):
+    _note(f"case ball {label} N={x.shape[0]} Q={c.shape[0]} r={radius} K={K}")
+    bq = bq if bq is not None else gpu.BallQuery()
+    idx, cnt = bq.query(_dev(x), _dev(c), radius, K)
+    widx, wcnt = orc.ball_query(x, c, radius, K)
+    assert np.array_equal(cnt.cpu().numpy(), wcnt)
+    assert np.array_equal(idx.cpu().numpy(), widx)
+
+
+def test_ball_query_lattice_and_edges(gpu, orc):
+    x = synth.lattice(8)
+    _check_ball(gpu, orc, x, x, 1.01, 4, "lattice r 1.01")
+    _check_ball(gpu, orc, x, x, 1.0, 3, "lattice r 1 (strict)")
+    _check_ball(gpu, orc, x, x[:50], 2.5, 64, "lattice K 64")
+    far = np.array([[100.0, 0.0, 0.0], [-3.0, -3.0, -3.0]], dtype=np.float32)
+    _check_ball(gpu, orc, x, far, 1.0, 8, "empty balls")
+    _check_ball(gpu, orc, x[:1], x[:3], 1.5, 5, "one point")
+
+
+@pytest.mark.parametrize("radius,K", [(0.2, 16), (0.8, 32), (3.0, 64)])
+def test_ball_query_sampled_centres(gpu, orc, radius, K):
+    # the set-abstraction pattern: sample centres with the sampler, group around them
+    x = synth.scene_planes_blobs(40000, seed=61)
+    idx = gpu.Sampler().sample(_dev(x), 2000).cpu().numpy()
+    bq = gpu.BallQuery()
+    _check_ball(gpu, orc, x, x[idx], radius, K, "scene", bq)
+    d = np.repeat(synth.random_cloud(3000, 7, scale=2.0), 3, axis=0)  # duplicates
+    _check_ball(gpu, orc, d, d[::7], radius, K, "duplicates", bq)

@@ -558,3 +558,20 @@ def test_nearest_sample_matches_brute_force(orc, shape):
     assert np.array_equal(orc.nn_d2(s, q), _brute_nn_d2(s, q))
     if s.shape[0] > 1:
         assert np.array_equal(orc.nn_d2(s, s, True), _brute_nn_d2(s, s, True))
+
+
+def test_ball_query_lattice_closed_form(orc):
+    # on the integer lattice an interior point has 6 neighbours at distance 1: radius
+    # 1.01 holds 7 points (i-64, i-8, i-1, i, i+1, i+8, i+64); radius 1 holds only the
+    # point itself (strictly inside); a corner has 4
+    x = synth.lattice(8)
+    i = 3 + 8 * 3 + 64 * 3
+    idx, cnt = orc.ball_query(x, x[[i, 0]], 1.01, 4)
+    assert cnt.tolist() == [7, 4]
+    assert idx.tolist() == [[i - 64, i - 8, i - 1, i], [0, 1, 8, 64]]
+    idx, cnt = orc.ball_query(x, x[[i]], 1.0, 3)
+    assert cnt.tolist() == [1] and idx.tolist() == [[i, i, i]]
+    idx, cnt = orc.ball_query(x, x[[i]], 1.01, 9)
+    assert idx.tolist() == [[i - 64, i - 8, i - 1, i, i + 1, i + 8, i + 64, i - 64, i - 64]]
+    idx, cnt = orc.ball_query(x, np.array([[50.0, 50.0, 50.0]], dtype=np.float32), 1.0, 2)
+    assert cnt.tolist() == [0] and idx.tolist() == [[-1, -1]]
