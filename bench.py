@@ -232,9 +232,17 @@ def variants_leg(torch, hav, synth) -> dict:
     bidx = hav.Sampler().sample(big, 1 << 18)
     bs = big[bidx.long()].contiguous()
     (_, cov), ms_cov = timed(lambda: nn.d2(bs, big), reps=5)
+    # the grouping that follows sampling: 32 neighbours within 0.5 m of 65,536 sampled
+    # centres of the same cloud
+    cidx = hav.Sampler().sample(big, 1 << 16)
+    cen = big[cidx.long()].contiguous()
+    bq = hav.BallQuery()
+    (_, cnt), ms_bq = timed(lambda: bq.query(big, cen, 0.5, 32), reps=5)
     return {"workload": "KITTI-like 16,384 -> 4,096 (half box, half ground plane); fixed voxel for "
                         "RVS = the 1-layer adaptive size %.4f" % s_fix, "strategies": out,
-            "covering_1M_262k": {"radius": round(float(torch.sqrt(cov).cpu()[0]), 4), "ms": round(ms_cov, 3)}}
+            "covering_1M_262k": {"radius": round(float(torch.sqrt(cov).cpu()[0]), 4), "ms": round(ms_cov, 3)},
+            "ball_query_1M_65k_r0.5_k32": {"ms": round(ms_bq, 3),
+                                           "mean_in_ball": round(float(cnt.double().mean().cpu()), 1)}}
 
 
 def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
