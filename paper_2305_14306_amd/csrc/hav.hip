@@ -1573,11 +1573,17 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   float4 pt[kPerThread];
   uint32_t live = 0;
   uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
+  uint32_t tg[kPerThread];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {  // tags and points in one round trip
+    const int64_t S = base + k * kThreads;
+    tg[k] = w.tag_s[S];
+    pt[k] = w.pts[S];
+  }
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
-    const int64_t S = base + k * kThreads;
-    const bool ok = w.tag_s[S] == 0;
-    pt[k] = ok ? w.pts[S] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool ok = tg[k] == 0;
+    if (!ok) pt[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (ok) {
       live |= 1u << k;
       const uint32_t bx = __float_as_uint(pt[k].x), by = __float_as_uint(pt[k].y),
@@ -1660,14 +1666,16 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   }
   __syncthreads();
   int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
-  // thread t owns entries t + j*kThreads; a dense table's minima are issued four at a
-  // time so that their round trips overlap (the atomic's old value says whether this
+  // thread t owns entries t + j*kThreads; a dense table's minima are issued eight at a
+  // time, so that their round trips overlap (the atomic's old value says whether this
   // tile is the voxel's first, which then records the slot)
-  for (int e0 = 0; e0 < kLdsCap; e0 += 4 * kThreads) {
-    uint64_t key[4], val[4];
+  constexpr int kQ = 8;
+  static_assert(kLdsCap % (kQ * kThreads) == 0, "select entries per thread");
+  for (int e0 = 0; e0 < kLdsCap; e0 += kQ * kThreads) {
+    uint64_t key[kQ], val[kQ];
     uint32_t has = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kQ; ++j) {
       const int e = e0 + j * kThreads + static_cast<int>(threadIdx.x);
       key[j] = 0ull;
       val[j] = lvals[e];
@@ -1686,18 +1694,18 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
     if (!has) continue;
     if (!dense) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < kQ; ++j)
         if (((has >> j) & 1u) && select_hashed(w, key[j], val[j], list, &s_ncl) && win) wcount(key[j]);
       continue;
     }
-    uint64_t old[4];
+    uint64_t old[kQ];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < kQ; ++j)
       old[j] = ((has >> j) & 1u) ? atomicMin(&w.svals[static_cast<uint32_t>(key[j])],
                                              static_cast<unsigned long long>(val[j]))
                                  : 0ull;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kQ; ++j) {
       if (((has >> j) & 1u) && old[j] == ~0ull) {
         list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(key[j]);
         if (win) wcount(unpack(key[j]));
@@ -1782,8 +1790,12 @@ __global__ void __launch_bounds__(kThreads) k_trim_hist(Src src, int L, int roun
   if (!arrive_last(h, bx, gx)) return;
   // last block: the total histogram (emptied as read), then the digit holding rank
   for (int i = threadIdx.x; i < kTrimBins; i += kThreads) {
+    uint32_t v[kGroups];
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) v[q] = take(&h->hist[q][i]);  // all in flight at once
     uint32_t t = 0;
-    for (int q = 0; q < kGroups; ++q) t += take(&h->hist[q][i]);
+#pragma unroll
+    for (int q = 0; q < kGroups; ++q) t += v[q];
     lh[i] = t;
   }
   __syncthreads();
@@ -1890,12 +1902,18 @@ __device__ void settle_ties(const Ws& w, Header* h) {
   __shared__ uint64_t lp[kTieLds];
   __shared__ int32_t lo[kTieLds];
   __shared__ uint64_t ls[kTieRank];
+  // the groups' queue lengths, read and reset in parallel (one round trip)
+  if (threadIdx.x < kGroups) {
+    const uint32_t t = take(&h->tie_cur[threadIdx.x][0]);
+    cnt_g[threadIdx.x + 1] = t < w.tie_seg ? t : static_cast<uint32_t>(w.tie_seg);
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
     for (int q = 0; q < kGroups; ++q) {
-      const uint32_t t = take(&h->tie_cur[q][0]);
+      const uint32_t t = cnt_g[q + 1];
       cnt_g[q] = acc;
-      acc += t < w.tie_seg ? t : static_cast<uint32_t>(w.tie_seg);
+      acc += t;
     }
     cnt_g[kGroups] = acc;
     s_rank = c->rank;
@@ -2015,62 +2033,85 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
   const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
   const int g = tile & (kGroups - 1);
   __shared__ uint32_t s_base;
-  __shared__ uint32_t s_wbase[kThreads / 64];
-  for (int i0 = 0; i0 < n; i0 += kThreads) {
-    const int i = i0 + threadIdx.x;
-    bool tie = false;
-    uint64_t p = 0;
-    int32_t orig = 0;
-    if (i < n) {
-      const int32_t s = list[i];
-      const uint64_t key = sel_key(w, c, s);
-      orig = static_cast<int32_t>(w.svals[s] & 0xFFFFFFFFull);
-      if (!dense) w.skeys[s] = kEmptyKey;
-      w.svals[s] = ~0ull;
-      if (w.pmode && orig >= 0 && orig < w.n) stand_in(w, c, h->frame, s, key, orig);
-      bool keep = true;
-      if (trim) {
-        p = voxel_priority(key);
-        if (mode == 0) {
-          const uint64_t hi = shift >= 64 ? 0ull : (p >> shift);
-          keep = hi < pref_hi;
-          tie = hi == pref_hi;
-        } else if (mode == 1) {
-          keep = p < blo;
-          tie = !keep && p <= bhi;
-        } else {
-          keep = false;
-          tie = true;
-        }
-      }
-      if (keep && orig >= 0 && orig < w.n) {
-        w.tag_o[orig] = lt;
-        w.tag_s[w.invp[orig]] = lt;
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  // A tile owns at most kTile voxels: each thread takes its (up to kMP) list entries in
+  // one go, so every step's loads are in flight together (list, then table words, then
+  // the kept points' sorted slots) instead of one dependent chain per entry.
+  constexpr int kMP = kTile / kThreads;
+  int32_t sl[kMP];
+#pragma unroll
+  for (int k = 0; k < kMP; ++k) {
+    const int i = static_cast<int>(threadIdx.x) + k * kThreads;
+    sl[k] = i < n ? list[i] : -1;
+  }
+  uint64_t sv[kMP], sk[kMP];
+#pragma unroll
+  for (int k = 0; k < kMP; ++k) {
+    sv[k] = sl[k] >= 0 ? w.svals[sl[k]] : ~0ull;
+    sk[k] = (sl[k] >= 0 && !dense) ? w.skeys[sl[k]] : 0ull;
+  }
+  const uint32_t nx = c->sel_nv[0], ny = c->sel_nv[1];
+  int32_t orig[kMP];
+  uint64_t pr[kMP];
+  uint32_t keepm = 0, tiem = 0;
+#pragma unroll
+  for (int k = 0; k < kMP; ++k) {
+    orig[k] = -1;
+    pr[k] = 0;
+    if (sl[k] < 0) continue;
+    const int32_t s = sl[k];
+    uint64_t key = sk[k];
+    if (dense) {
+      const uint32_t u = static_cast<uint32_t>(s), t = u / nx;
+      key = pack_key(u % nx, t % ny, t / ny);
+    }
+    orig[k] = static_cast<int32_t>(sv[k] & 0xFFFFFFFFull);
+    if (!dense) w.skeys[s] = kEmptyKey;
+    w.svals[s] = ~0ull;
+    if (w.pmode && orig[k] >= 0 && orig[k] < w.n) stand_in(w, c, h->frame, s, key, orig[k]);
+    bool keep = true, tie = false;
+    if (trim) {
+      const uint64_t p = voxel_priority(key);
+      pr[k] = p;
+      if (mode == 0) {
+        const uint64_t hi = shift >= 64 ? 0ull : (p >> shift);
+        keep = hi < pref_hi;
+        tie = hi == pref_hi;
+      } else if (mode == 1) {
+        keep = p < blo;
+        tie = !keep && p <= bhi;
+      } else {
+        keep = false;
+        tie = true;
       }
     }
-    const uint64_t bal = __ballot(tie);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) s_wbase[wv] = static_cast<uint32_t>(__popcll(bal));
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t tot = 0;
-      for (int q = 0; q < kThreads / 64; ++q) {
-        const uint32_t t = s_wbase[q];
-        s_wbase[q] = tot;
-        tot += t;
-      }
-      s_base = tot ? atomicAdd(&h->tie_cur[g][0], tot) : 0u;
+    if (keep && orig[k] >= 0 && orig[k] < w.n) keepm |= 1u << k;
+    if (tie) tiem |= 1u << k;
+  }
+  int32_t ip[kMP];
+#pragma unroll
+  for (int k = 0; k < kMP; ++k) ip[k] = ((keepm >> k) & 1u) ? w.invp[orig[k]] : -1;
+#pragma unroll
+  for (int k = 0; k < kMP; ++k) {
+    if (ip[k] < 0) continue;
+    w.tag_o[orig[k]] = lt;
+    w.tag_s[ip[k]] = lt;
+  }
+  // the bucket's members go to the group's queue (positions by a block scan and one
+  // atomic per block)
+  uint32_t ex;
+  const uint32_t tot = block_exclusive_scan<kThreads>(static_cast<uint32_t>(__popc(tiem)), &ex, s_tmp);
+  if (threadIdx.x == 0) s_base = tot ? atomicAdd(&h->tie_cur[g][0], tot) : 0u;
+  __syncthreads();
+  uint32_t pos = s_base + ex;
+#pragma unroll
+  for (int k = 0; k < kMP; ++k) {
+    if (!((tiem >> k) & 1u)) continue;
+    if (pos < w.tie_seg) {
+      st_agent(&w.tie_p[g * w.tie_seg + pos], pr[k]);
+      st_agent(&w.tie_o[g * w.tie_seg + pos], orig[k]);
     }
-    __syncthreads();
-    if (tie) {
-      const uint32_t pos =
-          s_base + s_wbase[wv] + static_cast<uint32_t>(__popcll(bal & ((1ull << lane) - 1ull)));
-      if (pos < w.tie_seg) {
-        st_agent(&w.tie_p[g * w.tie_seg + pos], p);
-        st_agent(&w.tie_o[g * w.tie_seg + pos], orig);
-      }
-    }
-    __syncthreads();
+    ++pos;
   }
   if (threadIdx.x == 0) w.scn[tile] = 0;
   if (!arrive_last(h, bx, gx)) return;
