@@ -107,6 +107,9 @@ struct Frame {
   float mn[3], mx[3];
   float hi0;
   float bscale[3];
+  // box-counting prior of the search's count model: Cnt(s) ~ prior_c (prior_s / s)^prior_d
+  float prior_s, prior_c, prior_d;
+  int32_t prior_ok;
 };
 
 struct Ctrl {
@@ -407,14 +410,28 @@ __device__ void plan_search(SState* st, const Plan& P, const Frame& fr, uint32_t
   }
   const int left = P.t_max - st->evals;
   const int D = left < P.depth ? left : P.depth;
-  // with no count at hi, the model starts from one voxel at hi0
-  float sref = st->c_hi ? st->hi : fr.hi0, cref = st->c_hi ? static_cast<float>(st->c_hi) : 1.0f;
-  float dim = 2.0f;
+  // the model: through the counts at both bracket ends when known; else through the
+  // one known count with the binning's box-counting dimension; else the box-counting
+  // prior itself (or one voxel at hi0, dimension 2, when the binning gave none)
+  const float dim0 = fr.prior_ok ? fr.prior_d : 2.0f;
+  float sref, cref, dim = dim0;
   if (st->c_lo && st->c_hi && st->lo > 0.0f && st->c_lo > st->c_hi) {
+    sref = st->hi;
+    cref = static_cast<float>(st->c_hi);
     dim = __logf(static_cast<float>(st->c_lo) / static_cast<float>(st->c_hi)) / __logf(st->hi / st->lo);
-  } else if (st->c_lo && !st->c_hi) {
+  } else if (st->c_hi) {
+    sref = st->hi;
+    cref = static_cast<float>(st->c_hi);
+  } else if (st->c_lo) {
     sref = st->lo;
     cref = static_cast<float>(st->c_lo);
+  } else if (fr.prior_ok) {
+    sref = fr.prior_s;
+    cref = fr.prior_c;
+  } else {
+    sref = fr.hi0;
+    cref = 1.0f;
+    dim = 2.0f;
   }
   float lo = st->lo, hi = st->hi;
   int nc = 0;
@@ -720,6 +737,8 @@ __device__ int frame_from_partials(const Ws& w, const Plan& P, Frame* fr, int id
     fr->bscale[a] = ext[a] > 0.0f ? static_cast<float>(1 << bb[a]) / ext[a] : 0.0f;
     if (!isfinite(fr->bscale[a])) fr->bscale[a] = 0.0f;
   }
+  fr->prior_s = fr->prior_c = fr->prior_d = 0.0f;
+  fr->prior_ok = 0;  // (set by the binning's scan)
   fr->status = status;
   return status;
 }
@@ -854,11 +873,56 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Src src) {
   }
   __syncthreads();
   const uint32_t x = threadIdx.x < kBinChunk ? s_tot[threadIdx.x] : 0u;
+  // box counting for the search's prior: occupied cells, and occupied groups of 8
+  // consecutive cells (the parent cells, each axis halved, when every axis has cell
+  // bits: the lowest three bits of a cell number are one bit of each axis). A block
+  // holds 16 cells, two whole groups; one packed atomic per block.
+  static_assert(kBinChunk == 16, "two parent groups per scan block");
+  {
+    const uint64_t occ = __ballot(threadIdx.x < kBinChunk && x != 0u);
+    if (threadIdx.x == 0 && occ) {
+      const uint32_t groups = ((occ & 0xFFull) ? 1u : 0u) + ((occ & 0xFF00ull) ? 1u : 0u);
+      atomicAdd(&w.h->acc[3][bx & (kGroups - 1)][0], (groups << 16) | static_cast<uint32_t>(__popcll(occ)));
+    }
+  }
   uint32_t ex;
   const uint32_t chunk_total = block_exclusive_scan<kThreads>(x, &ex, s_tmp);
   if (threadIdx.x < kBinChunk) w.binpre[bx * kBinChunk + threadIdx.x] = ex;
   if (threadIdx.x == 0) atomicExch(&w.bsum[bx], chunk_total);
   if (!arrive_last(w.h, bx, gx)) return;
+  __shared__ uint32_t s_occ[2];
+  if (threadIdx.x < 2) s_occ[threadIdx.x] = 0u;
+  __syncthreads();
+  if (threadIdx.x < kGroups) {
+    const uint32_t v = take(&w.h->acc[3][threadIdx.x][0]);
+    if (v) {
+      atomicAdd(&s_occ[0], v & 0xFFFFu);
+      atomicAdd(&s_occ[1], v >> 16);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // prior: occupied cells at the binning cell size (geometric mean over the axes that
+    // have cells), dimension from the parent level; not when the cells are nearly all
+    // occupied (the fine level is saturated and says nothing about finer scales)
+    Frame* f = &w.h->frame;
+    const uint32_t o12 = s_occ[0], o9 = s_occ[1];
+    float lsum = 0.0f;
+    int na = 0;
+    for (int a = 0; a < 3; ++a)
+      if (f->bbits[a] > 0 && f->bscale[a] > 0.0f) {
+        lsum += __logf(1.0f / f->bscale[a]);
+        ++na;
+      }
+    f->prior_ok = 0;
+    if (na > 0 && o9 > 0 && o12 > 0 && o12 <= static_cast<uint32_t>(kBins) * 3u / 4u) {
+      const float d = __log2f(static_cast<float>(o12) / static_cast<float>(o9));
+      f->prior_d = d < 1.0f ? 1.0f : (d > 3.0f ? 3.0f : d);
+      f->prior_s = __expf(lsum / static_cast<float>(na));
+      f->prior_c = static_cast<float>(o12);
+      f->prior_ok = isfinite(f->prior_s) && f->prior_s > 0.0f ? 1 : 0;
+    }
+  }
   const uint32_t y = threadIdx.x < static_cast<int>(gx) ? peek(&w.bsum[threadIdx.x]) : 0u;
   uint32_t ey;
   block_exclusive_scan<kThreads>(y, &ey, s_tmp);
