@@ -587,9 +587,10 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
     }
     set_select_grid(c, P, h->frame);
   } else {
-    // the first pass's candidates, published for the search kernel
+    // the first pass's candidates, planned in LDS and published for the search kernel
     c->done = 0;
-    SState* s0 = reinterpret_cast<SState*>(h->pub);
+    __shared__ SState s_init;
+    SState* s0 = &s_init;
     s0->lo = 0.0f;
     s0->hi = h->frame.hi0;
     s0->c_hi = 0;
@@ -604,6 +605,7 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
     s0->s_final = 0.0f;
     s0->c_final = 0;
     plan_search(s0, P, h->frame, c->m, c->upper);
+    for (int i = 0; i < kPubWords; ++i) h->pub[i] = reinterpret_cast<const uint32_t*>(s0)[i];
   }
 }
 
@@ -663,11 +665,31 @@ __global__ void __launch_bounds__(kThreads) k_bbox(Src src) {
 __device__ int frame_from_partials(const Ws& w, const Plan& P, Frame* fr, int identity) {
   __shared__ uint32_t s_v[7][kThreads / 64];
   uint32_t v[7] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u};
-  for (int b = threadIdx.x; b < w.nbbox; b += kThreads) {
-    const uint32_t* p = w.part + b * 8;
-    for (int k = 0; k < 3; ++k) v[k] = min(v[k], p[k]);
-    for (int k = 3; k < 6; ++k) v[k] = max(v[k], p[k]);
-    v[6] |= p[6];
+  const uint64_t magic = w.h->magic;  // in flight with the partials
+  // every thread's partials (at most four: nbbox <= kMaxBBoxBlocks) in one round trip
+  static_assert(kMaxBBoxBlocks <= 4 * kThreads, "bbox partials per thread");
+  const uint4* p4 = reinterpret_cast<const uint4*>(w.part);
+  uint4 pa[4], pb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int b = threadIdx.x + j * kThreads;
+    if (b < w.nbbox) {
+      pa[j] = p4[2 * b];
+      pb[j] = p4[2 * b + 1];
+    } else {
+      pa[j] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u);
+      pb[j] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    v[0] = min(v[0], pa[j].x);
+    v[1] = min(v[1], pa[j].y);
+    v[2] = min(v[2], pa[j].z);
+    v[3] = max(v[3], pa[j].w);
+    v[4] = max(v[4], pb[j].x);
+    v[5] = max(v[5], pb[j].y);
+    v[6] |= pb[j].z;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -689,7 +711,7 @@ __device__ int frame_from_partials(const Ws& w, const Plan& P, Frame* fr, int id
   }
   __syncthreads();
   int status = HAV_OK;
-  if (w.h->magic != P.magic) status = HAV_ERR_WORKSPACE_NOT_INIT;
+  if (magic != P.magic) status = HAV_ERR_WORKSPACE_NOT_INIT;
   else if (v[6]) status = HAV_ERR_NONFINITE;
   float E = 0.0f;
   for (int a = 0; a < 3; ++a) {
@@ -822,11 +844,24 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
   if (st != HAV_OK) return;
   const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
   const int64_t beg = bx * chunk, end = min(w.n, beg + chunk);
-  for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) {
-    const float rx = xyz[3 * i] - fr.mn[0];
-    const float ry = xyz[3 * i + 1] - fr.mn[1];
-    const float rz = xyz[3 * i + 2] - fr.mn[2];
-    atomicAdd(&hist[cell_code(rx, ry, rz, fr)], 1u);
+  // 16 points per thread per round, all loads in flight together
+  constexpr int kBP = 16;
+  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
+    float px[kBP], py[kBP], pz[kBP];
+#pragma unroll
+    for (int k = 0; k < kBP; ++k) {
+      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
+      if (i < end) {
+        px[k] = xyz[3 * i];
+        py[k] = xyz[3 * i + 1];
+        pz[k] = xyz[3 * i + 2];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kBP; ++k) {
+      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
+      if (i < end) atomicAdd(&hist[cell_code(px[k] - fr.mn[0], py[k] - fr.mn[1], pz[k] - fr.mn[2], fr)], 1u);
+    }
   }
   __syncthreads();
   for (int b = threadIdx.x; b < kBins; b += kThreads)
@@ -854,22 +889,24 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Src src) {
   const int q = threadIdx.x / kBinChunk;
   const int nq = (w.nbb + kParts - 1) / kParts;
   const int b0 = q * nq, b1 = min(w.nbb, b0 + nq);
+  // this thread's counts (at most 32: nbb <= kMaxBinBlocks) in registers, one round trip
+  constexpr int kQ = kMaxBinBlocks / kParts;
+  static_assert(kMaxBinBlocks % kParts == 0, "bin blocks per part");
+  uint32_t v[kQ];
   uint32_t sum = 0;
-  for (int b = b0; b < b1; ++b) sum += w.bh[static_cast<size_t>(b) * kBins + bin];
+#pragma unroll
+  for (int j = 0; j < kQ; ++j) v[j] = b0 + j < b1 ? w.bh[static_cast<size_t>(b0 + j) * kBins + bin] : 0u;
+#pragma unroll
+  for (int j = 0; j < kQ; ++j) sum += v[j];
   s_q[q][lb] = sum;
   __syncthreads();
   uint32_t run = 0;
   for (int qq = 0; qq < q; ++qq) run += s_q[qq][lb];
   if (q == kParts - 1) s_tot[lb] = run + sum;
-  for (int b = b0; b < b1; b += 8) {
-    uint32_t v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = b + j < b1 ? w.bh[static_cast<size_t>(b + j) * kBins + bin] : 0u;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      if (b + j < b1) w.bh[static_cast<size_t>(b + j) * kBins + bin] = run;
-      run += v[j];
-    }
+  for (int j = 0; j < kQ; ++j) {
+    if (b0 + j < b1) w.bh[static_cast<size_t>(b0 + j) * kBins + bin] = run;
+    run += v[j];
   }
   __syncthreads();
   const uint32_t x = threadIdx.x < kBinChunk ? s_tot[threadIdx.x] : 0u;
@@ -907,11 +944,17 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Src src) {
     // occupied (the fine level is saturated and says nothing about finer scales)
     Frame* f = &w.h->frame;
     const uint32_t o12 = s_occ[0], o9 = s_occ[1];
+    int bbl[3];
+    float bsl[3];
+    for (int a = 0; a < 3; ++a) {  // loads first, all in flight
+      bbl[a] = f->bbits[a];
+      bsl[a] = f->bscale[a];
+    }
     float lsum = 0.0f;
     int na = 0;
     for (int a = 0; a < 3; ++a)
-      if (f->bbits[a] > 0 && f->bscale[a] > 0.0f) {
-        lsum += __logf(1.0f / f->bscale[a]);
+      if (bbl[a] > 0 && bsl[a] > 0.0f) {
+        lsum += __logf(1.0f / bsl[a]);
         ++na;
       }
     f->prior_ok = 0;
@@ -948,20 +991,40 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
   __shared__ Frame fr;
   __shared__ uint32_t off[kBins];
   if (threadIdx.x == 0) fr = w.h->frame;
-  for (int b = threadIdx.x; b < kBins; b += kThreads)
+  static_assert(kBins % kThreads == 0, "cells per thread");
+#pragma unroll
+  for (int j = 0; j < kBins / kThreads; ++j) {
+    const int b = threadIdx.x + j * kThreads;
     off[b] = w.bh[static_cast<size_t>(bx) * kBins + b] + w.binpre[b] + w.bsum[b / kBinChunk];
+  }
   __syncthreads();
   const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
   const int64_t beg = bx * chunk, end = min(w.n, beg + chunk);
-  for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) {
-    const float rx = xyz[3 * i] - fr.mn[0];
-    const float ry = xyz[3 * i + 1] - fr.mn[1];
-    const float rz = xyz[3 * i + 2] - fr.mn[2];
-    const uint32_t pos = atomicAdd(&off[cell_code(rx, ry, rz, fr)], 1u);
-    if (pos < w.n) {
-      const int64_t S = slot_of(pos);
-      w.pts[S] = make_float4(rx, ry, rz, __int_as_float(static_cast<int32_t>(i)));
-      w.invp[i] = static_cast<int32_t>(S);
+  constexpr int kBP = 16;
+  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
+    float px[kBP], py[kBP], pz[kBP];
+#pragma unroll
+    for (int k = 0; k < kBP; ++k) {
+      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
+      if (i < end) {
+        px[k] = xyz[3 * i];
+        py[k] = xyz[3 * i + 1];
+        pz[k] = xyz[3 * i + 2];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kBP; ++k) {
+      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
+      if (i >= end) continue;
+      const float rx = px[k] - fr.mn[0];
+      const float ry = py[k] - fr.mn[1];
+      const float rz = pz[k] - fr.mn[2];
+      const uint32_t pos = atomicAdd(&off[cell_code(rx, ry, rz, fr)], 1u);
+      if (pos < w.n) {
+        const int64_t S = slot_of(pos);
+        w.pts[S] = make_float4(rx, ry, rz, __int_as_float(static_cast<int32_t>(i)));
+        w.invp[i] = static_cast<int32_t>(S);
+      }
     }
   }
 }
