@@ -549,7 +549,25 @@ __device__ void set_window(Ctrl* c, float sig) {
   c->win = 1;
 }
 
+__device__ void layer_init_ctrl(Header* h, const Plan& P, int L, SState* s0);
+
+// Start layer L; all threads of the block call it. The bulk clearing is spread over
+// the block, the controller and the first plan (built in LDS from a register copy of
+// the frame, so the plan's arithmetic waits on no memory) are thread 0's.
 __device__ void layer_init(Header* h, const Plan& P, int L) {
+  __shared__ SState s_init;
+  for (int i = threadIdx.x; i < 2 * kMaxCand * kGroups; i += kThreads)
+    h->sacc[i / (kMaxCand * kGroups)][(i / kGroups) % kMaxCand][i % kGroups][0] = 0;
+  if (threadIdx.x < kGroups) h->sq_dgrp[threadIdx.x][0] = 0;
+  if (threadIdx.x == 0) layer_init_ctrl(h, P, L, &s_init);
+  __syncthreads();
+  if (!P.fixed)
+    for (int i = threadIdx.x; i < kPubWords; i += kThreads)
+      h->pub[i] = reinterpret_cast<const uint32_t*>(&s_init)[i];
+}
+
+__device__ void layer_init_ctrl(Header* h, const Plan& P, int L, SState* s0) {
+  const Frame fl = h->frame;
   Ctrl* c = &h->ctrl;
   c->layer = L;
   c->m = P.m[L];
@@ -557,7 +575,7 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
   c->evals = 0;
   c->accepted = 0;
   c->lo = 0.0f;
-  c->hi = h->frame.hi0;
+  c->hi = fl.hi0;
   c->ncand = 0;
   c->trim = 0;
   c->need = 0;
@@ -569,12 +587,8 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
   c->win = 0;
   h->info.m[L] = static_cast<int32_t>(P.m[L]);
   h->info.layers = L + 1;
-  for (int b = 0; b < 2; ++b)
-    for (int k = 0; k < kMaxCand; ++k)
-      for (int g = 0; g < kGroups; ++g) h->sacc[b][k][g][0] = 0;
   h->sq_ticket[0] = 0;
   h->sq_done[0] = 0;
-  for (int g = 0; g < kGroups; ++g) h->sq_dgrp[g][0] = 0;
   h->sq_gen[0] = 0;
   h->sq_fin[0] = 0;
   h->sq_err[0] = 0;
@@ -585,14 +599,12 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
       c->v_final[ax] = P.fixed_v[ax];
       c->inv_final[ax] = 1.0f / P.fixed_v[ax];
     }
-    set_select_grid(c, P, h->frame);
+    set_select_grid(c, P, fl);
   } else {
-    // the first pass's candidates, planned in LDS and published for the search kernel
+    // the first pass's candidates, planned in LDS (published by layer_init)
     c->done = 0;
-    __shared__ SState s_init;
-    SState* s0 = &s_init;
     s0->lo = 0.0f;
-    s0->hi = h->frame.hi0;
+    s0->hi = fl.hi0;
     s0->c_hi = 0;
     s0->c_lo = 0;
     s0->evals = 0;
@@ -604,8 +616,7 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
     s0->prev_hashed = 0;
     s0->s_final = 0.0f;
     s0->c_final = 0;
-    plan_search(s0, P, h->frame, c->m, c->upper);
-    for (int i = 0; i < kPubWords; ++i) h->pub[i] = reinterpret_cast<const uint32_t*>(s0)[i];
+    plan_search(s0, P, fl, P.m[L], P.upper[L]);
   }
 }
 
@@ -746,7 +757,7 @@ __device__ int frame_from_partials(const Ws& w, const Plan& P, Frame* fr, int id
     int best = 0;
     float bv = -1.0f;
     for (int a = 0; a < 3; ++a) {
-      const float q = ext[a] / static_cast<float>(1 << bb[a]);
+      const float q = ldexpf(ext[a], -bb[a]);  // (exact: a power-of-two scaling)
       if (q > bv) {
         bv = q;
         best = a;
@@ -779,22 +790,47 @@ __device__ void publish_frame(const Ws& w, const Frame& fr, int block) {
   }
 }
 
-__device__ __forceinline__ uint32_t cell_code(float rx, float ry, float rz, const Frame& fr) {
-  const float r[3] = {rx, ry, rz};
-  uint32_t c[3];
-#pragma unroll
+// The cell numbering of a frame, in registers: per axis the scale, the top cell, the
+// bit count and the 4-bit positions of its bits in the cell number (packed), so that
+// numbering a point touches no memory.
+struct CellCoder {
+  float scale[3];
+  uint32_t lim[3];
+  int bb[3];
+  uint64_t pos[3];
+};
+
+__device__ __forceinline__ CellCoder make_coder(const Frame& fr) {
+  CellCoder k;
   for (int a = 0; a < 3; ++a) {
-    const float q = r[a] * fr.bscale[a];
-    const uint32_t lim = (1u << fr.bbits[a]) - 1u;
-    c[a] = q >= static_cast<float>(lim) ? lim : static_cast<uint32_t>(q);
+    k.scale[a] = fr.bscale[a];
+    k.bb[a] = fr.bbits[a];
+    k.lim[a] = (1u << k.bb[a]) - 1u;
+    k.pos[a] = 0ull;
   }
-  uint32_t code = 0;
-  int pos = 0;
+  uint32_t p = 0;
   for (int j = 0; j < kBinBits; ++j)
     for (int a = 0; a < 3; ++a)
-      if (j < fr.bbits[a]) code |= ((c[a] >> j) & 1u) << pos++;
+      if (j < k.bb[a]) k.pos[a] |= static_cast<uint64_t>(p++) << (4 * j);
+  return k;
+}
+
+// The cell number of offset (rx, ry, rz): per axis the cell index floor(r * scale),
+// clamped to the top cell, its bits interleaved into the number (Morton order).
+__device__ __forceinline__ uint32_t cell_code_k(float rx, float ry, float rz, const CellCoder& k) {
+  const float r[3] = {rx, ry, rz};
+  uint32_t code = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float q = r[a] * k.scale[a];
+    const uint32_t c = q >= static_cast<float>(k.lim[a]) ? k.lim[a] : static_cast<uint32_t>(q);
+#pragma unroll
+    for (int j = 0; j < kBinBits; ++j)
+      if (j < k.bb[a]) code |= ((c >> j) & 1u) << ((k.pos[a] >> (4 * j)) & 15u);
+  }
   return code;
 }
+
 
 template <class Src>
 __global__ void __launch_bounds__(kThreads) k_identity(Src src) {
@@ -846,6 +882,8 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
   const int64_t beg = bx * chunk, end = min(w.n, beg + chunk);
   // 16 points per thread per round, all loads in flight together
   constexpr int kBP = 16;
+  const CellCoder kc = make_coder(fr);
+  const float m0 = fr.mn[0], m1 = fr.mn[1], m2 = fr.mn[2];
   for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
     float px[kBP], py[kBP], pz[kBP];
 #pragma unroll
@@ -860,7 +898,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
       const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
-      if (i < end) atomicAdd(&hist[cell_code(px[k] - fr.mn[0], py[k] - fr.mn[1], pz[k] - fr.mn[2], fr)], 1u);
+      if (i < end) atomicAdd(&hist[cell_code_k(px[k] - m0, py[k] - m1, pz[k] - m2, kc)], 1u);
     }
   }
   __syncthreads();
@@ -976,8 +1014,9 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Src src) {
     c->pend_nc = 0;
     c->pend_set = 0;
     c->pend_hashed = 0;
-    layer_init(w.h, P, 0);
   }
+  __syncthreads();
+  layer_init(w.h, P, 0);
 }
 
 template <class Src>
@@ -1001,6 +1040,8 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
   const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
   const int64_t beg = bx * chunk, end = min(w.n, beg + chunk);
   constexpr int kBP = 16;
+  const CellCoder kc = make_coder(fr);
+  const float m0 = fr.mn[0], m1 = fr.mn[1], m2 = fr.mn[2];
   for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
     float px[kBP], py[kBP], pz[kBP];
 #pragma unroll
@@ -1016,10 +1057,10 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
     for (int k = 0; k < kBP; ++k) {
       const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
       if (i >= end) continue;
-      const float rx = px[k] - fr.mn[0];
-      const float ry = py[k] - fr.mn[1];
-      const float rz = pz[k] - fr.mn[2];
-      const uint32_t pos = atomicAdd(&off[cell_code(rx, ry, rz, fr)], 1u);
+      const float rx = px[k] - m0;
+      const float ry = py[k] - m1;
+      const float rz = pz[k] - m2;
+      const uint32_t pos = atomicAdd(&off[cell_code_k(rx, ry, rz, kc)], 1u);
       if (pos < w.n) {
         const int64_t S = slot_of(pos);
         w.pts[S] = make_float4(rx, ry, rz, __int_as_float(static_cast<int32_t>(i)));
@@ -1456,7 +1497,10 @@ __device__ __forceinline__ int run_ticket(const Ws& w, const Plan& P, SearchShar
   }
   __syncthreads();
   Ctrl* c = &h->ctrl;
-  if (threadIdx.x == 0) search_step(&st, S.cnt, P, h->frame, c->m, c->upper);
+  if (threadIdx.x == 0) {
+    const Frame fl = h->frame;  // one round trip, then the step's arithmetic waits on nothing
+    search_step(&st, S.cnt, P, fl, c->m, c->upper);
+  }
   __syncthreads();
   if (st.done) {
     if (threadIdx.x == 0) {
@@ -2338,7 +2382,7 @@ __global__ void __launch_bounds__(kThreads) k_pad(Src src, int Lc) {
   }
   if (!arrive_last(h, bx, gx)) return;
   if (need > 0) scan_reset(w, h, gx);
-  if (threadIdx.x == 0 && L + 1 < P.nlayers) layer_init(h, P, L + 1);
+  if (L + 1 < P.nlayers) layer_init(h, P, L + 1);
 }
 
 // Ascending output: every picked point's index, in index order.
