@@ -2335,12 +2335,13 @@ __device__ void scan_reset(const Ws& w, Header* h, int nb) {
 }
 
 // Pad (when the layer found fewer voxels than m): mark the lowest-index unsampled
-// points; then start the next layer.
+// points; then start the next layer. Not for a cloud's last layer (k_out pads it).
 template <class Src>
 __global__ void __launch_bounds__(kThreads) k_pad(Src src, int Lc) {
   int bx, gx;
   const Cloud& cd = cloud_of(src, kKScan, bx, gx);
   if (!layer_due(cd, Lc)) return;
+  if (Lc + 1 >= cd.P.nlayers) return;  // the last layer's pad is part of the output scan
   const Ws& w = cd.w;
   const Plan& P = cd.P;
   Header* h = w.h;
@@ -2400,32 +2401,47 @@ __global__ void __launch_bounds__(kThreads) k_out(Src src) {
     return;
   }
   __shared__ uint32_t s_tmp[kThreads / 64];
+  // the last layer's pad is done here, in the same scan: with zb unsampled points before
+  // point i, a sampled point goes to (i - zb) + min(zb, need) and an unsampled one is
+  // padded (to position i) while zb < need
+  const uint32_t need = h->ctrl.need;
   const int lb = scan_ticket(h);
   const int64_t base = lb * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
   uint8_t t[kScanPer];
-  uint32_t cnt = 0;
+  uint32_t cz = 0;
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
-    t[k] = base + k < w.n ? w.tag_o[base + k] : 0;
-    cnt += (t[k] != 0);
+    t[k] = base + k < w.n ? w.tag_o[base + k] : 1;
+    cz += (t[k] == 0);
   }
   uint32_t ex;
-  const uint32_t tot = block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
+  const uint32_t tot = block_exclusive_scan<kThreads>(cz, &ex, s_tmp);
   const uint32_t before = scan_prefix(w, tot, lb);
   if (before != ~0u) {
-    uint32_t r = before + ex;
+    uint32_t zb = before + ex;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
+      const int64_t i = base + k;
+      if (i >= w.n) continue;
+      int64_t r = -1;
+      bool padded = false;
       if (t[k]) {
-        if (r < M) {
-          idx[r] = static_cast<int32_t>(base + k);
-          if (w.xyz_out) {
-            // centre / mean modes: what stands for the point; else the point itself
-            const float* src = (w.pmode ? w.pt_out : w.xyz) + 3 * (base + k);
-            for (int a = 0; a < 3; ++a) w.xyz_out[3 * r + a] = src[a];
-          }
+        r = (i - zb) + (zb < need ? zb : need);
+      } else {
+        if (zb < need) {
+          r = i;
+          padded = true;
         }
-        ++r;
+        ++zb;
+      }
+      if (r >= 0 && r < M) {
+        idx[r] = static_cast<int32_t>(i);
+        if (w.xyz_out) {
+          // centre / mean modes: what stands for the point; else (and for a padded
+          // point) the point itself
+          const float* src = (w.pmode && !padded ? w.pt_out : w.xyz) + 3 * i;
+          for (int a = 0; a < 3; ++a) w.xyz_out[3 * r + a] = src[a];
+        }
       }
     }
   } else if (threadIdx.x == 0) {
@@ -3049,7 +3065,7 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
     for (int r = 0; r < P.rounds[l]; ++r)
       HAV_LAUNCH(k_trim_hist<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l, r);
     HAV_LAUNCH(k_mark<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l);
-    HAV_LAUNCH(k_pad<One>, dim3(w.nscan), dim3(kThreads), 0, st, one, l);
+    if (l + 1 < P.nlayers) HAV_LAUNCH(k_pad<One>, dim3(w.nscan), dim3(kThreads), 0, st, one, l);
   }
   HAV_LAUNCH(k_out<One>, dim3(w.nscan), dim3(kThreads), 0, st, one);
   return HAV_OK;
@@ -3185,7 +3201,7 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
     for (int r = 0; r < max_rounds; ++r)
       HAV_LAUNCH(k_trim_hist<Many>, dim3(T[kKTile]), dim3(kThreads), 0, st, many, l, r);
     HAV_LAUNCH(k_mark<Many>, dim3(T[kKTile]), dim3(kThreads), 0, st, many, l);
-    HAV_LAUNCH(k_pad<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many, l);
+    if (l + 1 < max_layers) HAV_LAUNCH(k_pad<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many, l);
   }
   HAV_LAUNCH(k_out<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many);
   return HAV_OK;
