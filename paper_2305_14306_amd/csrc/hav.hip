@@ -224,7 +224,7 @@ struct Ws {
   int32_t* scl;                  // claims [ntile_ws][kTile]
   int32_t* scn;                  // [ntile_ws]
   uint64_t* tie_p;               // [kGroups][tie_seg]
-  int32_t* tie_o;
+  int64_t* tie_o;                // (sorted slot << 32) | original index
   uint32_t* tcnt;                // scan tile counts [nscan_ws]
   float* pt_out;                 // points modes: what stands for each kept point [n_ws][3]
   unsigned long long* msum;      // mean mode: per voxel slot fixed-point sums [slots][3]
@@ -2071,7 +2071,6 @@ __device__ void settle_ties(const Ws& w, Header* h) {
   __shared__ uint64_t s_pfx, s_thr;
   __shared__ uint32_t s_rank, s_remain, s_nm;
   __shared__ uint64_t lp[kTieLds];
-  __shared__ int32_t lo[kTieLds];
   __shared__ uint64_t ls[kTieRank];
   // the groups' queue lengths, read and reset in parallel (one round trip)
   if (threadIdx.x < kGroups) {
@@ -2103,12 +2102,31 @@ __device__ void settle_ties(const Ws& w, Header* h) {
     while (j >= cnt_g[q + 1]) ++q;
     return static_cast<int64_t>(q) * w.tie_seg + (j - cnt_g[q]);
   };
+  // a staged bucket: a thread's members (at most kTP) loaded in one round trip, the
+  // priorities copied to LDS for the radix rounds, both kept in registers for the marking
+  constexpr int kTP = kTieLds / kThreads;
+  static_assert(kTieLds % kThreads == 0, "staged members per thread");
+  uint64_t rp[kTP];
+  int64_t ro[kTP];
   if (staged) {
-    for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
-      const int64_t at = locate(j);
-      lp[j] = ld_agent(&w.tie_p[at]);
-      lo[j] = ld_agent(&w.tie_o[at]);
+    int64_t at[kTP];
+#pragma unroll
+    for (int q = 0; q < kTP; ++q) {
+      const uint32_t j = threadIdx.x + q * kThreads;
+      at[q] = j < total ? locate(j) : -1;
     }
+#pragma unroll
+    for (int q = 0; q < kTP; ++q) {
+      rp[q] = ~0ull;
+      ro[q] = -1;
+      if (at[q] >= 0) {
+        rp[q] = ld_agent(&w.tie_p[at[q]]);
+        ro[q] = ld_agent(&w.tie_o[at[q]]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kTP; ++q)
+      if (at[q] >= 0) lp[threadIdx.x + q * kThreads] = rp[q];
     __syncthreads();
   }
   auto prio = [&](uint32_t j) -> uint64_t { return staged ? lp[j] : ld_agent(&w.tie_p[locate(j)]); };
@@ -2168,16 +2186,22 @@ __device__ void settle_ties(const Ws& w, Header* h) {
   __syncthreads();
   const uint64_t thr = s_thr;  // the rank-th smallest priority of the bucket
   const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
-  for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
-    int64_t at = 0;
-    if (!staged) at = locate(j);
-    const uint64_t p = staged ? lp[j] : ld_agent(&w.tie_p[at]);
-    if (p <= thr) {
-      const int32_t orig = staged ? lo[j] : ld_agent(&w.tie_o[at]);
-      if (orig >= 0 && orig < w.n) {
-        w.tag_o[orig] = lt;
-        w.tag_s[w.invp[orig]] = lt;
-      }
+  auto pick = [&](int64_t v) {
+    const int32_t orig = static_cast<int32_t>(v & 0xFFFFFFFFll);
+    const int64_t slot = v >> 32;
+    if (orig >= 0 && orig < w.n && slot >= 0 && slot < w.npad) {
+      w.tag_o[orig] = lt;
+      w.tag_s[slot] = lt;
+    }
+  };
+  if (staged) {
+#pragma unroll
+    for (int q = 0; q < kTP; ++q)
+      if (threadIdx.x + q * kThreads < total && rp[q] <= thr) pick(ro[q]);
+  } else {
+    for (uint32_t j = threadIdx.x; j < total; j += kThreads) {
+      const int64_t at = locate(j);
+      if (ld_agent(&w.tie_p[at]) <= thr) pick(ld_agent(&w.tie_o[at]));
     }
   }
 }
@@ -2259,20 +2283,23 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
     if (keep && orig[k] >= 0 && orig[k] < w.n) keepm |= 1u << k;
     if (tie) tiem |= 1u << k;
   }
+  // the bucket's members go to the group's queue (positions by a block scan and one
+  // atomic per block); the atomic and the sorted-slot loads of the kept points and of
+  // the bucket's members are in flight together
+  uint32_t ex;
+  const uint32_t tot = block_exclusive_scan<kThreads>(static_cast<uint32_t>(__popc(tiem)), &ex, s_tmp);
+  const uint32_t qb = (threadIdx.x == 0 && tot) ? atomicAdd(&h->tie_cur[g][0], tot) : 0u;
   int32_t ip[kMP];
 #pragma unroll
-  for (int k = 0; k < kMP; ++k) ip[k] = ((keepm >> k) & 1u) ? w.invp[orig[k]] : -1;
+  for (int k = 0; k < kMP; ++k)
+    ip[k] = (((keepm | tiem) >> k) & 1u) && orig[k] >= 0 && orig[k] < w.n ? w.invp[orig[k]] : -1;
+  if (threadIdx.x == 0) s_base = qb;
 #pragma unroll
   for (int k = 0; k < kMP; ++k) {
-    if (ip[k] < 0) continue;
+    if (!((keepm >> k) & 1u) || ip[k] < 0) continue;
     w.tag_o[orig[k]] = lt;
     w.tag_s[ip[k]] = lt;
   }
-  // the bucket's members go to the group's queue (positions by a block scan and one
-  // atomic per block)
-  uint32_t ex;
-  const uint32_t tot = block_exclusive_scan<kThreads>(static_cast<uint32_t>(__popc(tiem)), &ex, s_tmp);
-  if (threadIdx.x == 0) s_base = tot ? atomicAdd(&h->tie_cur[g][0], tot) : 0u;
   __syncthreads();
   uint32_t pos = s_base + ex;
 #pragma unroll
@@ -2280,7 +2307,9 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
     if (!((tiem >> k) & 1u)) continue;
     if (pos < w.tie_seg) {
       st_agent(&w.tie_p[g * w.tie_seg + pos], pr[k]);
-      st_agent(&w.tie_o[g * w.tie_seg + pos], orig[k]);
+      st_agent(&w.tie_o[g * w.tie_seg + pos],
+               static_cast<int64_t>((static_cast<uint64_t>(static_cast<uint32_t>(ip[k])) << 32) |
+                                    static_cast<uint32_t>(orig[k])));
     }
     ++pos;
   }
@@ -2569,7 +2598,7 @@ __host__ __device__ inline Layout make_layout(int64_t n, int depth, int pmode = 
   L.scl = o;    o = align_up(o + static_cast<size_t>(L.ntile_ws) * kTile * 4);
   L.scn = o;    o = align_up(o + static_cast<size_t>(L.ntile_ws) * 4);
   L.tie_p = o;  o = align_up(o + static_cast<size_t>(kGroups) * L.tie_seg * 8);
-  L.tie_o = o;  o = align_up(o + static_cast<size_t>(kGroups) * L.tie_seg * 4);
+  L.tie_o = o;  o = align_up(o + static_cast<size_t>(kGroups) * L.tie_seg * 8);
   L.tcnt = o;   o = align_up(o + static_cast<size_t>(L.nscan_ws) * 4);
   const size_t slots = pmode == 2 ? static_cast<size_t>(L.cap_ws) * kSelDense : 0;
   L.pto = o;    o = align_up(o + (pmode ? N * 12 : 0));
@@ -2606,7 +2635,7 @@ __host__ __device__ inline Ws make_ws(char* base, const Layout& L, int64_t n) {
   w.scl = reinterpret_cast<int32_t*>(base + L.scl);
   w.scn = reinterpret_cast<int32_t*>(base + L.scn);
   w.tie_p = reinterpret_cast<uint64_t*>(base + L.tie_p);
-  w.tie_o = reinterpret_cast<int32_t*>(base + L.tie_o);
+  w.tie_o = reinterpret_cast<int64_t*>(base + L.tie_o);
   w.tcnt = reinterpret_cast<uint32_t*>(base + L.tcnt);
   w.pmode = L.pmode;
   w.pt_out = L.pmode ? reinterpret_cast<float*>(base + L.pto) : nullptr;
