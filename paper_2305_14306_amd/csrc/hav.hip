@@ -72,7 +72,6 @@ constexpr int kTile = 2048;                     // points per search/select tile
 constexpr int kPerThread = kTile / kThreads;    // 8
 constexpr int kLdsCap = 4096;                   // select: LDS voxel map entries (2x tile)
 constexpr int kBrickCap = 1024;                 // search: LDS brick table per candidate
-constexpr int kBrickProbe = 64;                 // LDS probes before a run goes to the global table
 constexpr int kMaxCand = 7;                     // candidate scales per search pass
 constexpr int kMaxDepth = kMaxCand;
 constexpr int kDefaultDepth = 4;
@@ -1121,23 +1120,6 @@ __device__ __forceinline__ bool layer_due(const Cloud& cd, int L) {
   return !cd.P.identity && L < cd.P.nlayers && cd.w.h->frame.status == HAV_OK;
 }
 
-// LDS insert of one (key, bits) run into a candidate's hash table, at most
-// kBrickProbe probes. Returns false if the table was too crowded.
-template <int kCap>
-__device__ __forceinline__ bool lds_try_or(uint64_t* tk, uint64_t* tv, uint64_t key, uint64_t bits) {
-  uint32_t hs = table_hash(key) & (kCap - 1);
-  for (int pr = 0; pr < kBrickProbe; ++pr) {
-    uint64_t kk = tk[hs];
-    if (kk == kEmptyKey) kk = lds_cas(&tk[hs], kEmptyKey, key);
-    if (kk == kEmptyKey || kk == key) {
-      __hip_atomic_fetch_or(&tv[hs], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      return true;
-    }
-    hs = (hs + 1) & (kCap - 1);
-  }
-  return false;
-}
-
 constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr float kSpecMult = 16.0f;
 
@@ -1303,37 +1285,84 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
         __hip_atomic_fetch_or(&tv[cur], cb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       continue;
     }
-    // sparse tile: LDS hash on the brick id, overflow straight to the global table
+    // sparse tile: the brick ids go through three direct-mapped LDS levels (keys in
+    // lkeys, bits in lvals). A run stores its key in its level-1 slot and, after a
+    // barrier, ORs its bits in if the slot holds its key (the runs of one key all
+    // do); the others try a level-2 slot (other bits of the hash) the same way, then
+    // level 3, and the few left go straight to the global table. A key sits in at most
+    // one slot, and no run probes, so there are no chains of LDS round trips. The
+    // thread's runs are formed first (run q ends before point q).
     const int dense = st.cand_dense[ci];
     const uint64_t nbx = st.cand_nb[ci][0], nby = st.cand_nb[ci][1];
     uint64_t* tk = lkeys + ci * kBrickCap;
-    uint64_t cur = kEmptyKey, cb = 0ull;
-    for (int k = 0; k <= kPerThread; ++k) {
-      uint64_t key = kEmptyKey, bit = 0ull;
-      if (k < kPerThread) {
-        if (!(live & (1u << k))) continue;
-        const uint32_t gx = axis_coord(pt[k].x, ix);
-        const uint32_t gy = axis_coord(pt[k].y, iy);
-        const uint32_t gz = axis_coord(pt[k].z, iz);
-        key = dense ? (static_cast<uint64_t>(gx >> kBrickShift) +
-                       nbx * (static_cast<uint64_t>(gy >> kBrickShift) + nby * (gz >> kBrickShift)))
-                    : brick_key(gx, gy, gz);
-        bit = brick_bit(gx, gy, gz);
-        if (key == cur) {
-          cb |= bit;
-          continue;
+    uint64_t rk[kPerThread + 1], rb[kPerThread + 1];
+    uint32_t pend = 0;
+    {
+      uint64_t cur = kEmptyKey, cb = 0ull;
+#pragma unroll
+      for (int k = 0; k <= kPerThread; ++k) {
+        uint64_t key = kEmptyKey, bit = 0ull;
+        if (k < kPerThread) {
+          if (!(live & (1u << k))) continue;
+          const uint32_t gx = axis_coord(pt[k].x, ix);
+          const uint32_t gy = axis_coord(pt[k].y, iy);
+          const uint32_t gz = axis_coord(pt[k].z, iz);
+          key = dense ? (static_cast<uint64_t>(gx >> kBrickShift) +
+                         nbx * (static_cast<uint64_t>(gy >> kBrickShift) + nby * (gz >> kBrickShift)))
+                      : brick_key(gx, gy, gz);
+          bit = brick_bit(gx, gy, gz);
+          if (key == cur) {
+            cb |= bit;
+            continue;
+          }
+        }
+        if (cur != kEmptyKey) {
+          rk[k] = cur;
+          rb[k] = cb;
+          pend |= 1u << k;
+        }
+        cur = key;
+        cb = bit;
+      }
+    }
+    // levels: slots [0, 512) on hash bits 0-8, [512, 768) on bits 12-19, [768, 1024)
+    // on bits 22-29
+    static_assert(kBrickCap == 1024, "direct-mapped levels of the LDS brick table");
+    uint32_t hh[kPerThread + 1];
+#pragma unroll
+    for (int q = 0; q <= kPerThread; ++q) hh[q] = ((pend >> q) & 1u) ? table_hash(rk[q]) : 0u;
+#pragma unroll
+    for (int lv = 0; lv < 3; ++lv) {
+      const uint32_t base = lv == 0 ? 0u : (lv == 1 ? 512u : 768u);
+      const uint32_t mask = lv == 0 ? 511u : 255u;
+      const int shift = lv == 0 ? 0 : (lv == 1 ? 12 : 22);
+#pragma unroll
+      for (int q = 0; q <= kPerThread; ++q)
+        if ((pend >> q) & 1u)
+          __hip_atomic_store(&tk[base + ((hh[q] >> shift) & mask)], rk[q], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q <= kPerThread; ++q) {
+        const uint32_t e = base + ((hh[q] >> shift) & mask);
+        if (((pend >> q) & 1u) &&
+            __hip_atomic_load(&tk[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == rk[q]) {
+          __hip_atomic_fetch_or(&tv[e], rb[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          pend &= ~(1u << q);
         }
       }
-      if (cur != kEmptyKey && !lds_try_or<kBrickCap>(tk, tv, cur, cb)) {
-        const uint32_t f =
-            dense ? dense_or(ctab_masks(w, set, ci), static_cast<uint32_t>(cur), cb,
-                             claims(w, set, ci, tile), &sh.ncl[ci])
-                  : global_or(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, cur, cb,
-                                claims(w, set, ci, tile), &sh.ncl[ci]);
-        if (f) atomicAdd(&sh.fresh[ci], f);
+    }
+    if (pend) {
+      uint32_t f = 0;
+#pragma unroll
+      for (int q = 0; q <= kPerThread; ++q) {
+        if (!((pend >> q) & 1u)) continue;
+        f += dense ? dense_or(ctab_masks(w, set, ci), static_cast<uint32_t>(rk[q]), rb[q],
+                              claims(w, set, ci, tile), &sh.ncl[ci])
+                   : global_or(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, rk[q], rb[q],
+                               claims(w, set, ci, tile), &sh.ncl[ci]);
       }
-      cur = key;
-      cb = bit;
+      if (f) atomicAdd(&sh.fresh[ci], f);
     }
   }
   __syncthreads();
