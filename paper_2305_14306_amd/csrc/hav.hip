@@ -284,8 +284,9 @@ struct Cloud {
   Plan P;
 };
 
-// Grid kinds: how many blocks a kernel gives a cloud of n points.
-enum Kind : int { kKBBox = 0, kKBin, kKBScan, kKTile, kKOne, kKScan, kKinds };
+// Grid kinds: how many blocks a kernel gives a cloud of n points (kKScat: the
+// binning blocks and one more, which starts layer 1 while the others scatter).
+enum Kind : int { kKBBox = 0, kKBin, kKBScan, kKTile, kKOne, kKScan, kKScat, kKinds };
 
 __host__ __device__ inline int64_t blocks_of(int kind, int64_t n) {
   switch (kind) {
@@ -294,6 +295,7 @@ __host__ __device__ inline int64_t blocks_of(int kind, int64_t n) {
     case kKBScan: return kBinChunks;
     case kKTile: return (n + kTile - 1) / kTile;
     case kKOne: return 1;
+    case kKScat: return blocks_of(kKBin, n) + 1;
     default: return (n + kScanTile - 1) / kScanTile;
   }
 }
@@ -964,6 +966,15 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Src src) {
   if (threadIdx.x < kBinChunk) w.binpre[bx * kBinChunk + threadIdx.x] = ex;
   if (threadIdx.x == 0) atomicExch(&w.bsum[bx], chunk_total);
   if (!arrive_last(w.h, bx, gx)) return;
+  const uint32_t y = threadIdx.x < static_cast<int>(gx) ? peek(&w.bsum[threadIdx.x]) : 0u;
+  uint32_t ey;
+  block_exclusive_scan<kThreads>(y, &ey, s_tmp);
+  if (threadIdx.x < static_cast<int>(gx)) w.bsum[threadIdx.x] = ey;
+}
+
+// The search's prior from the binning's occupancy counts, the controller's reset and
+// the start of layer 1 (one block; the frame is complete once the scan has run).
+__device__ void start_search(const Ws& w, const Plan& P) {
   __shared__ uint32_t s_occ[2];
   if (threadIdx.x < 2) s_occ[threadIdx.x] = 0u;
   __syncthreads();
@@ -1003,10 +1014,6 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Src src) {
       f->prior_ok = isfinite(f->prior_s) && f->prior_s > 0.0f ? 1 : 0;
     }
   }
-  const uint32_t y = threadIdx.x < static_cast<int>(gx) ? peek(&w.bsum[threadIdx.x]) : 0u;
-  uint32_t ey;
-  block_exclusive_scan<kThreads>(y, &ey, s_tmp);
-  if (threadIdx.x < static_cast<int>(gx)) w.bsum[threadIdx.x] = ey;
   if (threadIdx.x == 0) {
     Ctrl* c = &w.h->ctrl;
     c->set = 0;
@@ -1021,11 +1028,15 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Src src) {
 template <class Src>
 __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
   int bx, gx;
-  const Cloud& cd = cloud_of(src, kKBin, bx, gx);
+  const Cloud& cd = cloud_of(src, kKScat, bx, gx);
   const Ws& w = cd.w;
   if (cd.P.identity) return;
   const float* __restrict__ xyz = w.xyz;
   if (w.h->frame.status != HAV_OK) return;
+  if (bx == gx - 1) {  // the extra block
+    start_search(w, cd.P);
+    return;
+  }
   __shared__ Frame fr;
   __shared__ uint32_t off[kBins];
   if (threadIdx.x == 0) fr = w.h->frame;
@@ -3112,7 +3123,7 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
   }
   HAV_LAUNCH(k_bin_count<One>, dim3(w.nbb), dim3(kThreads), 0, st, one);
   HAV_LAUNCH(k_bin_scan<One>, dim3(kBinChunks), dim3(kThreads), 0, st, one);
-  HAV_LAUNCH(k_bin_scatter<One>, dim3(w.nbb), dim3(kThreads), 0, st, one);
+  HAV_LAUNCH(k_bin_scatter<One>, dim3(w.nbb + 1), dim3(kThreads), 0, st, one);
   const int sgrid = search_grid(w.ntile, P.depth, false, p->search_blocks);
   const size_t eval_lds = 2 * static_cast<size_t>(P.depth) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
@@ -3246,7 +3257,7 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
   if (!any_work) return HAV_OK;
   HAV_LAUNCH(k_bin_count<Many>, dim3(T[kKBin]), dim3(kThreads), 0, st, many);
   HAV_LAUNCH(k_bin_scan<Many>, dim3(T[kKBScan]), dim3(kThreads), 0, st, many);
-  HAV_LAUNCH(k_bin_scatter<Many>, dim3(T[kKBin]), dim3(kThreads), 0, st, many);
+  HAV_LAUNCH(k_bin_scatter<Many>, dim3(T[kKScat]), dim3(kThreads), 0, st, many);
   const int sgrid = search_grid(T[kKTile], q.depth, true, p->search_blocks);
   const size_t eval_lds = 2 * static_cast<size_t>(q.depth) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
