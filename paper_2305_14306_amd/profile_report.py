@@ -3,8 +3,10 @@
     python -m paper_2305_14306_amd.profile_report stats RESULTS_DB OUT.txt --command "..."
     python -m paper_2305_14306_amd.profile_report pmc FETCH_DB WRITE_DB OUT.txt --kernel k_search \
         --command-fetch "..." --command-write "..."
+    python -m paper_2305_14306_amd.profile_report counters RESULTS_DB OUT.txt --command "..."
 
 `stats` lists every kernel of a --kernel-trace --stats run (calls, total, average).
+`counters` lists, per kernel, the average per dispatch of every counter of one --pmc run.
 `pmc` turns two counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) into HBM
 bytes per launch of one kernel. Each counter is scaled by the factor that makes it read
 the known traffic of a plain elementwise kernel of the same runs (bench.py
@@ -117,6 +119,24 @@ def write_pmc(args) -> None:
         fh.write("\n".join(lines) + "\n")
 
 
+def write_counters(args) -> None:
+    con = sqlite3.connect(args.db)
+    names = sorted({r[0] for r in con.execute("select distinct counter_name from counters_collection")})
+    per = {c: counter_per_dispatch(args.db, c) for c in names}
+    kernels = sorted({k for c in names for k in per[c]})
+    lines = [f"# rocprofv3 counters, average per dispatch", f"# command: {args.command}",
+             f"# {'kernel':30s} {'dispatches':>10s} " + " ".join(f"{c:>32s}" for c in names)]
+    for k in kernels:
+        n = len(per[names[0]].get(k, []))
+        vals = []
+        for c in names:
+            v = per[c].get(k, [0.0])
+            vals.append(sum(v) / len(v))
+        lines.append(f"{k:32s} {n:10d} " + " ".join(f"{v:32.0f}" for v in vals))
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="what", required=True)
@@ -131,9 +151,15 @@ def main(argv=None) -> int:
     p.add_argument("--kernel", default="k_search")
     p.add_argument("--command-fetch", required=True)
     p.add_argument("--command-write", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("db")
+    c.add_argument("out")
+    c.add_argument("--command", required=True)
     args = ap.parse_args(argv)
     if args.what == "stats":
         write_stats(args)
+    elif args.what == "counters":
+        write_counters(args)
     else:
         write_pmc(args)
     return 0
