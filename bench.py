@@ -122,6 +122,36 @@ def batch_leg(torch, hav, synth, steps: int) -> dict:
             "speedup": round(t_s / t_b, 3), "batched_Mpoints_per_s": round(total_n / t_b / 1e3, 1)}
 
 
+def sizes_leg(torch, hav, synth, reps: int) -> dict:
+    """The bench stage (scene cloud -> N/4, default parameters) at 2^18 .. 2^24 input
+    points: how the per-call time and the throughput grow with the cloud on one GPU
+    (median of `reps` calls after two untimed ones, CUDA events on the current stream)."""
+    import numpy as np
+
+    rows = {}
+    for e in (18, 20, 22, 24):
+        N = 1 << e
+        x = torch.from_numpy(synth.scene_planes_blobs(N, seed=3)).cuda()
+        M = N // 4
+        s = hav.Sampler()
+        out = torch.empty(M, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            s.sample(x, M, out=out)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.sample(x, M, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        rows[f"2^{e}"] = {"ms": round(ms, 4), "Mpoints_per_s": round(N / ms / 1e3, 1)}
+        print(f"bench: sizes 2^{e} {rows[f'2^{e}']}", file=sys.stderr, flush=True)
+        del s, x, out
+    return {"workload": "scene cloud of 2^18 .. 2^24 points -> N/4 (default parameters)", "points": rows}
+
+
 def fig7_leg(torch, hav, synth, reps: int) -> dict:
     """The latency study of Sec. 4.2 (Fig. 7): LiDAR-shaped clouds of 2^14, 2^16 and
     2^18 points, each downsampled in 3 steps of ratio 2 by HAVSampler, farthest point
@@ -353,6 +383,8 @@ def main() -> int:
                     help="skip the selection-strategy comparison (Table 6 of the paper)")
     ap.add_argument("--no-fig7", action="store_true",
                     help="skip the latency comparison with FPS and RPS (Fig. 7 of the paper)")
+    ap.add_argument("--no-sizes", action="store_true",
+                    help="skip the same stage at 2^18 .. 2^24 input points")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter "
@@ -450,6 +482,8 @@ def main() -> int:
         result["serve"] = serve_leg(torch, hav, synth, args.serve_requests,
                                     min(500, args.serve_requests // 10))
         print(f"bench: serve {result['serve']}", file=sys.stderr, flush=True)
+    if not args.no_sizes:
+        result["sizes"] = sizes_leg(torch, hav, synth, 10)
     if not args.no_fig7:
         result["fig7"] = fig7_leg(torch, hav, synth, 3)
     if not args.no_variants:

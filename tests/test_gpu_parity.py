@@ -183,6 +183,13 @@ def test_scene_single_stage_1m(gpu, orc):
     _check(gpu, orc, x, x.shape[0] // 4, label="scene 1M->262144")
 
 
+def test_scene_single_stage_8m_ragged(gpu, orc):
+    # eight times the bench cloud and a ragged tail: the binning blocks take several
+    # rounds of points each, every search block several tiles per pass
+    x = synth.scene_planes_blobs((1 << 23) + 4321, seed=11)
+    _check(gpu, orc, x, x.shape[0] // 4, label="scene 8M+4321 -> N/4")
+
+
 # ------------------------------------------------------------------ workspace contract, tuning
 
 def test_uninitialised_workspace_is_reported(gpu):
