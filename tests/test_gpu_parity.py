@@ -107,14 +107,14 @@ def test_degenerate(gpu, orc):
                                 dict(aspect=(1.0, 1.0, 0.5)), dict(aspect=(3.0, 0.75, 0.125)),
                                 dict(fixed_voxel=0.34), dict(fixed_voxel=(0.34, 0.34, 0.30)),
                                 dict(layers=1, fixed_voxel=2.0)])
-def test_config1_params(gpu, orc, kw):
+def test_kitti_like_params(gpu, orc, kw):
     x = synth.uniform_box_with_ground()
-    _check(gpu, orc, x, 4096, gpu.params(**kw), f"cfg1 {kw}")
+    _check(gpu, orc, x, 4096, gpu.params(**kw), f"kitti-like 16384 {kw}")
 
 
 @pytest.mark.parametrize("M", [1, 100, 1000, 4096, 8191, 16383, 16384])
-def test_config1_sizes(gpu, orc, M):
-    _check(gpu, orc, synth.uniform_box_with_ground(), M, label="cfg1")
+def test_kitti_like_sizes(gpu, orc, M):
+    _check(gpu, orc, synth.uniform_box_with_ground(), M, label="kitti-like 16384")
 
 
 # ------------------------------------------------------------------ device-side errors
