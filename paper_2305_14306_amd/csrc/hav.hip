@@ -2936,7 +2936,7 @@ __global__ void __launch_bounds__(kThreads) k_search_prep(Many src, int L) {
 // clouds (starting from a rotating position), one whose current pass still has tiles
 // to hand out, takes a ticket there and runs it. Waits are only for tiles that running
 // blocks hold, so any grid size makes progress.
-__global__ void __launch_bounds__(kThreads) k_search_many(Many src, int L) {
+__global__ void __launch_bounds__(kThreads) k_search_many(Many src) {
   BatchDev* bd = src.bd;
   const int nact = bd->nact;
   if (nact == 0) return;
@@ -3264,7 +3264,7 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
   for (int l = 0; l < max_layers; ++l) {
     if (any_search) {
       HAV_LAUNCH(k_search_prep, dim3(1), dim3(kThreads), 0, st, many, l);
-      HAV_LAUNCH(k_search_many, dim3(sgrid), dim3(kThreads), eval_lds, st, many, l);
+      HAV_LAUNCH(k_search_many, dim3(sgrid), dim3(kThreads), eval_lds, st, many);
     }
     HAV_LAUNCH(k_select<Many>, dim3(T[kKTile]), dim3(kThreads), sel_lds, st, many, l);
     for (int r = 0; r < max_rounds; ++r)
@@ -3445,7 +3445,8 @@ hav_status_t hav_sample_batch(const float* xyz_concat, const int64_t* offsets_ho
   int64_t mo = 0;
   for (int32_t i = 0; i < B; ++i) {
     specs[i] = CloudSpec{xyz_concat + 3 * offsets_host[i], idx_concat + mo,
-                         info_dev ? info_dev + i : nullptr, base + W.seg[i], N[i], M_host[i], N[i]};
+                         info_dev ? info_dev + i : nullptr, base + W.seg[i], N[i], M_host[i], N[i],
+                         nullptr};
     mo += M_host[i];
   }
   return run_batch(specs.data(), B, params, base, W.BL, static_cast<hipStream_t>(stream));

@@ -324,8 +324,8 @@ constexpr int kBallMaxK = 64;
 // is empty. count[j] = the number of points inside. Cells are at least the radius wide,
 // so the 27 cells around the centre's cell hold every candidate. Each thread keeps its
 // K smallest indices sorted in its own LDS row.
-__global__ void __launch_bounds__(kNnThreads) k_ball(NnWs w, const float* __restrict__ xyz,
-                                                    const float* __restrict__ ctr, int64_t Q, float r2,
+__global__ void __launch_bounds__(kNnThreads) k_ball(NnWs w, const float* __restrict__ ctr,
+                                                    int64_t Q, float r2,
                                                     int32_t K, int32_t* __restrict__ out,
                                                     int32_t* __restrict__ count) {
   const NnHdr& h = *w.h;
@@ -494,7 +494,7 @@ hav_status_t hav_ball_query(const float* xyz, int64_t N, const float* centres, i
   hipLaunchKernelGGL(k_nn_scan, dim3(static_cast<unsigned>(kNnCells / kNnScanTile)), dim3(kNnThreads), 0, st, w, N);
   hipLaunchKernelGGL(k_nn_scatter, dim3(gs), dim3(kNnThreads), 0, st, w, xyz, N);
   const unsigned gq = static_cast<unsigned>(std::min<int64_t>(65536, (Q + kNnThreads - 1) / kNnThreads));
-  hipLaunchKernelGGL(k_ball, dim3(gq), dim3(kNnThreads), 0, st, w, xyz, centres, Q, r2, K, idx, count);
+  hipLaunchKernelGGL(k_ball, dim3(gq), dim3(kNnThreads), 0, st, w, centres, Q, r2, K, idx, count);
   hipLaunchKernelGGL(k_nn_clear, dim3(1024), dim3(256), 0, st, w);
   return hipGetLastError() == hipSuccess ? HAV_OK : HAV_ERR_HIP;
 }
