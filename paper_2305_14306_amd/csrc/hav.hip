@@ -1389,8 +1389,8 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
   const int rep = tile & (kReps - 1);
   for (int c0 = 0; c0 < nc; c0 += kGrp) {
     uint32_t slot[4 * kGrp];
-    uint64_t bits[4 * kGrp];
-    uint32_t valid = 0, hot = 0;
+    uint64_t bits[4 * kGrp], hkey[4 * kGrp];
+    uint32_t valid = 0, hot = 0, hm = 0;
     uint32_t f[kGrp] = {};
 #pragma unroll
     for (int q = 0; q < 4 * kGrp; ++q) {
@@ -1425,15 +1425,51 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
         lkeys[e] = kEmptyKey;
         lvals[e] = 0ull;
       }
-      if (!dense) {  // hashed table: probe one entry at a time
-        f[q / 4] += global_or(ctab_keys(w, set, ci), ctab_masks(w, set, ci), w.cmask, key, b,
-                              claims(w, set, ci, tile), &sh.ncl[ci]);
+      if (!dense) {  // hashed table: the slot is found below
+        slot[q] = table_hash(key) & w.cmask;
+        hkey[q] = key;
+        bits[q] = b;
+        hm |= 1u << q;
         continue;
       }
       slot[q] = static_cast<uint32_t>(key);
       bits[q] = b;
       valid |= 1u << q;
       if (st.cand_hot[ci]) hot |= 1u << q;
+    }
+    // hashed tables: the entries probe in lockstep, one load round trip per probe step
+    // for all of them; an empty slot is claimed with a CAS (and recorded), and the
+    // entries then join the table updates below (tables hold at most half their slots
+    // in keys, so every probe ends)
+    const uint32_t hashed = hm;
+    while (hm) {
+      unsigned long long kk[4 * kGrp];
+#pragma unroll
+      for (int q = 0; q < 4 * kGrp; ++q)
+        kk[q] = ((hm >> q) & 1u) ? ld_agent(ctab_keys(w, set, c0 + q / 4) + slot[q]) : 0ull;
+#pragma unroll
+      for (int q = 0; q < 4 * kGrp; ++q) {
+        if (!((hm >> q) & 1u) || kk[q] != kEmptyKey) continue;
+        const unsigned long long prev =
+            atomicCAS(ctab_keys(w, set, c0 + q / 4) + slot[q], kEmptyKey, static_cast<unsigned long long>(hkey[q]));
+        if (prev == kEmptyKey) {
+          st_agent(claims(w, set, c0 + q / 4, tile) + atomicAdd(&sh.ncl[c0 + q / 4], 1),
+                   static_cast<int32_t>(slot[q]));
+          kk[q] = hkey[q];
+        } else {
+          kk[q] = prev;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4 * kGrp; ++q) {
+        if (!((hm >> q) & 1u)) continue;
+        if (kk[q] == hkey[q]) {
+          hm &= ~(1u << q);
+          valid |= 1u << q;
+        } else {
+          slot[q] = (slot[q] + 1) & w.cmask;
+        }
+      }
     }
     // hot words: the tile's replica first
     uint64_t old[4 * kGrp];
@@ -1463,7 +1499,7 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
     for (int q = 0; q < 4 * kGrp; ++q) {
       if (!((valid >> q) & 1u)) continue;
       f[q / 4] += static_cast<uint32_t>(__popcll(bits[q] & ~old[q]));
-      if (old[q] == 0ull)
+      if (old[q] == 0ull && !((hashed >> q) & 1u))  // (a hashed slot was recorded when claimed)
         st_agent(claims(w, set, c0 + q / 4, tile) + atomicAdd(&sh.ncl[c0 + q / 4], 1),
                  static_cast<int32_t>(slot[q]));
     }
@@ -1683,31 +1719,6 @@ __device__ __forceinline__ bool lds_try_min(uint64_t* tk, uint64_t* tv, uint64_t
   return false;  // unreachable: the map holds twice the tile's points
 }
 
-// Global selection-table update of voxel `key` (dense: slot index) with `val`.
-// Hashed selection-table update of voxel `key` (packed coordinate) with `val`; true
-// if this call claimed the voxel's slot (and recorded it).
-__device__ __forceinline__ bool select_hashed(const Ws& w, uint64_t key, uint64_t val,
-                                              int32_t* list, int* s_ncl) {
-  uint32_t sl = table_hash(key) & w.cmask;
-  while (true) {
-    const unsigned long long k = w.skeys[sl];
-    const unsigned long long cur = w.svals[sl];
-    if (k == key) {
-      if (val < cur) atomicMin(&w.svals[sl], static_cast<unsigned long long>(val));
-      return false;
-    }
-    if (k == kEmptyKey) {
-      const unsigned long long prev = atomicCAS(&w.skeys[sl], kEmptyKey, key);
-      if (prev == kEmptyKey || prev == key) {
-        if (prev == kEmptyKey) list[atomicAdd(s_ncl, 1)] = static_cast<int32_t>(sl);
-        atomicMin(&w.svals[sl], static_cast<unsigned long long>(val));
-        return prev == kEmptyKey;
-      }
-    }
-    sl = (sl + 1) & w.cmask;
-  }
-}
-
 // The digit whose bucket holds rank (0-based) in a 256-bin histogram, and the rank
 // inside that bucket: one bin per thread and a block scan. Every thread gets both.
 __device__ void find_digit(const uint32_t* hist, uint32_t rank, int* digit, uint32_t* rest) {
@@ -1904,9 +1915,40 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
     }
     if (!has) continue;
     if (!dense) {
+      // hashed table: the entries probe in lockstep (one load round trip per probe step
+      // for all of them); the CAS that fills an empty slot claims the voxel
+      uint32_t sl[kQ];
+      uint32_t pend = has;
 #pragma unroll
-      for (int j = 0; j < kQ; ++j)
-        if (((has >> j) & 1u) && select_hashed(w, key[j], val[j], list, &s_ncl) && win) wcount(key[j]);
+      for (int j = 0; j < kQ; ++j) sl[j] = ((has >> j) & 1u) ? table_hash(key[j]) & w.cmask : 0u;
+      while (pend) {
+        unsigned long long kk[kQ];
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) kk[j] = ((pend >> j) & 1u) ? w.skeys[sl[j]] : 0ull;
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) {
+          if (!((pend >> j) & 1u) || kk[j] != kEmptyKey) continue;
+          const unsigned long long prev =
+              atomicCAS(&w.skeys[sl[j]], kEmptyKey, static_cast<unsigned long long>(key[j]));
+          if (prev == kEmptyKey) {
+            list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(sl[j]);
+            if (win) wcount(key[j]);
+            kk[j] = key[j];
+          } else {
+            kk[j] = prev;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kQ; ++j) {
+          if (!((pend >> j) & 1u)) continue;
+          if (kk[j] == key[j]) {
+            atomicMin(&w.svals[sl[j]], static_cast<unsigned long long>(val[j]));
+            pend &= ~(1u << j);
+          } else {
+            sl[j] = (sl[j] + 1) & w.cmask;
+          }
+        }
+      }
       continue;
     }
     uint64_t old[kQ];
