@@ -1437,33 +1437,25 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
       valid |= 1u << q;
       if (st.cand_hot[ci]) hot |= 1u << q;
     }
-    // hashed tables: the entries probe in lockstep, one load round trip per probe step
-    // for all of them; an empty slot is claimed with a CAS (and recorded), and the
-    // entries then join the table updates below (tables hold at most half their slots
-    // in keys, so every probe ends)
+    // hashed tables: the entries probe in lockstep, one CAS round trip per probe step for
+    // all of them (the CAS both looks the slot up and claims it when empty; a claim is
+    // recorded), then join the table updates below (tables hold at most half their
+    // slots in keys, so every probe ends)
     const uint32_t hashed = hm;
     while (hm) {
       unsigned long long kk[4 * kGrp];
 #pragma unroll
       for (int q = 0; q < 4 * kGrp; ++q)
-        kk[q] = ((hm >> q) & 1u) ? ld_agent(ctab_keys(w, set, c0 + q / 4) + slot[q]) : 0ull;
-#pragma unroll
-      for (int q = 0; q < 4 * kGrp; ++q) {
-        if (!((hm >> q) & 1u) || kk[q] != kEmptyKey) continue;
-        const unsigned long long prev =
-            atomicCAS(ctab_keys(w, set, c0 + q / 4) + slot[q], kEmptyKey, static_cast<unsigned long long>(hkey[q]));
-        if (prev == kEmptyKey) {
-          st_agent(claims(w, set, c0 + q / 4, tile) + atomicAdd(&sh.ncl[c0 + q / 4], 1),
-                   static_cast<int32_t>(slot[q]));
-          kk[q] = hkey[q];
-        } else {
-          kk[q] = prev;
-        }
-      }
+        kk[q] = ((hm >> q) & 1u) ? atomicCAS(ctab_keys(w, set, c0 + q / 4) + slot[q], kEmptyKey,
+                                             static_cast<unsigned long long>(hkey[q]))
+                                 : 0ull;
 #pragma unroll
       for (int q = 0; q < 4 * kGrp; ++q) {
         if (!((hm >> q) & 1u)) continue;
-        if (kk[q] == hkey[q]) {
+        if (kk[q] == kEmptyKey)
+          st_agent(claims(w, set, c0 + q / 4, tile) + atomicAdd(&sh.ncl[c0 + q / 4], 1),
+                   static_cast<int32_t>(slot[q]));
+        if (kk[q] == kEmptyKey || kk[q] == hkey[q]) {
           hm &= ~(1u << q);
           valid |= 1u << q;
         } else {
@@ -1915,8 +1907,8 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
     }
     if (!has) continue;
     if (!dense) {
-      // hashed table: the entries probe in lockstep (one load round trip per probe step
-      // for all of them); the CAS that fills an empty slot claims the voxel
+      // hashed table: the entries probe in lockstep, one CAS round trip per probe step
+      // for all of them (the CAS both looks the slot up and, when empty, claims the voxel)
       uint32_t sl[kQ];
       uint32_t pend = has;
 #pragma unroll
@@ -1924,19 +1916,16 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
       while (pend) {
         unsigned long long kk[kQ];
 #pragma unroll
-        for (int j = 0; j < kQ; ++j) kk[j] = ((pend >> j) & 1u) ? w.skeys[sl[j]] : 0ull;
+        for (int j = 0; j < kQ; ++j)
+          kk[j] = ((pend >> j) & 1u)
+                      ? atomicCAS(&w.skeys[sl[j]], kEmptyKey, static_cast<unsigned long long>(key[j]))
+                      : 0ull;
 #pragma unroll
         for (int j = 0; j < kQ; ++j) {
           if (!((pend >> j) & 1u) || kk[j] != kEmptyKey) continue;
-          const unsigned long long prev =
-              atomicCAS(&w.skeys[sl[j]], kEmptyKey, static_cast<unsigned long long>(key[j]));
-          if (prev == kEmptyKey) {
-            list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(sl[j]);
-            if (win) wcount(key[j]);
-            kk[j] = key[j];
-          } else {
-            kk[j] = prev;
-          }
+          list[atomicAdd(&s_ncl, 1)] = static_cast<int32_t>(sl[j]);
+          if (win) wcount(key[j]);
+          kk[j] = key[j];
         }
 #pragma unroll
         for (int j = 0; j < kQ; ++j) {
