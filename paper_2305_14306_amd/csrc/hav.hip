@@ -1149,24 +1149,18 @@ struct EvalShared {
 // cached in an earlier pass.
 
 // OR `bits` into the brick table entry of `key` (hashed table); returns the number
-// of bits that were not set before. A tile that claims an empty slot records it.
+// of bits that were not set before. Each probe step is one CAS, which both finds the
+// key and claims an empty slot; a tile that claims a slot records it.
 __device__ __forceinline__ uint32_t global_or(unsigned long long* keys, unsigned long long* masks,
                                                 uint32_t cmask, uint64_t key, uint64_t bits,
                                                 int32_t* list, int* s_ncl) {
   uint32_t s = table_hash(key) & cmask;
   while (true) {
-    const unsigned long long k = ld_agent(&keys[s]);
-    if (k == key) {
+    const unsigned long long prev = atomicCAS(&keys[s], kEmptyKey, static_cast<unsigned long long>(key));
+    if (prev == kEmptyKey || prev == key) {
+      if (prev == kEmptyKey) st_agent(&list[atomicAdd(s_ncl, 1)], static_cast<int32_t>(s));
       const unsigned long long old = atomicOr(&masks[s], static_cast<unsigned long long>(bits));
       return static_cast<uint32_t>(__popcll(bits & ~old));
-    }
-    if (k == kEmptyKey) {
-      const unsigned long long prev = atomicCAS(&keys[s], kEmptyKey, key);
-      if (prev == kEmptyKey || prev == key) {
-        if (prev == kEmptyKey) st_agent(&list[atomicAdd(s_ncl, 1)], static_cast<int32_t>(s));
-        const unsigned long long old = atomicOr(&masks[s], static_cast<unsigned long long>(bits));
-        return static_cast<uint32_t>(__popcll(bits & ~old));
-      }
     }
     s = (s + 1) & cmask;
   }
