@@ -2615,8 +2615,14 @@ int depth_of(const hav_params_t* p) {
   return p->spec_depth == 0 ? kDefaultDepth : p->spec_depth;
 }
 
+// Table slots for a stage of n points: a power of two >= 2n, and at least kMinTableCap.
+// The floor matters for small clouds of large extent (LiDAR sweeps): their brick and
+// voxel grids at the fine sizes are far larger than 2n, and a bigger table keeps more
+// candidates on the dense (unprobed) path and the hashed ones sparse, for at most
+// ~170 MiB per workspace.
+constexpr uint64_t kMinTableCap = uint64_t(1) << 20;
 __host__ __device__ inline uint32_t table_cap(int64_t n) {
-  uint64_t cap = 1024;
+  uint64_t cap = kMinTableCap;
   while (cap < 2 * static_cast<uint64_t>(n)) cap <<= 1;
   return static_cast<uint32_t>(cap);
 }
