@@ -73,6 +73,8 @@ constexpr int kPerThread = kTile / kThreads;    // 8
 constexpr int kLdsCap = 4096;                   // select: LDS voxel map entries (2x tile)
 constexpr int kBrickCap = 1024;                 // search: LDS brick table per candidate
 constexpr int kMaxCand = 7;                     // candidate scales per search pass
+constexpr int kSplitTickets = 512;              // search tickets per pass up to which a tile's
+                                                // candidates get tickets of their own
 constexpr int kMaxDepth = kMaxCand;
 constexpr int kDefaultDepth = 4;
 constexpr int kGroups = 16;
@@ -1096,19 +1098,21 @@ __device__ __forceinline__ void st_agent(T* p, T v) {
 // (>= 0), or -(1 + r * kHotCap + slot) for a word of hot replica r. Bit k of
 // `hashed` marks candidates whose brick table is hashed (its keys are cleared too).
 // Uses block-shared s_cn[kMaxCand + 1]; all threads call it.
-__device__ void clear_claims(const Ws& w, int set, int nc, uint32_t hashed, int tile, int* s_cn) {
-  if (threadIdx.x < nc) s_cn[threadIdx.x + 1] = ld_agent(claim_n(w, set, threadIdx.x, tile));
+__device__ void clear_claims(const Ws& w, int set, int k0, int k1, uint32_t hashed, int tile, int* s_cn) {
+  const int nk = k1 > k0 ? k1 - k0 : 0;
+  if (static_cast<int>(threadIdx.x) < nk) s_cn[threadIdx.x + 1] = ld_agent(claim_n(w, set, k0 + threadIdx.x, tile));
   __syncthreads();
   if (threadIdx.x == 0) {
     s_cn[0] = 0;
-    for (int k = 0; k < nc; ++k) s_cn[k + 1] += s_cn[k];
+    for (int j = 0; j < nk; ++j) s_cn[j + 1] += s_cn[j];
   }
   __syncthreads();
-  const int total = s_cn[nc];
+  const int total = s_cn[nk];
   for (int e = threadIdx.x; e < total; e += kThreads) {
-    int k = 0;
-    while (e >= s_cn[k + 1]) ++k;
-    const int32_t id = ld_agent(claims(w, set, k, tile) + (e - s_cn[k]));
+    int j = 0;
+    while (e >= s_cn[j + 1]) ++j;
+    const int k = k0 + j;
+    const int32_t id = ld_agent(claims(w, set, k, tile) + (e - s_cn[j]));
     if (id >= 0) {
       if ((hashed >> k) & 1u) atomicExch(ctab_keys(w, set, k) + id, static_cast<unsigned long long>(kEmptyKey));
       atomicExch(ctab_masks(w, set, k) + id, 0ull);
@@ -1123,7 +1127,7 @@ __device__ void clear_claims(const Ws& w, int set, int nc, uint32_t hashed, int 
 // The claims of the search's last pass, for one tile.
 __device__ void clear_pending(const Ws& w, const Ctrl* c, int tile) {
   __shared__ int s_cn[kMaxCand + 1];
-  clear_claims(w, c->pend_set, c->pend_nc, c->pend_hashed, tile, s_cn);
+  clear_claims(w, c->pend_set, 0, c->pend_nc, c->pend_hashed, tile, s_cn);
 }
 
 // Whether a cloud has work in layer L (batched grids skip the others).
@@ -1236,10 +1240,11 @@ __device__ __forceinline__ void finish_tile(float4 (&pt)[kPerThread], const uint
 // candidate fixed by the launch's depth) are clean on entry and left clean.
 __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState& st,
                                             EvalShared& sh, uint64_t* lvals, uint64_t* lkeys,
-                                            const float4 (&pt)[kPerThread], uint32_t live) {
-  const int nc = st.nc, set = st.set;
-  if (threadIdx.x < nc) {
-    const int k = threadIdx.x;
+                                            const float4 (&pt)[kPerThread], uint32_t live, int cb,
+                                            int ce, int lb) {
+  const int set = st.set;
+  if (cb + static_cast<int>(threadIdx.x) < ce) {
+    const int k = cb + threadIdx.x;
     sh.ncl[k] = 0;
     uint32_t l[3], u[3];
     for (int a = 0; a < 3; ++a) {
@@ -1260,9 +1265,9 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
     sh.boxr[k][1] = 1.0f / static_cast<float>(static_cast<uint32_t>(dy));
   }
   __syncthreads();
-  for (int ci = 0; ci < nc; ++ci) {
+  for (int ci = cb; ci < ce; ++ci) {
     const float ix = st.cand_inv[ci][0], iy = st.cand_inv[ci][1], iz = st.cand_inv[ci][2];
-    uint64_t* tv = lvals + ci * kBrickCap;
+    uint64_t* tv = lvals + (ci - lb) * kBrickCap;
     if (sh.box[ci][5] != 0) {
       const uint32_t bl0 = sh.box[ci][0], bl1 = sh.box[ci][1], bl2 = sh.box[ci][2];
       const uint32_t bdx = sh.box[ci][3], bdy = sh.box[ci][4];
@@ -1299,7 +1304,7 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
     // thread's runs are formed first (run q ends before point q).
     const int dense = st.cand_dense[ci];
     const uint64_t nbx = st.cand_nb[ci][0], nby = st.cand_nb[ci][1];
-    uint64_t* tk = lkeys + ci * kBrickCap;
+    uint64_t* tk = lkeys + (ci - lb) * kBrickCap;
     uint64_t rk[kPerThread + 1], rb[kPerThread + 1];
     uint32_t pend = 0;
     {
@@ -1381,7 +1386,7 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
   static_assert(kBrickCap == 4 * kThreads, "four flush entries per thread");
   constexpr int kGrp = 3;
   const int rep = tile & (kReps - 1);
-  for (int c0 = 0; c0 < nc; c0 += kGrp) {
+  for (int c0 = cb; c0 < ce; c0 += kGrp) {
     uint32_t slot[4 * kGrp];
     uint64_t bits[4 * kGrp], hkey[4 * kGrp];
     uint32_t valid = 0, hot = 0, hm = 0;
@@ -1390,10 +1395,10 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
     for (int q = 0; q < 4 * kGrp; ++q) {
       const int ci = c0 + q / 4;
       const int le = (q % 4) * kThreads + threadIdx.x;
-      const int e = ci * kBrickCap + le;
+      const int e = (ci - lb) * kBrickCap + le;
       slot[q] = 0;
       bits[q] = 0ull;
-      if (ci >= nc) continue;
+      if (ci >= ce) continue;
       const uint32_t vol = sh.box[ci][5];
       const int dense = st.cand_dense[ci];
       uint64_t key, b;
@@ -1494,7 +1499,8 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
       if (f[k]) atomicAdd(&sh.fresh[c0 + k], f[k]);
   }
   __syncthreads();
-  if (threadIdx.x < nc) st_agent(claim_n(w, set, threadIdx.x, tile), static_cast<int32_t>(sh.ncl[threadIdx.x]));
+  if (cb + static_cast<int>(threadIdx.x) < ce)
+    st_agent(claim_n(w, set, cb + threadIdx.x, tile), static_cast<int32_t>(sh.ncl[cb + threadIdx.x]));
 }
 
 // Block-shared state of the search kernels.
@@ -1504,6 +1510,7 @@ struct SearchShared {
   uint32_t cnt[kMaxCand];
   int cn[kMaxCand + 1];
   int cloud, pass, tile, go, last;
+  int rank, part;  // the ticket's place in its pass, and its candidate (-1: all of them)
 };
 
 enum TicketResult : int { kTicketDone = 0, kTicketPublished = 1, kTicketFinished = 2 };
@@ -1517,29 +1524,35 @@ enum TicketResult : int { kTicketDone = 0, kTicketPublished = 1, kTicketFinished
 __device__ __forceinline__ int run_ticket(const Ws& w, const Plan& P, SearchShared& S,
                                           uint64_t* lvals, uint64_t* lkeys,
                                           float4 (&pt)[kPerThread], const uint32_t (&tg)[kPerThread],
-                                          int p, int tile) {
+                                          int p, int tile, int rank, int ntk, int part) {
   Header* h = w.h;
   SState& st = S.st;
   const int nc = st.nc;
-  const int ntile = w.ntile;
-  clear_claims(w, st.prev_set, st.prev_nc, st.prev_hashed, tile, S.cn);
-  if (threadIdx.x < nc) S.sh.fresh[threadIdx.x] = 0;
+  // this ticket's candidates: all of the pass's, or candidate `part` alone (then the
+  // LDS holds one candidate's tables); the previous pass's claims likewise
+  const int cb = part < 0 ? 0 : part, ce = part < 0 ? nc : (part < nc ? part + 1 : part);
+  const int pb = part < 0 ? 0 : part;
+  const int pe = part < 0 ? st.prev_nc : (part < st.prev_nc ? part + 1 : part);
+  clear_claims(w, st.prev_set, pb, pe, st.prev_hashed, tile, S.cn);
+  if (cb + static_cast<int>(threadIdx.x) < ce) S.sh.fresh[cb + threadIdx.x] = 0;
   __syncthreads();
-  uint32_t live;
-  finish_tile(pt, tg, live, S.sh);
-  eval_loaded(w, tile, st, S.sh, lvals, lkeys, pt, live);
+  if (cb < ce) {
+    uint32_t live;
+    finish_tile(pt, tg, live, S.sh);
+    eval_loaded(w, tile, st, S.sh, lvals, lkeys, pt, live, cb, ce, part < 0 ? 0 : part);
+  }
   __syncthreads();
-  if (threadIdx.x < nc && S.sh.fresh[threadIdx.x])
-    atomicAdd(&h->sacc[p & 1][threadIdx.x][tile & (kGroups - 1)][0], S.sh.fresh[threadIdx.x]);
+  if (cb + static_cast<int>(threadIdx.x) < ce && S.sh.fresh[cb + threadIdx.x])
+    atomicAdd(&h->sacc[p & 1][cb + threadIdx.x][rank & (kGroups - 1)][0], S.sh.fresh[cb + threadIdx.x]);
   // this tile's clears, table updates and counts are complete before it counts as done
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    // two-level completion count: a pass's tiles of group g = tile % kGroups, then the
+    // two-level completion count: a pass's tickets of group g = rank % kGroups, then the
     // groups (every pass adds exactly gsize and ngroups)
-    const int g = tile & (kGroups - 1);
-    const uint32_t gsize = static_cast<uint32_t>((ntile - g + kGroups - 1) / kGroups);
-    const uint32_t ngroups = static_cast<uint32_t>(ntile < kGroups ? ntile : kGroups);
+    const int g = rank & (kGroups - 1);
+    const uint32_t gsize = static_cast<uint32_t>((ntk - g + kGroups - 1) / kGroups);
+    const uint32_t ngroups = static_cast<uint32_t>(ntk < kGroups ? ntk : kGroups);
     int last = 0;
     const uint32_t d = atomicAdd(&h->sq_dgrp[g][0], 1u);
     if (d % gsize == gsize - 1) {
@@ -1636,7 +1649,7 @@ __device__ void mark_search_failed(Header* h) {
 // ticket, waits until that pass's candidates are published and runs it (run_ticket).
 // A block only ever waits for tiles that running blocks hold, so the launch needs no
 // co-resident grid and no kernel boundary per pass.
-__global__ void __launch_bounds__(kThreads) k_search(One src, int L) {
+__global__ void __launch_bounds__(kThreads) k_search(One src, int L, int split) {
   int bx, gx;
   const Cloud& cd = cloud_of(src, kKTile, bx, gx);
   if (!layer_due(cd, L)) return;
@@ -1647,20 +1660,24 @@ __global__ void __launch_bounds__(kThreads) k_search(One src, int L) {
   extern __shared__ uint64_t lds[];
   __shared__ SearchShared S;
   uint64_t *lvals, *lkeys;
-  search_lds_init(lds, P.depth, lvals, lkeys);
+  search_lds_init(lds, split > 1 ? 1 : P.depth, lvals, lkeys);
   const int ntile = w.ntile;
+  const int ntk = ntile * split;  // tickets of a pass
   int cur = -1;  // pass whose state S.st holds
   float4 pt[kPerThread];
   while (true) {
     __syncthreads();  // every thread has read the previous ticket's shared fields
     if (threadIdx.x == 0) {
       const uint32_t t = atomicAdd(&h->sq_ticket[0], 1u);
-      const int p = static_cast<int>(t / static_cast<uint32_t>(ntile));
+      const int p = static_cast<int>(t / static_cast<uint32_t>(ntk));
+      const int r = static_cast<int>(t - static_cast<uint32_t>(p) * static_cast<uint32_t>(ntk));
       S.pass = p;
-      S.tile = static_cast<int>(t - static_cast<uint32_t>(p) * static_cast<uint32_t>(ntile));
+      S.rank = r;
+      S.tile = r % ntile;
+      S.part = split > 1 ? r / ntile : -1;
     }
     __syncthreads();
-    const int p = S.pass, tile = S.tile;
+    const int p = S.pass, tile = S.tile, rank = S.rank, part = S.part;
     if (p >= P.t_max) break;  // every pass makes at least one evaluation
     uint32_t tg[kPerThread];
     issue_tile(w, tile, pt, tg);  // in flight during the wait and the state and claim reads
@@ -1673,7 +1690,7 @@ __global__ void __launch_bounds__(kThreads) k_search(One src, int L) {
       __syncthreads();
       cur = p;
     }
-    const int r = run_ticket(w, P, S, lvals, lkeys, pt, tg, p, tile);
+    const int r = run_ticket(w, P, S, lvals, lkeys, pt, tg, p, tile, rank, ntk, part);
     if (r == kTicketFinished) break;
     if (r == kTicketPublished) cur = p + 1;
   }
@@ -3050,7 +3067,7 @@ __global__ void __launch_bounds__(kThreads) k_search_many(Many src) {
       cur_c = c;
       cur_p = p;
     }
-    const int r = run_ticket(w, P, S, lvals, lkeys, pt, tg, p, tile);
+    const int r = run_ticket(w, P, S, lvals, lkeys, pt, tg, p, tile, tile, w.ntile, -1);
     if (r == kTicketPublished) cur_p = p + 1;
     if (r == kTicketFinished) {
       if (threadIdx.x == 0) atomicAdd(&bd->nfin[0], 1u);
@@ -3155,11 +3172,15 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
   HAV_LAUNCH(k_bin_count<One>, dim3(w.nbb), dim3(kThreads), 0, st, one);
   HAV_LAUNCH(k_bin_scan<One>, dim3(kBinChunks), dim3(kThreads), 0, st, one);
   HAV_LAUNCH(k_bin_scatter<One>, dim3(w.nbb + 1), dim3(kThreads), 0, st, one);
-  const int sgrid = search_grid(w.ntile, P.depth, false, p->search_blocks);
-  const size_t eval_lds = 2 * static_cast<size_t>(P.depth) * kBrickCap * sizeof(uint64_t);
+  // a cloud of few tiles splits each tile's candidates over tickets of their own, so that
+  // more blocks share a pass (each holds one candidate's LDS tables)
+  const int split = w.ntile * P.depth <= kSplitTickets ? P.depth : 1;
+  const int sdepth = split > 1 ? 1 : P.depth;
+  const int sgrid = search_grid(w.ntile * split, sdepth, false, p->search_blocks);
+  const size_t eval_lds = 2 * static_cast<size_t>(sdepth) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
   for (int l = 0; l < P.nlayers; ++l) {
-    if (!P.fixed) HAV_LAUNCH(k_search, dim3(sgrid), dim3(kThreads), eval_lds, st, one, l);
+    if (!P.fixed) HAV_LAUNCH(k_search, dim3(sgrid), dim3(kThreads), eval_lds, st, one, l, split);
     HAV_LAUNCH(k_select<One>, dim3(w.ntile), dim3(kThreads), sel_lds, st, one, l);
     if (w.pmode == 2) HAV_LAUNCH(k_mean, dim3(w.ntile), dim3(kThreads), 0, st, one, l);
     for (int r = 0; r < P.rounds[l]; ++r)
