@@ -1891,29 +1891,58 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   }
   __syncthreads();
   int32_t* list = w.scl + static_cast<size_t>(tile) * kTile;
-  // thread t owns entries t + j*kThreads; a dense table's minima are issued eight at a
-  // time, so that their round trips overlap (the atomic's old value says whether this
-  // tile is the voxel's first, which then records the slot)
-  constexpr int kQ = 8;
-  static_assert(kLdsCap % (kQ * kThreads) == 0, "select entries per thread");
-  for (int e0 = 0; e0 < kLdsCap; e0 += kQ * kThreads) {
+  // The occupied map entries (at most kTile: each holds a point) move to the front of
+  // the map with their voxel keys, so that the table updates below take one round.
+  uint32_t tot = 0;
+  {
+    __shared__ uint32_t s_cmp[kThreads / 64];
+    constexpr int kSP = kLdsCap / kThreads;
+    uint64_t ck[kSP], cv[kSP];
+    uint32_t occ = 0;
+#pragma unroll
+    for (int j = 0; j < kSP; ++j) {
+      const int e = j * kThreads + static_cast<int>(threadIdx.x);
+      cv[j] = lvals[e];
+      ck[j] = 0ull;
+      if (cv[j] == ~0ull || (vol && e >= static_cast<int>(vol))) continue;
+      if (vol) {
+        const uint32_t gx = bl0 + static_cast<uint32_t>(e) % bdx;
+        const uint32_t t2 = static_cast<uint32_t>(e) / bdx;
+        const uint32_t gy = bl1 + t2 % bdy, gz = bl2 + t2 / bdy;
+        ck[j] = dense ? gx + nx * (gy + ny * gz) : pack_key(gx, gy, gz);
+      } else {
+        ck[j] = lkeys[e];
+      }
+      occ |= 1u << j;
+    }
+    uint32_t ex;
+    tot = block_exclusive_scan<kThreads>(static_cast<uint32_t>(__popc(occ)), &ex, s_cmp);
+    // (every thread read its entries before the scan's barrier)
+#pragma unroll
+    for (int j = 0; j < kSP; ++j) {
+      if (!((occ >> j) & 1u)) continue;
+      const uint32_t pos = ex + static_cast<uint32_t>(__popc(occ & ((1u << j) - 1u)));
+      lkeys[pos] = ck[j];
+      lvals[pos] = cv[j];
+    }
+    __syncthreads();
+  }
+  // thread t owns entries t + j*kThreads; a dense table's minima are issued together, so
+  // that their round trips overlap (the atomic's old value says whether this tile is the
+  // voxel's first, which then records the slot)
+  constexpr int kQ = kTile / kThreads;
+  const int ntot = static_cast<int>(tot);
+  for (int e0 = 0; e0 < ntot; e0 += kQ * kThreads) {
     uint64_t key[kQ], val[kQ];
     uint32_t has = 0;
 #pragma unroll
     for (int j = 0; j < kQ; ++j) {
       const int e = e0 + j * kThreads + static_cast<int>(threadIdx.x);
       key[j] = 0ull;
+      val[j] = ~0ull;
+      if (e >= ntot) continue;
+      key[j] = lkeys[e];
       val[j] = lvals[e];
-      if (val[j] == ~0ull) continue;
-      if (vol) {
-        if (e >= static_cast<int>(vol)) continue;
-        const uint32_t gx = bl0 + static_cast<uint32_t>(e) % bdx;
-        const uint32_t t2 = static_cast<uint32_t>(e) / bdx;
-        const uint32_t gy = bl1 + t2 % bdy, gz = bl2 + t2 / bdy;
-        key[j] = dense ? gx + nx * (gy + ny * gz) : pack_key(gx, gy, gz);
-      } else {
-        key[j] = lkeys[e];
-      }
       has |= 1u << j;
     }
     if (!has) continue;
