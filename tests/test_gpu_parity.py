@@ -242,6 +242,14 @@ def test_spec_depth_does_not_change_results(gpu, orc, depth):
     _check(gpu, orc, synth.lattice(8), 60, gpu.params(spec_depth=depth), f"lattice depth {depth}")
 
 
+@pytest.mark.parametrize("n,depth", [(262144, 4), (262145, 4), (300000, 3), (300000, 7)])
+def test_split_ticket_boundary(gpu, orc, n, depth):
+    # a search pass of at most 512 tickets (tiles x depth) gives each tile's candidates
+    # tickets of their own: both sides of that boundary, and depths on either side of it
+    x = synth.scene_planes_blobs(n, seed=31)
+    _check(gpu, orc, x, n // 4, gpu.params(spec_depth=depth), f"split boundary n={n} depth={depth}")
+
+
 @pytest.mark.parametrize("kw", [dict(spec_budget=1), dict(spec_budget=1024), dict(search_blocks=1),
                                 dict(search_blocks=7), dict(search_blocks=5000),
                                 dict(spec_depth=3, spec_budget=1, search_blocks=64)])
