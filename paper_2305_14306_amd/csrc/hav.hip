@@ -1708,6 +1708,8 @@ __device__ __forceinline__ uint64_t sel_key(const Ws& w, const Ctrl* c, int32_t 
   return pack_key(gx, t % ny, t / ny);
 }
 
+// LDS voxel map insert of one (key, value) run: linear probing from the key's hash slot
+// (an empty slot is claimed by CAS); the slot's value takes the minimum.
 __device__ __forceinline__ bool lds_try_min(uint64_t* tk, uint64_t* tv, uint64_t key, uint64_t v) {
   uint32_t hs = table_hash(key) & (kLdsCap - 1);
   for (int pr = 0; pr < kLdsCap; ++pr) {
