@@ -1,4 +1,5 @@
-"""Autotuner for the sampler's tuning fields (speculation depth and budget, search grid).
+"""Autotuner for the sampler's tuning fields (speculation depth and budget, search grid,
+table load factor).
 
 The tuning fields of hav_params_t never change a result, only the time it takes, so
 the tuner times every candidate on the caller's own input (or a batch), checks that all
@@ -22,13 +23,14 @@ from . import hav
 DEPTHS = (2, 4, 6)
 BUDGETS = (4, 16, 64)
 GRIDS = (0, 256)
+TABLES = (0, 1)  # table_scale: the tables' slots are doubled per step (load factor halved)
 
 
-def candidates(depths=DEPTHS, budgets=BUDGETS, grids=GRIDS):
-    for d, b, g in itertools.product(depths, budgets, grids):
+def candidates(depths=DEPTHS, budgets=BUDGETS, grids=GRIDS, tables=TABLES):
+    for d, b, g, t in itertools.product(depths, budgets, grids, tables):
         if d == 1 and b != budgets[0]:
             continue  # the budget only matters when a pass speculates
-        yield dict(spec_depth=d, spec_budget=b, search_blocks=g)
+        yield dict(spec_depth=d, spec_budget=b, search_blocks=g, table_scale=t)
 
 
 def _time(fn, reps: int) -> float:

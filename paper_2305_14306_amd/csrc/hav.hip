@@ -2662,34 +2662,38 @@ __host__ __device__ inline size_t align_up(size_t x) { return (x + kAlign - 1) &
 int depth_of(const hav_params_t* p) {
   return p->spec_depth == 0 ? kDefaultDepth : p->spec_depth;
 }
+int tscale_of(const hav_params_t* p) { return p->table_scale; }
 
-// Table slots for a stage of n points: a power of two >= 2n, and at least kMinTableCap.
+// Table slots for a stage of n points: a power of two >= 2n, and at least kMinTableCap,
+// times 2^tscale (the tuning field table_scale), at most 2^31.
 // The floor matters for small clouds of large extent (LiDAR sweeps): their brick and
 // voxel grids at the fine sizes are far larger than 2n, and a bigger table keeps more
 // candidates on the dense (unprobed) path and the hashed ones sparse, for at most
 // ~170 MiB per workspace.
 constexpr uint64_t kMinTableCap = uint64_t(1) << 20;
-__host__ __device__ inline uint32_t table_cap(int64_t n) {
+__host__ __device__ inline uint32_t table_cap(int64_t n, int tscale) {
   uint64_t cap = kMinTableCap;
   while (cap < 2 * static_cast<uint64_t>(n)) cap <<= 1;
-  return static_cast<uint32_t>(cap);
+  cap <<= tscale;
+  return static_cast<uint32_t>(cap < (uint64_t(1) << 31) ? cap : (uint64_t(1) << 31));
 }
 
 struct Layout {
   size_t hdr, pts, invp, tag_s, tag_o, part, bh, binpre, bsum, ckeys, cmasks, ccl, hrep, ccn, skeys, svals, scl,
       scn, tie_p, tie_o, tcnt, pto, msum, mcnt, total;
   int64_t n_ws;
-  int32_t pmode;
+  int32_t pmode, tscale;
   uint32_t cap_ws;
   int32_t ntile_ws, nscan_ws, ncmax;
   int64_t tie_seg;
 };
 
-__host__ __device__ inline Layout make_layout(int64_t n, int depth, int pmode = 0) {
+__host__ __device__ inline Layout make_layout(int64_t n, int depth, int tscale, int pmode = 0) {
   Layout L;
   L.n_ws = n;
   L.pmode = pmode;
-  L.cap_ws = table_cap(n);
+  L.tscale = tscale;
+  L.cap_ws = table_cap(n, tscale);
   L.ntile_ws = static_cast<int32_t>((n + kTile - 1) / kTile);
   L.nscan_ws = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
   L.ncmax = depth;
@@ -2729,7 +2733,7 @@ __host__ __device__ inline Layout make_layout(int64_t n, int depth, int pmode = 
 
 __host__ __device__ inline uint64_t magic_of(const Layout& L) {
   return kMagic ^ (static_cast<uint64_t>(L.n_ws) << 8) ^ (static_cast<uint64_t>(L.ncmax) << 56) ^
-         (static_cast<uint64_t>(L.pmode) << 48);
+         (static_cast<uint64_t>(L.pmode) << 48) ^ (static_cast<uint64_t>(L.tscale) << 44);
 }
 
 // Device view of the workspace for a stage of n points (n <= the workspace's size).
@@ -2767,7 +2771,7 @@ __host__ __device__ inline Ws make_ws(char* base, const Layout& L, int64_t n) {
   w.nscan = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
   w.nbb = static_cast<int32_t>(blocks_of(kKBin, n));
   w.nbbox = static_cast<int32_t>(blocks_of(kKBBox, n));
-  w.cap = table_cap(n);
+  w.cap = table_cap(n, L.tscale);
   w.cmask = w.cap - 1;
   w.cap_ws = L.cap_ws;
   w.ntile_ws = L.ntile_ws;
@@ -2799,6 +2803,7 @@ bool params_any_ok(const hav_params_t* p) {
   if (p->spec_depth < 0 || p->spec_depth > kMaxDepth) return false;
   if (p->spec_budget < 0 || p->spec_budget > 1024) return false;
   if (p->search_blocks < 0 || p->search_blocks > 65536) return false;
+  if (p->table_scale < 0 || p->table_scale > 3) return false;
   if (!std::isfinite(p->trim_window) || p->trim_window > 64.0f) return false;
   if (p->select < HAV_SELECT_CENTRE_CLOSEST || p->select > HAV_SELECT_MEAN) return false;
   for (int a = 0; a < 3; ++a) {
@@ -2838,7 +2843,7 @@ __host__ __device__ inline int trim_rounds(int64_t v) {
 
 // The sampling parameters a plan needs (plain values, so a kernel can take them).
 struct ParamLite {
-  int32_t layers, ratio, t_max, depth, fixed, spec_budget;
+  int32_t layers, ratio, t_max, depth, tscale, fixed, spec_budget;
   double sigma;
   float trim_window;
   float aspect[3], fixed_v[3];
@@ -2852,6 +2857,7 @@ ParamLite lite_of(const hav_params_t* p) {
   q.ratio = p->layer_ratio;
   q.t_max = p->t_max;
   q.depth = depth_of(p);
+  q.tscale = tscale_of(p);
   q.fixed = (p->flags & HAV_FIXED_VOXEL) ? 1 : 0;
   q.spec_budget = p->spec_budget;
   q.sigma = p->sigma;
@@ -2879,7 +2885,7 @@ struct CloudSpec {
 __host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite& q) {
   Cloud cd;
   const int pmode = q.select == HAV_SELECT_CENTRE ? 1 : (q.select == HAV_SELECT_MEAN ? 2 : 0);
-  const Layout L = make_layout(c.n_cap, q.depth, pmode);
+  const Layout L = make_layout(c.n_cap, q.depth, q.tscale, pmode);
   cd.w = make_ws(c.seg, L, c.n);
   cd.w.xyz = c.xyz;
   cd.w.xyz_out = c.xyz_out;
@@ -3238,9 +3244,9 @@ struct ChainLayout {
   size_t buf0 = 0, buf1 = 0, local = 0, total = 0;
 };
 
-ChainLayout make_chain_layout(int64_t N, const int64_t* M, int depth) {
+ChainLayout make_chain_layout(int64_t N, const int64_t* M, int depth, int tscale) {
   ChainLayout C;
-  C.stage = make_layout(N, depth);
+  C.stage = make_layout(N, depth, tscale);
   size_t o = align_up(C.stage.total);
   C.buf0 = o;  o = align_up(o + static_cast<size_t>(M[0]) * 12);
   C.buf1 = o;  o = align_up(o + static_cast<size_t>(M[0]) * 12);
@@ -3375,14 +3381,14 @@ bool batch_args_ok(int32_t B, const int64_t* N, const int64_t* M) {
   return true;
 }
 
-BatchWsLayout make_batch_ws_layout(int32_t B, const int64_t* N, int depth) {
+BatchWsLayout make_batch_ws_layout(int32_t B, const int64_t* N, int depth, int tscale) {
   BatchWsLayout W;
   W.BL = make_batch_layout(B, N);
   size_t o = align_up(W.BL.total);
   W.seg.resize(static_cast<size_t>(B));
   for (int32_t i = 0; i < B; ++i) {
     W.seg[i] = o;
-    o = align_up(o + make_layout(N[i], depth).total);
+    o = align_up(o + make_layout(N[i], depth, tscale).total);
   }
   W.total = o;
   return W;
@@ -3434,14 +3440,14 @@ const char* hav_status_string(hav_status_t s) {
 
 size_t hav_workspace_size(int64_t N, int64_t M, const hav_params_t* params) {
   if (N < 1 || M < 1 || M > N || N > kMaxPoints || !params_any_ok(params)) return 0;
-  return make_layout(N, depth_of(params), points_mode(params)).total;
+  return make_layout(N, depth_of(params), tscale_of(params), points_mode(params)).total;
 }
 
 hav_status_t hav_workspace_init(int64_t N, const hav_params_t* params, void* ws, size_t ws_bytes,
                                 void* stream) {
   if (!ws || N < 1 || N > kMaxPoints || !params_any_ok(params)) return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
-  const Layout L = make_layout(N, depth_of(params), points_mode(params));
+  const Layout L = make_layout(N, depth_of(params), tscale_of(params), points_mode(params));
   if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   return init_ws(static_cast<char*>(ws), L, static_cast<hipStream_t>(stream));
 }
@@ -3453,7 +3459,7 @@ hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params
       !params_ok(params))
     return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
-  const Layout L = make_layout(N, depth_of(params));
+  const Layout L = make_layout(N, depth_of(params), tscale_of(params));
   if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   return run_stage(xyz, N, M, params, idx, static_cast<char*>(ws), L, info_dev,
                    static_cast<hipStream_t>(stream));
@@ -3466,7 +3472,7 @@ hav_status_t hav_sample_points(const float* xyz, int64_t N, int64_t M, const hav
       !params_any_ok(params))
     return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
-  const Layout L = make_layout(N, depth_of(params), points_mode(params));
+  const Layout L = make_layout(N, depth_of(params), tscale_of(params), points_mode(params));
   if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   return run_stage(xyz, N, M, params, idx, static_cast<char*>(ws), L, info_dev,
                    static_cast<hipStream_t>(stream), xyz_out);
@@ -3489,7 +3495,7 @@ extern "C" {
 size_t hav_batch_workspace_size(int32_t B, const int64_t* N_host, const int64_t* M_host,
                                 const hav_params_t* params) {
   if (!batch_args_ok(B, N_host, M_host) || !params_ok(params)) return 0;
-  return make_batch_ws_layout(B, N_host, depth_of(params)).total;
+  return make_batch_ws_layout(B, N_host, depth_of(params), tscale_of(params)).total;
 }
 
 hav_status_t hav_batch_workspace_init(int32_t B, const int64_t* N_host, const hav_params_t* params,
@@ -3497,11 +3503,11 @@ hav_status_t hav_batch_workspace_init(int32_t B, const int64_t* N_host, const ha
   if (!ws || !batch_args_ok(B, N_host, nullptr) || !params_ok(params)) return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
   const int depth = depth_of(params);
-  const BatchWsLayout W = make_batch_ws_layout(B, N_host, depth);
+  const BatchWsLayout W = make_batch_ws_layout(B, N_host, depth, tscale_of(params));
   if (ws_bytes < W.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   char* base = static_cast<char*>(ws);
   for (int32_t i = 0; i < B; ++i) {
-    const hav_status_t s = init_ws(base + W.seg[i], make_layout(N_host[i], depth),
+    const hav_status_t s = init_ws(base + W.seg[i], make_layout(N_host[i], depth, tscale_of(params)),
                                    static_cast<hipStream_t>(stream));
     if (s != HAV_OK) return s;
   }
@@ -3521,7 +3527,7 @@ hav_status_t hav_sample_batch(const float* xyz_concat, const int64_t* offsets_ho
   for (int32_t i = 0; i < B; ++i) N[i] = offsets_host[i + 1] - offsets_host[i];
   if (!batch_args_ok(B, N.data(), M_host)) return HAV_ERR_INVALID_ARG;
   const int depth = depth_of(params);
-  const BatchWsLayout W = make_batch_ws_layout(B, N.data(), depth);
+  const BatchWsLayout W = make_batch_ws_layout(B, N.data(), depth, tscale_of(params));
   if (ws_bytes < W.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   char* base = static_cast<char*>(ws);
   std::vector<CloudSpec> specs(static_cast<size_t>(B));
@@ -3618,7 +3624,7 @@ size_t hav_chain_workspace_size(int64_t N, const int64_t* M_host, int32_t n_stag
   if (N < 1 || N > kMaxPoints || !params_ok(params) ||
       !chain_sizes_ok(N, M_host, n_stages))
     return 0;
-  return make_chain_layout(N, M_host, depth_of(params)).total;
+  return make_chain_layout(N, M_host, depth_of(params), tscale_of(params)).total;
 }
 
 hav_status_t hav_sample_chain(const float* xyz, int64_t N, const int64_t* M_host,
@@ -3628,7 +3634,7 @@ hav_status_t hav_sample_chain(const float* xyz, int64_t N, const int64_t* M_host
       !chain_sizes_ok(N, M_host, n_stages))
     return HAV_ERR_INVALID_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
-  const ChainLayout C = make_chain_layout(N, M_host, depth_of(params));
+  const ChainLayout C = make_chain_layout(N, M_host, depth_of(params), tscale_of(params));
   if (ws_bytes < C.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);

@@ -49,8 +49,8 @@ def test_struct_layout_matches_header(hav, tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(hav_params_t), offsetof(hav_params_t, sigma),
          offsetof(hav_params_t, flags), offsetof(hav_params_t, fixed_voxel), sizeof(hav_info_t));
-  printf("%zu %zu %zu\n", offsetof(hav_info_t, m), offsetof(hav_info_t, count),
-         offsetof(hav_info_t, padded));
+  printf("%zu %zu %zu %zu\n", offsetof(hav_info_t, m), offsetof(hav_info_t, count),
+         offsetof(hav_info_t, padded), offsetof(hav_params_t, table_scale));
   return 0;
 }
 ''')
@@ -59,7 +59,7 @@ int main(void) {
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     P, I = hav.Params, hav.Info
     want = [C.sizeof(P), P.sigma.offset, P.flags.offset, P.fixed_voxel.offset, C.sizeof(I),
-            I.m.offset, I.count.offset, I.padded.offset]
+            I.m.offset, I.count.offset, I.padded.offset, P.table_scale.offset]
     assert [int(x) for x in out] == want
 
 
@@ -68,6 +68,7 @@ def test_params_default(hav):
     assert p.abi_version == hav.ABI_VERSION
     assert (p.layers, p.layer_ratio, p.t_max, p.flags) == (2, 4, 20, 0)
     assert p.sigma == 0.05 and list(p.aspect) == [1.0, 1.0, 1.0]
+    assert p.table_scale == 0
 
 
 def test_status_strings(hav):
@@ -81,6 +82,8 @@ def test_workspace_size(hav):
     a = hav.workspace_size(16384, 4096, p)
     b = hav.workspace_size(1 << 20, 1 << 18, p)
     assert 0 < a < b
+    # table_scale doubles the table slots per step (a tuning field: speed, never results)
+    assert hav.workspace_size(1 << 20, 1 << 18, hav.params(table_scale=1)) > b
     assert hav.workspace_size(0, 1, p) == 0
     assert hav.workspace_size(10, 11, p) == 0
     assert hav.workspace_size(10, 0, p) == 0
@@ -116,7 +119,8 @@ def test_host_rejects_bad_arguments(hav):
                dict(aspect=(1.0, 0.0, 1.0)), dict(aspect=(1.0, float("inf"), 1.0)),
                dict(fixed_voxel=0.0), dict(fixed_voxel=float("nan")), dict(spec_depth=8),
                dict(spec_depth=-1), dict(spec_budget=-1), dict(spec_budget=1025),
-               dict(search_blocks=-1), dict(search_blocks=65537),
+               dict(search_blocks=-1), dict(search_blocks=65537), dict(table_scale=-1),
+               dict(table_scale=4),
                dict(trim_window=64.5), dict(trim_window=float("nan")), dict(trim_window=float("inf")),
                dict(select=2), dict(select=-1)):
         assert _call(hav, p=hav.params(**kw)) == E, kw

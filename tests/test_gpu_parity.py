@@ -252,7 +252,8 @@ def test_split_ticket_boundary(gpu, orc, n, depth):
 
 @pytest.mark.parametrize("kw", [dict(spec_budget=1), dict(spec_budget=1024), dict(search_blocks=1),
                                 dict(search_blocks=7), dict(search_blocks=5000),
-                                dict(spec_depth=3, spec_budget=1, search_blocks=64)])
+                                dict(spec_depth=3, spec_budget=1, search_blocks=64), dict(table_scale=2),
+                                dict(table_scale=3, spec_depth=7)])
 def test_tuning_fields_do_not_change_results(gpu, orc, kw):
     x = synth.scene_planes_blobs(60000, seed=23)
     _check(gpu, orc, x, 15000, gpu.params(**kw), f"tuning {kw}")
