@@ -1652,23 +1652,39 @@ __device__ void mark_search_failed(Header* h) {
 __global__ void __launch_bounds__(kThreads) k_search(One src, int L, int split) {
   int bx, gx;
   const Cloud& cd = cloud_of(src, kKTile, bx, gx);
-  if (!layer_due(cd, L)) return;
   const Ws& w = cd.w;
   const Plan& P = cd.P;
   Header* h = w.h;
-  if (h->ctrl.done) return;  // fixed voxel size: no search
+  if (cd.P.identity || L >= cd.P.nlayers) return;
   extern __shared__ uint64_t lds[];
   __shared__ SearchShared S;
+  __shared__ uint32_t s_first;
+  // The launch's first round trip: the frame status, the done flag (fixed voxel size:
+  // no search), the block's first ticket and the first pass's state, all in flight
+  // together. Pass 0's state was published by the launch that started the layer, and
+  // a later pass cannot be published before this block's pass-0 ticket is done, so the
+  // copy is the one the ticket needs whenever that ticket is of pass 0. (A ticket taken
+  // when there is nothing to search is harmless: the next layer resets the counter.)
+  const uint32_t pub0 = threadIdx.x < kPubWords ? ld_agent(&h->pub[threadIdx.x]) : 0u;
+  if (threadIdx.x == 0) {
+    const int status = h->frame.status;
+    const int done = h->ctrl.done;
+    s_first = atomicAdd(&h->sq_ticket[0], 1u);
+    S.go = status == HAV_OK && !done ? 1 : 0;
+  }
   uint64_t *lvals, *lkeys;
   search_lds_init(lds, split > 1 ? 1 : P.depth, lvals, lkeys);
+  __syncthreads();
+  if (!S.go) return;
   const int ntile = w.ntile;
   const int ntk = ntile * split;  // tickets of a pass
   int cur = -1;  // pass whose state S.st holds
+  bool first = true;
   float4 pt[kPerThread];
   while (true) {
     __syncthreads();  // every thread has read the previous ticket's shared fields
     if (threadIdx.x == 0) {
-      const uint32_t t = atomicAdd(&h->sq_ticket[0], 1u);
+      const uint32_t t = first ? s_first : atomicAdd(&h->sq_ticket[0], 1u);
       const int p = static_cast<int>(t / static_cast<uint32_t>(ntk));
       const int r = static_cast<int>(t - static_cast<uint32_t>(p) * static_cast<uint32_t>(ntk));
       S.pass = p;
@@ -1681,7 +1697,11 @@ __global__ void __launch_bounds__(kThreads) k_search(One src, int L, int split) 
     if (p >= P.t_max) break;  // every pass makes at least one evaluation
     uint32_t tg[kPerThread];
     issue_tile(w, tile, pt, tg);  // in flight during the wait and the state and claim reads
-    if (p != cur) {
+    if (first && p == 0) {
+      if (threadIdx.x < kPubWords) reinterpret_cast<uint32_t*>(&S.st)[threadIdx.x] = pub0;
+      __syncthreads();
+      cur = 0;
+    } else if (p != cur) {
       if (threadIdx.x == 0) S.go = wait_pass(h, p, nullptr);
       __syncthreads();
       if (S.go <= 0) break;
@@ -1690,6 +1710,7 @@ __global__ void __launch_bounds__(kThreads) k_search(One src, int L, int split) 
       __syncthreads();
       cur = p;
     }
+    first = false;
     const int r = run_ticket(w, P, S, lvals, lkeys, pt, tg, p, tile, rank, ntk, part);
     if (r == kTicketFinished) break;
     if (r == kTicketPublished) cur = p + 1;
