@@ -100,6 +100,17 @@ def test_degenerate(gpu, orc):
     _check(gpu, orc, big, 500, label="huge extent")
 
 
+def test_degenerate_at_scale(gpu, orc):
+    # the pad paths across many scan blocks: one voxel at every size (every point
+    # identical), heavy duplicates, and a cloud on a line
+    _check(gpu, orc, np.full((200000, 3), -7.25, np.float32), 50000, label="identical 200k")
+    y = np.repeat(synth.random_cloud(20000, 8, scale=5.0), 8, axis=0)
+    _check(gpu, orc, y, 40000, label="duplicates 160k")
+    line = np.zeros((300000, 3), np.float32)
+    line[:, 1] = np.linspace(-3, 9, 300000, dtype=np.float32)
+    _check(gpu, orc, line, 75000, label="line 300k")
+
+
 # ------------------------------------------------------------------ parameters
 
 @pytest.mark.parametrize("kw", [dict(), dict(layers=1), dict(layers=3), dict(layers=8, layer_ratio=2),
