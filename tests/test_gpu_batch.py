@@ -85,6 +85,16 @@ def test_batch_single_cloud_equals_single_call(gpu, orc):
     assert np.array_equal(got[0], alone)
 
 
+def test_batch_large_and_tiny(gpu, orc):
+    # a 1M-point cloud beside tiny ones and a LiDAR sweep: the batched search serves
+    # clouds of very different tile counts in one launch
+    clouds = [synth.scene_planes_blobs(1 << 20, seed=41), synth.random_cloud(1, 3),
+              synth.random_cloud(5, 4), synth.random_cloud(3000, 5, kind="clustered"),
+              synth.lidar_points(200000, seed=42)]
+    Ms = [max(1, c.shape[0] // 4) for c in clouds]
+    _check_batch(gpu, orc, clouds, Ms, label="large and tiny")
+
+
 def test_batch_lidar_64(gpu, orc):
     clouds, Ms = synth.batch_lidar_clouds()
     _check_batch(gpu, orc, clouds, Ms, label="lidar x64")
