@@ -2450,6 +2450,10 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
   if (threadIdx.x == 0) w.scn[tile] = 0;
   if (!arrive_last(h, bx, gx)) return;
   settle_ties(w, h);
+  // a layer that found at least m voxels has nothing to pad: start the next layer
+  // here, so that the padding pass finds the controller past its layer and ends at once
+  __syncthreads();
+  if (c->need == 0 && L + 1 < cd.P.nlayers) layer_init(h, cd.P, L + 1);
 }
 
 // ----------------------------------------------------------------------------- scans over tag_o
@@ -2509,10 +2513,11 @@ __global__ void __launch_bounds__(kThreads) k_pad(Src src, int Lc) {
   const Plan& P = cd.P;
   Header* h = w.h;
   Ctrl* c = &h->ctrl;
-  const uint32_t need = c->need;
-  const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
   const int L = c->layer;
-  if (need > 0) {
+  if (L != Lc) return;  // nothing to pad: the marking pass has started the next layer
+  const uint32_t need = c->need;
+  const uint8_t lt = static_cast<uint8_t>(L + 1);
+  {
     __shared__ uint32_t s_tmp[kThreads / 64];
     const int lb = scan_ticket(h);
     const int64_t base = lb * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
@@ -2545,8 +2550,8 @@ __global__ void __launch_bounds__(kThreads) k_pad(Src src, int Lc) {
     }
   }
   if (!arrive_last(h, bx, gx)) return;
-  if (need > 0) scan_reset(w, h, gx);
-  if (L + 1 < P.nlayers) layer_init(h, P, L + 1);
+  scan_reset(w, h, gx);
+  layer_init(h, P, L + 1);
 }
 
 // Ascending output: every picked point's index, in index order.
