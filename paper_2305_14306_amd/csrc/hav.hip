@@ -2501,6 +2501,22 @@ __device__ void scan_reset(const Ws& w, Header* h, int nb) {
   if (threadIdx.x == 0) atomicExch(&h->ord[0], 0u);
 }
 
+// A thread's kScanPer consecutive tags (from `base`), one 16-byte load where the run is
+// whole and aligned; past the end a tag reads as 1 (sampled: neither counted nor padded).
+__device__ __forceinline__ void load_tags(const uint8_t* __restrict__ tag, int64_t base, int64_t n,
+                                          uint8_t (&t)[kScanPer]) {
+  static_assert(kScanPer == 16, "one 16-byte load per thread");
+  if (base + kScanPer <= n && (reinterpret_cast<uintptr_t>(tag + base) & 15u) == 0) {
+    const uint4 v = *reinterpret_cast<const uint4*>(tag + base);
+    const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) t[k] = static_cast<uint8_t>(wv[k >> 2] >> (8 * (k & 3)));
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) t[k] = base + k < n ? tag[base + k] : 1;
+  }
+}
+
 // Pad (when the layer found fewer voxels than m): mark the lowest-index unsampled
 // points; then start the next layer. Not for a cloud's last layer (k_out pads it).
 template <class Src>
@@ -2522,12 +2538,10 @@ __global__ void __launch_bounds__(kThreads) k_pad(Src src, int Lc) {
     const int lb = scan_ticket(h);
     const int64_t base = lb * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
     uint8_t t[kScanPer];
+    load_tags(w.tag_o, base, w.n, t);
     uint32_t cnt = 0;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      t[k] = base + k < w.n ? w.tag_o[base + k] : 1;
-      cnt += (t[k] == 0);
-    }
+    for (int k = 0; k < kScanPer; ++k) cnt += (t[k] == 0);
     uint32_t ex;
     const uint32_t tot = block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
     const uint32_t before = scan_prefix(w, tot, lb);
@@ -2576,15 +2590,20 @@ __global__ void __launch_bounds__(kThreads) k_out(Src src) {
   const int lb = scan_ticket(h);
   const int64_t base = lb * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
   uint8_t t[kScanPer];
+  load_tags(w.tag_o, base, w.n, t);
   uint32_t cz = 0;
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
-    t[k] = base + k < w.n ? w.tag_o[base + k] : 1;
-    cz += (t[k] == 0);
-  }
+  for (int k = 0; k < kScanPer; ++k) cz += (t[k] == 0);
   uint32_t ex;
   const uint32_t tot = block_exclusive_scan<kThreads>(cz, &ex, s_tmp);
   const uint32_t before = scan_prefix(w, tot, lb);
+  // a point's output position is the number of outputs before it, so the block's outputs
+  // fill the range [r0, r1): staged in LDS, then written out coalesced
+  __shared__ int32_t s_o[kScanTile];
+  const int64_t t0 = lb * static_cast<int64_t>(kScanTile);
+  const int64_t t1 = min(w.n, t0 + kScanTile);
+  const int64_t r0 = (t0 - before) + min(before, need);
+  const int64_t r1 = (t1 - (before + tot)) + min(before + tot, need);
   if (before != ~0u) {
     uint32_t zb = before + ex;
 #pragma unroll
@@ -2603,7 +2622,7 @@ __global__ void __launch_bounds__(kThreads) k_out(Src src) {
         ++zb;
       }
       if (r >= 0 && r < M) {
-        idx[r] = static_cast<int32_t>(i);
+        s_o[r - r0] = static_cast<int32_t>(i);
         if (w.xyz_out) {
           // centre / mean modes: what stands for the point; else (and for a padded
           // point) the point itself
@@ -2615,6 +2634,9 @@ __global__ void __launch_bounds__(kThreads) k_out(Src src) {
   } else if (threadIdx.x == 0) {
     atomicOr(&h->scan_bad[0], 1u);
   }
+  __syncthreads();
+  if (before != ~0u)
+    for (int64_t j = threadIdx.x; r0 + j < min(r1, M); j += kThreads) idx[r0 + j] = s_o[j];
   if (!arrive_last(h, bx, gx)) return;
   scan_reset(w, h, gx);
   if (threadIdx.x == 0) {
