@@ -2546,7 +2546,9 @@ __global__ void __launch_bounds__(kThreads) k_pad(Src src, int Lc) {
     const uint32_t tot = block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
     const uint32_t before = scan_prefix(w, tot, lb);
     if (before == ~0u) {
-      if (threadIdx.x == 0) h->frame.status = HAV_ERR_HIP;
+      // reported by the last block: every block still arrives, so the scan and
+      // arrival counters are left clean for the next call
+      if (threadIdx.x == 0) atomicOr(&h->scan_bad[0], 1u);
     } else {
       uint32_t r = before + ex;
 #pragma unroll
@@ -2564,7 +2566,17 @@ __global__ void __launch_bounds__(kThreads) k_pad(Src src, int Lc) {
     }
   }
   if (!arrive_last(h, bx, gx)) return;
+  __shared__ uint32_t s_bad;
+  if (threadIdx.x == 0) s_bad = take(&h->scan_bad[0]);
+  __syncthreads();
   scan_reset(w, h, gx);
+  if (s_bad) {
+    if (threadIdx.x == 0) {
+      h->frame.status = HAV_ERR_HIP;
+      h->info.status = HAV_ERR_HIP;
+    }
+    return;
+  }
   layer_init(h, P, L + 1);
 }
 
