@@ -249,6 +249,14 @@ hav_status_t hav_graph_capture_end(void* stream, hav_graph_t** graph);
 hav_status_t hav_graph_launch(hav_graph_t* graph, void* stream);
 void hav_graph_destroy(hav_graph_t* graph);
 
+/* Test hook for the failure path of the tag scans (for tests, not for callers). Sets,
+ * for the current device, how many polls a scan block makes for the counts of the blocks
+ * before it before it gives up (default 1 << 22; `limit` = 0 restores it). A call whose
+ * scan gives up reports HAV_ERR_HIP in info->status; every block still finishes and the
+ * workspace stays usable. Synchronous; affects calls issued after it returns.
+ * Returns HAV_ERR_HIP if the device copy fails. */
+hav_status_t hav_debug_scan_spin_limit(uint32_t limit);
+
 /* Measurement support. While enabled (on != 0), every kernel launch the library makes
  * is bracketed by a pair of HIP events recorded on the call's stream; the events are
  * kept by the library. Off by default; timing adds the event records to the stream. */

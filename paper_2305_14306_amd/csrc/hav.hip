@@ -65,6 +65,11 @@
 #include "hav_device.hpp"
 
 namespace hav {
+
+// Polls before a tag scan's bounded wait gives up (per device; a test hook lowers it).
+constexpr uint32_t kScanSpinDefault = 1u << 22;
+__device__ uint32_t g_scan_spin_limit = kScanSpinDefault;
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -2472,11 +2477,12 @@ __device__ uint32_t scan_prefix(const Ws& w, uint32_t mine, int lb) {
     s_bad = 0;
   }
   __syncthreads();
+  const uint32_t limit = g_scan_spin_limit;
   uint32_t sum = 0;
   for (int i = threadIdx.x; i < lb; i += kThreads) {
     uint32_t v, spins = 0;
     while ((v = ld_agent(&w.tcnt[i])) == 0u) {
-      if (++spins > kSpinLimit) {
+      if (++spins > limit) {
         s_bad = 1;
         break;
       }
@@ -3646,6 +3652,12 @@ void hav_graph_destroy(hav_graph_t* g) {
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   delete g;
+}
+
+hav_status_t hav_debug_scan_spin_limit(uint32_t limit) {
+  const uint32_t v = limit ? limit : hav::kScanSpinDefault;
+  return hipMemcpyToSymbol(HIP_SYMBOL(hav::g_scan_spin_limit), &v, sizeof(v)) == hipSuccess ? HAV_OK
+                                                                                         : HAV_ERR_HIP;
 }
 
 hav_status_t hav_timing_enable(int32_t on) {

@@ -173,12 +173,22 @@ def lib():
         L.hav_ball_query.restype = C.c_int
         L.hav_ball_query.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_float, C.c_int32, vp, vp, vp,
                                      C.c_size_t, vp]
+        L.hav_debug_scan_spin_limit.restype = C.c_int
+        L.hav_debug_scan_spin_limit.argtypes = [C.c_uint32]
         L.hav_timing_enable.restype = C.c_int
         L.hav_timing_enable.argtypes = [C.c_int32]
         L.hav_timing_collect.restype = C.c_int
         L.hav_timing_collect.argtypes = [C.c_char_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         _lib = L
     return _lib
+
+
+def debug_scan_spin_limit(limit: int) -> None:
+    """Test hook: polls before a tag scan's wait gives up on the current device (0 =
+    default). Lets tests drive the scans' failure path from the host."""
+    st = lib().hav_debug_scan_spin_limit(int(limit))
+    if st != OK:
+        raise HavError(st, "hav_debug_scan_spin_limit")
 
 
 def timing_enable(on: bool = True) -> None:

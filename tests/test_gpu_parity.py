@@ -146,6 +146,40 @@ def test_device_errors(gpu, orc):
     _check(gpu, orc, x, 100, label="after error")
 
 
+def test_scan_give_up_reports_and_recovers(gpu, orc):
+    # tag scans whose bounded waits give up after one poll (forced from the host): the
+    # call reports HAV_ERR_HIP, every block still finishes, and the next calls on the same
+    # workspace are exact again. Every point is identical, so layer 1 pads (the padding
+    # scan runs) and so does the output scan; 1M points make 256 scan blocks.
+    import torch
+    x = np.full((1 << 20, 3), 2.5, np.float32)
+    M = 1 << 18
+    st, want, winfo = orc.sample(x, M, _oracle_params(orc, gpu.params()))
+    assert st == 0
+    xd = _to_dev(x)
+    s = gpu.Sampler()
+    seen = []
+    torch.cuda.synchronize()
+    gpu.debug_scan_spin_limit(1)
+    try:
+        for _ in range(3):
+            _note("case scan give-up, spin limit 1, identical 1M")
+            _, info = s.sample(xd, M, with_info=True)
+            seen.append(info["status"])
+    finally:
+        torch.cuda.synchronize()
+        gpu.debug_scan_spin_limit(0)
+    assert set(seen) <= {0, gpu.ERR_HIP}, seen
+    for _ in range(2):
+        _note("case after scan give-up, identical 1M")
+        idx, info = s.sample(xd, M, with_info=True)
+        assert info["status"] == 0
+        assert info == winfo, (info, winfo)
+        assert np.array_equal(idx.cpu().numpy(), want)
+    if gpu.ERR_HIP not in seen:
+        pytest.skip("no scan wait gave up after one poll: the failure path was not reached")
+
+
 def test_determinism_and_workspace_independence(gpu, orc):
     import torch
     x = synth.scene_planes_blobs(200000, seed=9)
