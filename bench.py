@@ -77,10 +77,12 @@ def measured_traffic():
         return None
 
 
-def batch_leg(torch, hav, synth, steps: int) -> dict:
+def batch_leg(torch, hav, synth, steps: int, tune: bool = True) -> dict:
     """64 uneven LiDAR-shaped clouds (N_i ~ U{20k..200k}, M_i = N_i / 4): one batched
     call against 64 sequential single-cloud calls on the same stream, each with its own
-    initialised workspace. Both produce the same indices (checked)."""
+    initialised workspace. Both produce the same indices (checked). Then the autotuner
+    picks the tuning fields for this batch, and the tuned call is timed as a replayed
+    HIP graph (checked against the eager result)."""
     import numpy as np
     clouds, Ms = synth.batch_lidar_clouds()
     offs = np.concatenate([[0], np.cumsum([c.shape[0] for c in clouds])]).astype(np.int64)
@@ -117,9 +119,39 @@ def batch_leg(torch, hav, synth, steps: int) -> dict:
 
     t_b = timed(batched)
     t_s = timed(per_cloud)
-    return {"workload": "64 LiDAR-shaped clouds, N_i ~ U{20k..200k} (sum %d), M_i = N_i/4" % total_n,
-            "batched_ms": round(t_b, 4), "per_cloud_ms": round(t_s, 4),
-            "speedup": round(t_s / t_b, 3), "batched_Mpoints_per_s": round(total_n / t_b / 1e3, 1)}
+    res = {"workload": "64 LiDAR-shaped clouds, N_i ~ U{20k..200k} (sum %d), M_i = N_i/4" % total_n,
+           "batched_ms": round(t_b, 4), "per_cloud_ms": round(t_s, 4),
+           "speedup": round(t_s / t_b, 3), "batched_Mpoints_per_s": round(total_n / t_b / 1e3, 1)}
+    if not tune:
+        return res
+    # the autotuned fields (speculation depth, table load factor, search grid, workgroup
+    # shape), then the tuned call recorded once into a HIP graph and replayed
+    from paper_2305_14306_amd import autotune
+    best, table = autotune.tune_batch(xyz, offs, Ms, reps=3, cands=list(autotune.batch_candidates()))
+    pt = hav.params(**best)
+    ts_ = hav.Sampler()
+    out_t = torch.empty_like(out)
+    gstream = torch.cuda.Stream()
+    with torch.cuda.stream(gstream):
+        ts_.sample_batch(xyz, offs, Ms, pt, out=out_t, stream=gstream)
+    gstream.synchronize()
+    graph = hav.Graph.capture(gstream, lambda: ts_.sample_batch(xyz, offs, Ms, pt, out=out_t,
+                                                                stream=gstream))
+    try:
+        out_t.fill_(-1)
+        torch.cuda.synchronize()
+        graph.launch(gstream)
+        gstream.synchronize()
+        assert torch.equal(out_t, out), "graph replay of the tuned batch differs"
+        with torch.cuda.stream(gstream):
+            t_g = timed(lambda: graph.launch(gstream))
+    finally:
+        graph.close()
+    res.update({"tuned_fields": best, "tuned_candidates": len(table),
+                "tuned_eager_ms": round(min(ms for _, ms in table), 4),
+                "tuned_graph_ms": round(t_g, 4), "tuned_graph_speedup": round(t_s / t_g, 3),
+                "tuned_graph_Mpoints_per_s": round(total_n / t_g / 1e3, 1)})
+    return res
 
 
 def sizes_leg(torch, hav, synth, reps: int) -> dict:
@@ -288,20 +320,21 @@ def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
     import numpy as np
     tr = synth.serving_trace(n_requests)
     nmax = 1 << 21
-    scene = synth.scene_planes_blobs(nmax, seed=31)
-    lidar = synth.lidar_scan(seed=32, n_azimuth=int(np.ceil(nmax / (64 * 0.85))) + 2048)[:nmax]
-    bases = [torch.from_numpy(np.ascontiguousarray(lidar)).pin_memory(),
-             torch.from_numpy(np.ascontiguousarray(scene)).pin_memory()]
-    rng = np.random.default_rng(8)
+    bases = [torch.from_numpy(b).pin_memory() for b in synth.serving_bases(nmax)]
+    offs = synth.serving_windows(tr, nmax)
     views = []
     for i in range(n_requests):
         b = bases[int(tr["kind"][i])]
-        n = int(tr["n"][i])
-        o = int(rng.integers(0, b.shape[0] - n + 1))
+        n, o = int(tr["n"][i]), int(offs[i])
         views.append(b[o:o + n])
+    # a random sample of the served results is compared with the same cloud sampled alone
+    check = set(int(i) for i in np.random.default_rng(9).choice(n_requests, size=min(48, n_requests),
+                                                                 replace=False))
+
+    kept = {}
 
     def replay(max_batch, streams):
-        srv = hav.Server(48 << 30, max_batch=max_batch, streams=streams)
+        srv = hav.Server(budget, max_batch=max_batch, streams=streams)
         lat = np.zeros(n_requests)
         t_sub = np.zeros(n_requests)
         outstanding = []
@@ -315,6 +348,8 @@ def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
                         return
                     assert r[0] == 0, r[0]
                     lat[i] = r[3]
+                    if i in check:
+                        kept.setdefault(i, []).append(r[1])
                     outstanding.pop(0)
             for i in range(n_requests):
                 target = t0 + float(tr["t_arrival"][i])
@@ -344,28 +379,84 @@ def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
                 "batches": int(stats["batches"]), "max_batch": int(stats["max_batch_seen"]),
                 "slots": int(stats["slots"]), "hbm_GiB": round(stats["hbm_used"] / 2 ** 30, 2)}
 
+    budget = 48 << 30
     cont = replay(64, 2)
     fifo = replay(1, 1)
+    # the sampled requests: served (in the mix and FIFO) = alone
+    s = hav.Sampler()
+    agree = 0
+    for i in sorted(check):
+        x = views[i].cuda()
+        alone = s.sample(x, int(tr["m"][i])).cpu().numpy()
+        got = kept.get(i, [])
+        assert len(got) == 2 and all(np.array_equal(g, alone) for g in got), f"request {i} differs"
+        agree += 1
     return {"workload": "Poisson 2000/s, N lognormal median 1e5 (sigma_ln 1, <= 2^21), "
                         "LiDAR/scene mix, M = N/4 or N/16, %d requests (first %d discarded)"
                         % (n_requests, warm),
+            "hbm_budget_GiB": budget / 2 ** 30,
             "continuous": cont, "fifo": fifo,
-            "p99_speedup": round(fifo["p99_ms"] / cont["p99_ms"], 3)}
+            "p99_speedup": round(fifo["p99_ms"] / cont["p99_ms"], 3),
+            "verified_vs_alone": f"{agree} of {len(check)} sampled requests identical"}
 
 
-def cpu_baseline(x, M: int, budget_s: float) -> dict:
+def host_cpu() -> dict:
+    """The host's CPU model, logical CPU count and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    allowed = sorted(os.sched_getaffinity(0))
+    return {"model": model, "nproc": os.cpu_count(), "allowed": len(allowed), "_cpus": allowed}
+
+
+def cpu_baseline(x, M: int, budget_s: float, cpu: dict) -> dict:
+    """The oracle as it is, single-threaded, pinned in-process to one allowed core (the
+    process has touched the GPU, so it is not re-launched under taskset)."""
     import oracle
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        st, _, _ = oracle.sample(x, M)
-        assert st == 0
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 20:
-            break
+    core = cpu["_cpus"][0]
+    before = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {core})
+    try:
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            st, _, _ = oracle.sample(x, M)
+            assert st == 0
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or reps >= 20:
+                break
+    finally:
+        os.sched_setaffinity(0, before)
     return {"value": round(x.shape[0] * reps / el / 1e6, 4), "unit": "Mpoints/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "pinned_core": core, "cpu_model": cpu["model"], "nproc": cpu["nproc"],
             "sample": f"{reps} full runs of the same 1,048,576 -> 262,144 stage, single thread"}
+
+
+def cpu_batch_baseline(synth, cpu: dict, max_threads: int = 16) -> dict:
+    """The oracle on the 64-cloud batch, one cloud per thread across the allowed host
+    cores (at most max_threads: the GPU machine's CPU share), clouds handed out largest
+    first; the oracle's C entry point runs without the interpreter lock."""
+    import concurrent.futures as cf
+    import oracle
+    clouds, Ms = synth.batch_lidar_clouds()
+    threads = max(1, min(max_threads, cpu["allowed"]))
+    order = sorted(range(len(clouds)), key=lambda i: -clouds[i].shape[0])
+    oracle.lib()
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        sts = list(ex.map(lambda i: oracle.sample(clouds[i], Ms[i])[0], order))
+    el = time.perf_counter() - t0
+    assert all(st == 0 for st in sts)
+    total = sum(c.shape[0] for c in clouds)
+    return {"value": round(total / el / 1e6, 4), "unit": "Mpoints/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu["model"], "nproc": cpu["nproc"],
+            "sample": f"the 64-cloud batch ({total} points) once, one cloud per thread"}
 
 
 def main() -> int:
@@ -452,11 +543,15 @@ def main() -> int:
         torch.cuda.synchronize()
 
     value = N / (ms * 1e-3) / 1e6
+    call_bytes = algorithmic_bytes(N, M, info)
+    call_gbs = call_bytes / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "kernel": DOMINANT, "launch_us": round(launch_ms * 1e3, 2),
                 "bytes_per_launch": launch_bytes,
-                "whole_call_alg_bytes": algorithmic_bytes(N, M, info)}
+                "whole_call_alg_bytes": call_bytes,
+                "call_achieved": round(call_gbs, 2),
+                "call_frac": round(call_gbs / HBM_PEAK_GBS, 4)}
     result = {
         "metric": "input Mpoints/s (1M->250k)",
         "value": round(value, 3),
@@ -490,7 +585,10 @@ def main() -> int:
         result["variants"] = variants_leg(torch, hav, synth)
         print(f"bench: variants {result['variants']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(x, M, args.cpu_seconds)
+        cpu = host_cpu()
+        result["cpu_baseline"] = cpu_baseline(x, M, args.cpu_seconds, cpu)
+        if not args.no_batch:
+            result["cpu_batch_baseline"] = cpu_batch_baseline(synth, cpu)
     print(json.dumps(result), flush=True)
     return 0
 

@@ -257,6 +257,15 @@ void hav_graph_destroy(hav_graph_t* graph);
  * Returns HAV_ERR_HIP if the device copy fails. */
 hav_status_t hav_debug_scan_spin_limit(uint32_t limit);
 
+/* Test hook for the failure path of the voxel search (for tests, not for callers). Sets,
+ * for the current device, how many polls a search block makes while it waits for the
+ * pass it holds a ticket of to be published, before it gives up (default 1 << 22;
+ * `limit` = 0 restores it). A search that gives up reports HAV_ERR_HIP in info->status
+ * and leaves its workspace needing hav_workspace_init again (a batch marks every cloud
+ * that was searching); every block still finishes. Synchronous; affects calls issued
+ * after it returns. Returns HAV_ERR_HIP if the device copy fails. */
+hav_status_t hav_debug_search_spin_limit(uint32_t limit);
+
 /* Measurement support. While enabled (on != 0), every kernel launch the library makes
  * is bracketed by a pair of HIP events recorded on the call's stream; the events are
  * kept by the library. Off by default; timing adds the event records to the stream. */

@@ -107,6 +107,8 @@ def lib():
         L.oracle_keys.argtypes = [f32p, C.c_int64, f32p, f32p, i32p, C.POINTER(C.c_uint64), f32p]
         L.oracle_keys.restype = None
         L.oracle_priority.argtypes = [C.c_uint64]
+        L.oracle_take_visits.restype = C.c_int64
+        L.oracle_take_visits.argtypes = []
         L.oracle_priority.restype = C.c_uint64
         L.oracle_pow2_ceil.argtypes = [C.c_float]
         L.oracle_pow2_ceil.restype = C.c_float
@@ -228,6 +230,12 @@ def keys(xyz, mn, v):
     lib().oracle_keys(_ptr(a, C.c_float), n, _ptr(mn, C.c_float), _ptr(v, C.c_float),
                       _ptr(g, C.c_int32), _ptr(k, C.c_uint64), _ptr(d2, C.c_float))
     return g, k, d2
+
+
+def take_visits() -> int:
+    """Point visits (Cnt evaluations and selection passes, each point of R once) of the
+    oracle calls made on this thread since the previous take_visits()."""
+    return int(lib().oracle_take_visits())
 
 
 def priority(key: int) -> int:

@@ -159,9 +159,15 @@ void voxel_of_scale(float s, const float* aspect, float* v, float* inv) {
   }
 }
 
+// Point visits of the calls made on this thread: every Cnt evaluation and every
+// selection pass visits each point of R once (the O(N)-per-evaluation claim of Sec. 4.2
+// and Table 1; the tests compare it with sum over layers of (evals + 1) * |R|).
+thread_local int64_t g_visits = 0;
+
 // Cnt(R, v): number of non-empty voxels among the points still in R (Sec. 3.3).
 int64_t count_voxels(const float* xyz, const std::vector<int64_t>& R, const float* mn,
                      const float* inv) {
+  g_visits += static_cast<int64_t>(R.size());
   std::unordered_set<uint64_t> seen;
   seen.reserve(R.size() * 2 + 16);
   for (int64_t i : R) seen.insert(voxel_key(xyz + 3 * i, mn, inv, nullptr, nullptr));
@@ -361,6 +367,7 @@ int32_t sample_stage(const float* xyz, int64_t N, int64_t M, const OracleParams*
     // to the lowest index.
     std::unordered_map<uint64_t, std::pair<uint32_t, int64_t>> best;
     best.reserve(R.size() * 2 + 16);
+    g_visits += static_cast<int64_t>(R.size());
     for (int64_t i : R) {
       int32_t g[3];
       float r[3];
@@ -563,6 +570,13 @@ void oracle_keys(const float* xyz, int64_t N, const float* mn, const float* v, i
 }
 
 uint64_t oracle_priority(uint64_t key) { return voxel_priority(key); }
+
+// Point visits made on the calling thread since the last call of this function.
+int64_t oracle_take_visits(void) {
+  const int64_t v = g_visits;
+  g_visits = 0;
+  return v;
+}
 
 float oracle_pow2_ceil(float E) { return pow2_ceil(std::max(E, std::ldexp(1.0f, -64))); }
 

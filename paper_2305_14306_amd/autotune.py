@@ -33,6 +33,12 @@ def candidates(depths=DEPTHS, budgets=BUDGETS, grids=GRIDS, tables=TABLES):
         yield dict(spec_depth=d, spec_budget=b, search_blocks=g, table_scale=t)
 
 
+def batch_candidates():
+    """A short candidate list for batches of many LiDAR-sized clouds: speculation depth,
+    table load factor and the default search grid."""
+    return list(candidates(depths=(2, 4), budgets=(16,), grids=(0,), tables=(0, 1)))
+
+
 def _time(fn, reps: int) -> float:
     import torch
     fn()

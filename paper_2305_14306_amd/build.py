@@ -27,10 +27,16 @@ HIPCC_FLAGS = [
     "-fno-fast-math",
     "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-fno-gpu-flush-denormals-to-zero",
+    # no packed fp32 instructions in device code; hipcc hands these cc1 flags to the host
+    # pass too, whose target has no such feature: it says so once per function, and
+    # build() drops exactly that line (HOST_NOISE) from the output
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-I", os.path.join(ROOT, "include"),
 ]
+
+
+HOST_NOISE = "'-packed-fp32-ops' is not a recognized feature for this target (ignoring feature)"
 
 
 def build(verbose: bool = False) -> str:
@@ -39,7 +45,12 @@ def build(verbose: bool = False) -> str:
     cmd = [hipcc] + HIPCC_FLAGS + ["-o", tmp] + SOURCES
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "".join(line for line in r.stdout.splitlines(keepends=True) if line.strip() != HOST_NOISE)
+    if out:
+        sys.stderr.write(out)
+    if r.returncode != 0:
+        raise subprocess.CalledProcessError(r.returncode, cmd, out)
     os.replace(tmp, LIB)
     return LIB
 

@@ -66,9 +66,12 @@
 
 namespace hav {
 
-// Polls before a tag scan's bounded wait gives up (per device; a test hook lowers it).
+// Polls before a tag scan's bounded wait gives up, and before a voxel-search wait for a
+// pass's publication gives up (per device; test hooks lower them).
 constexpr uint32_t kScanSpinDefault = 1u << 22;
 __device__ uint32_t g_scan_spin_limit = kScanSpinDefault;
+constexpr uint32_t kSearchSpinDefault = 1u << 22;
+__device__ uint32_t g_search_spin_limit = kSearchSpinDefault;
 
 namespace {
 
@@ -1140,7 +1143,6 @@ __device__ __forceinline__ bool layer_due(const Cloud& cd, int L) {
   return !cd.P.identity && L < cd.P.nlayers && cd.w.h->frame.status == HAV_OK;
 }
 
-constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr float kSpecMult = 16.0f;
 
 struct EvalShared {
@@ -1617,10 +1619,11 @@ __device__ __forceinline__ int run_ticket(const Ws& w, const Plan& P, SearchShar
 // cloud's search has ended (drop the ticket); -1: a wait gave up (error flag raised).
 __device__ int wait_pass(Header* h, int p, uint32_t* err) {
   uint32_t spins = 0;
+  const uint32_t limit = g_search_spin_limit;
   while (ld_agent(&h->sq_gen[0]) < static_cast<uint32_t>(p)) {
     if (ld_agent(&h->sq_fin[0])) return 0;
     if (ld_agent(&h->sq_err[0]) || (err && ld_agent(err))) return -1;
-    if (++spins > kSpinLimit) {
+    if (++spins > limit) {
       atomicOr(&h->sq_err[0], 1u);
       if (err) atomicOr(err, 1u);
       return -1;
@@ -3104,6 +3107,7 @@ __global__ void __launch_bounds__(kThreads) k_search_many(Many src) {
       // wave 0: lane k looks at searching cloud start + k (+ 64 j)
       const int lane = threadIdx.x;
       uint32_t spins = 0;
+      const uint32_t limit = g_search_spin_limit;
       while (true) {
         int pick = -1;
         for (int base = 0; base < nact && pick < 0; base += 64) {
@@ -3138,7 +3142,7 @@ __global__ void __launch_bounds__(kThreads) k_search_many(Many src) {
           if (lane == 0) S.go = 0;
           break;
         }
-        if (++spins > kSpinLimit) {
+        if (++spins > limit) {
           if (lane == 0) {
             atomicOr(&bd->err[0], 1u);
             S.go = 0;
@@ -3658,6 +3662,13 @@ hav_status_t hav_debug_scan_spin_limit(uint32_t limit) {
   const uint32_t v = limit ? limit : hav::kScanSpinDefault;
   return hipMemcpyToSymbol(HIP_SYMBOL(hav::g_scan_spin_limit), &v, sizeof(v)) == hipSuccess ? HAV_OK
                                                                                          : HAV_ERR_HIP;
+}
+
+hav_status_t hav_debug_search_spin_limit(uint32_t limit) {
+  const uint32_t v = limit ? limit : hav::kSearchSpinDefault;
+  return hipMemcpyToSymbol(HIP_SYMBOL(hav::g_search_spin_limit), &v, sizeof(v)) == hipSuccess
+             ? HAV_OK
+             : HAV_ERR_HIP;
 }
 
 hav_status_t hav_timing_enable(int32_t on) {

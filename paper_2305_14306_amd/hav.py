@@ -175,6 +175,8 @@ def lib():
                                      C.c_size_t, vp]
         L.hav_debug_scan_spin_limit.restype = C.c_int
         L.hav_debug_scan_spin_limit.argtypes = [C.c_uint32]
+        L.hav_debug_search_spin_limit.restype = C.c_int
+        L.hav_debug_search_spin_limit.argtypes = [C.c_uint32]
         L.hav_timing_enable.restype = C.c_int
         L.hav_timing_enable.argtypes = [C.c_int32]
         L.hav_timing_collect.restype = C.c_int
@@ -189,6 +191,14 @@ def debug_scan_spin_limit(limit: int) -> None:
     st = lib().hav_debug_scan_spin_limit(int(limit))
     if st != OK:
         raise HavError(st, "hav_debug_scan_spin_limit")
+
+
+def debug_search_spin_limit(limit: int) -> None:
+    """Test hook: polls before a voxel-search wait for a pass gives up on the current
+    device (0 = default). Lets tests drive the search's failure path from the host."""
+    st = lib().hav_debug_search_spin_limit(int(limit))
+    if st != OK:
+        raise HavError(st, "hav_debug_search_spin_limit")
 
 
 def timing_enable(on: bool = True) -> None:
@@ -285,6 +295,7 @@ class Sampler:
         self.ws = None
         self.ws_key = None
         self.info = None
+        self._n_info = 0
 
     def _workspace(self, nbytes: int, N, p: Params, stream=None):
         """N: a point count (single clouds and chains) or a tuple of counts (batches)."""
@@ -317,6 +328,25 @@ class Sampler:
             self.info = torch.zeros(n * C.sizeof(Info), dtype=torch.uint8, device=self.device)
         return self.info
 
+    def _read(self, n: int):
+        """The reports of the last call (waits for it). A status that leaves the workspace
+        needing initialisation (a search wait that gave up, a workspace set up for
+        another size) makes the next call initialise it again."""
+        out = read_info(self.info[:n * C.sizeof(Info)], n)
+        if any(r["status"] in (ERR_HIP, ERR_WORKSPACE_NOT_INIT) for r in out):
+            self.ws_key = None
+        return out
+
+    def check(self):
+        """Wait for the last call on this Sampler and raise HavError if the device
+        reported an error for it (non-finite input, an unsupported frame, a workspace
+        that was not initialised, a wait that gave up). Returns its reports."""
+        out = self._read(self._n_info)
+        for r in out:
+            if r["status"] != OK:
+                raise HavError(r["status"], "device")
+        return out
+
     def sample(self, xyz, M: int, p: Params | None = None, out=None, with_info: bool = False,
                stream=None):
         torch = _torch()
@@ -328,15 +358,15 @@ class Sampler:
             raise HavError(ERR_INVALID_ARG, "hav_workspace_size")
         ws = self._workspace(nbytes, N, p, stream)
         idx = out if out is not None else torch.empty(int(M), dtype=torch.int32, device=xyz.device)
-        info = self._info(1) if with_info else None
+        info = self._info(1)
         st = lib().hav_sample(C.c_void_p(xyz.data_ptr()), N, int(M), C.byref(p),
                               C.c_void_p(idx.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
-                              C.c_void_p(info.data_ptr()) if info is not None else None,
-                              _stream_ptr(stream))
+                              C.c_void_p(info.data_ptr()), _stream_ptr(stream))
         if st != OK:
             raise HavError(st, "hav_sample")
+        self._n_info = 1
         if with_info:
-            return idx, read_info(info[:C.sizeof(Info)])[0]
+            return idx, self._read(1)[0]
         return idx
 
     def sample_points(self, xyz, M: int, p: Params, with_info: bool = False, stream=None):
@@ -351,16 +381,16 @@ class Sampler:
         ws = self._workspace(nbytes, N, p, stream)
         idx = torch.empty(int(M), dtype=torch.int32, device=xyz.device)
         pts = torch.empty((int(M), 3), dtype=torch.float32, device=xyz.device)
-        info = self._info(1) if with_info else None
+        info = self._info(1)
         st = lib().hav_sample_points(C.c_void_p(xyz.data_ptr()), N, int(M), C.byref(p),
                                      C.c_void_p(idx.data_ptr()), C.c_void_p(pts.data_ptr()),
                                      C.c_void_p(ws.data_ptr()), ws.numel(),
-                                     C.c_void_p(info.data_ptr()) if info is not None else None,
-                                     _stream_ptr(stream))
+                                     C.c_void_p(info.data_ptr()), _stream_ptr(stream))
         if st != OK:
             raise HavError(st, "hav_sample_points")
+        self._n_info = 1
         if with_info:
-            return idx, pts, read_info(info[:C.sizeof(Info)])[0]
+            return idx, pts, self._read(1)[0]
         return idx, pts
 
     def chain(self, xyz, Ms, p: Params | None = None, out=None, with_info: bool = False,
@@ -375,21 +405,20 @@ class Sampler:
         ws = self._workspace(nbytes, N, p, stream)
         total = int(sum(int(m) for m in Ms))
         idx = out if out is not None else torch.empty(total, dtype=torch.int32, device=xyz.device)
-        info = self._info(len(Ms)) if with_info else None
+        info = self._info(len(Ms))
         arr = (C.c_int64 * len(Ms))(*[int(m) for m in Ms])
         st = lib().hav_sample_chain(C.c_void_p(xyz.data_ptr()), N, arr, len(Ms), C.byref(p),
                                     C.c_void_p(idx.data_ptr()), C.c_void_p(ws.data_ptr()),
-                                    ws.numel(),
-                                    C.c_void_p(info.data_ptr()) if info is not None else None,
-                                    _stream_ptr(stream))
+                                    ws.numel(), C.c_void_p(info.data_ptr()), _stream_ptr(stream))
         if st != OK:
             raise HavError(st, "hav_sample_chain")
+        self._n_info = len(Ms)
         parts, off = [], 0
         for m in Ms:
             parts.append(idx[off:off + int(m)])
             off += int(m)
         if with_info:
-            return parts, read_info(info[:len(Ms) * C.sizeof(Info)], len(Ms))
+            return parts, self._read(len(Ms))
         return parts
 
 
@@ -412,31 +441,38 @@ class Sampler:
         ws = self._workspace(nbytes, Ns, p, stream)
         total = sum(Ms)
         idx = out if out is not None else torch.empty(total, dtype=torch.int32, device=xyz_concat.device)
-        info = self._info(B) if with_info else None
+        info = self._info(B)
         st = lib().hav_sample_batch(C.c_void_p(xyz_concat.data_ptr()), _i64(offsets), _i64(Ms), B,
                                     C.byref(p), C.c_void_p(idx.data_ptr()), C.c_void_p(ws.data_ptr()),
-                                    ws.numel(),
-                                    C.c_void_p(info.data_ptr()) if info is not None else None,
-                                    _stream_ptr(stream))
+                                    ws.numel(), C.c_void_p(info.data_ptr()), _stream_ptr(stream))
         if st != OK:
             raise HavError(st, "hav_sample_batch")
+        self._n_info = B
         parts, off = [], 0
         for m in Ms:
             parts.append(idx[off:off + m])
             off += m
         if with_info:
-            return parts, read_info(info[:B * C.sizeof(Info)], B)
+            return parts, self._read(B)
         return parts
 
 
 def sample(xyz, M: int, p: Params | None = None, with_info: bool = False):
-    """One-shot hav_sample on the current stream: returns idx [M] int32 (ascending)."""
-    return Sampler(xyz.device).sample(xyz, M, p, with_info=with_info)
+    """One-shot hav_sample on the current stream: returns idx [M] int32 (ascending).
+    Waits for the call and raises HavError if the device reported an error."""
+    s = Sampler(xyz.device)
+    idx = s.sample(xyz, M, p)
+    info = s.check()[0]
+    return (idx, info) if with_info else idx
 
 
 def chain(xyz, Ms, p: Params | None = None, with_info: bool = False):
-    """One-shot hav_sample_chain: returns one original-index tensor per stage."""
-    return Sampler(xyz.device).chain(xyz, Ms, p, with_info=with_info)
+    """One-shot hav_sample_chain: returns one original-index tensor per stage. Waits for
+    the call and raises HavError if the device reported an error for any stage."""
+    s = Sampler(xyz.device)
+    parts = s.chain(xyz, Ms, p)
+    info = s.check()
+    return (parts, info) if with_info else parts
 
 
 class Server:

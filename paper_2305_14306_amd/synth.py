@@ -206,6 +206,22 @@ def serving_trace(n_requests: int = 10000, rate_hz: float = 2000.0, seed: int = 
     return {"t_arrival": t, "n": n, "m": m, "kind": kind}
 
 
+def serving_bases(n_max: int = 1 << 21):
+    """The two base clouds the serving requests are windows of: a LiDAR sweep (seed 32,
+    azimuth-major, so a window of consecutive points is a sector) and a scene cloud
+    (seed 31, shuffled), each of n_max points."""
+    scene = scene_planes_blobs(n_max, seed=31)
+    lidar = lidar_scan(seed=32, n_azimuth=int(math.ceil(n_max / (64 * 0.85))) + 2048)[:n_max]
+    return [np.ascontiguousarray(lidar), np.ascontiguousarray(scene)]
+
+
+def serving_windows(trace, n_base: int, seed: int = 8):
+    """Start offset of each request's window in its base cloud (uniform over the
+    windows that fit)."""
+    rng = np.random.default_rng(seed)
+    return np.array([int(rng.integers(0, n_base - int(n) + 1)) for n in trace["n"]], dtype=np.int64)
+
+
 def lattice(side: int = 8) -> np.ndarray:
     """Integer lattice {0..side-1}^3; point (x, y, z) has index x + side*y + side^2*z."""
     z, y, x = np.meshgrid(np.arange(side), np.arange(side), np.arange(side), indexing="ij")

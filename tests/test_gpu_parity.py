@@ -180,6 +180,39 @@ def test_scan_give_up_reports_and_recovers(gpu, orc):
         pytest.skip("no scan wait gave up after one poll: the failure path was not reached")
 
 
+def test_search_give_up_reports_and_sampler_recovers(gpu, orc):
+    # a voxel search whose bounded waits give up after one poll (forced from the host):
+    # the call reports HAV_ERR_HIP and leaves the workspace needing initialisation; the
+    # Sampler sees the status, initialises it again, and the next calls are exact. The
+    # one-shot hav.sample raises for such a call.
+    import torch
+    x = synth.scene_planes_blobs()
+    M = x.shape[0] // 4
+    st, want, winfo = orc.sample(x, M)
+    assert st == 0
+    xd = _to_dev(x)
+    s = gpu.Sampler()
+    torch.cuda.synchronize()
+    gpu.debug_search_spin_limit(1)
+    try:
+        _note("case search give-up, spin limit 1, scene 1M")
+        s.sample(xd, M)
+        with pytest.raises(gpu.HavError) as e:
+            s.check()
+        assert e.value.status == gpu.ERR_HIP
+        with pytest.raises(gpu.HavError):
+            gpu.sample(xd, M)
+    finally:
+        torch.cuda.synchronize()
+        gpu.debug_search_spin_limit(0)
+    for _ in range(2):
+        _note("case after search give-up, scene 1M")
+        idx = s.sample(xd, M)
+        info = s.check()[0]
+        assert info == winfo, (info, winfo)
+        assert np.array_equal(idx.cpu().numpy(), want)
+
+
 def test_determinism_and_workspace_independence(gpu, orc):
     import torch
     x = synth.scene_planes_blobs(200000, seed=9)

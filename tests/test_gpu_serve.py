@@ -121,3 +121,74 @@ def test_serve_errors_and_identity(gpu, orc):
     assert res[1][0] == gpu.ERR_NONFINITE
     assert res[2][0] == 0 and np.array_equal(res[2][1], np.arange(5000, dtype=np.int32))
     assert res[3][0] == 0 and list(res[3][1]) == [0]
+
+
+# ------------------------------------------------------------ the serving workload itself
+
+@pytest.fixture(scope="module")
+def trace_requests():
+    """A slice of the serving workload: the first 48 requests of the Poisson trace
+    (LiDAR sectors and scene windows, M = N/4 or N/16), plus the trace's first requests
+    of the 2^20 and 2^21 slot classes, built exactly as the bench replays them."""
+    tr = synth.serving_trace(10000)
+    bases = synth.serving_bases()
+    offs = synth.serving_windows(tr, bases[0].shape[0])
+    n = tr["n"]
+    pick = list(range(48))
+    for lo, hi, extra in (((1 << 19), (1 << 20), 1), ((1 << 20), (1 << 21), 2)):
+        cand = [int(i) for i in np.nonzero((n > lo) & (n <= hi))[0] if int(i) not in pick]
+        pick += cand[:extra]
+    reqs = []
+    for i in pick:
+        b = bases[int(tr["kind"][i])]
+        o, k = int(offs[i]), int(n[i])
+        reqs.append((np.ascontiguousarray(b[o:o + k]), int(tr["m"][i])))
+    return reqs
+
+
+def test_serve_trace_mix_equals_alone(gpu, orc, trace_requests):
+    reqs = trace_requests
+    classes = {int(np.ceil(np.log2(x.shape[0]))) for x, _ in reqs}
+    assert {19, 20, 21} <= classes, classes  # the largest slot classes are exercised
+    srv = gpu.Server(24 << 30, max_batch=16, streams=2)
+    try:
+        _note(f"case serve trace slice {len(reqs)} requests, classes {sorted(classes)}")
+        res = _serve_all(gpu, srv, reqs)
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert stats["completed"] == stats["submitted"] == len(reqs)
+    assert stats["max_batch_seen"] > 1
+    for i, ((x, M), (st, idx, info, lat)) in enumerate(zip(reqs, res)):
+        _note(f"  request {i} N={x.shape[0]} M={M}")
+        assert st == 0, (i, st)
+        assert np.array_equal(idx, _alone(gpu, x, M)), i
+        ost, want, winfo = orc.sample(x, M)
+        assert ost == 0
+        assert np.array_equal(idx, want), i
+        assert info == winfo, i
+
+
+def test_serve_search_give_up_then_slot_recovers(gpu, orc, trace_requests):
+    # a search whose bounded wait gives up (forced from the host) marks its workspace
+    # for initialisation; the server must initialise the slot again, so the next request
+    # on the same slot is exact
+    x, M = max(trace_requests, key=lambda r: r[0].shape[0])
+    import torch
+    pinned = torch.from_numpy(x).pin_memory()
+    srv = gpu.Server(4 << 30, max_batch=4, streams=1)
+    try:
+        _note(f"case serve search give-up N={x.shape[0]}")
+        gpu.debug_search_spin_limit(1)
+        try:
+            st, _, info, _ = srv.wait(srv.submit(pinned, M))
+        finally:
+            gpu.debug_search_spin_limit(0)
+        assert st == gpu.ERR_HIP, st
+        st, idx, info, _ = srv.wait(srv.submit(pinned, M))
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert st == 0
+    assert stats["slots_created"] == 1  # the same slot served both requests
+    assert np.array_equal(idx, orc.sample(x, M)[1])

@@ -383,19 +383,37 @@ def test_chain_composes_stages(orc):
 
 
 def test_linear_time(orc):
-    # Sec. 4.2 / Table 1: O(N) per counter evaluation and at most t_max evaluations,
-    # so time / (points x evaluations) stays flat as N grows
-    rates = []
+    # Sec. 4.2 / Table 1: O(N) per counter evaluation and at most t_max evaluations.
+    # Exact pin: every evaluation and the selection pass visit each still-unsampled point
+    # once, so the oracle's point visits equal sum over layers of (evals + 1) * |R_l|.
     for e in (14, 16, 18):
         n = 1 << e
         x = synth.scene_planes_blobs(n, seed=3)
-        t0 = time.perf_counter()
+        orc.take_visits()
         st, idx, info = orc.sample(x, n // 4)
-        dt = time.perf_counter() - t0
+        visits = orc.take_visits()
         assert st == 0 and all(ev <= 20 for ev in info["evals"])
-        work = n * sum(ev + 1 for ev in info["evals"])
-        rates.append(dt / work)
-    assert max(rates) / min(rates) < 4.0, rates
+        want, R = 0, n
+        for L in range(info["layers"]):
+            want += (info["evals"][L] + 1) * R
+            R -= info["m"][L]
+        assert visits == want, (e, visits, want)
+    # Timing: doubling N keeps the time per point visit within 1.6x (a quadratic step
+    # would double it; the growth that remains is the hash sets outgrowing the caches)
+    rates = []
+    for e in (18, 19):
+        n = 1 << e
+        x = synth.scene_planes_blobs(n, seed=3)
+        best = None
+        for _ in range(2):
+            orc.take_visits()
+            t0 = time.perf_counter()
+            st, _, _ = orc.sample(x, n // 4)
+            dt = time.perf_counter() - t0
+            v = orc.take_visits()
+            best = dt / v if best is None else min(best, dt / v)
+        rates.append(best)
+    assert rates[1] / rates[0] < 1.6, rates
 
 
 # ---------------------------------------------------------------- comparators (Fig. 7)
