@@ -95,9 +95,9 @@ typedef struct {
                           depends on it) */
   uint32_t select_seed;/* generator seed of HAV_SELECT_RANDOM */
   int32_t table_scale; /* tuning only: the brick and voxel tables get 2^table_scale times their
-                          default slots (a power of two >= max(2N, 2^20)), so that their load
-                          factor halves per step; 0..3, default 0. Changes the workspace size,
-                          never a result. */
+                          default slots (a power of two >= max(N, min(8N, 2^20))), so that their
+                          load factor halves per step; 0..3, default 0. Changes the workspace
+                          size, never a result. */
 } hav_params_t;
 
 /* Per-call report, written by the device into caller memory (info_dev). */

@@ -95,7 +95,7 @@ constexpr int kBinChunks = kBins / kBinChunk;
 constexpr int kMaxBBoxBlocks = 1024;
 constexpr int kScanTile = 4096;                 // tag scans: 16 per thread
 constexpr int kScanPer = kScanTile / kThreads;
-constexpr int kSelDense = 4;                    // voxel value slots per brick-table slot
+constexpr int kSelDense = 8;                    // voxel value slots per brick-table slot
 constexpr uint64_t kMagic = 0x4841565F57533031ull;
 constexpr int kMaxDevices = 64;
 constexpr int kTieLds = 1024;                   // trim bucket staged in LDS up to this size
@@ -2668,9 +2668,13 @@ __global__ void __launch_bounds__(kThreads) k_out(Src src) {
 
 // ----------------------------------------------------------------------------- workspace init
 
+// keep_if: a workspace whose magic already equals it is left as it is (every block reads
+// the magic before any block could clear it, and a clearing block only zeroes it, so all
+// blocks take the same decision); 0 clears unconditionally.
 __global__ void __launch_bounds__(kThreads) k_ws_init(Ws w, size_t nct, size_t ncn, size_t nst,
                                                       size_t nsv, size_t nsn, size_t nhr, size_t nsc,
-                                                      size_t nms) {
+                                                      size_t nms, uint64_t keep_if) {
+  if (keep_if != 0 && w.h->magic == keep_if) return;
   const size_t stride = static_cast<size_t>(gridDim.x) * kThreads;
   const size_t t0 = blockIdx.x * static_cast<size_t>(kThreads) + threadIdx.x;
   for (size_t i = t0; i < nct; i += stride) {
@@ -2733,16 +2737,21 @@ int depth_of(const hav_params_t* p) {
 }
 int tscale_of(const hav_params_t* p) { return p->table_scale; }
 
-// Table slots for a stage of n points: a power of two >= 2n, and at least kMinTableCap,
-// times 2^tscale (the tuning field table_scale), at most 2^31.
-// The floor matters for small clouds of large extent (LiDAR sweeps): their brick and
-// voxel grids at the fine sizes are far larger than 2n, and a bigger table keeps more
-// candidates on the dense (unprobed) path and the hashed ones sparse, for at most
-// ~170 MiB per workspace.
+// Table slots for a stage of n points: a power of two >= n, and >= min(8n, 2^20), times
+// 2^tscale (the tuning field table_scale), at most 2^31. A table never holds more keys
+// than the stage has points, so with at least n slots every probe ends (a key is found
+// or claims an empty slot). The 8n floor matters for small clouds of large extent
+// (LiDAR sweeps): their brick and voxel grids at the fine sizes are far larger than n,
+// and a bigger table keeps more candidates on the dense (unprobed) path and the hashed
+// ones sparse.
 constexpr uint64_t kMinTableCap = uint64_t(1) << 20;
+constexpr uint64_t kTableFloorMult = 8;
 __host__ __device__ inline uint32_t table_cap(int64_t n, int tscale) {
-  uint64_t cap = kMinTableCap;
-  while (cap < 2 * static_cast<uint64_t>(n)) cap <<= 1;
+  const uint64_t nn = static_cast<uint64_t>(n);
+  const uint64_t floor_cap = kTableFloorMult * nn < kMinTableCap ? kTableFloorMult * nn : kMinTableCap;
+  const uint64_t want = nn > floor_cap ? nn : floor_cap;
+  uint64_t cap = 1;
+  while (cap < want) cap <<= 1;
   cap <<= tscale;
   return static_cast<uint32_t>(cap < (uint64_t(1) << 31) ? cap : (uint64_t(1) << 31));
 }
@@ -3325,15 +3334,18 @@ ChainLayout make_chain_layout(int64_t N, const int64_t* M, int depth, int tscale
   return C;
 }
 
-hav_status_t init_ws(char* base, const Layout& L, hipStream_t st) {
+// Initialise a workspace for layout L; with `only_if_needed`, a workspace already
+// initialised for L (its magic matches) is left alone (one cheap launch reads the magic).
+hav_status_t init_ws(char* base, const Layout& L, hipStream_t st, bool only_if_needed = false) {
   Ws w = make_ws(base, L, L.n_ws);
   const size_t nct = 2 * static_cast<size_t>(L.ncmax) * L.cap_ws;
   const size_t ncn = 2 * static_cast<size_t>(L.ncmax) * L.ntile_ws;
-  HAV_LAUNCH(k_ws_init, dim3(2048), dim3(kThreads), 0, st, w, nct, ncn,
+  HAV_LAUNCH(k_ws_init, dim3(only_if_needed ? 512 : 2048), dim3(kThreads), 0, st, w, nct, ncn,
              static_cast<size_t>(L.cap_ws), static_cast<size_t>(L.cap_ws) * kSelDense,
              static_cast<size_t>(L.ntile_ws),
              2 * static_cast<size_t>(L.ncmax) * kReps * kHotCap, static_cast<size_t>(L.nscan_ws),
-             L.pmode == 2 ? static_cast<size_t>(L.cap_ws) * kSelDense : size_t(0));
+             L.pmode == 2 ? static_cast<size_t>(L.cap_ws) * kSelDense : size_t(0),
+             only_if_needed ? magic_of(L) : uint64_t(0));
   HAV_LAUNCH(k_ws_seal, dim3(1), dim3(64), 0, st, w.h, magic_of(L));
   return HAV_OK;
 }

@@ -258,3 +258,11 @@ def test_ball_query_rejects_bad_arguments(hav):
                  (ptr, 100, ptr, 10, 1.0, 65, ptr, ptr, ptr, ws)]:          # K > 64
         assert L.hav_ball_query(*args, None) == 1, args
     assert L.hav_ball_query(ptr, 100, ptr, 10, 1.0, 8, ptr, ptr, ptr, 64, None) == 2
+
+
+def test_workspace_footprint(hav):
+    # tables sized from N: a 16,384-point cloud needs at most 32 MiB, a 1M-point one at
+    # most 320 MiB (27x its 12 MiB cloud)
+    assert hav.workspace_size(16384, 4096) <= 32 << 20
+    assert hav.workspace_size(1 << 20, 1 << 18) <= 320 << 20
+
