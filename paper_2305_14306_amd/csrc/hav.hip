@@ -95,7 +95,7 @@ constexpr int kBinChunks = kBins / kBinChunk;
 constexpr int kMaxBBoxBlocks = 1024;
 constexpr int kScanTile = 4096;                 // tag scans: 16 per thread
 constexpr int kScanPer = kScanTile / kThreads;
-constexpr int kSelDense = 8;                    // voxel value slots per brick-table slot
+constexpr int kSelDense = 4;                    // voxel value slots per brick-table slot (at least)
 constexpr uint64_t kMagic = 0x4841565F57533031ull;
 constexpr int kMaxDevices = 64;
 constexpr int kTieLds = 1024;                   // trim bucket staged in LDS up to this size
@@ -2756,12 +2756,25 @@ __host__ __device__ inline uint32_t table_cap(int64_t n, int tscale) {
   return static_cast<uint32_t>(cap < (uint64_t(1) << 31) ? cap : (uint64_t(1) << 31));
 }
 
+// Voxel value slots of the selection table: kSelDense per brick-table slot and at least
+// a power of two >= 8n (times 2^tscale), at most 2^31. A voxel grid at the chosen size
+// that fits is indexed directly (no probing); at scene density the grid of the last
+// layer is a few times the point count.
+__host__ __device__ inline uint32_t sel_cap_of(int64_t n, int tscale) {
+  uint64_t want = static_cast<uint64_t>(table_cap(n, tscale)) * kSelDense;
+  uint64_t c = 1;
+  while (c < 8 * static_cast<uint64_t>(n)) c <<= 1;
+  c <<= tscale;
+  if (c > want) want = c;
+  return static_cast<uint32_t>(want < (uint64_t(1) << 31) ? want : (uint64_t(1) << 31));
+}
+
 struct Layout {
   size_t hdr, pts, invp, tag_s, tag_o, part, bh, binpre, bsum, ckeys, cmasks, ccl, hrep, ccn, skeys, svals, scl,
       scn, tie_p, tie_o, tcnt, pto, msum, mcnt, total;
   int64_t n_ws;
   int32_t pmode, tscale;
-  uint32_t cap_ws;
+  uint32_t cap_ws, sel_ws;
   int32_t ntile_ws, nscan_ws, ncmax;
   int64_t tie_seg;
 };
@@ -2772,6 +2785,7 @@ __host__ __device__ inline Layout make_layout(int64_t n, int depth, int tscale, 
   L.pmode = pmode;
   L.tscale = tscale;
   L.cap_ws = table_cap(n, tscale);
+  L.sel_ws = sel_cap_of(n, tscale);
   L.ntile_ws = static_cast<int32_t>((n + kTile - 1) / kTile);
   L.nscan_ws = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
   L.ncmax = depth;
@@ -2795,13 +2809,13 @@ __host__ __device__ inline Layout make_layout(int64_t n, int depth, int tscale, 
   L.hrep = o;   o = align_up(o + tabs * kReps * kHotCap * 8);
   L.ccn = o;    o = align_up(o + tabs * L.ntile_ws * 4);
   L.skeys = o;  o = align_up(o + static_cast<size_t>(L.cap_ws) * 8);
-  L.svals = o;  o = align_up(o + static_cast<size_t>(L.cap_ws) * kSelDense * 8);
+  L.svals = o;  o = align_up(o + static_cast<size_t>(L.sel_ws) * 8);
   L.scl = o;    o = align_up(o + static_cast<size_t>(L.ntile_ws) * kTile * 4);
   L.scn = o;    o = align_up(o + static_cast<size_t>(L.ntile_ws) * 4);
   L.tie_p = o;  o = align_up(o + static_cast<size_t>(kGroups) * L.tie_seg * 8);
   L.tie_o = o;  o = align_up(o + static_cast<size_t>(kGroups) * L.tie_seg * 8);
   L.tcnt = o;   o = align_up(o + static_cast<size_t>(L.nscan_ws) * 4);
-  const size_t slots = pmode == 2 ? static_cast<size_t>(L.cap_ws) * kSelDense : 0;
+  const size_t slots = pmode == 2 ? static_cast<size_t>(L.sel_ws) : 0;
   L.pto = o;    o = align_up(o + (pmode ? N * 12 : 0));
   L.msum = o;   o = align_up(o + slots * 24);
   L.mcnt = o;   o = align_up(o + slots * 4);
@@ -2976,7 +2990,7 @@ __host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite&
   P.fixed = q.fixed;
   P.magic = magic_of(L);
   P.cap = cd.w.cap;
-  P.sel_cap = cd.w.cap * static_cast<uint32_t>(kSelDense);
+  P.sel_cap = sel_cap_of(cd.w.n, q.tscale);
   P.spec_mult = q.spec_budget ? static_cast<float>(q.spec_budget) : kSpecMult;
   P.win_sigma = q.trim_window == 0.0f ? kWinSigma : q.trim_window;
   P.select = q.select;
@@ -3341,10 +3355,10 @@ hav_status_t init_ws(char* base, const Layout& L, hipStream_t st, bool only_if_n
   const size_t nct = 2 * static_cast<size_t>(L.ncmax) * L.cap_ws;
   const size_t ncn = 2 * static_cast<size_t>(L.ncmax) * L.ntile_ws;
   HAV_LAUNCH(k_ws_init, dim3(only_if_needed ? 512 : 2048), dim3(kThreads), 0, st, w, nct, ncn,
-             static_cast<size_t>(L.cap_ws), static_cast<size_t>(L.cap_ws) * kSelDense,
+             static_cast<size_t>(L.cap_ws), static_cast<size_t>(L.sel_ws),
              static_cast<size_t>(L.ntile_ws),
              2 * static_cast<size_t>(L.ncmax) * kReps * kHotCap, static_cast<size_t>(L.nscan_ws),
-             L.pmode == 2 ? static_cast<size_t>(L.cap_ws) * kSelDense : size_t(0),
+             L.pmode == 2 ? static_cast<size_t>(L.sel_ws) : size_t(0),
              only_if_needed ? magic_of(L) : uint64_t(0));
   HAV_LAUNCH(k_ws_seal, dim3(1), dim3(64), 0, st, w.h, magic_of(L));
   return HAV_OK;
