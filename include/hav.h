@@ -148,6 +148,23 @@ hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params
                         int32_t* idx, void* ws, size_t ws_bytes, hav_info_t* info_dev,
                         void* stream);
 
+/* ---- Sampling without a caller workspace, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as hav_sample, minus the workspace: the call uses a
+ * workspace the library holds in its own device memory, one per device (a static array
+ * of HAV_STATIC_WORKSPACE_BYTES, held by each GPU the library runs on until the process
+ * ends). The call allocates nothing: it (re)initialises that workspace on the device
+ * when it holds another layout or was left dirty by a call that gave up, then samples.
+ *   N  1 <= M <= N <= HAV_STATIC_MAX_POINTS; a larger N, or tuning fields whose workspace
+ *      does not fit the array (spec_depth above 5 or table_scale above 0), return
+ *      HAV_ERR_WORKSPACE_TOO_SMALL at once and enqueue nothing.
+ * Every call on a device shares that device's workspace: calls that overlap on one
+ * device (two streams, two threads) race and give undefined results; serialise them. */
+#define HAV_STATIC_MAX_POINTS 32768
+#define HAV_STATIC_WORKSPACE_BYTES (64u << 20)
+hav_status_t hav_sample_static(const float* xyz, int64_t N, int64_t M, const hav_params_t* params,
+                               int32_t* idx, hav_info_t* info_dev, void* stream);
+
 /* Workspace for hav_sample_chain with stage sizes M_host[0..n_stages-1]; initialise it
  * with hav_workspace_init(N, params, ...). */
 size_t hav_chain_workspace_size(int64_t N, const int64_t* M_host, int32_t n_stages,

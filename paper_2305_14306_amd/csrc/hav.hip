@@ -3364,6 +3364,28 @@ hav_status_t init_ws(char* base, const Layout& L, hipStream_t st, bool only_if_n
   return HAV_OK;
 }
 
+// ----------------------------------------------------------------------------- static workspace
+
+// The workspace of hav_sample_static: one per device, in the library's own device memory,
+// laid out for kStaticPoints points at any N up to that (so calls of different sizes
+// share one initialisation). Host code never passes `scratch` itself to a kernel: its
+// name is a host-side stand-in; the device address comes from hipGetSymbolAddress, once
+// per device (static_ptr).
+constexpr int64_t kStaticPoints = HAV_STATIC_MAX_POINTS;
+constexpr size_t kStaticBytes = HAV_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+char* static_ptr(int dev) {
+  static std::once_flag once[kMaxDevices];
+  static char* ptr[kMaxDevices] = {};
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::call_once(once[dev], [dev]() {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) ptr[dev] = static_cast<char*>(p);
+  });
+  return ptr[dev];
+}
+
 // ----------------------------------------------------------------------------- batched host side
 
 constexpr int32_t kMaxBatch = 4096;
@@ -3559,6 +3581,25 @@ hav_status_t hav_sample(const float* xyz, int64_t N, int64_t M, const hav_params
   if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
   return run_stage(xyz, N, M, params, idx, static_cast<char*>(ws), L, info_dev,
                    static_cast<hipStream_t>(stream));
+}
+
+hav_status_t hav_sample_static(const float* xyz, int64_t N, int64_t M, const hav_params_t* params,
+                               int32_t* idx, hav_info_t* info_dev, void* stream) {
+  if (!xyz || !idx || N < 1 || M < 1 || M > N || N > kMaxPoints || !params_ok(params))
+    return HAV_ERR_INVALID_ARG;
+  if (N > kStaticPoints) return HAV_ERR_WORKSPACE_TOO_SMALL;
+  const Layout L = make_layout(kStaticPoints, depth_of(params), tscale_of(params));
+  if (L.total > kStaticBytes) return HAV_ERR_WORKSPACE_TOO_SMALL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return HAV_ERR_HIP;
+  char* ws = static_ptr(dev);
+  if (!ws) return HAV_ERR_HIP;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  // (re)initialised on the device when it holds another layout, or none yet, or a call
+  // that gave up left it dirty; else left as the last call left it
+  const hav_status_t s = init_ws(ws, L, st, true);
+  if (s != HAV_OK) return s;
+  return run_stage(xyz, N, M, params, idx, ws, L, info_dev, st);
 }
 
 hav_status_t hav_sample_points(const float* xyz, int64_t N, int64_t M, const hav_params_t* params,

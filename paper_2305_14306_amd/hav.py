@@ -115,6 +115,8 @@ def lib():
         L.hav_sample.restype = C.c_int
         L.hav_sample.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(Params), i32p, vp, C.c_size_t,
                                  vp, vp]
+        L.hav_sample_static.restype = C.c_int
+        L.hav_sample_static.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(Params), i32p, vp, vp]
         L.hav_sample_points.restype = C.c_int
         L.hav_sample_points.argtypes = [vp, C.c_int64, C.c_int64, C.POINTER(Params), i32p, vp, vp,
                                         C.c_size_t, vp, vp]
@@ -455,6 +457,27 @@ class Sampler:
         if with_info:
             return parts, self._read(B)
         return parts
+
+
+STATIC_MAX_POINTS = 32768
+
+
+def sample_static(xyz, M: int, p: Params | None = None, out=None, info=None, stream=None):
+    """hav_sample_static: hav_sample on the library's own per-device workspace (nothing
+    is allocated by the call; N <= STATIC_MAX_POINTS). `out` [M] int32 and `info` (a
+    device buffer of sizeof(Info) bytes) are optional; calls on one device must not
+    overlap. Returns idx."""
+    torch = _torch()
+    _check_xyz(xyz)
+    p = p if p is not None else params()
+    idx = out if out is not None else torch.empty(int(M), dtype=torch.int32, device=xyz.device)
+    st = lib().hav_sample_static(C.c_void_p(xyz.data_ptr()), xyz.shape[0], int(M), C.byref(p),
+                                 C.c_void_p(idx.data_ptr()),
+                                 C.c_void_p(info.data_ptr()) if info is not None else None,
+                                 _stream_ptr(stream))
+    if st != OK:
+        raise HavError(st, "hav_sample_static")
+    return idx
 
 
 def sample(xyz, M: int, p: Params | None = None, with_info: bool = False):

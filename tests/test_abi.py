@@ -266,3 +266,20 @@ def test_workspace_footprint(hav):
     assert hav.workspace_size(16384, 4096) <= 32 << 20
     assert hav.workspace_size(1 << 20, 1 << 18) <= 320 << 20
 
+
+def test_static_entry_rejects_on_the_host(hav):
+    # argument errors and sizes the library's own workspace cannot hold are refused
+    # before anything is enqueued (fake device addresses, never touched)
+    lib = hav.lib()
+
+    def call(N=100, M=10, p=None, xyz=0x10000, idx=0x20000):
+        p = p if p is not None else hav.params()
+        return lib.hav_sample_static(C.c_void_p(xyz), N, M, C.byref(p), C.c_void_p(idx), None, None)
+
+    assert call(xyz=0) == hav.ERR_INVALID_ARG
+    assert call(idx=0) == hav.ERR_INVALID_ARG
+    assert call(M=101) == hav.ERR_INVALID_ARG
+    assert call(p=hav.params(select=3)) == hav.ERR_INVALID_ARG
+    assert call(N=hav.STATIC_MAX_POINTS + 1) == hav.ERR_WORKSPACE_TOO_SMALL
+    assert call(p=hav.params(spec_depth=7)) == hav.ERR_WORKSPACE_TOO_SMALL
+    assert call(p=hav.params(table_scale=1)) == hav.ERR_WORKSPACE_TOO_SMALL
