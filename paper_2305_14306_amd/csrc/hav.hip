@@ -103,9 +103,11 @@ constexpr float kWinSigma = 6.0f;                // default trim window half-wid
 constexpr int kTieRank = 128;                   // bucket members ranked directly up to this many
 constexpr int kTrimBits = 8;                    // priority digit of one trim round
 constexpr int kTrimBins = 1 << kTrimBits;
+constexpr int kWinBins = 1024;                  // trim window: bins of its priority histogram
 constexpr int kHotCap = 4096;                   // brick grids this small use replicas
 constexpr int kReps = 16;                       // replicas of a hot brick table
 constexpr int kClaimCap = 2 * kTile;            // claims per tile and candidate
+constexpr int kClrReg = 4;                      // search: claims a thread clears from registers
 constexpr int64_t kMaxPoints = (int64_t(1) << 30) - 1;  // table slots stay below 2^31
 
 // ----------------------------------------------------------------------------- state
@@ -143,6 +145,7 @@ struct Ctrl {
   int32_t trim_mode;
   uint32_t c_final;     // voxels the search counted at s_final (0: no search)
   int32_t win;          // a window was set for the selection kernel to test
+  int32_t wshift;       // window priority bin: (p - blo) >> wshift
   uint64_t blo, bhi;
 };
 
@@ -197,6 +200,7 @@ struct alignas(256) Header {
   uint32_t sync_grp[kGroups][kStride];
   uint32_t acc[kMaxCand][kGroups][kStride];
   uint32_t hist[kGroups][kTrimBins];  // trim: priority digit histograms
+  uint32_t whist[kWinBins];       // trim window: voxels per priority bin
   uint32_t tie_cur[kGroups][kStride];
   uint32_t ord[kStride];          // dispatch-order block ids of the tag scans
   uint32_t scan_bad[kStride];     // a tag-scan wait gave up
@@ -557,6 +561,9 @@ __device__ void set_window(Ctrl* c, float sig) {
   const double lo = (x - kWin * sd) * 0x1p64, hi = (x + kWin * sd) * 0x1p64;
   c->blo = lo <= 0.0 ? 0ull : (lo >= 0x1p64 ? ~0ull : static_cast<uint64_t>(lo));
   c->bhi = hi >= 0x1p64 ? ~0ull : (hi <= 0.0 ? 0ull : static_cast<uint64_t>(hi));
+  int sh = 0;
+  while (((c->bhi - c->blo) >> sh) >= static_cast<uint64_t>(kWinBins)) ++sh;
+  c->wshift = sh;
   c->win = 1;
 }
 
@@ -570,6 +577,7 @@ __device__ void layer_init(Header* h, const Plan& P, int L) {
   for (int i = threadIdx.x; i < 2 * kMaxCand * kGroups; i += kThreads)
     h->sacc[i / (kMaxCand * kGroups)][(i / kGroups) % kMaxCand][i % kGroups][0] = 0;
   if (threadIdx.x < kGroups) h->sq_dgrp[threadIdx.x][0] = 0;
+
   if (threadIdx.x == 0) layer_init_ctrl(h, P, L, &s_init);
   __syncthreads();
   if (!P.fixed)
@@ -1206,9 +1214,10 @@ __device__ __forceinline__ void issue_tile(const Ws& w, int tile, float4 (&pt)[k
   }
 }
 
-// Keep the live points (tag 0) and reduce the tile's offset range into sh.tb.
-__device__ __forceinline__ void finish_tile(float4 (&pt)[kPerThread], const uint32_t (&tg)[kPerThread],
-                                            uint32_t& live, EvalShared& sh) {
+// Keep the live points (tag 0) and reduce the tile's offset range: each wave's share into
+// sh.red (finish_tile_a), then, after a barrier, the tile's into sh.tb (finish_tile_b).
+__device__ __forceinline__ void finish_tile_a(float4 (&pt)[kPerThread], const uint32_t (&tg)[kPerThread],
+                                              uint32_t& live, EvalShared& sh) {
   live = 0;
   uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
 #pragma unroll
@@ -1232,23 +1241,25 @@ __device__ __forceinline__ void finish_tile(float4 (&pt)[kPerThread], const uint
   }
   if (lane == 0)
     for (int q = 0; q < 6; ++q) sh.red[wv][q] = r[q];
-  __syncthreads();
+}
+__device__ __forceinline__ void finish_tile_b(EvalShared& sh) {
   if (threadIdx.x < 6) {
     const int q = threadIdx.x;
     uint32_t v = q < 3 ? 0xFFFFFFFFu : 0u;
     for (int j = 0; j < kThreads / 64; ++j) v = q < 3 ? min(v, sh.red[j][q]) : max(v, sh.red[j][q]);
     sh.tb[q] = v;
   }
-  __syncthreads();
 }
 
 // Cnt contributions of one loaded tile at the pass's candidates, added to sh.fresh.
 // The LDS tables (lvals: box words or hash values, lkeys: hash keys; slots per
 // candidate fixed by the launch's depth) are clean on entry and left clean.
+// `mid` runs (all threads) between the LDS phase and the global flush.
+template <class Mid>
 __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState& st,
                                             EvalShared& sh, uint64_t* lvals, uint64_t* lkeys,
                                             const float4 (&pt)[kPerThread], uint32_t live, int cb,
-                                            int ce, int lb) {
+                                            int ce, int lb, Mid&& mid) {
   const int set = st.set;
   if (cb + static_cast<int>(threadIdx.x) < ce) {
     const int k = cb + threadIdx.x;
@@ -1383,6 +1394,7 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
     }
   }
   __syncthreads();
+  mid();
   // One global update per distinct brick of the tile, LDS entries emptied as read.
   // Thread t owns entries t + j*kThreads (j < 4) of each candidate; the updates of up
   // to three candidates are issued together so that their round trips overlap. A hot
@@ -1540,14 +1552,65 @@ __device__ __forceinline__ int run_ticket(const Ws& w, const Plan& P, SearchShar
   const int cb = part < 0 ? 0 : part, ce = part < 0 ? nc : (part < nc ? part + 1 : part);
   const int pb = part < 0 ? 0 : part;
   const int pe = part < 0 ? st.prev_nc : (part < st.prev_nc ? part + 1 : part);
-  clear_claims(w, st.prev_set, pb, pe, st.prev_hashed, tile, S.cn);
+  // The previous pass's claims of this tile are cleared in three steps whose round trips
+  // overlap the tile's own work (the two passes use different table sets): the claim
+  // counts load with the tile's bounds reduction, the claims (up to kClrReg per thread
+  // in registers) with the box setup and LDS phase, and the exchanges are issued
+  // before the flush without being waited for (the ticket's final wait covers them).
+  const int nk = pe > pb ? pe - pb : 0;
+  const int pset = st.prev_set;
+  const uint32_t phashed = st.prev_hashed;
+  int32_t ccount = 0;
+  if (static_cast<int>(threadIdx.x) < nk) ccount = ld_agent(claim_n(w, pset, pb + threadIdx.x, tile));
   if (cb + static_cast<int>(threadIdx.x) < ce) S.sh.fresh[cb + threadIdx.x] = 0;
+  uint32_t live = 0;
+  if (cb < ce) finish_tile_a(pt, tg, live, S.sh);
+  if (static_cast<int>(threadIdx.x) < nk) S.cn[threadIdx.x + 1] = ccount;
   __syncthreads();
-  if (cb < ce) {
-    uint32_t live;
-    finish_tile(pt, tg, live, S.sh);
-    eval_loaded(w, tile, st, S.sh, lvals, lkeys, pt, live, cb, ce, part < 0 ? 0 : part);
+  if (cb < ce) finish_tile_b(S.sh);
+  if (threadIdx.x == 0) {
+    S.cn[0] = 0;
+    for (int j = 0; j < nk; ++j) S.cn[j + 1] += S.cn[j];
   }
+  __syncthreads();
+  const int ctotal = S.cn[nk];
+  int32_t cid[kClrReg];
+  int ck[kClrReg];
+#pragma unroll
+  for (int q = 0; q < kClrReg; ++q) {
+    const int e = static_cast<int>(threadIdx.x) + q * kThreads;
+    ck[q] = -1;
+    cid[q] = 0;
+    if (e < ctotal) {
+      int j = 0;
+      while (e >= S.cn[j + 1]) ++j;
+      ck[q] = pb + j;
+      cid[q] = ld_agent(claims(w, pset, pb + j, tile) + (e - S.cn[j]));
+    }
+  }
+  auto clear_one = [&](int k, int32_t id) {
+    if (id >= 0) {
+      if ((phashed >> k) & 1u) atomicExch(ctab_keys(w, pset, k) + id, static_cast<unsigned long long>(kEmptyKey));
+      atomicExch(ctab_masks(w, pset, k) + id, 0ull);
+    } else {
+      const int32_t q = -1 - id;
+      atomicExch(hrep_of(w, pset, k, q / kHotCap) + (q % kHotCap), 0ull);
+    }
+  };
+  auto clear_issue = [&]() {
+#pragma unroll
+    for (int q = 0; q < kClrReg; ++q)
+      if (ck[q] >= 0) clear_one(ck[q], cid[q]);
+    for (int e = static_cast<int>(threadIdx.x) + kClrReg * kThreads; e < ctotal; e += kThreads) {
+      int j = 0;
+      while (e >= S.cn[j + 1]) ++j;
+      clear_one(pb + j, ld_agent(claims(w, pset, pb + j, tile) + (e - S.cn[j])));
+    }
+  };
+  if (cb < ce)
+    eval_loaded(w, tile, st, S.sh, lvals, lkeys, pt, live, cb, ce, part < 0 ? 0 : part, clear_issue);
+  else
+    clear_issue();
   __syncthreads();
   if (cb + static_cast<int>(threadIdx.x) < ce && S.sh.fresh[cb + threadIdx.x])
     atomicAdd(&h->sacc[p & 1][cb + threadIdx.x][rank & (kGroups - 1)][0], S.sh.fresh[cb + threadIdx.x]);
@@ -1617,6 +1680,8 @@ __device__ __forceinline__ int run_ticket(const Ws& w, const Plan& P, SearchShar
 
 // Wait (thread 0) until pass p of the cloud behind `h` is published. 1: go on; 0: the
 // cloud's search has ended (drop the ticket); -1: a wait gave up (error flag raised).
+// (Measured: sleeping longer between polls makes the launch slower, since a publication
+// is noticed late.)
 __device__ int wait_pass(Header* h, int p, uint32_t* err) {
   uint32_t spins = 0;
   const uint32_t limit = g_search_spin_limit;
@@ -1656,7 +1721,9 @@ __device__ void mark_search_failed(Header* h) {
 // a queue of tickets: ticket t is tile t % ntile of pass t / ntile. A block takes a
 // ticket, waits until that pass's candidates are published and runs it (run_ticket).
 // A block only ever waits for tiles that running blocks hold, so the launch needs no
-// co-resident grid and no kernel boundary per pass.
+// co-resident grid and no kernel boundary per pass. (The one ticket counter also
+// staggers the blocks' starts a little, which spreads their bursts of table atomics:
+// measured, static first tickets per block made the launch slower, not faster.)
 __global__ void __launch_bounds__(kThreads) k_search(One src, int L, int split) {
   int bx, gx;
   const Cloud& cd = cloud_of(src, kKTile, bx, gx);
@@ -1667,12 +1734,6 @@ __global__ void __launch_bounds__(kThreads) k_search(One src, int L, int split) 
   extern __shared__ uint64_t lds[];
   __shared__ SearchShared S;
   __shared__ uint32_t s_first;
-  // The launch's first round trip: the frame status, the done flag (fixed voxel size:
-  // no search), the block's first ticket and the first pass's state, all in flight
-  // together. Pass 0's state was published by the launch that started the layer, and
-  // a later pass cannot be published before this block's pass-0 ticket is done, so the
-  // copy is the one the ticket needs whenever that ticket is of pass 0. (A ticket taken
-  // when there is nothing to search is harmless: the next layer resets the counter.)
   const uint32_t pub0 = threadIdx.x < kPubWords ? ld_agent(&h->pub[threadIdx.x]) : 0u;
   if (threadIdx.x == 0) {
     const int status = h->frame.status;
@@ -1788,7 +1849,6 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   Header* h = w.h;
   Ctrl* c = &h->ctrl;
   const int tile = bx;
-  clear_pending(w, c, tile);
   extern __shared__ uint64_t lds[];
   uint64_t* lvals = lds;
   uint64_t* lkeys = lds + kLdsCap;
@@ -1814,10 +1874,16 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   // trim window test of a voxel this tile claimed first (every voxel has one such tile)
   const int win = c->win;
   const uint64_t blo = c->blo, bhi = c->bhi;
+  const int wshift = c->wshift;
+  uint32_t* whist = h->whist;
   auto wcount = [&](uint64_t pk) {
     const uint64_t p = voxel_priority(pk);
-    if (p < blo) atomicAdd(&s_below, 1u);
-    else if (p <= bhi) atomicAdd(&s_inwin, 1u);
+    if (p < blo) {
+      atomicAdd(&s_below, 1u);
+    } else if (p <= bhi) {
+      atomicAdd(&s_inwin, 1u);
+      atomicAdd(&whist[(p - blo) >> wshift], 1u);
+    }
   };
   auto unpack = [&](uint64_t key) -> uint64_t {
     if (!dense) return key;
@@ -1836,6 +1902,9 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
     tg[k] = w.tag_s[S];
     pt[k] = w.pts[S];
   }
+  // the search's last pass's claims in this tile, cleared while the tile loads are in
+  // flight (the search tables are not the selection's)
+  clear_pending(w, c, tile);
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
     const bool ok = tg[k] == 0;
@@ -2035,38 +2104,81 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   }
   if (!arrive_last(h, bx, gx)) return;
   __shared__ uint32_t s_sum[3];
+  __shared__ int s_mode;
+  __shared__ uint32_t s_rank, s_bin, s_brank;
+  __shared__ uint32_t s_tmp2[kThreads / 64];
   if (threadIdx.x < 3) s_sum[threadIdx.x] = 0;
   __syncthreads();
   if (threadIdx.x < 3 * kGroups) {
     const uint32_t v = take(&h->acc[threadIdx.x / kGroups][threadIdx.x % kGroups][0]);
     if (v) atomicAdd(&s_sum[threadIdx.x / kGroups], v);
   }
+  // the window's priority histogram, read and emptied (thread t: bins 4t .. 4t+3)
+  constexpr int kWB = kWinBins / kThreads;
+  static_assert(kWinBins % kThreads == 0, "window bins per thread");
+  uint32_t hv[kWB];
+#pragma unroll
+  for (int j = 0; j < kWB; ++j) hv[j] = win ? take(&whist[threadIdx.x * kWB + j]) : 0u;
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  const uint32_t nvox = s_sum[0], below = s_sum[1], inwin = s_sum[2];
-  c->pend_nc = 0;
-  c->ncand = nvox;
-  c->trim = nvox > c->m ? 1 : 0;
-  c->need = nvox < c->m ? c->m - nvox : 0u;
-  c->prefix = 0;
-  c->rank = c->m - 1;
-  c->rounds_done = 0;
-  c->trim_mode = 0;
-  if (c->trim && !cd.P.fixed) {
-    // the window holds the threshold iff fewer than m voxels lie below it and at
-    // least m lie below or inside it
-    if (win && nvox == c->c_final && below < c->m && c->m <= below + inwin) {
-      c->trim_mode = 1;
-      c->rank = c->m - 1 - below;
-    } else {
-      c->trim_mode = 2;
+  if (threadIdx.x == 0) {
+    const uint32_t nvox = s_sum[0], below = s_sum[1], inwin = s_sum[2];
+    c->pend_nc = 0;
+    c->ncand = nvox;
+    c->trim = nvox > c->m ? 1 : 0;
+    c->need = nvox < c->m ? c->m - nvox : 0u;
+    c->prefix = 0;
+    c->rank = c->m - 1;
+    c->rounds_done = 0;
+    c->trim_mode = 0;
+    if (c->trim && !cd.P.fixed) {
+      // the window holds the threshold iff fewer than m voxels lie below it and at
+      // least m lie below or inside it
+      if (win && nvox == c->c_final && below < c->m && c->m <= below + inwin) {
+        c->trim_mode = 1;
+        c->rank = c->m - 1 - below;
+      } else {
+        c->trim_mode = 2;
+      }
+    }
+    s_mode = c->trim_mode;
+    s_rank = c->rank;
+    s_bin = 0;
+    s_brank = 0;
+    const int Lc = c->layer;
+    h->info.count[Lc] = static_cast<int32_t>(nvox);
+    h->info.trimmed[Lc] = nvox > c->m ? static_cast<int32_t>(nvox - c->m) : 0;
+    h->info.padded[Lc] = static_cast<int32_t>(c->need);
+    h->info.s[Lc] = c->s_final;
+  }
+  __syncthreads();
+  if (s_mode != 1) return;
+  // the bin of the window holding the threshold (the rank-th smallest in-window
+  // priority): the bucket narrows to that bin, and the rank to the rank inside it
+  uint32_t t = 0;
+#pragma unroll
+  for (int j = 0; j < kWB; ++j) t += hv[j];
+  uint32_t ex;
+  block_exclusive_scan<kThreads>(t, &ex, s_tmp2);
+  const uint32_t rank = s_rank;
+  if (rank >= ex && rank < ex + t) {
+    uint32_t e = ex;
+#pragma unroll
+    for (int j = 0; j < kWB; ++j) {
+      if (rank >= e && rank < e + hv[j]) {
+        s_bin = threadIdx.x * kWB + j;
+        s_brank = rank - e;
+      }
+      e += hv[j];
     }
   }
-  const int Lc = c->layer;
-  h->info.count[Lc] = static_cast<int32_t>(nvox);
-  h->info.trimmed[Lc] = nvox > c->m ? static_cast<int32_t>(nvox - c->m) : 0;
-  h->info.padded[Lc] = static_cast<int32_t>(c->need);
-  h->info.s[Lc] = c->s_final;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint64_t lo_b = blo + (static_cast<uint64_t>(s_bin) << wshift);
+    const uint64_t span = (wshift >= 64 ? ~0ull : ((1ull << wshift) - 1ull));
+    c->blo = lo_b;
+    c->bhi = (bhi - lo_b > span) ? lo_b + span : bhi;
+    c->rank = s_brank;
+  }
 }
 
 // ----------------------------------------------------------------------------- trim
@@ -2330,10 +2442,10 @@ __device__ void settle_ties(const Ws& w, Header* h) {
   const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
   auto pick = [&](int64_t v) {
     const int32_t orig = static_cast<int32_t>(v & 0xFFFFFFFFll);
-    const int64_t slot = v >> 32;
-    if (orig >= 0 && orig < w.n && slot >= 0 && slot < w.npad) {
+    const int64_t slot = v >> 32;  // -1 in a cloud's last layer (no sorted tag is kept)
+    if (orig >= 0 && orig < w.n) {
       w.tag_o[orig] = lt;
-      w.tag_s[slot] = lt;
+      if (slot >= 0 && slot < w.npad) w.tag_s[slot] = lt;
     }
   };
   if (staged) {
@@ -2369,6 +2481,9 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
   const uint64_t pref_hi = shift >= 64 ? 0ull : (c->prefix >> shift);
   const uint8_t lt = static_cast<uint8_t>(c->layer + 1);
   const int g = tile & (kGroups - 1);
+  // no later layer reads the sorted-order tags after a cloud's last layer (the output
+  // scan reads the original-order ones): the picks' sorted slots are not looked up
+  const bool last_layer = L + 1 >= cd.P.nlayers;
   __shared__ uint32_t s_base;
   __shared__ uint32_t s_tmp[kThreads / 64];
   // A tile owns at most kTile voxels: each thread takes its (up to kMP) list entries in
@@ -2434,13 +2549,14 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
   int32_t ip[kMP];
 #pragma unroll
   for (int k = 0; k < kMP; ++k)
-    ip[k] = (((keepm | tiem) >> k) & 1u) && orig[k] >= 0 && orig[k] < w.n ? w.invp[orig[k]] : -1;
+    ip[k] = !last_layer && (((keepm | tiem) >> k) & 1u) && orig[k] >= 0 && orig[k] < w.n ? w.invp[orig[k]]
+                                                                                       : -1;
   if (threadIdx.x == 0) s_base = qb;
 #pragma unroll
   for (int k = 0; k < kMP; ++k) {
-    if (!((keepm >> k) & 1u) || ip[k] < 0) continue;
+    if (!((keepm >> k) & 1u)) continue;  // (kept: orig is a point of the cloud)
     w.tag_o[orig[k]] = lt;
-    w.tag_s[ip[k]] = lt;
+    if (ip[k] >= 0) w.tag_s[ip[k]] = lt;
   }
   __syncthreads();
   uint32_t pos = s_base + ex;
