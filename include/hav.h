@@ -396,6 +396,31 @@ hav_status_t hav_ball_query(const float* xyz, int64_t N, const float* centres, i
                             int32_t K, int32_t* idx, int32_t* count, void* ws, size_t ws_bytes,
                             void* stream);
 
+/* Ball query on the sampler's own spatial structure: the grouping step after sampling
+ * in a set-abstraction block (Sec. 3.1 places the sampler in front of grouping), with
+ * the sampled points as centres and no second sort of the cloud. A hav_sample call
+ * leaves its workspace holding the cloud counting-sorted by spatial cell (with each
+ * point's place in that order and the cells' extents); this call finds each centre's
+ * neighbours in the few cells its ball overlaps. Results are those of hav_ball_query
+ * with centres[j] = xyz[idx[j]]: the n = min(K, count[j]) lowest indices i with
+ * d2 < radius^2 (strict), d2 in float32 as ((dx*dx + dy*dy) + dz*dz), dx = x_i - c_j, no
+ * fused multiply-add, radius^2 = fl(radius * radius), ascending, the rest of the row
+ * repeating out[j][0]; count[j] the number of points inside.
+ *   xyz [N][3] float32 device: the cloud of the preceding hav_sample call on `ws`.
+ *   idx [M] int32 device: the centres, distinct points of the cloud (e.g. that call's
+ *       picks); 1 <= M <= N. out [M][K] int32 device; count [M] int32 device or NULL.
+ *   1 <= K <= 64; radius > 0 finite.
+ *   ws, ws_bytes, params: the workspace and parameters of that hav_sample call (same N),
+ *       enqueued before this call on the same stream; no call may use ws in between.
+ * The call reads the workspace's sorted cloud and borrows its per-tile selection lists
+ * (returned to their initialised state). If the workspace does not hold this cloud's
+ * sorted points (another N, M == N, a chained call, or a call that reported an error),
+ * or a centre is not a point of the cloud (or appears twice), that row is all -1 and its
+ * count -1. Host-checkable errors return at once. */
+hav_status_t hav_ball_query_sampled(const float* xyz, int64_t N, const int32_t* idx, int64_t M,
+                                    float radius, int32_t K, int32_t* out, int32_t* count,
+                                    void* ws, size_t ws_bytes, const hav_params_t* params, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

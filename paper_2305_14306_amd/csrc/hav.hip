@@ -192,7 +192,8 @@ static_assert(sizeof(SState) % 4 == 0 && kPubWords <= kThreads, "search state wo
 
 struct alignas(256) Header {
   uint64_t magic;
-  uint64_t pad0[31];
+  int64_t binned_n;     // points of the stage whose sorted cloud the workspace holds (0: none)
+  uint64_t pad0[30];
   alignas(256) Frame frame;
   alignas(256) Ctrl ctrl;
   alignas(256) hav_info_t info;
@@ -647,6 +648,7 @@ __global__ void __launch_bounds__(kThreads) k_bbox(Src src) {
   const Cloud& cd = cloud_of(src, kKBBox, bx, gx);
   const Ws& w = cd.w;
   const float* __restrict__ xyz = w.xyz;
+  if (bx == 0 && threadIdx.x == 0) w.h->binned_n = 0;  // (set again once this call has binned)
   uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
   uint32_t hi[3] = {0u, 0u, 0u};
   uint32_t bad = 0;
@@ -834,20 +836,28 @@ __device__ __forceinline__ CellCoder make_coder(const Frame& fr) {
   return k;
 }
 
-// The cell number of offset (rx, ry, rz): per axis the cell index floor(r * scale),
-// clamped to the top cell, its bits interleaved into the number (Morton order).
-__device__ __forceinline__ uint32_t cell_code_k(float rx, float ry, float rz, const CellCoder& k) {
-  const float r[3] = {rx, ry, rz};
+// The cell index of offset r along axis a: floor(r * scale), clamped to the top cell
+// (and to 0 below: a point's r is never negative, a bound of a search range can be).
+// Non-decreasing in r.
+__device__ __forceinline__ uint32_t cell_index(float r, const CellCoder& k, int a) {
+  const float q = r * k.scale[a];
+  return !(q >= 0.0f) ? 0u : (q >= static_cast<float>(k.lim[a]) ? k.lim[a] : static_cast<uint32_t>(q));
+}
+// The cell number of cell indices (cx, cy, cz): their bits interleaved (Morton order).
+__device__ __forceinline__ uint32_t cell_code_of(const uint32_t (&c)[3], const CellCoder& k) {
   uint32_t code = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float q = r[a] * k.scale[a];
-    const uint32_t c = q >= static_cast<float>(k.lim[a]) ? k.lim[a] : static_cast<uint32_t>(q);
 #pragma unroll
     for (int j = 0; j < kBinBits; ++j)
-      if (j < k.bb[a]) code |= ((c >> j) & 1u) << ((k.pos[a] >> (4 * j)) & 15u);
+      if (j < k.bb[a]) code |= ((c[a] >> j) & 1u) << ((k.pos[a] >> (4 * j)) & 15u);
   }
   return code;
+}
+// The cell number of offset (rx, ry, rz).
+__device__ __forceinline__ uint32_t cell_code_k(float rx, float ry, float rz, const CellCoder& k) {
+  const uint32_t c[3] = {cell_index(rx, k, 0), cell_index(ry, k, 1), cell_index(rz, k, 2)};
+  return cell_code_of(c, k);
 }
 
 
@@ -1038,6 +1048,7 @@ __device__ void start_search(const Ws& w, const Plan& P) {
     c->pend_nc = 0;
     c->pend_set = 0;
     c->pend_hashed = 0;
+    w.h->binned_n = w.n;  // the sorted cloud (scattered by this launch) stays for grouping
   }
   __syncthreads();
   layer_init(w.h, P, 0);
@@ -2843,6 +2854,165 @@ __global__ void __launch_bounds__(kThreads) k_compose(const int32_t* __restrict_
   }
 }
 
+// ----------------------------------------------------------------------------- grouping
+
+// Ball query on the sampler's own spatial structure (the grouping that follows sampling
+// in a set-abstraction block, Sec. 3.1): after a call on this workspace, the cloud sits
+// counting-sorted by binning cell (pts, with invp from each point to its slot and the
+// cell offsets of the scan), so the points near a centre are the points of the few cells
+// its ball overlaps. No second sort of the cloud is made: the centres are bucketed by the
+// tile holding them (in the selection's per-tile lists, free once a call has ended), and
+// one block per tile stages, cell by cell, the cells its centres' balls overlap.
+constexpr int kBallMaxK = 64;
+constexpr int kBallStage = 1024;  // points staged in LDS at a time
+
+__device__ __forceinline__ bool ball_ready(const Ws& w) {
+  return w.h->binned_n == w.n && w.h->frame.status == HAV_OK;
+}
+
+__device__ __forceinline__ uint32_t cell_start(const Ws& w, uint32_t code) {
+  return code >= static_cast<uint32_t>(kBins) ? static_cast<uint32_t>(w.n)
+                                              : w.binpre[code] + w.bsum[code / kBinChunk];
+}
+
+// Bucket each centre j (point idx[j]) by the tile holding its sorted slot. A centre
+// that is not a point of the cloud, or any centre when the workspace does not hold this
+// cloud's sorted points, gets an empty row (-1) and count -1.
+__global__ void __launch_bounds__(kThreads) k_ball_bucket(Ws w, const int32_t* __restrict__ idx, int64_t M,
+                                                         int32_t K, int32_t* out, int32_t* count) {
+  const bool ready = ball_ready(w);
+  for (int64_t j = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; j < M;
+       j += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const int32_t i = idx[j];
+    bool ok = ready && i >= 0 && i < w.n;
+    if (ok) {
+      const int64_t t = w.invp[i] / kTile;
+      const int pos = atomicAdd(&w.scn[t], 1);
+      if (pos < kTile) w.scl[t * kTile + pos] = static_cast<int32_t>(j);
+      else ok = false;  // (more than a tile's points: the centres were not distinct)
+    }
+    if (!ok) {
+      for (int q = 0; q < K; ++q) out[j * K + q] = -1;
+      if (count) count[j] = -1;
+    }
+  }
+}
+
+// One block per tile: the K lowest indices i with d2 < r2 for each of its centres, d2 in
+// float32 as ((dx dx + dy dy) + dz dz) of the original coordinates (dx = x_i - c), the
+// rest of a row repeating its first entry; count = points inside. A centre scans the
+// cells whose index range covers its coordinate offset +- the radius widened by 1e-3 of
+// itself and by 1e-6 of the offset (more than the rounding of d2, of dx and of the
+// offsets r = fl(p - origin) the cells were assigned by); cell_index is non-decreasing
+// in r, so every point inside the ball lies in a scanned cell.
+__global__ void __launch_bounds__(kThreads) k_ball_group(Ws w, const float* __restrict__ xyz,
+                                                        const int32_t* __restrict__ idx, float radius,
+                                                        float r2, int32_t K, int32_t* out, int32_t* count) {
+  if (!ball_ready(w)) return;  // (then the lists were not touched, and may be laid out otherwise)
+  const int t = blockIdx.x;
+  const int nc = w.scn[t];
+  if (nc == 0) return;
+  __shared__ CellCoder s_kc;
+  __shared__ float s_mn[3];
+  __shared__ uint32_t s_box[6];
+  __shared__ float4 s_pt[kBallStage];
+  __shared__ int32_t s_row[kThreads * kBallMaxK];
+  int32_t* row = s_row + threadIdx.x * kBallMaxK;
+  if (threadIdx.x == 0) {
+    const Frame f = w.h->frame;
+    s_kc = make_coder(f);
+    for (int a = 0; a < 3; ++a) s_mn[a] = f.mn[a];
+  }
+  __syncthreads();
+  const int ncap = nc < kTile ? nc : kTile;
+  for (int c0 = 0; c0 < ncap; c0 += kThreads) {
+    const int k = c0 + static_cast<int>(threadIdx.x);
+    const bool has = k < ncap;
+    int64_t j = -1;
+    float cx[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
+    if (has) {
+      j = w.scl[static_cast<int64_t>(t) * kTile + k];
+      const int64_t ci = idx[j];
+      for (int a = 0; a < 3; ++a) {
+        cx[a] = xyz[3 * ci + a];
+        const float rc = cx[a] - s_mn[a];
+        const float rad = radius * 1.001f + 1e-6f * (fabsf(rc) + radius);
+        lo[a] = cell_index(rc - rad, s_kc, a);
+        hi[a] = cell_index(rc + rad, s_kc, a);
+      }
+    }
+    // the block's box of cells
+    __shared__ uint32_t s_red[kThreads / 64][6];
+    {
+      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+      uint32_t r[6];
+      for (int a = 0; a < 3; ++a) {
+        r[a] = __ockl_wfred_min_u32(lo[a]);
+        r[3 + a] = __ockl_wfred_max_u32(hi[a]);
+      }
+      if (lane == 0)
+        for (int q = 0; q < 6; ++q) s_red[wv][q] = r[q];
+      __syncthreads();
+      if (threadIdx.x < 6) {
+        const int q = threadIdx.x;
+        uint32_t v = q < 3 ? 0xFFFFFFFFu : 0u;
+        for (int ww = 0; ww < kThreads / 64; ++ww) v = q < 3 ? min(v, s_red[ww][q]) : max(v, s_red[ww][q]);
+        s_box[q] = v;
+      }
+      __syncthreads();
+    }
+    int n = 0;
+    int64_t total = 0;
+    for (uint32_t iz = s_box[2]; iz <= s_box[5]; ++iz)
+      for (uint32_t iy = s_box[1]; iy <= s_box[4]; ++iy)
+        for (uint32_t ix = s_box[0]; ix <= s_box[3]; ++ix) {
+          const bool mine = has && ix >= lo[0] && ix <= hi[0] && iy >= lo[1] && iy <= hi[1] &&
+                            iz >= lo[2] && iz <= hi[2];
+          if (!__syncthreads_or(mine)) continue;
+          const uint32_t cc[3] = {ix, iy, iz};
+          const uint32_t code = cell_code_of(cc, s_kc);
+          const uint32_t cb = cell_start(w, code), ce = cell_start(w, code + 1);
+          for (uint32_t p0 = cb; p0 < ce; p0 += kBallStage) {
+            const int np = static_cast<int>(min(static_cast<uint32_t>(kBallStage), ce - p0));
+            for (int q = threadIdx.x; q < np; q += kThreads) {
+              const float4 rec = w.pts[slot_of(static_cast<int64_t>(p0) + q)];
+              const int64_t o = __float_as_int(rec.w);
+              s_pt[q] = make_float4(xyz[3 * o], xyz[3 * o + 1], xyz[3 * o + 2], rec.w);
+            }
+            __syncthreads();
+            if (mine) {
+              for (int q = 0; q < np; ++q) {
+                const float4 pq = s_pt[q];
+                const float dx = pq.x - cx[0], dy = pq.y - cx[1], dz = pq.z - cx[2];
+                const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+                const float d2 = (xx + yy) + zz;
+                if (!(d2 < r2)) continue;
+                ++total;
+                const int32_t id = __float_as_int(pq.w);
+                if (n == K && id >= row[K - 1]) continue;
+                int u = n < K ? n : K - 1;  // insert into the sorted row; the largest drops out
+                while (u > 0 && row[u - 1] > id) {
+                  row[u] = row[u - 1];
+                  --u;
+                }
+                row[u] = id;
+                if (n < K) ++n;
+              }
+            }
+            __syncthreads();
+          }
+        }
+    if (has) {
+      int32_t* o = out + j * static_cast<int64_t>(K);
+      for (int q = 0; q < K; ++q) o[q] = q < n ? row[q] : (n > 0 ? row[0] : -1);
+      if (count) count[j] = static_cast<int32_t>(total < 0x7FFFFFFF ? total : 0x7FFFFFFF);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) w.scn[t] = 0;  // (the selection expects its counts at zero)
+}
+
 // ============================================================================ host side
 
 constexpr size_t kAlign = 256;
@@ -3883,6 +4053,23 @@ hav_status_t hav_timing_collect(const char* kernel, int32_t* launches, double* t
   *launches = n;
   *total_ms = ms;
   return status;
+}
+
+hav_status_t hav_ball_query_sampled(const float* xyz, int64_t N, const int32_t* idx, int64_t M,
+                                    float radius, int32_t K, int32_t* out, int32_t* count,
+                                    void* ws, size_t ws_bytes, const hav_params_t* params, void* stream) {
+  if (!xyz || !idx || !out || !ws || N < 1 || N > kMaxPoints || M < 1 || M > N || K < 1 ||
+      K > kBallMaxK || !(radius > 0.0f) || !std::isfinite(radius) || !params_any_ok(params))
+    return HAV_ERR_INVALID_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return HAV_ERR_INVALID_ARG;
+  const Layout L = make_layout(N, depth_of(params), tscale_of(params), points_mode(params));
+  if (ws_bytes < L.total) return HAV_ERR_WORKSPACE_TOO_SMALL;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const Ws w = make_ws(static_cast<char*>(ws), L, N);
+  const float r2 = radius * radius;
+  HAV_LAUNCH(k_ball_bucket, dim3(grid_for(M)), dim3(kThreads), 0, st, w, idx, M, K, out, count);
+  HAV_LAUNCH(k_ball_group, dim3(w.ntile), dim3(kThreads), 0, st, w, xyz, idx, radius, r2, K, out, count);
+  return HAV_OK;
 }
 
 size_t hav_chain_workspace_size(int64_t N, const int64_t* M_host, int32_t n_stages,

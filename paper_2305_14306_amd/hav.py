@@ -175,6 +175,9 @@ def lib():
         L.hav_ball_query.restype = C.c_int
         L.hav_ball_query.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_float, C.c_int32, vp, vp, vp,
                                      C.c_size_t, vp]
+        L.hav_ball_query_sampled.restype = C.c_int
+        L.hav_ball_query_sampled.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_float, C.c_int32, vp, vp,
+                                             vp, C.c_size_t, C.POINTER(Params), vp]
         L.hav_debug_scan_spin_limit.restype = C.c_int
         L.hav_debug_scan_spin_limit.argtypes = [C.c_uint32]
         L.hav_debug_search_spin_limit.restype = C.c_int
@@ -423,6 +426,31 @@ class Sampler:
             return parts, self._read(len(Ms))
         return parts
 
+
+    def ball_query(self, xyz, idx, radius: float, K: int, p: Params | None = None, stream=None):
+        """hav_ball_query_sampled: for each centre xyz[idx[j]] the K lowest-index points
+        strictly inside the radius, found through this Sampler's workspace as the last
+        sample() call on the same cloud left it (call it right after that sample(), with
+        the same parameters). Returns (out [M, K] int32, count [M] int32)."""
+        torch = _torch()
+        _check_xyz(xyz)
+        p = p if p is not None else params()
+        if not (isinstance(idx, torch.Tensor) and idx.is_cuda and idx.dtype == torch.int32
+                and idx.dim() == 1 and idx.is_contiguous()):
+            raise ValueError("idx must be a contiguous int32 CUDA tensor of shape [M]")
+        if self.ws is None:
+            raise HavError(ERR_INVALID_ARG, "ball_query: sample() this cloud first")
+        M = idx.shape[0]
+        out = torch.empty((M, int(K)), dtype=torch.int32, device=xyz.device)
+        cnt = torch.empty(M, dtype=torch.int32, device=xyz.device)
+        st = lib().hav_ball_query_sampled(C.c_void_p(xyz.data_ptr()), xyz.shape[0],
+                                          C.c_void_p(idx.data_ptr()), M, float(radius), int(K),
+                                          C.c_void_p(out.data_ptr()), C.c_void_p(cnt.data_ptr()),
+                                          C.c_void_p(self.ws.data_ptr()), self.ws.numel(), C.byref(p),
+                                          _stream_ptr(stream))
+        if st != OK:
+            raise HavError(st, "hav_ball_query_sampled")
+        return out, cnt
 
     def sample_batch(self, xyz_concat, offsets, Ms, p: Params | None = None, out=None,
                      with_info: bool = False, stream=None):

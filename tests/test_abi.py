@@ -283,3 +283,24 @@ def test_static_entry_rejects_on_the_host(hav):
     assert call(N=hav.STATIC_MAX_POINTS + 1) == hav.ERR_WORKSPACE_TOO_SMALL
     assert call(p=hav.params(spec_depth=7)) == hav.ERR_WORKSPACE_TOO_SMALL
     assert call(p=hav.params(table_scale=1)) == hav.ERR_WORKSPACE_TOO_SMALL
+
+
+def test_sampled_ball_query_rejects_on_the_host(hav):
+    lib = hav.lib()
+    p = hav.params()
+
+    def call(N=100, M=10, r=0.5, K=8, ws_bytes=1 << 30, ws=0x30000, idx=0x20000):
+        return lib.hav_ball_query_sampled(C.c_void_p(0x10000), N, C.c_void_p(idx), M, r, K,
+                                          C.c_void_p(0x40000), None, C.c_void_p(ws), ws_bytes,
+                                          C.byref(p), None)
+
+    E = hav.ERR_INVALID_ARG
+    assert call(idx=0) == E
+    assert call(M=0) == E
+    assert call(M=101) == E
+    assert call(K=0) == E
+    assert call(K=65) == E
+    assert call(r=0.0) == E
+    assert call(r=float("inf")) == E
+    assert call(ws=0x30010) == E
+    assert call(ws_bytes=hav.workspace_size(100, 10) - 1) == hav.ERR_WORKSPACE_TOO_SMALL

@@ -104,3 +104,76 @@ def test_ball_query_sampled_centres(gpu, orc, radius, K):
     _check_ball(gpu, orc, x, x[idx], radius, K, "scene", bq)
     d = np.repeat(synth.random_cloud(3000, 7, scale=2.0), 3, axis=0)  # duplicates
     _check_ball(gpu, orc, d, d[::7], radius, K, "duplicates", bq)
+
+
+# ---------------------------------------------------- grouping on the sampler's own structure
+
+def _check_sampled_ball(gpu, orc, s, x, idx_dev, radius, K, label, rows=None, p=None):
+    """hav_ball_query_sampled on Sampler s (which just sampled x) against the oracle's
+    ball query with centres x[idx], on every centre or on the sampled rows."""
+    idx = idx_dev.cpu().numpy()
+    _note(f"case sampled ball {label} N={x.shape[0]} M={idx.shape[0]} r={radius} K={K}")
+    out, cnt = s.ball_query(_dev(x), idx_dev, radius, K, p)
+    out, cnt = out.cpu().numpy(), cnt.cpu().numpy()
+    sel = np.arange(idx.shape[0]) if rows is None else rows
+    widx, wcnt = orc.ball_query(x, x[idx[sel]], radius, K)
+    assert np.array_equal(cnt[sel], wcnt)
+    assert np.array_equal(out[sel], widx)
+    return out, cnt
+
+
+@pytest.mark.parametrize("radius,K", [(0.2, 16), (0.8, 32), (3.0, 64), (9.0, 1)])
+def test_ball_query_on_sampler_structure(gpu, orc, radius, K):
+    # the set-abstraction block: sample, then group around the picks through the
+    # sampler's sorted cloud (radii below, near and above the spatial cell size)
+    x = synth.scene_planes_blobs(40000, seed=61)
+    s = gpu.Sampler()
+    idx = s.sample(_dev(x), 2000)
+    _check_sampled_ball(gpu, orc, s, x, idx, radius, K, "scene 40k")
+    # a LiDAR sweep (wide, sparse far away) and a cloud with duplicated points
+    y = synth.lidar_points(1 << 15, seed=62)
+    idx = s.sample(_dev(y), 4096)
+    _check_sampled_ball(gpu, orc, s, y, idx, radius, K, "lidar 32k")
+    d = np.repeat(synth.random_cloud(3000, 7, scale=2.0), 3, axis=0)
+    idx = s.sample(_dev(d), 900)
+    _check_sampled_ball(gpu, orc, s, d, idx, radius, K, "duplicates")
+
+
+def test_ball_query_on_sampler_structure_full_size(gpu, orc):
+    # the bench's grouping: 65,536 centres of the 1M scene, r = 0.5, K = 32; the oracle
+    # (brute force) checks 512 rows drawn at random; the next sample call on the same
+    # workspace stays exact (the borrowed lists are returned initialised)
+    x = synth.scene_planes_blobs()
+    s = gpu.Sampler()
+    idx = s.sample(_dev(x), 1 << 16)
+    rows = np.random.default_rng(5).choice(1 << 16, 512, replace=False)
+    _check_sampled_ball(gpu, orc, s, x, idx, 0.5, 32, "scene 1M", rows=rows)
+    again = s.sample(_dev(x), 1 << 18).cpu().numpy()
+    assert np.array_equal(again, orc.sample(x, 1 << 18)[1])
+
+
+def test_ball_query_on_sampler_structure_refuses_other_state(gpu, orc):
+    import torch
+    x = synth.random_cloud(5000, 3, scale=5.0)
+    s = gpu.Sampler()
+    idx = s.sample(_dev(x), 1000)
+    # a workspace that holds another cloud size: rows of -1, count -1
+    y = synth.random_cloud(6000, 4, scale=5.0)
+    s.sample(_dev(y), 1000)
+    out, cnt = s.ball_query(_dev(x), idx, 0.5, 8)
+    assert (out.cpu().numpy() == -1).all() and (cnt.cpu().numpy() == -1).all()
+    # M == N leaves no sorted cloud behind
+    s.sample(_dev(x), 5000)
+    out, cnt = s.ball_query(_dev(x), torch.arange(5000, dtype=torch.int32, device="cuda"), 0.5, 8)
+    assert (cnt.cpu().numpy() == -1).all()
+    # centres outside the cloud get -1 rows; the others are exact
+    idx = s.sample(_dev(x), 1000)
+    bad = idx.clone()
+    bad[::10] = 7000
+    out, cnt = s.ball_query(_dev(x), bad, 0.5, 8)
+    o, c = out.cpu().numpy(), cnt.cpu().numpy()
+    assert (c[::10] == -1).all() and (o[::10] == -1).all()
+    keep = np.ones(1000, bool)
+    keep[::10] = False
+    wi, wc = orc.ball_query(x, x[idx.cpu().numpy()[keep]], 0.5, 8)
+    assert np.array_equal(c[keep], wc) and np.array_equal(o[keep], wi)
