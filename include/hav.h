@@ -98,6 +98,10 @@ typedef struct {
                           default slots (a power of two >= max(N, min(8N, 2^20))), so that their
                           load factor halves per step; 0..3, default 0. Changes the workspace
                           size, never a result. */
+  int32_t bin_points;  /* tuning only: points each binning workgroup sorts (the spatial binning
+                          that precedes the search), 2048, 4096 or 8192; 0 = default (4096).
+                          Fewer points per workgroup mean more workgroups and larger binning
+                          histograms. Changes the workspace size, never a result. */
 } hav_params_t;
 
 /* Per-call report, written by the device into caller memory (info_dev). */

@@ -1,5 +1,5 @@
 """Autotuner for the sampler's tuning fields (speculation depth and budget, search grid,
-table load factor).
+table load factor, and the binning workgroup's share of the cloud).
 
 The tuning fields of hav_params_t never change a result, only the time it takes, so
 the tuner times every candidate on the caller's own input (or a batch), checks that all
@@ -33,10 +33,20 @@ def candidates(depths=DEPTHS, budgets=BUDGETS, grids=GRIDS, tables=TABLES):
         yield dict(spec_depth=d, spec_budget=b, search_blocks=g, table_scale=t)
 
 
+BINS = (0, 2048, 8192)  # bin_points: the binning workgroup's points (0 = 4,096)
+
+
+def with_bins(cands, bins=BINS):
+    """Each candidate once per binning workgroup shape."""
+    for c in cands:
+        for b in bins:
+            yield dict(c, bin_points=b)
+
+
 def batch_candidates():
     """A short candidate list for batches of many LiDAR-sized clouds: speculation depth,
-    table load factor and the default search grid."""
-    return list(candidates(depths=(2, 4), budgets=(16,), grids=(0,), tables=(0, 1)))
+    table load factor and the binning workgroup's points, with the default search grid."""
+    return list(with_bins(candidates(depths=(2, 4), budgets=(16,), grids=(0,), tables=(0, 1))))
 
 
 def _time(fn, reps: int) -> float:

@@ -303,14 +303,27 @@ struct Cloud {
 // binning blocks and one more, which starts layer 1 while the others scatter).
 enum Kind : int { kKBBox = 0, kKBin, kKBScan, kKTile, kKOne, kKScan, kKScat, kKinds };
 
-__host__ __device__ inline int64_t blocks_of(int kind, int64_t n) {
+// Layout tuning code: the tuning field table_scale in bits 0-3, and the binning block's
+// points (the tuning field bin_points) in bits 4-5: 0 = 4,096, 1 = 2,048, 2 = 8,192.
+__host__ __device__ inline int tab_scale(int tcode) { return tcode & 15; }
+__host__ __device__ inline int bin_shift(int tcode) {
+  const int b = (tcode >> 4) & 3;
+  return b == 1 ? 11 : (b == 2 ? 13 : 12);
+}
+
+// bshift: log2 of the points of a binning block (a tuning field: the binning
+// workgroup's share of the cloud).
+__host__ __device__ inline int64_t blocks_of(int kind, int64_t n, int bshift = 12) {
   switch (kind) {
     case kKBBox: return n < 2048 ? 1 : (n + 2047) / 2048 < kMaxBBoxBlocks ? (n + 2047) / 2048 : kMaxBBoxBlocks;
-    case kKBin: return n < 4096 ? 1 : (n + 4095) / 4096 < kMaxBinBlocks ? (n + 4095) / 4096 : kMaxBinBlocks;
+    case kKBin: {
+      const int64_t bp = int64_t(1) << bshift;
+      return n < bp ? 1 : (n + bp - 1) / bp < kMaxBinBlocks ? (n + bp - 1) / bp : kMaxBinBlocks;
+    }
     case kKBScan: return kBinChunks;
     case kKTile: return (n + kTile - 1) / kTile;
     case kKOne: return 1;
-    case kKScat: return blocks_of(kKBin, n) + 1;
+    case kKScat: return blocks_of(kKBin, n, bshift) + 1;
     default: return (n + kScanTile - 1) / kScanTile;
   }
 }
@@ -322,10 +335,11 @@ struct BlockRef {
 struct alignas(256) BatchDev {
   int32_t B;
   int32_t depth;               // speculation depth (the same for every cloud of a call)
+  int32_t bshift;              // log2 points of a binning block (likewise)
   int32_t kind_off[kKinds];    // where each kind's block map starts in bmap
   int32_t kind_total[kKinds];
   int32_t nact;                // clouds searching in the current layer
-  int32_t pad[2];
+  int32_t pad[1];
   Cloud* clouds;               // [B]
   BlockRef* bmap;              // [sum of kind_total]
   int32_t* act;                // [B] the searching clouds
@@ -3021,7 +3035,8 @@ __host__ __device__ inline size_t align_up(size_t x) { return (x + kAlign - 1) &
 int depth_of(const hav_params_t* p) {
   return p->spec_depth == 0 ? kDefaultDepth : p->spec_depth;
 }
-int tscale_of(const hav_params_t* p) { return p->table_scale; }
+int bin_code(int32_t bin_points) { return bin_points == 2048 ? 1 : (bin_points == 8192 ? 2 : 0); }
+int tscale_of(const hav_params_t* p) { return p->table_scale | (bin_code(p->bin_points) << 4); }
 
 // Table slots for a stage of n points: a power of two >= n, and >= min(8n, 2^20), times
 // 2^tscale (the tuning field table_scale), at most 2^31. A table never holds more keys
@@ -3070,8 +3085,8 @@ __host__ __device__ inline Layout make_layout(int64_t n, int depth, int tscale, 
   L.n_ws = n;
   L.pmode = pmode;
   L.tscale = tscale;
-  L.cap_ws = table_cap(n, tscale);
-  L.sel_ws = sel_cap_of(n, tscale);
+  L.cap_ws = table_cap(n, tab_scale(tscale));
+  L.sel_ws = sel_cap_of(n, tab_scale(tscale));
   L.ntile_ws = static_cast<int32_t>((n + kTile - 1) / kTile);
   L.nscan_ws = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
   L.ncmax = depth;
@@ -3086,7 +3101,7 @@ __host__ __device__ inline Layout make_layout(int64_t n, int depth, int tscale, 
   L.tag_s = o;  o = align_up(o + NP);
   L.tag_o = o;  o = align_up(o + N);
   L.part = o;   o = align_up(o + static_cast<size_t>(kMaxBBoxBlocks) * 8 * 4);
-  L.bh = o;     o = align_up(o + static_cast<size_t>(kBins) * blocks_of(kKBin, n) * 4);
+  L.bh = o;     o = align_up(o + static_cast<size_t>(kBins) * blocks_of(kKBin, n, bin_shift(tscale)) * 4);
   L.binpre = o; o = align_up(o + static_cast<size_t>(kBins) * 4);
   L.bsum = o;   o = align_up(o + static_cast<size_t>(kBinChunks) * 4);
   L.ckeys = o;  o = align_up(o + tabs * L.cap_ws * 8);
@@ -3147,9 +3162,9 @@ __host__ __device__ inline Ws make_ws(char* base, const Layout& L, int64_t n) {
   w.ntile = static_cast<int32_t>((n + kTile - 1) / kTile);
   w.npad = static_cast<int64_t>(w.ntile) * kTile;
   w.nscan = static_cast<int32_t>((n + kScanTile - 1) / kScanTile);
-  w.nbb = static_cast<int32_t>(blocks_of(kKBin, n));
+  w.nbb = static_cast<int32_t>(blocks_of(kKBin, n, bin_shift(L.tscale)));
   w.nbbox = static_cast<int32_t>(blocks_of(kKBBox, n));
-  w.cap = table_cap(n, L.tscale);
+  w.cap = table_cap(n, tab_scale(L.tscale));
   w.cmask = w.cap - 1;
   w.cap_ws = L.cap_ws;
   w.ntile_ws = L.ntile_ws;
@@ -3182,6 +3197,8 @@ bool params_any_ok(const hav_params_t* p) {
   if (p->spec_budget < 0 || p->spec_budget > 1024) return false;
   if (p->search_blocks < 0 || p->search_blocks > 65536) return false;
   if (p->table_scale < 0 || p->table_scale > 3) return false;
+  if (p->bin_points != 0 && p->bin_points != 2048 && p->bin_points != 4096 && p->bin_points != 8192)
+    return false;
   if (!std::isfinite(p->trim_window) || p->trim_window > 64.0f) return false;
   if (p->select < HAV_SELECT_CENTRE_CLOSEST || p->select > HAV_SELECT_MEAN) return false;
   for (int a = 0; a < 3; ++a) {
@@ -3276,7 +3293,7 @@ __host__ __device__ inline Cloud make_cloud(const CloudSpec& c, const ParamLite&
   P.fixed = q.fixed;
   P.magic = magic_of(L);
   P.cap = cd.w.cap;
-  P.sel_cap = sel_cap_of(cd.w.n, q.tscale);
+  P.sel_cap = sel_cap_of(cd.w.n, tab_scale(q.tscale));
   P.spec_mult = q.spec_budget ? static_cast<float>(q.spec_budget) : kSpecMult;
   P.win_sigma = q.trim_window == 0.0f ? kWinSigma : q.trim_window;
   P.select = q.select;
@@ -3329,6 +3346,7 @@ __global__ void __launch_bounds__(64) k_setup(SetupArgs a) {
     BatchDev* bd = a.bd;
     bd->B = a.B;
     bd->depth = a.q.depth;
+    bd->bshift = bin_shift(a.q.tscale);
     for (int k = 0; k < kKinds; ++k) {
       bd->kind_off[k] = a.kind_off[k];
       bd->kind_total[k] = a.kind_total[k];
@@ -3352,7 +3370,7 @@ __global__ void __launch_bounds__(kThreads) k_map(BatchDev* bd) {
   uint32_t carry = 0;
   for (int c0 = 0; c0 < B; c0 += kThreads) {
     const int c = c0 + threadIdx.x;
-    const uint32_t nb = c < B ? static_cast<uint32_t>(blocks_of(kind, bd->clouds[c].w.n)) : 0u;
+    const uint32_t nb = c < B ? static_cast<uint32_t>(blocks_of(kind, bd->clouds[c].w.n, bd->bshift)) : 0u;
     uint32_t ex;
     const uint32_t tot = block_exclusive_scan<kThreads>(nb, &ex, s_tmp);
     for (uint32_t b = 0; b < nb; ++b) {
@@ -3683,12 +3701,12 @@ struct BatchLayout {
   int32_t kind_off[kKinds] = {}, kind_total[kKinds] = {};
 };
 
-BatchLayout make_batch_layout(int32_t B, const int64_t* n) {
+BatchLayout make_batch_layout(int32_t B, const int64_t* n, int bshift) {
   BatchLayout BL;
   int64_t off = 0;
   for (int k = 0; k < kKinds; ++k) {
     int64_t t = 0;
-    for (int32_t i = 0; i < B; ++i) t += blocks_of(k, n[i]);
+    for (int32_t i = 0; i < B; ++i) t += blocks_of(k, n[i], bshift);
     BL.kind_off[k] = static_cast<int32_t>(off);
     BL.kind_total[k] = static_cast<int32_t>(t);
     off += t;
@@ -3787,7 +3805,7 @@ bool batch_args_ok(int32_t B, const int64_t* N, const int64_t* M) {
 
 BatchWsLayout make_batch_ws_layout(int32_t B, const int64_t* N, int depth, int tscale) {
   BatchWsLayout W;
-  W.BL = make_batch_layout(B, N);
+  W.BL = make_batch_layout(B, N, bin_shift(tscale));
   size_t o = align_up(W.BL.total);
   W.seg.resize(static_cast<size_t>(B));
   for (int32_t i = 0; i < B; ++i) {
@@ -3824,6 +3842,8 @@ hav_params_t hav_params_default(void) {
   p.trim_window = 0.0f;
   p.select = HAV_SELECT_CENTRE_CLOSEST;
   p.select_seed = 0;
+  p.table_scale = 0;
+  p.bin_points = 0;
   return p;
 }
 

@@ -41,6 +41,7 @@ class Params(C.Structure):
         ("select", C.c_int32),
         ("select_seed", C.c_uint32),
         ("table_scale", C.c_int32),
+        ("bin_points", C.c_int32),
     ]
 
 
@@ -226,13 +227,14 @@ def status_string(status: int) -> str:
 
 def params(layers=2, layer_ratio=4, t_max=20, sigma=0.05, aspect=(1.0, 1.0, 1.0),
            fixed_voxel=None, spec_depth=0, spec_budget=0, search_blocks=0,
-           trim_window=0.0, select=0, select_seed=0, table_scale=0) -> Params:
+           trim_window=0.0, select=0, select_seed=0, table_scale=0, bin_points=0) -> Params:
     p = lib().hav_params_default()
     p.layers, p.layer_ratio, p.t_max, p.sigma = layers, layer_ratio, t_max, sigma
     p.spec_depth, p.spec_budget, p.search_blocks = spec_depth, spec_budget, search_blocks
     p.trim_window = trim_window
     p.select, p.select_seed = select, select_seed
     p.table_scale = table_scale
+    p.bin_points = bin_points
     for a in range(3):
         p.aspect[a] = aspect[a]
     if fixed_voxel is not None:
@@ -309,7 +311,8 @@ class Sampler:
             self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
             self.ws_key = None
         pmode = int(p.select) if int(p.select) >= SELECT_CENTRE else 0  # layout differs
-        key = (N if isinstance(N, tuple) else int(N), int(p.spec_depth), pmode, int(p.table_scale))
+        key = (N if isinstance(N, tuple) else int(N), int(p.spec_depth), pmode, int(p.table_scale),
+               int(p.bin_points))
         if self.ws_key != key:
             if isinstance(N, tuple):
                 st = lib().hav_batch_workspace_init(len(N), _i64(N), C.byref(p),

@@ -49,8 +49,9 @@ def test_struct_layout_matches_header(hav, tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu\n", sizeof(hav_params_t), offsetof(hav_params_t, sigma),
          offsetof(hav_params_t, flags), offsetof(hav_params_t, fixed_voxel), sizeof(hav_info_t));
-  printf("%zu %zu %zu %zu\n", offsetof(hav_info_t, m), offsetof(hav_info_t, count),
-         offsetof(hav_info_t, padded), offsetof(hav_params_t, table_scale));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(hav_info_t, m), offsetof(hav_info_t, count),
+         offsetof(hav_info_t, padded), offsetof(hav_params_t, table_scale),
+         offsetof(hav_params_t, bin_points));
   return 0;
 }
 ''')
@@ -59,7 +60,7 @@ int main(void) {
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     P, I = hav.Params, hav.Info
     want = [C.sizeof(P), P.sigma.offset, P.flags.offset, P.fixed_voxel.offset, C.sizeof(I),
-            I.m.offset, I.count.offset, I.padded.offset, P.table_scale.offset]
+            I.m.offset, I.count.offset, I.padded.offset, P.table_scale.offset, P.bin_points.offset]
     assert [int(x) for x in out] == want
 
 
@@ -120,7 +121,7 @@ def test_host_rejects_bad_arguments(hav):
                dict(fixed_voxel=0.0), dict(fixed_voxel=float("nan")), dict(spec_depth=8),
                dict(spec_depth=-1), dict(spec_budget=-1), dict(spec_budget=1025),
                dict(search_blocks=-1), dict(search_blocks=65537), dict(table_scale=-1),
-               dict(table_scale=4),
+               dict(table_scale=4), dict(bin_points=1000), dict(bin_points=16384),
                dict(trim_window=64.5), dict(trim_window=float("nan")), dict(trim_window=float("inf")),
                dict(select=2), dict(select=-1)):
         assert _call(hav, p=hav.params(**kw)) == E, kw

@@ -71,7 +71,8 @@ def test_batch_small_uneven(gpu, orc):
 @pytest.mark.parametrize("kw", [dict(layers=1), dict(layers=3, sigma=0.0), dict(t_max=3),
                                 dict(fixed_voxel=0.5), dict(aspect=(1.0, 2.0, 0.5)),
                                 dict(spec_depth=1), dict(spec_depth=3), dict(trim_window=-1.0),
-                                dict(trim_window=0.02), dict(select=1, select_seed=7), dict(table_scale=1)])
+                                dict(trim_window=0.02), dict(select=1, select_seed=7), dict(table_scale=1),
+                                dict(bin_points=2048), dict(bin_points=8192, spec_depth=2)])
 def test_batch_params(gpu, orc, kw):
     clouds, Ms = _mixed_small()
     _check_batch(gpu, orc, clouds, Ms, gpu.params(**kw), label=str(kw))

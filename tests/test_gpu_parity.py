@@ -331,10 +331,21 @@ def test_split_ticket_boundary(gpu, orc, n, depth):
 @pytest.mark.parametrize("kw", [dict(spec_budget=1), dict(spec_budget=1024), dict(search_blocks=1),
                                 dict(search_blocks=7), dict(search_blocks=5000),
                                 dict(spec_depth=3, spec_budget=1, search_blocks=64), dict(table_scale=2),
-                                dict(table_scale=3, spec_depth=7)])
+                                dict(table_scale=3, spec_depth=7), dict(bin_points=2048),
+                                dict(bin_points=8192), dict(bin_points=2048, table_scale=1)])
 def test_tuning_fields_do_not_change_results(gpu, orc, kw):
     x = synth.scene_planes_blobs(60000, seed=23)
     _check(gpu, orc, x, 15000, gpu.params(**kw), f"tuning {kw}")
+
+
+@pytest.mark.parametrize("bp", [2048, 8192])
+def test_binning_block_shape_at_scale(gpu, orc, bp):
+    # the binning workgroup's share changes the binning blocks (and, past 512 blocks, is
+    # capped): a 1M scene and a 2M+ ragged cloud, results unchanged
+    x = synth.scene_planes_blobs()
+    _check(gpu, orc, x, x.shape[0] // 4, gpu.params(bin_points=bp), f"bin points {bp} scene 1M")
+    y = synth.scene_planes_blobs((1 << 21) + 77, seed=12)
+    _check(gpu, orc, y, y.shape[0] // 16, gpu.params(bin_points=bp), f"bin points {bp} 2M ragged")
 
 
 @pytest.mark.parametrize("tw", [-1.0, 0.02, 0.5, 64.0])
