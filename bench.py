@@ -296,15 +296,65 @@ def variants_leg(torch, hav, synth) -> dict:
     (_, cov), ms_cov = timed(lambda: nn.d2(bs, big), reps=5)
     # the grouping that follows sampling: 32 neighbours within 0.5 m of 65,536 sampled
     # centres of the same cloud
-    cidx = hav.Sampler().sample(big, 1 << 16)
+    sb = hav.Sampler()
+    cidx = sb.sample(big, 1 << 16)
     cen = big[cidx.long()].contiguous()
     bq = hav.BallQuery()
     (_, cnt), ms_bq = timed(lambda: bq.query(big, cen, 0.5, 32), reps=5)
+    # the same grouping through the sampler's own sorted cloud (no second sort), checked
+    # equal to the standalone query
+    (sidx, scnt), ms_sbq = timed(lambda: sb.ball_query(big, cidx, 0.5, 32), reps=5)
+    gidx, _ = bq.query(big, cen, 0.5, 32)
+    assert torch.equal(sidx, gidx) and torch.equal(scnt, cnt), "grouping routes differ"
     return {"workload": "KITTI-like 16,384 -> 4,096 (half box, half ground plane); fixed voxel for "
                         "RVS = the 1-layer adaptive size %.4f" % s_fix, "strategies": out,
             "covering_1M_262k": {"radius": round(float(torch.sqrt(cov).cpu()[0]), 4), "ms": round(ms_cov, 3)},
             "ball_query_1M_65k_r0.5_k32": {"ms": round(ms_bq, 3),
-                                           "mean_in_ball": round(float(cnt.double().mean().cpu()), 1)}}
+                                           "mean_in_ball": round(float(cnt.double().mean().cpu()), 1),
+                                           "on_sampler_structure_ms": round(ms_sbq, 3)}}
+
+
+def quality_leg(torch, hav, synth) -> dict:
+    """Quality context (Sec. 3.1, Fig. 3): the covering radius (largest distance from a
+    point of a stage's input to its nearest sample) of HAVSampler, farthest point
+    sampling (start 0) and random point sampling at each stage of the LiDAR chain
+    (16,384 -> 4,096 -> 1,024 -> 256 from the sweep) and at stages 2-3 of the scene chain
+    (262,144 -> 65,536 -> 16,384 from the 1M scene's first stage). Every stage works on
+    HAVSampler's previous stage, so the three samplers see the same input. GPU samplers,
+    exact GPU nearest-sample distances (hav_nn)."""
+    nn = hav.NearestSample()
+    f, r = hav.FPS(), hav.RPS()
+
+    def cover(x, idx):
+        _, mx = nn.d2(x[idx.long()].contiguous(), x)
+        return round(float(torch.sqrt(mx).cpu()[0]), 4)
+
+    def chain_rows(x, Ms, skip):
+        rows = []
+        parts = hav.Sampler().chain(x, Ms)
+        cur = x
+        for j, m in enumerate(Ms):
+            if j >= skip:
+                loc = hav.Sampler().sample(cur, m)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fi = f.sample(cur, m)
+                e1.record()
+                torch.cuda.synchronize()
+                ri = r.sample(cur.shape[0], m, 1000 + j)
+                rows.append({"stage": f"{cur.shape[0]} -> {m}", "hav": cover(cur, loc),
+                             "fps": cover(cur, fi), "rps": cover(cur, ri),
+                             "fps_ms": round(e0.elapsed_time(e1), 2)})
+                print(f"bench: quality {rows[-1]}", file=sys.stderr, flush=True)
+            cur = x[parts[j].long()].contiguous()
+        return rows
+
+    lidar = torch.from_numpy(synth.lidar_scan()).cuda()
+    scene = torch.from_numpy(synth.scene_planes_blobs()).cuda()
+    N = scene.shape[0]
+    return {"metric": "covering radius (m), lower is better",
+            "lidar_chain": chain_rows(lidar, [16384, 4096, 1024, 256], 0),
+            "scene_chain_stages_2_3": chain_rows(scene, [N // 4, N // 16, N // 64], 1)}
 
 
 def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
@@ -379,9 +429,29 @@ def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
                 "batches": int(stats["batches"]), "max_batch": int(stats["max_batch_seen"]),
                 "slots": int(stats["slots"]), "hbm_GiB": round(stats["hbm_used"] / 2 ** 30, 2)}
 
+    def capacity(max_batch, streams, count):
+        """Served throughput with every request waiting at once (the first `count`
+        requests of the trace, submitted back to back): the server's capacity."""
+        srv = hav.Server(budget, max_batch=max_batch, streams=streams)
+        try:
+            t0 = time.perf_counter()
+            tickets = [srv.submit(views[i], int(tr["m"][i])) for i in range(count)]
+            for t in tickets:
+                assert srv.wait(t)[0] == 0
+            el = time.perf_counter() - t0
+            stats = srv.stats()
+        finally:
+            srv.close()
+        pts = float(tr["n"][:count].sum())
+        return {"Mpoints_per_s": round(pts / el / 1e6, 1), "requests_per_s": round(count / el, 1),
+                "batches": int(stats["batches"]), "max_batch": int(stats["max_batch_seen"])}
+
     budget = 48 << 30
     cont = replay(64, 2)
     fifo = replay(1, 1)
+    ncap = min(2000, n_requests)
+    cap_cont = capacity(64, 2, ncap)
+    cap_fifo = capacity(1, 1, ncap)
     # the sampled requests: served (in the mix and FIFO) = alone
     s = hav.Sampler()
     agree = 0
@@ -397,6 +467,8 @@ def serve_leg(torch, hav, synth, n_requests: int, warm: int) -> dict:
             "hbm_budget_GiB": budget / 2 ** 30,
             "continuous": cont, "fifo": fifo,
             "p99_speedup": round(fifo["p99_ms"] / cont["p99_ms"], 3),
+            "capacity": {"requests": ncap, "continuous": cap_cont, "fifo": cap_fifo,
+                         "speedup": round(cap_cont["Mpoints_per_s"] / cap_fifo["Mpoints_per_s"], 3)},
             "verified_vs_alone": f"{agree} of {len(check)} sampled requests identical"}
 
 
@@ -476,6 +548,8 @@ def main() -> int:
                     help="skip the latency comparison with FPS and RPS (Fig. 7 of the paper)")
     ap.add_argument("--no-sizes", action="store_true",
                     help="skip the same stage at 2^18 .. 2^24 input points")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the covering-radius comparison with FPS and RPS")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 256 MiB read + 256 MiB write elementwise kernel (counter "
@@ -584,6 +658,8 @@ def main() -> int:
     if not args.no_variants:
         result["variants"] = variants_leg(torch, hav, synth)
         print(f"bench: variants {result['variants']}", file=sys.stderr, flush=True)
+    if not args.no_quality:
+        result["quality"] = quality_leg(torch, hav, synth)
     if not args.no_cpu_baseline:
         cpu = host_cpu()
         result["cpu_baseline"] = cpu_baseline(x, M, args.cpu_seconds, cpu)
