@@ -333,8 +333,9 @@ hav_status_t hav_sample_points(const float* xyz, int64_t N, int64_t M, const hav
  * multiply-add, so results are reproducible bit for bit. idx holds M indices in
  * selection order (not sorted). Coordinates must be finite.
  *   xyz [N][3] float32 device; 1 <= M <= N <= HAV_FPS_MAX_POINTS; 0 <= start < N.
- *   blocks: 0 = automatic; else 1..256 blocks share the cloud (cooperative launch when
- *   more than one; N must fit 4 points per thread of 1024-thread blocks).
+ *   blocks: 0 = automatic; else 1..256 blocks share the cloud (N must fit 4 points per
+ *   thread of 1024-thread blocks, and the device must hold all the blocks at once, else
+ *   HAV_ERR_HIP).
  *   ws: hav_fps_workspace_size(N) bytes of device memory, no initialisation needed;
  *   one call at a time per workspace.
  * Returns HAV_ERR_INVALID_ARG / HAV_ERR_WORKSPACE_TOO_SMALL / HAV_ERR_HIP at once. A

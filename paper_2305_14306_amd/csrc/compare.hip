@@ -9,7 +9,11 @@
 // candidate in a per-step slot (value words, then a tag word written with release
 // order) and every block reads all slots (acquire) and takes the same maximum, so a
 // step costs one exchange instead of a kernel boundary. The blocks must all be
-// resident: the launch is cooperative, and every wait is bounded.
+// resident at once: the host launches at most as many as the device holds (its
+// occupancy times its compute units, one 1024-thread block per compute unit), and every
+// wait is bounded, so a grid that other work keeps from starting whole raises the error
+// flag instead of hanging. (An ordinary launch, not a cooperative one: a cooperative
+// launch also made rocprofv3 fail when the process ended.)
 //
 // RPS keeps the m points of smallest SplitMix64 key and returns them in ascending
 // order. The m-th smallest of n evenly spread keys lies near the fraction m / (n + 1)
@@ -19,7 +23,6 @@
 // pass writes the kept indices in order (block counts chained in dispatch order).
 
 #include <hip/hip_runtime.h>
-#include <hip/hip_cooperative_groups.h>
 
 #include <cmath>
 #include <cstdint>
@@ -218,13 +221,25 @@ __global__ void k_fps_clear(FpsSlot* slots, uint32_t* err) {
 
 size_t fps_ws_bytes() { return 2 * kFpsMaxBlocks * sizeof(FpsSlot) + 256; }
 
+// Blocks of k_fps<kT, PER> the current device holds at once (0 if unknown).
+template <int kT, int PER>
+int fps_resident_blocks() {
+  int dev = 0, per_cu = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_fps<kT, PER>), kT,
+                                                    0) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+// hipErrorInvalidConfiguration when the device cannot hold `blocks` blocks at once.
 template <int kT, int PER>
 hipError_t launch_fps(int blocks, const float* xyz, int64_t n, int64_t m, int64_t start, int32_t* out,
                       FpsSlot* slots, uint32_t* err, hipStream_t st) {
-  void* args[] = {&xyz, &n, &m, &start, &out, &slots, &err};
-  const void* fn = reinterpret_cast<const void*>(&k_fps<kT, PER>);
-  if (blocks == 1) return hipLaunchKernel(fn, dim3(1), dim3(kT), args, 0, st);
-  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kT), args, 0, st);
+  if (blocks > 1 && blocks > fps_resident_blocks<kT, PER>()) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_fps<kT, PER>), dim3(blocks), dim3(kT), 0, st, xyz, n, m, start, out, slots, err);
+  return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------- RPS
