@@ -2876,9 +2876,15 @@ __global__ void __launch_bounds__(kThreads) k_compose(const int32_t* __restrict_
 // cell offsets of the scan), so the points near a centre are the points of the few cells
 // its ball overlaps. No second sort of the cloud is made: the centres are bucketed by the
 // tile holding them (in the selection's per-tile lists, free once a call has ended), and
-// one block per tile stages, cell by cell, the cells its centres' balls overlap.
+// one block per tile stages the cells its centres' balls overlap through LDS, in cell
+// order, a buffer at a time; a wave tests 64 staged points against one centre per step.
 constexpr int kBallMaxK = 64;
-constexpr int kBallStage = 1024;  // points staged in LDS at a time
+constexpr int kBallBuf = 2048;        // points staged in LDS per fill
+constexpr int kBallFill = 64;         // cells (or parts of one) per fill: one per lane
+constexpr int kBallRowWords = 5120;   // LDS words for the group's sorted rows
+constexpr int kBallGroup = kThreads;  // centres per group at most
+static_assert(kBins / 64 == 64, "one word of the needed-cell bitmap per lane");
+static_assert(kBallBuf % kThreads == 0, "staged points per thread");
 
 __device__ __forceinline__ bool ball_ready(const Ws& w) {
   return w.h->binned_n == w.n && w.h->frame.status == HAV_OK;
@@ -2888,6 +2894,18 @@ __device__ __forceinline__ uint32_t cell_start(const Ws& w, uint32_t code) {
   return code >= static_cast<uint32_t>(kBins) ? static_cast<uint32_t>(w.n)
                                               : w.binpre[code] + w.bsum[code / kBinChunk];
 }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int32_t lane_of(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 // Bucket each centre j (point idx[j]) by the tile holding its sorted slot. A centre
 // that is not a point of the cloud, or any centre when the workspace does not hold this
@@ -2914,116 +2932,257 @@ __global__ void __launch_bounds__(kThreads) k_ball_bucket(Ws w, const int32_t* _
 
 // One block per tile: the K lowest indices i with d2 < r2 for each of its centres, d2 in
 // float32 as ((dx dx + dy dy) + dz dz) of the original coordinates (dx = x_i - c), the
-// rest of a row repeating its first entry; count = points inside. A centre scans the
+// rest of a row repeating its first entry; count = points inside. A centre needs the
 // cells whose index range covers its coordinate offset +- the radius widened by 1e-3 of
 // itself and by 1e-6 of the offset (more than the rounding of d2, of dx and of the
 // offsets r = fl(p - origin) the cells were assigned by); cell_index is non-decreasing
-// in r, so every point inside the ball lies in a scanned cell.
+// in r, so every point inside the ball lies in a needed cell.
+//
+// The block takes its centres in groups (as many as their rows fit in LDS). For a group
+// it marks the needed cells in a 4,096-bit map, then walks the map in cell order: wave 0
+// lists the next needed cells and cuts them to the buffer (a cell larger than the
+// buffer is taken in parts), every thread stages its share of the points (the sorted
+// record for the original index, then the original coordinates), and each wave takes
+// every fourth centre of the group: the fill's cells inside the centre's cell box are
+// found with one ballot (a cell per lane), and their points are tested 64 at a time.
+// A centre's row of the K lowest indices so far lives one entry per lane while its wave
+// works on it (insertion: a ballot counts the smaller entries, the larger ones shift up
+// a lane) and in LDS between fills. Each point of a needed cell is staged once per
+// group, so no index enters a row twice.
 __global__ void __launch_bounds__(kThreads) k_ball_group(Ws w, const float* __restrict__ xyz,
                                                         const int32_t* __restrict__ idx, float radius,
                                                         float r2, int32_t K, int32_t* out, int32_t* count) {
   if (!ball_ready(w)) return;  // (then the lists were not touched, and may be laid out otherwise)
   const int t = blockIdx.x;
-  const int nc = w.scn[t];
-  if (nc == 0) return;
+  const int nc_all = min(w.scn[t], kTile);
+  if (nc_all == 0) return;
+  __shared__ uint32_t s_cs[kBins + 1];
+  __shared__ float4 s_buf[kBallBuf];
+  __shared__ int32_t s_row[kBallRowWords];
+  __shared__ float4 s_cen[kBallGroup];
+  __shared__ uint32_t s_box[3][kBallGroup];
+  __shared__ uint32_t s_tot[kBallGroup];
+  __shared__ unsigned long long s_need[kBins / 64];
+  __shared__ uint32_t s_list[kBallFill];
+  __shared__ uint32_t s_fxy[kBallFill], s_fz[kBallFill], s_foff[kBallFill], s_flen[kBallFill],
+      s_fbeg[kBallFill];
+  __shared__ int s_nf, s_ntot, s_cur, s_more;
+  __shared__ uint32_t s_curoff;
   __shared__ CellCoder s_kc;
   __shared__ float s_mn[3];
-  __shared__ uint32_t s_box[6];
-  __shared__ float4 s_pt[kBallStage];
-  __shared__ int32_t s_row[kThreads * kBallMaxK];
-  int32_t* row = s_row + threadIdx.x * kBallMaxK;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int kWaves = kThreads / 64;
   if (threadIdx.x == 0) {
     const Frame f = w.h->frame;
     s_kc = make_coder(f);
     for (int a = 0; a < 3; ++a) s_mn[a] = f.mn[a];
   }
+  for (int c = threadIdx.x; c <= kBins; c += kThreads) s_cs[c] = cell_start(w, c);
   __syncthreads();
-  const int ncap = nc < kTile ? nc : kTile;
-  for (int c0 = 0; c0 < ncap; c0 += kThreads) {
-    const int k = c0 + static_cast<int>(threadIdx.x);
-    const bool has = k < ncap;
-    int64_t j = -1;
-    float cx[3] = {0.0f, 0.0f, 0.0f};
-    uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
-    if (has) {
-      j = w.scl[static_cast<int64_t>(t) * kTile + k];
+  const CellCoder kc = s_kc;
+  const int G = min(kBallGroup, kBallRowWords / K);
+  for (int g0 = 0; g0 < nc_all; g0 += G) {
+    const int ng = min(G, nc_all - g0);
+    if (threadIdx.x < kBins / 64) s_need[threadIdx.x] = 0ull;
+    for (int q = threadIdx.x; q < ng * K; q += kThreads) s_row[q] = INT32_MAX;
+    if (threadIdx.x == 0) {
+      s_cur = 0;
+      s_curoff = 0u;
+    }
+    __syncthreads();
+    if (static_cast<int>(threadIdx.x) < ng) {
+      const int c = threadIdx.x;
+      const int32_t j = w.scl[static_cast<int64_t>(t) * kTile + g0 + c];
       const int64_t ci = idx[j];
+      float cx[3];
+      uint32_t lo[3], hi[3];
       for (int a = 0; a < 3; ++a) {
         cx[a] = xyz[3 * ci + a];
         const float rc = cx[a] - s_mn[a];
         const float rad = radius * 1.001f + 1e-6f * (fabsf(rc) + radius);
-        lo[a] = cell_index(rc - rad, s_kc, a);
-        hi[a] = cell_index(rc + rad, s_kc, a);
+        lo[a] = cell_index(rc - rad, kc, a);
+        hi[a] = cell_index(rc + rad, kc, a);
+        s_box[a][c] = lo[a] | (hi[a] << 16);
       }
+      s_cen[c] = make_float4(cx[0], cx[1], cx[2], __int_as_float(j));
+      s_tot[c] = 0u;
+      for (uint32_t iz = lo[2]; iz <= hi[2]; ++iz)
+        for (uint32_t iy = lo[1]; iy <= hi[1]; ++iy)
+          for (uint32_t ix = lo[0]; ix <= hi[0]; ++ix) {
+            const uint32_t cc[3] = {ix, iy, iz};
+            const uint32_t code = cell_code_of(cc, kc);
+            atomicOr(&s_need[code >> 6], 1ull << (code & 63));
+          }
     }
-    // the block's box of cells
-    __shared__ uint32_t s_red[kThreads / 64][6];
-    {
-      const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-      uint32_t r[6];
-      for (int a = 0; a < 3; ++a) {
-        r[a] = __ockl_wfred_min_u32(lo[a]);
-        r[3 + a] = __ockl_wfred_max_u32(hi[a]);
+    __syncthreads();
+    for (;;) {
+      // wave 0: the next needed cells in cell order (a lane per bitmap word)
+      const int cur = s_cur;
+      const uint32_t curoff = s_curoff;
+      uint32_t tot_codes = 0u;
+      if (wv == 0) {
+        unsigned long long wd = s_need[lane];
+        const int cw = cur >> 6;
+        if (lane < cw) wd = 0ull;
+        else if (lane == cw) wd &= ~0ull << (cur & 63);
+        const uint32_t cnt = static_cast<uint32_t>(__popcll(wd));
+        const uint32_t inc = wave_incl_scan(cnt);
+        tot_codes = static_cast<uint32_t>(__shfl(static_cast<int>(inc), 63, 64));
+        uint32_t r = inc - cnt;
+        while (wd && r < static_cast<uint32_t>(kBallFill)) {
+          s_list[r++] = static_cast<uint32_t>(lane * 64 + __ffsll(static_cast<long long>(wd)) - 1);
+          wd &= wd - 1;
+        }
       }
-      if (lane == 0)
-        for (int q = 0; q < 6; ++q) s_red[wv][q] = r[q];
       __syncthreads();
-      if (threadIdx.x < 6) {
-        const int q = threadIdx.x;
-        uint32_t v = q < 3 ? 0xFFFFFFFFu : 0u;
-        for (int ww = 0; ww < kThreads / 64; ++ww) v = q < 3 ? min(v, s_red[ww][q]) : max(v, s_red[ww][q]);
-        s_box[q] = v;
-      }
-      __syncthreads();
-    }
-    int n = 0;
-    int64_t total = 0;
-    for (uint32_t iz = s_box[2]; iz <= s_box[5]; ++iz)
-      for (uint32_t iy = s_box[1]; iy <= s_box[4]; ++iy)
-        for (uint32_t ix = s_box[0]; ix <= s_box[3]; ++ix) {
-          const bool mine = has && ix >= lo[0] && ix <= hi[0] && iy >= lo[1] && iy <= hi[1] &&
-                            iz >= lo[2] && iz <= hi[2];
-          if (!__syncthreads_or(mine)) continue;
-          const uint32_t cc[3] = {ix, iy, iz};
-          const uint32_t code = cell_code_of(cc, s_kc);
-          const uint32_t cb = cell_start(w, code), ce = cell_start(w, code + 1);
-          for (uint32_t p0 = cb; p0 < ce; p0 += kBallStage) {
-            const int np = static_cast<int>(min(static_cast<uint32_t>(kBallStage), ce - p0));
-            for (int q = threadIdx.x; q < np; q += kThreads) {
-              const float4 rec = w.pts[slot_of(static_cast<int64_t>(p0) + q)];
-              const int64_t o = __float_as_int(rec.w);
-              s_pt[q] = make_float4(xyz[3 * o], xyz[3 * o + 1], xyz[3 * o + 2], rec.w);
-            }
-            __syncthreads();
-            if (mine) {
-              for (int q = 0; q < np; ++q) {
-                const float4 pq = s_pt[q];
-                const float dx = pq.x - cx[0], dy = pq.y - cx[1], dz = pq.z - cx[2];
-                const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-                const float d2 = (xx + yy) + zz;
-                if (!(d2 < r2)) continue;
-                ++total;
-                const int32_t id = __float_as_int(pq.w);
-                if (n == K && id >= row[K - 1]) continue;
-                int u = n < K ? n : K - 1;  // insert into the sorted row; the largest drops out
-                while (u > 0 && row[u - 1] > id) {
-                  row[u] = row[u - 1];
-                  --u;
-                }
-                row[u] = id;
-                if (n < K) ++n;
-              }
-            }
-            __syncthreads();
+      if (wv == 0) {
+        // cut the listed cells to the buffer: a lane per cell
+        const int nl = static_cast<int>(min(tot_codes, static_cast<uint32_t>(kBallFill)));
+        uint32_t code = 0u, base = 0u, cs = 0u, sz = 0u;
+        if (lane < nl) {
+          code = s_list[lane];
+          base = s_cs[code];
+          cs = base + (static_cast<int>(code) == cur ? curoff : 0u);
+          sz = s_cs[code + 1] - cs;
+        }
+        const uint32_t incl = wave_incl_scan(sz);
+        const uint32_t exs = incl - sz;
+        const uint32_t take = exs >= static_cast<uint32_t>(kBallBuf) ? 0u : min(sz, kBallBuf - exs);
+        const unsigned long long hasm = __ballot(take > 0u);
+        if (take > 0u) {
+          const int e = __popcll(hasm & ((1ull << lane) - 1ull));
+          uint32_t cc[3] = {0u, 0u, 0u};
+          for (int a = 0; a < 3; ++a)
+            for (int j = 0; j < kBinBits; ++j)
+              if (j < kc.bb[a]) cc[a] |= ((code >> ((kc.pos[a] >> (4 * j)) & 15u)) & 1u) << j;
+          s_fxy[e] = cc[0] | (cc[1] << 16);
+          s_fz[e] = cc[2];
+          s_foff[e] = exs;
+          s_flen[e] = take;
+          s_fbeg[e] = cs;
+        }
+        const unsigned long long short_m = __ballot(lane < nl && take < sz);
+        const int p = short_m ? __ffsll(static_cast<long long>(short_m)) - 1 : (nl > 0 ? nl - 1 : 0);
+        const uint32_t code_p = static_cast<uint32_t>(lane_of(static_cast<int32_t>(code), p));
+        const uint32_t off_p = static_cast<uint32_t>(lane_of(static_cast<int32_t>(cs - base + take), p));
+        const uint32_t all = static_cast<uint32_t>(lane_of(static_cast<int32_t>(incl), 63));
+        if (lane == 0) {
+          s_nf = __popcll(hasm);
+          s_ntot = static_cast<int>(min(all, static_cast<uint32_t>(kBallBuf)));
+          if (short_m) {
+            s_cur = static_cast<int>(code_p);  // (the buffer ran out in or before this cell)
+            s_curoff = off_p;
+            s_more = 1;
+          } else if (nl > 0) {
+            s_cur = static_cast<int>(code_p) + 1;
+            s_curoff = 0u;
+            s_more = tot_codes > static_cast<uint32_t>(nl) ? 1 : 0;
+          } else {
+            s_more = 0;
           }
         }
-    if (has) {
-      int32_t* o = out + j * static_cast<int64_t>(K);
-      for (int q = 0; q < K; ++q) o[q] = q < n ? row[q] : (n > 0 ? row[0] : -1);
-      if (count) count[j] = static_cast<int32_t>(total < 0x7FFFFFFF ? total : 0x7FFFFFFF);
+      }
+      __syncthreads();
+      const int nf = s_nf, ntot = s_ntot;
+      const bool more = s_more != 0;
+      // stage: the sorted records of the fill's cells, then their original coordinates
+      {
+        int32_t o[kBallBuf / kThreads];
+#pragma unroll
+        for (int k = 0; k < kBallBuf / kThreads; ++k) {
+          const int q = k * kThreads + static_cast<int>(threadIdx.x);
+          o[k] = -1;
+          if (q < ntot) {
+            int lo = 0, hi = nf - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (static_cast<int>(s_foff[mid]) <= q) lo = mid;
+              else hi = mid - 1;
+            }
+            const int64_t L = static_cast<int64_t>(s_fbeg[lo]) + (q - static_cast<int>(s_foff[lo]));
+            o[k] = __float_as_int(w.pts[slot_of(L)].w);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kBallBuf / kThreads; ++k) {
+          const int q = k * kThreads + static_cast<int>(threadIdx.x);
+          if (o[k] >= 0) {
+            const int64_t oi = o[k];
+            s_buf[q] = make_float4(xyz[3 * oi], xyz[3 * oi + 1], xyz[3 * oi + 2], __int_as_float(o[k]));
+          }
+        }
+      }
+      __syncthreads();
+      // test: the fill's cells one per lane, each wave every kWaves-th centre
+      uint32_t fx = 0xFFFFFFFFu, fy = 0xFFFFFFFFu, fz = 0xFFFFFFFFu, foff = 0u, flen = 0u;
+      if (lane < nf) {
+        const uint32_t xy = s_fxy[lane];
+        fx = xy & 0xFFFFu;
+        fy = xy >> 16;
+        fz = s_fz[lane];
+        foff = s_foff[lane];
+        flen = s_flen[lane];
+      }
+      for (int c = wv; c < ng; c += kWaves) {
+        const uint32_t bx = s_box[0][c], by = s_box[1][c], bz = s_box[2][c];
+        unsigned long long cm = __ballot(lane < nf && fx >= (bx & 0xFFFFu) && fx <= (bx >> 16) &&
+                                         fy >= (by & 0xFFFFu) && fy <= (by >> 16) &&
+                                         fz >= (bz & 0xFFFFu) && fz <= (bz >> 16));
+        if (!cm) continue;
+        const float4 ce = s_cen[c];
+        int32_t rv = lane < K ? s_row[c * K + lane] : INT32_MAX;
+        uint32_t tot = 0u;
+        while (cm) {
+          const int e = __ffsll(static_cast<long long>(cm)) - 1;
+          cm &= cm - 1ull;
+          const int off = lane_of(static_cast<int32_t>(foff), e);
+          const int len = lane_of(static_cast<int32_t>(flen), e);
+          for (int b = 0; b < len; b += 64) {
+            bool hit = false;
+            int32_t id = INT32_MAX;
+            if (b + lane < len) {
+              const float4 pq = s_buf[off + b + lane];
+              const float dx = pq.x - ce.x, dy = pq.y - ce.y, dz = pq.z - ce.z;
+              const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+              const float d2 = (xx + yy) + zz;
+              hit = d2 < r2;
+              id = __float_as_int(pq.w);
+            }
+            const unsigned long long hm = __ballot(hit);
+            if (!hm) continue;
+            tot += static_cast<uint32_t>(__popcll(hm));
+            int32_t kth = lane_of(rv, K - 1);
+            unsigned long long im = __ballot(hit && id < kth);
+            while (im) {
+              const int l = __ffsll(static_cast<long long>(im)) - 1;
+              const int32_t nid = lane_of(id, l);
+              const int pos = __popcll(__ballot(rv < nid));
+              const int32_t up = __shfl_up(rv, 1, 64);
+              rv = lane < pos ? rv : (lane == pos ? nid : up);
+              if (lane >= K) rv = INT32_MAX;
+              kth = lane_of(rv, K - 1);
+              im &= ~(1ull << l);
+              im &= __ballot(id < kth);
+            }
+          }
+        }
+        if (lane < K) s_row[c * K + lane] = rv;
+        if (lane == 0) s_tot[c] += tot;
+      }
+      __syncthreads();
+      if (!more) break;
     }
+    // the group's rows are final
+    for (int c = wv; c < ng; c += kWaves) {
+      const int64_t j = __float_as_int(s_cen[c].w);
+      const int32_t rv = lane < K ? s_row[c * K + lane] : INT32_MAX;
+      const int n = __popcll(__ballot(lane < K && rv != INT32_MAX));
+      const int32_t first = lane_of(rv, 0);
+      if (lane < K) out[j * K + lane] = lane < n ? rv : (n > 0 ? first : -1);
+      if (lane == 0 && count) count[j] = static_cast<int32_t>(min(s_tot[c], 0x7FFFFFFFu));
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (threadIdx.x == 0) w.scn[t] = 0;  // (the selection expects its counts at zero)
 }
 

@@ -139,6 +139,25 @@ def test_ball_query_on_sampler_structure(gpu, orc, radius, K):
     _check_sampled_ball(gpu, orc, s, d, idx, radius, K, "duplicates")
 
 
+def test_ball_query_on_sampler_structure_groups_and_big_cells(gpu, orc):
+    # many centres per tile (half the cloud sampled: the tile's centres go in several
+    # groups whose rows fit in LDS, for K = 32 and K = 64), and one cell holding far more
+    # points than one LDS fill (a tight blob inside a wide cloud: the cell is staged in
+    # parts)
+    x = synth.scene_planes_blobs(40000, seed=63)
+    s = gpu.Sampler()
+    idx = s.sample(_dev(x), 20000)
+    for K in (32, 64):
+        _check_sampled_ball(gpu, orc, s, x, idx, 0.6, K, "scene 40k half")
+    rng = np.random.default_rng(64)
+    blob = (rng.normal(size=(9000, 3)) * 0.02).astype(np.float32)
+    wide = rng.uniform(-20.0, 20.0, size=(3000, 3)).astype(np.float32)
+    y = np.concatenate([blob, wide])[rng.permutation(12000)]
+    idx = s.sample(_dev(y), 3000)
+    for radius, K in ((0.01, 8), (0.05, 64), (30.0, 4)):
+        _check_sampled_ball(gpu, orc, s, y, idx, radius, K, "blob in a wide cloud")
+
+
 def test_ball_query_on_sampler_structure_full_size(gpu, orc):
     # the bench's grouping: 65,536 centres of the 1M scene, r = 0.5, K = 32; the oracle
     # (brute force) checks 512 rows drawn at random; the next sample call on the same
