@@ -2882,9 +2882,11 @@ constexpr int kBallMaxK = 64;
 constexpr int kBallBuf = 2048;        // points staged in LDS per fill
 constexpr int kBallFill = 64;         // cells (or parts of one) per fill: one per lane
 constexpr int kBallRowWords = 5120;   // LDS words for the group's sorted rows
-constexpr int kBallGroup = kThreads;  // centres per group at most
+constexpr int kBallThreads = 512;     // threads of a grouping block
+constexpr int kBallGroup = 256;       // centres per group at most
 static_assert(kBins / 64 == 64, "one word of the needed-cell bitmap per lane");
-static_assert(kBallBuf % kThreads == 0, "staged points per thread");
+static_assert(kBallBuf % kBallThreads == 0, "staged points per thread");
+static_assert(kBallGroup <= kBallThreads, "a thread per centre while a group loads");
 
 __device__ __forceinline__ bool ball_ready(const Ws& w) {
   return w.h->binned_n == w.n && w.h->frame.status == HAV_OK;
@@ -2946,10 +2948,10 @@ __global__ void __launch_bounds__(kThreads) k_ball_bucket(Ws w, const int32_t* _
 // every fourth centre of the group: the fill's cells inside the centre's cell box are
 // found with one ballot (a cell per lane), and their points are tested 64 at a time.
 // A centre's row of the K lowest indices so far lives one entry per lane while its wave
-// works on it (insertion: a ballot counts the smaller entries, the larger ones shift up
-// a lane) and in LDS between fills. Each point of a needed cell is staged once per
+// works on it (insertion: every lane above the new index takes its lower neighbour's
+// entry, a one-lane DPP shift) and in LDS between fills. Each point of a needed cell is staged once per
 // group, so no index enters a row twice.
-__global__ void __launch_bounds__(kThreads) k_ball_group(Ws w, const float* __restrict__ xyz,
+__global__ void __launch_bounds__(kBallThreads) k_ball_group(Ws w, const float* __restrict__ xyz,
                                                         const int32_t* __restrict__ idx, float radius,
                                                         float r2, int32_t K, int32_t* out, int32_t* count) {
   if (!ball_ready(w)) return;  // (then the lists were not touched, and may be laid out otherwise)
@@ -2971,20 +2973,20 @@ __global__ void __launch_bounds__(kThreads) k_ball_group(Ws w, const float* __re
   __shared__ CellCoder s_kc;
   __shared__ float s_mn[3];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr int kWaves = kThreads / 64;
+  constexpr int kWaves = kBallThreads / 64;
   if (threadIdx.x == 0) {
     const Frame f = w.h->frame;
     s_kc = make_coder(f);
     for (int a = 0; a < 3; ++a) s_mn[a] = f.mn[a];
   }
-  for (int c = threadIdx.x; c <= kBins; c += kThreads) s_cs[c] = cell_start(w, c);
+  for (int c = threadIdx.x; c <= kBins; c += kBallThreads) s_cs[c] = cell_start(w, c);
   __syncthreads();
   const CellCoder kc = s_kc;
   const int G = min(kBallGroup, kBallRowWords / K);
   for (int g0 = 0; g0 < nc_all; g0 += G) {
     const int ng = min(G, nc_all - g0);
     if (threadIdx.x < kBins / 64) s_need[threadIdx.x] = 0ull;
-    for (int q = threadIdx.x; q < ng * K; q += kThreads) s_row[q] = INT32_MAX;
+    for (int q = threadIdx.x; q < ng * K; q += kBallThreads) s_row[q] = INT32_MAX;
     if (threadIdx.x == 0) {
       s_cur = 0;
       s_curoff = 0u;
@@ -3087,10 +3089,10 @@ __global__ void __launch_bounds__(kThreads) k_ball_group(Ws w, const float* __re
       const bool more = s_more != 0;
       // stage: the sorted records of the fill's cells, then their original coordinates
       {
-        int32_t o[kBallBuf / kThreads];
+        int32_t o[kBallBuf / kBallThreads];
 #pragma unroll
-        for (int k = 0; k < kBallBuf / kThreads; ++k) {
-          const int q = k * kThreads + static_cast<int>(threadIdx.x);
+        for (int k = 0; k < kBallBuf / kBallThreads; ++k) {
+          const int q = k * kBallThreads + static_cast<int>(threadIdx.x);
           o[k] = -1;
           if (q < ntot) {
             int lo = 0, hi = nf - 1;
@@ -3104,8 +3106,8 @@ __global__ void __launch_bounds__(kThreads) k_ball_group(Ws w, const float* __re
           }
         }
 #pragma unroll
-        for (int k = 0; k < kBallBuf / kThreads; ++k) {
-          const int q = k * kThreads + static_cast<int>(threadIdx.x);
+        for (int k = 0; k < kBallBuf / kBallThreads; ++k) {
+          const int q = k * kBallThreads + static_cast<int>(threadIdx.x);
           if (o[k] >= 0) {
             const int64_t oi = o[k];
             s_buf[q] = make_float4(xyz[3 * oi], xyz[3 * oi + 1], xyz[3 * oi + 2], __int_as_float(o[k]));
@@ -3137,33 +3139,39 @@ __global__ void __launch_bounds__(kThreads) k_ball_group(Ws w, const float* __re
           cm &= cm - 1ull;
           const int off = lane_of(static_cast<int32_t>(foff), e);
           const int len = lane_of(static_cast<int32_t>(flen), e);
-          for (int b = 0; b < len; b += 64) {
-            bool hit = false;
-            int32_t id = INT32_MAX;
-            if (b + lane < len) {
-              const float4 pq = s_buf[off + b + lane];
-              const float dx = pq.x - ce.x, dy = pq.y - ce.y, dz = pq.z - ce.z;
-              const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
-              const float d2 = (xx + yy) + zz;
-              hit = d2 < r2;
-              id = __float_as_int(pq.w);
-            }
-            const unsigned long long hm = __ballot(hit);
-            if (!hm) continue;
-            tot += static_cast<uint32_t>(__popcll(hm));
-            int32_t kth = lane_of(rv, K - 1);
-            unsigned long long im = __ballot(hit && id < kth);
+          auto insert = [&](bool hit, int32_t id) {
+            // candidates below the K-th entry; inserting one that an earlier insert pushed
+            // past it only touches lanes >= K, which hold the row's overflow in order
+            unsigned long long im = __ballot(hit && id < lane_of(rv, K - 1));
             while (im) {
               const int l = __ffsll(static_cast<long long>(im)) - 1;
+              im &= im - 1ull;
               const int32_t nid = lane_of(id, l);
-              const int pos = __popcll(__ballot(rv < nid));
-              const int32_t up = __shfl_up(rv, 1, 64);
-              rv = lane < pos ? rv : (lane == pos ? nid : up);
-              if (lane >= K) rv = INT32_MAX;
-              kth = lane_of(rv, K - 1);
-              im &= ~(1ull << l);
-              im &= __ballot(id < kth);
+              const int32_t up = __builtin_amdgcn_update_dpp(INT32_MIN, rv, 0x138, 0xF, 0xF, false);
+              rv = rv > nid ? (up > nid ? up : nid) : rv;
             }
+          };
+          for (int b = 0; b < len; b += 128) {
+            const bool v0 = b + lane < len, v1 = b + 64 + lane < len;
+            float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0;
+            if (v0) p0 = s_buf[off + b + lane];
+            if (v1) p1 = s_buf[off + b + 64 + lane];
+            bool hit0 = false, hit1 = false;
+            if (v0) {
+              const float dx = p0.x - ce.x, dy = p0.y - ce.y, dz = p0.z - ce.z;
+              const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+              hit0 = ((xx + yy) + zz) < r2;
+            }
+            if (v1) {
+              const float dx = p1.x - ce.x, dy = p1.y - ce.y, dz = p1.z - ce.z;
+              const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
+              hit1 = ((xx + yy) + zz) < r2;
+            }
+            const unsigned long long hm0 = __ballot(hit0), hm1 = __ballot(hit1);
+            if (!(hm0 | hm1)) continue;
+            tot += static_cast<uint32_t>(__popcll(hm0) + __popcll(hm1));
+            if (hm0) insert(hit0, __float_as_int(p0.w));
+            if (hm1) insert(hit1, __float_as_int(p1.w));
           }
         }
         if (lane < K) s_row[c * K + lane] = rv;
@@ -4247,7 +4255,7 @@ hav_status_t hav_ball_query_sampled(const float* xyz, int64_t N, const int32_t* 
   const Ws w = make_ws(static_cast<char*>(ws), L, N);
   const float r2 = radius * radius;
   HAV_LAUNCH(k_ball_bucket, dim3(grid_for(M)), dim3(kThreads), 0, st, w, idx, M, K, out, count);
-  HAV_LAUNCH(k_ball_group, dim3(w.ntile), dim3(kThreads), 0, st, w, xyz, idx, radius, r2, K, out, count);
+  HAV_LAUNCH(k_ball_group, dim3(w.ntile), dim3(kBallThreads), 0, st, w, xyz, idx, radius, r2, K, out, count);
   return HAV_OK;
 }
 
