@@ -193,7 +193,10 @@ static_assert(sizeof(SState) % 4 == 0 && kPubWords <= kThreads, "search state wo
 struct alignas(256) Header {
   uint64_t magic;
   int64_t binned_n;     // points of the stage whose sorted cloud the workspace holds (0: none)
-  uint64_t pad0[30];
+  uint64_t pad0[14];
+  uint32_t ball_next;   // grouping: the next work item, and the number of items
+  uint32_t ball_items;
+  uint32_t pad1[30];
   alignas(256) Frame frame;
   alignas(256) Ctrl ctrl;
   alignas(256) hav_info_t info;
@@ -2875,9 +2878,11 @@ __global__ void __launch_bounds__(kThreads) k_compose(const int32_t* __restrict_
 // counting-sorted by binning cell (pts, with invp from each point to its slot and the
 // cell offsets of the scan), so the points near a centre are the points of the few cells
 // its ball overlaps. No second sort of the cloud is made: the centres are bucketed by the
-// tile holding them (in the selection's per-tile lists, free once a call has ended), and
-// one block per tile stages the cells its centres' balls overlap through LDS, in cell
-// order, a buffer at a time; a wave tests 64 staged points against one centre per step.
+// tile holding them (in the selection's per-tile lists, free once a call has ended); a
+// tile's centres form work items of at most a group each, and resident blocks take the
+// items in turn. A block stages the cells its group's balls overlap through LDS in cell
+// order, a buffer at a time, and a wave tests 64 staged points against one centre per
+// step.
 constexpr int kBallMaxK = 64;
 constexpr int kBallBuf = 2048;        // points staged in LDS per fill
 constexpr int kBallFill = 64;         // cells (or parts of one) per fill: one per lane
@@ -2932,32 +2937,61 @@ __global__ void __launch_bounds__(kThreads) k_ball_bucket(Ws w, const int32_t* _
   }
 }
 
-// One block per tile: the K lowest indices i with d2 < r2 for each of its centres, d2 in
-// float32 as ((dx dx + dy dy) + dz dz) of the original coordinates (dx = x_i - c), the
-// rest of a row repeating its first entry; count = points inside. A centre needs the
-// cells whose index range covers its coordinate offset +- the radius widened by 1e-3 of
-// itself and by 1e-6 of the offset (more than the rounding of d2, of dx and of the
-// offsets r = fl(p - origin) the cells were assigned by); cell_index is non-decreasing
-// in r, so every point inside the ball lies in a needed cell.
+// The grouping's work items: each tile's centres in groups of at most G (as many rows
+// as fit in LDS), listed in the trim queue's storage (written and read within a call, so
+// free between calls) as (tile << 32 | first centre << 16 | centres); the tiles' centre
+// counts go back to zero for the selection.
+__global__ void __launch_bounds__(kBallThreads) k_ball_plan(Ws w, int32_t G) {
+  if (!ball_ready(w)) return;
+  __shared__ uint32_t s_tmp[kBallThreads / 64];
+  uint32_t base = 0u;
+  for (int t0 = 0; t0 < w.ntile; t0 += kBallThreads) {
+    const int t = t0 + static_cast<int>(threadIdx.x);
+    uint32_t nc = 0u, ng = 0u;
+    if (t < w.ntile) {
+      nc = min(static_cast<uint32_t>(w.scn[t]), static_cast<uint32_t>(kTile));
+      ng = (nc + G - 1) / G;
+      w.scn[t] = 0;
+    }
+    uint32_t ex;
+    const uint32_t tot = block_exclusive_scan<kBallThreads>(ng, &ex, s_tmp);
+    for (uint32_t g = 0; g < ng; ++g) {
+      const uint32_t g0 = g * G;
+      w.tie_p[base + ex + g] = (static_cast<uint64_t>(t) << 32) | (static_cast<uint64_t>(g0) << 16) |
+                               min(static_cast<uint32_t>(G), nc - g0);
+    }
+    base += tot;
+  }
+  if (threadIdx.x == 0) {
+    w.h->ball_items = base;
+    w.h->ball_next = 0u;
+  }
+}
+
+// Blocks take work items until none is left. Per item, for each centre of its group:
+// the K lowest indices i with d2 < r2, d2 in float32 as ((dx dx + dy dy) + dz dz) of the
+// original coordinates (dx = x_i - c), the rest of a row repeating its first entry;
+// count = points inside. A centre needs the cells whose index range covers its
+// coordinate offset +- the radius widened by 1e-3 of itself and by 1e-6 of the offset
+// (more than the rounding of d2, of dx and of the offsets r = fl(p - origin) the cells
+// were assigned by); cell_index is non-decreasing in r, so every point inside the ball
+// lies in a needed cell.
 //
-// The block takes its centres in groups (as many as their rows fit in LDS). For a group
-// it marks the needed cells in a 4,096-bit map, then walks the map in cell order: wave 0
-// lists the next needed cells and cuts them to the buffer (a cell larger than the
-// buffer is taken in parts), every thread stages its share of the points (the sorted
-// record for the original index, then the original coordinates), and each wave takes
-// every fourth centre of the group: the fill's cells inside the centre's cell box are
-// found with one ballot (a cell per lane), and their points are tested 64 at a time.
-// A centre's row of the K lowest indices so far lives one entry per lane while its wave
-// works on it (insertion: every lane above the new index takes its lower neighbour's
-// entry, a one-lane DPP shift) and in LDS between fills. Each point of a needed cell is staged once per
-// group, so no index enters a row twice.
+// For a group the block marks the needed cells in a 4,096-bit map, then walks the map in
+// cell order: wave 0 lists the next needed cells and cuts them to the buffer (a cell
+// larger than the buffer is taken in parts), every thread stages its share of the
+// points (the sorted record for the original index, then the original coordinates), and
+// each wave takes every eighth centre of the group: the fill's cells inside the centre's
+// cell box are found with one ballot (a cell per lane), and their points are tested 64
+// at a time. A centre's row of the K lowest indices so far lives one entry per lane
+// while its wave works on it (insertion: every lane above the new index takes its lower
+// neighbour's entry, a one-lane DPP shift) and in LDS between fills. Each point of a
+// needed cell is staged once per group, so no index enters a row twice.
 __global__ void __launch_bounds__(kBallThreads) k_ball_group(Ws w, const float* __restrict__ xyz,
                                                         const int32_t* __restrict__ idx, float radius,
                                                         float r2, int32_t K, int32_t* out, int32_t* count) {
   if (!ball_ready(w)) return;  // (then the lists were not touched, and may be laid out otherwise)
-  const int t = blockIdx.x;
-  const int nc_all = min(w.scn[t], kTile);
-  if (nc_all == 0) return;
+  const uint32_t nitems = w.h->ball_items;
   __shared__ uint32_t s_cs[kBins + 1];
   __shared__ float4 s_buf[kBallBuf];
   __shared__ int32_t s_row[kBallRowWords];
@@ -2982,9 +3016,16 @@ __global__ void __launch_bounds__(kBallThreads) k_ball_group(Ws w, const float* 
   for (int c = threadIdx.x; c <= kBins; c += kBallThreads) s_cs[c] = cell_start(w, c);
   __syncthreads();
   const CellCoder kc = s_kc;
-  const int G = min(kBallGroup, kBallRowWords / K);
-  for (int g0 = 0; g0 < nc_all; g0 += G) {
-    const int ng = min(G, nc_all - g0);
+  __shared__ uint32_t s_it;
+  for (;;) {
+    if (threadIdx.x == 0) s_it = atomicAdd(&w.h->ball_next, 1u);
+    __syncthreads();
+    const uint32_t it = s_it;
+    if (it >= nitems) break;
+    const uint64_t item = w.tie_p[it];
+    const int t = static_cast<int>(item >> 32);
+    const int g0 = static_cast<int>((item >> 16) & 0xFFFFu);
+    const int ng = static_cast<int>(item & 0xFFFFu);
     if (threadIdx.x < kBins / 64) s_need[threadIdx.x] = 0ull;
     for (int q = threadIdx.x; q < ng * K; q += kBallThreads) s_row[q] = INT32_MAX;
     if (threadIdx.x == 0) {
@@ -3191,7 +3232,6 @@ __global__ void __launch_bounds__(kBallThreads) k_ball_group(Ws w, const float* 
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) w.scn[t] = 0;  // (the selection expects its counts at zero)
 }
 
 // ============================================================================ host side
@@ -4153,6 +4193,27 @@ hav_status_t hav_sample_batch(const float* xyz_concat, const int64_t* offsets_ho
 
 }  // extern "C"
 
+// Resident blocks of the grouping kernel on the current device: its grid (the blocks
+// take work items until none is left).
+int ball_blocks() {
+  static std::atomic<int> cache[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
+  int c = cache[dev].load(std::memory_order_relaxed);
+  if (c == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_ball_group),
+                                                     kBallThreads, 0) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        per_cu > 0 && cus > 0)
+      c = per_cu * cus;
+    else
+      c = 256;
+    cache[dev].store(c, std::memory_order_relaxed);
+  }
+  return c;
+}
+
 struct hav_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -4255,7 +4316,10 @@ hav_status_t hav_ball_query_sampled(const float* xyz, int64_t N, const int32_t* 
   const Ws w = make_ws(static_cast<char*>(ws), L, N);
   const float r2 = radius * radius;
   HAV_LAUNCH(k_ball_bucket, dim3(grid_for(M)), dim3(kThreads), 0, st, w, idx, M, K, out, count);
-  HAV_LAUNCH(k_ball_group, dim3(w.ntile), dim3(kBallThreads), 0, st, w, xyz, idx, radius, r2, K, out, count);
+  const int G = std::min(kBallGroup, kBallRowWords / K);
+  HAV_LAUNCH(k_ball_plan, dim3(1), dim3(kBallThreads), 0, st, w, G);
+  HAV_LAUNCH(k_ball_group, dim3(ball_blocks()), dim3(kBallThreads), 0, st, w, xyz, idx, radius, r2, K, out,
+             count);
   return HAV_OK;
 }
 
