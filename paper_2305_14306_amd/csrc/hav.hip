@@ -2938,29 +2938,65 @@ __global__ void __launch_bounds__(kThreads) k_ball_bucket(Ws w, const int32_t* _
 }
 
 // The grouping's work items: each tile's centres in groups of at most G (as many rows
-// as fit in LDS), listed in the trim queue's storage (written and read within a call, so
-// free between calls) as (tile << 32 | first centre << 16 | centres); the tiles' centre
-// counts go back to zero for the selection.
+// as fit in LDS), as (tile << 32 | first centre << 16 | centres), listed in the trim
+// queue's storage (written and read within a sampling call, so free between calls);
+// the tiles' centre counts go back to zero for the selection. The list is ordered by an
+// estimate of the item's work, largest first, so that the blocks taking items in turn
+// end together: the centres times the points of the binning cell at the tile's middle
+// (a centre scans the few cells around it), in classes of powers of two.
+constexpr int kBallCostClasses = 48;
 __global__ void __launch_bounds__(kBallThreads) k_ball_plan(Ws w, int32_t G) {
   if (!ball_ready(w)) return;
   __shared__ uint32_t s_tmp[kBallThreads / 64];
+  __shared__ uint32_t s_cls[kBallCostClasses];
+  __shared__ CellCoder s_kc;
+  if (threadIdx.x < kBallCostClasses) s_cls[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) s_kc = make_coder(w.h->frame);
+  __syncthreads();
+  const CellCoder kc = s_kc;
+  int64_t* tmp = w.tie_o;  // (the items in tile order, with their class in bits 56..61)
   uint32_t base = 0u;
   for (int t0 = 0; t0 < w.ntile; t0 += kBallThreads) {
     const int t = t0 + static_cast<int>(threadIdx.x);
-    uint32_t nc = 0u, ng = 0u;
+    uint32_t nc = 0u, ng = 0u, dens = 1u;
     if (t < w.ntile) {
       nc = min(static_cast<uint32_t>(w.scn[t]), static_cast<uint32_t>(kTile));
       ng = (nc + G - 1) / G;
       w.scn[t] = 0;
+      if (nc) {
+        const int64_t mid = min(static_cast<int64_t>(t) * kTile + kTile / 2, w.n - 1);
+        const float4 rec = w.pts[slot_of(mid)];
+        const uint32_t code = cell_code_k(rec.x, rec.y, rec.z, kc);
+        dens = max(1u, cell_start(w, code + 1) - cell_start(w, code));
+      }
     }
     uint32_t ex;
     const uint32_t tot = block_exclusive_scan<kBallThreads>(ng, &ex, s_tmp);
     for (uint32_t g = 0; g < ng; ++g) {
       const uint32_t g0 = g * G;
-      w.tie_p[base + ex + g] = (static_cast<uint64_t>(t) << 32) | (static_cast<uint64_t>(g0) << 16) |
-                               min(static_cast<uint32_t>(G), nc - g0);
+      const uint32_t cnt = min(static_cast<uint32_t>(G), nc - g0);
+      const uint64_t cost = static_cast<uint64_t>(cnt) * dens;
+      const int cls = 63 - __clzll(static_cast<long long>(cost));  // (cost >= 1)
+      atomicAdd(&s_cls[cls], 1u);
+      tmp[base + ex + g] = static_cast<int64_t>((static_cast<uint64_t>(cls) << 56) | (static_cast<uint64_t>(t) << 32) |
+                                                (static_cast<uint64_t>(g0) << 16) | cnt);
     }
     base += tot;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // class offsets, largest class first
+    uint32_t run = 0u;
+    for (int c = kBallCostClasses - 1; c >= 0; --c) {
+      const uint32_t v = s_cls[c];
+      s_cls[c] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < base; i += kBallThreads) {
+    const uint64_t v = static_cast<uint64_t>(tmp[i]);
+    const int cls = static_cast<int>(v >> 56);
+    w.tie_p[atomicAdd(&s_cls[cls], 1u)] = v & ((uint64_t(1) << 56) - 1);
   }
   if (threadIdx.x == 0) {
     w.h->ball_items = base;
