@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 DOMINANT = "k_search"
 KERNELS = ("k_frame", "k_bbox", "k_identity", "k_bin_count", "k_bin_scan", "k_bin_scatter", "k_search",
-           "k_select", "k_trim_hist", "k_mark", "k_pad", "k_out", "k_ws_init", "k_ws_seal",
+           "k_select", "k_trim_hist", "k_mark", "k_out", "k_ws_init", "k_ws_seal",
            "k_compose", "k_gather")
 PMC_FILE = os.path.join(ROOT, "profiles", "k_search_scene1M_pmc.txt")
 

@@ -30,11 +30,12 @@
 //                  the expected trim threshold
 //     k_trim_hist  (fixed voxel size only) radix rounds of the trim threshold
 //     k_mark       keep the voxels below the trim bucket, queue the bucket; the last
-//                  block ranks the bucket and marks up to the exact threshold
-//     k_pad        pad with the lowest-index unsampled points when there are fewer
-//                  voxels than m (one pass, tiles chained in dispatch order); starts
-//                  the next layer
-//   k_out          ascending output indices (one pass, same chaining)
+//                  block ranks the bucket and marks up to the exact threshold; when a
+//                  layer found fewer voxels than m it pads the lowest-index unsampled
+//                  points (a pass in index order that ends once enough are marked), and
+//                  it starts the next layer
+//   k_out          ascending output indices (one pass, tiles chained in dispatch order;
+//                  the last layer's pad folded in)
 //
 // Table hygiene: a workspace is initialised once (hav_workspace_init). Each kernel
 // that fills a table records the slots it claimed and a later kernel of the same call
@@ -2472,7 +2473,7 @@ __device__ void settle_ties(const Ws& w, Header* h) {
     const int32_t orig = static_cast<int32_t>(v & 0xFFFFFFFFll);
     const int64_t slot = v >> 32;  // -1 in a cloud's last layer (no sorted tag is kept)
     if (orig >= 0 && orig < w.n) {
-      w.tag_o[orig] = lt;
+      st_agent(&w.tag_o[orig], lt);  // (read back with agent-scope loads when the layer pads)
       if (slot >= 0 && slot < w.npad) w.tag_s[slot] = lt;
     }
   };
@@ -2485,6 +2486,59 @@ __device__ void settle_ties(const Ws& w, Header* h) {
       const int64_t at = locate(j);
       if (ld_agent(&w.tie_p[at]) <= thr) pick(ld_agent(&w.tie_o[at]));
     }
+  }
+}
+
+// Pad a layer that found fewer voxels than m, in the marking launch's last block: the
+// `need` lowest-index points still unsampled get the layer's tag (Sec. 3.3 leaves the
+// top-up open; this is the reading both the oracle and the library take). One block
+// walks the original-order tags a scan tile at a time and stops as soon as enough are
+// marked; the tags the launch's other blocks wrote are read with agent-scope loads.
+__device__ __forceinline__ void load_tags_agent(uint8_t* tag, int64_t base, int64_t n,
+                                                uint8_t (&t)[kScanPer]) {
+  uint32_t* w4 = reinterpret_cast<uint32_t*>(tag + base);  // (base is a multiple of 16)
+#pragma unroll
+  for (int j = 0; j < kScanPer / 4; ++j) {
+    const uint32_t v = base + 4 * j < n ? ld_agent(w4 + j) : 0x01010101u;  // (the region is whole words)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      t[4 * j + b] = base + 4 * j + b < n ? static_cast<uint8_t>(v >> (8 * b)) : static_cast<uint8_t>(1);
+  }
+}
+
+__device__ void pad_lowest(const Ws& w, int L, uint32_t need) {
+  __shared__ uint32_t s_tmp[kThreads / 64];
+  __shared__ uint32_t s_before;
+  const uint8_t lt = static_cast<uint8_t>(L + 1);
+  if (threadIdx.x == 0) s_before = 0u;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < w.n; b0 += kScanTile) {
+    const uint32_t before = s_before;
+    if (before >= need) break;
+    const int64_t base = b0 + static_cast<int64_t>(threadIdx.x) * kScanPer;
+    uint8_t t[kScanPer];
+    load_tags_agent(w.tag_o, base, w.n, t);
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) cnt += (t[k] == 0);
+    uint32_t ex;
+    const uint32_t tot = block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
+    uint32_t r = before + ex;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (t[k] != 0) continue;
+      if (r < need) {
+        const int64_t i = base + k;
+        w.tag_o[i] = lt;
+        w.tag_s[w.invp[i]] = lt;
+        if (w.pmode)
+          for (int a = 0; a < 3; ++a) w.pt_out[3 * i + a] = w.xyz[3 * i + a];
+      }
+      ++r;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_before = before + tot;
+    __syncthreads();
   }
 }
 
@@ -2583,7 +2637,10 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
 #pragma unroll
   for (int k = 0; k < kMP; ++k) {
     if (!((keepm >> k) & 1u)) continue;  // (kept: orig is a point of the cloud)
-    w.tag_o[orig[k]] = lt;
+    // a layer before the last may pad in this launch's last block, which reads the
+    // original-order tags of every block: those are stored at agent scope
+    if (last_layer) w.tag_o[orig[k]] = lt;
+    else st_agent(&w.tag_o[orig[k]], lt);
     if (ip[k] >= 0) w.tag_s[ip[k]] = lt;
   }
   __syncthreads();
@@ -2602,10 +2659,11 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
   if (threadIdx.x == 0) w.scn[tile] = 0;
   if (!arrive_last(h, bx, gx)) return;
   settle_ties(w, h);
-  // a layer that found at least m voxels has nothing to pad: start the next layer
-  // here, so that the padding pass finds the controller past its layer and ends at once
   __syncthreads();
-  if (c->need == 0 && L + 1 < cd.P.nlayers) layer_init(h, cd.P, L + 1);
+  if (L + 1 < cd.P.nlayers) {  // (a cloud's last layer is padded by the output scan)
+    if (c->need > 0) pad_lowest(w, L, c->need);
+    layer_init(h, cd.P, L + 1);
+  }
 }
 
 // ----------------------------------------------------------------------------- scans over tag_o
@@ -2668,69 +2726,6 @@ __device__ __forceinline__ void load_tags(const uint8_t* __restrict__ tag, int64
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) t[k] = base + k < n ? tag[base + k] : 1;
   }
-}
-
-// Pad (when the layer found fewer voxels than m): mark the lowest-index unsampled
-// points; then start the next layer. Not for a cloud's last layer (k_out pads it).
-template <class Src>
-__global__ void __launch_bounds__(kThreads) k_pad(Src src, int Lc) {
-  int bx, gx;
-  const Cloud& cd = cloud_of(src, kKScan, bx, gx);
-  if (!layer_due(cd, Lc)) return;
-  if (Lc + 1 >= cd.P.nlayers) return;  // the last layer's pad is part of the output scan
-  const Ws& w = cd.w;
-  const Plan& P = cd.P;
-  Header* h = w.h;
-  Ctrl* c = &h->ctrl;
-  const int L = c->layer;
-  if (L != Lc) return;  // nothing to pad: the marking pass has started the next layer
-  const uint32_t need = c->need;
-  const uint8_t lt = static_cast<uint8_t>(L + 1);
-  {
-    __shared__ uint32_t s_tmp[kThreads / 64];
-    const int lb = scan_ticket(h);
-    const int64_t base = lb * static_cast<int64_t>(kScanTile) + threadIdx.x * kScanPer;
-    uint8_t t[kScanPer];
-    load_tags(w.tag_o, base, w.n, t);
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) cnt += (t[k] == 0);
-    uint32_t ex;
-    const uint32_t tot = block_exclusive_scan<kThreads>(cnt, &ex, s_tmp);
-    const uint32_t before = scan_prefix(w, tot, lb);
-    if (before == ~0u) {
-      // reported by the last block: every block still arrives, so the scan and
-      // arrival counters are left clean for the next call
-      if (threadIdx.x == 0) atomicOr(&h->scan_bad[0], 1u);
-    } else {
-      uint32_t r = before + ex;
-#pragma unroll
-      for (int k = 0; k < kScanPer; ++k) {
-        if (t[k] == 0) {
-          if (r < need) {
-            w.tag_o[base + k] = lt;
-            w.tag_s[w.invp[base + k]] = lt;
-            if (w.pmode)
-              for (int a = 0; a < 3; ++a) w.pt_out[3 * (base + k) + a] = w.xyz[3 * (base + k) + a];
-          }
-          ++r;
-        }
-      }
-    }
-  }
-  if (!arrive_last(h, bx, gx)) return;
-  __shared__ uint32_t s_bad;
-  if (threadIdx.x == 0) s_bad = take(&h->scan_bad[0]);
-  __syncthreads();
-  scan_reset(w, h, gx);
-  if (s_bad) {
-    if (threadIdx.x == 0) {
-      h->frame.status = HAV_ERR_HIP;
-      h->info.status = HAV_ERR_HIP;
-    }
-    return;
-  }
-  layer_init(h, P, L + 1);
 }
 
 // Ascending output: every picked point's index, in index order.
@@ -3863,7 +3858,6 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
     for (int r = 0; r < P.rounds[l]; ++r)
       HAV_LAUNCH(k_trim_hist<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l, r);
     HAV_LAUNCH(k_mark<One>, dim3(w.ntile), dim3(kThreads), 0, st, one, l);
-    if (l + 1 < P.nlayers) HAV_LAUNCH(k_pad<One>, dim3(w.nscan), dim3(kThreads), 0, st, one, l);
   }
   HAV_LAUNCH(k_out<One>, dim3(w.nscan), dim3(kThreads), 0, st, one);
   return HAV_OK;
@@ -4024,7 +4018,6 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
     for (int r = 0; r < max_rounds; ++r)
       HAV_LAUNCH(k_trim_hist<Many>, dim3(T[kKTile]), dim3(kThreads), 0, st, many, l, r);
     HAV_LAUNCH(k_mark<Many>, dim3(T[kKTile]), dim3(kThreads), 0, st, many, l);
-    if (l + 1 < max_layers) HAV_LAUNCH(k_pad<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many, l);
   }
   HAV_LAUNCH(k_out<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many);
   return HAV_OK;
