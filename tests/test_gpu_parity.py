@@ -147,10 +147,11 @@ def test_device_errors(gpu, orc):
 
 
 def test_scan_give_up_reports_and_recovers(gpu, orc):
-    # tag scans whose bounded waits give up after one poll (forced from the host): the
+    # the output scan's bounded waits give up after one poll (forced from the host): the
     # call reports HAV_ERR_HIP, every block still finishes, and the next calls on the same
-    # workspace are exact again. Every point is identical, so layer 1 pads (the padding
-    # scan runs) and so does the output scan; 1M points make 256 scan blocks.
+    # workspace are exact again. Every point is identical, so layer 1 pads (in the marking
+    # launch's last block) and the output scan pads the last layer; 1M points make 256
+    # scan blocks.
     import torch
     x = np.full((1 << 20, 3), 2.5, np.float32)
     M = 1 << 18
