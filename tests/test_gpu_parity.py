@@ -214,6 +214,21 @@ def test_search_give_up_reports_and_sampler_recovers(gpu, orc):
         assert np.array_equal(idx.cpu().numpy(), want)
 
 
+def test_padding_in_layers_before_the_last(gpu, orc):
+    # clouds with few distinct positions: every layer finds fewer voxels than its m and
+    # pads with the lowest-index unsampled points, in layers before the last too (done
+    # by the marking launch's last block); one cloud needs several 4,096-point tag tiles
+    # of padding per layer; the points mode copies the padded points
+    rng = np.random.default_rng(71)
+    for n, ndist, M in ((20000, 37, 5000), (300000, 100, 100000)):
+        base = rng.uniform(-5.0, 5.0, size=(ndist, 3)).astype(np.float32)
+        x = base[rng.integers(0, ndist, n)]
+        _, info = _check(gpu, orc, x, M, gpu.params(layers=3), f"{ndist} distinct, 3 layers")
+        assert info["padded"][0] > 0 and info["padded"][1] > 0, info["padded"]
+    x = np.repeat(rng.uniform(-5.0, 5.0, size=(40, 3)).astype(np.float32), 250, axis=0)
+    _check_points(gpu, orc, x, 3000, gpu.params(select=3, layers=3), "40 distinct, mean, 3 layers")
+
+
 def test_determinism_and_workspace_independence(gpu, orc):
     import torch
     x = synth.scene_planes_blobs(200000, seed=9)
