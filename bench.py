@@ -521,8 +521,8 @@ def cpu_baseline(x, M: int, budget_s: float, cpu: dict) -> dict:
 
 def cpu_batch_baseline(synth, cpu: dict, max_threads: int = 16) -> dict:
     """The oracle on the 64-cloud batch, one cloud per thread across the allowed host
-    cores (at most max_threads: the GPU machine's CPU share), clouds handed out largest
-    first; the oracle's C entry point runs without the interpreter lock."""
+    cores (at most max_threads, the CPU share a one-GPU host gives this process), clouds
+    handed out largest first; the oracle's C entry point runs without the interpreter lock."""
     import concurrent.futures as cf
     import oracle
     clouds, Ms = synth.batch_lidar_clouds()
@@ -566,7 +566,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the sampler works on "
-              "one cloud per GPU and this build has no multi-GPU path", file=sys.stderr)
+              "one cloud per GPU and the library has no multi-GPU path", file=sys.stderr)
         return 2
 
     import numpy as np
