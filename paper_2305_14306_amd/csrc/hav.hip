@@ -918,21 +918,13 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
   const float* __restrict__ xyz = w.xyz;
   __shared__ Frame fr;
   __shared__ uint32_t hist[kBins];
-  Frame f;
-  const int st = frame_from_partials(w, P, &f, 0);
-  if (threadIdx.x == 0) fr = f;
-  for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0;
-  __syncthreads();
-  publish_frame(w, fr, bx);
-  if (st != HAV_OK) return;
   const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
   const int64_t beg = bx * chunk, end = min(w.n, beg + chunk);
-  // 16 points per thread per round, all loads in flight together
+  // 16 points per thread per round, all loads in flight together; the first round's
+  // loads are issued before the frame's partials, so the two round trips overlap
   constexpr int kBP = 16;
-  const CellCoder kc = make_coder(fr);
-  const float m0 = fr.mn[0], m1 = fr.mn[1], m2 = fr.mn[2];
-  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
-    float px[kBP], py[kBP], pz[kBP];
+  float px[kBP], py[kBP], pz[kBP];
+  auto load = [&](int64_t i0) {
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
       const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
@@ -942,6 +934,19 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
         pz[k] = xyz[3 * i + 2];
       }
     }
+  };
+  load(beg);
+  Frame f;
+  const int st = frame_from_partials(w, P, &f, 0);
+  if (threadIdx.x == 0) fr = f;
+  for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0;
+  __syncthreads();
+  publish_frame(w, fr, bx);
+  if (st != HAV_OK) return;
+  const CellCoder kc = make_coder(fr);
+  const float m0 = fr.mn[0], m1 = fr.mn[1], m2 = fr.mn[2];
+  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
+    if (i0 != beg) load(i0);
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
       const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
@@ -1086,21 +1091,11 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
   }
   __shared__ Frame fr;
   __shared__ uint32_t off[kBins];
-  if (threadIdx.x == 0) fr = w.h->frame;
-  static_assert(kBins % kThreads == 0, "cells per thread");
-#pragma unroll
-  for (int j = 0; j < kBins / kThreads; ++j) {
-    const int b = threadIdx.x + j * kThreads;
-    off[b] = w.bh[static_cast<size_t>(bx) * kBins + b] + w.binpre[b] + w.bsum[b / kBinChunk];
-  }
-  __syncthreads();
   const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
   const int64_t beg = bx * chunk, end = min(w.n, beg + chunk);
   constexpr int kBP = 16;
-  const CellCoder kc = make_coder(fr);
-  const float m0 = fr.mn[0], m1 = fr.mn[1], m2 = fr.mn[2];
-  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
-    float px[kBP], py[kBP], pz[kBP];
+  float px[kBP], py[kBP], pz[kBP];
+  auto load = [&](int64_t i0) {
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
       const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
@@ -1110,6 +1105,20 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
         pz[k] = xyz[3 * i + 2];
       }
     }
+  };
+  load(beg);  // (in flight with the frame and the offsets)
+  if (threadIdx.x == 0) fr = w.h->frame;
+  static_assert(kBins % kThreads == 0, "cells per thread");
+#pragma unroll
+  for (int j = 0; j < kBins / kThreads; ++j) {
+    const int b = threadIdx.x + j * kThreads;
+    off[b] = w.bh[static_cast<size_t>(bx) * kBins + b] + w.binpre[b] + w.bsum[b / kBinChunk];
+  }
+  __syncthreads();
+  const CellCoder kc = make_coder(fr);
+  const float m0 = fr.mn[0], m1 = fr.mn[1], m2 = fr.mn[2];
+  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
+    if (i0 != beg) load(i0);
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
       const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
