@@ -219,6 +219,7 @@ struct alignas(256) Header {
   uint32_t sq_fin[kStride];
   uint32_t sq_err[kStride];
   alignas(256) uint32_t pub[kPubWords];
+  uint32_t pub_first[HAV_MAX_LAYERS][kPubWords];  // each layer's first pass, planned at the start
 };
 
 // Device view of the workspace for one stage.
@@ -586,25 +587,51 @@ __device__ void set_window(Ctrl* c, float sig) {
   c->win = 1;
 }
 
-__device__ void layer_init_ctrl(Header* h, const Plan& P, int L, SState* s0);
+__device__ void layer_init_ctrl(Header* h, const Plan& P, int L);
 
 // Start layer L; all threads of the block call it. The bulk clearing is spread over
-// the block, the controller and the first plan (built in LDS from a register copy of
-// the frame, so the plan's arithmetic waits on no memory) are thread 0's.
+// the block, the controller is thread 0's. (The layer's first search pass was planned
+// when the call started: first_plans.)
 __device__ void layer_init(Header* h, const Plan& P, int L) {
-  __shared__ SState s_init;
   for (int i = threadIdx.x; i < 2 * kMaxCand * kGroups; i += kThreads)
     h->sacc[i / (kMaxCand * kGroups)][(i / kGroups) % kMaxCand][i % kGroups][0] = 0;
   if (threadIdx.x < kGroups) h->sq_dgrp[threadIdx.x][0] = 0;
-
-  if (threadIdx.x == 0) layer_init_ctrl(h, P, L, &s_init);
-  __syncthreads();
-  if (!P.fixed)
-    for (int i = threadIdx.x; i < kPubWords; i += kThreads)
-      h->pub[i] = reinterpret_cast<const uint32_t*>(&s_init)[i];
+  if (threadIdx.x == 0) layer_init_ctrl(h, P, L);
 }
 
-__device__ void layer_init_ctrl(Header* h, const Plan& P, int L, SState* s0) {
+// The first search pass of every layer, one thread per layer, into the header. A
+// layer's first pass depends only on the frame (with the binning's prior) and the
+// layer's budget: it starts from the whole bracket [0, hi0] and uses table set 0 (the
+// tables of both sets are empty between layers, as at the start of a call).
+__device__ void first_plans(Header* h, const Plan& P, const Frame& frame_in) {
+  __shared__ SState s_pl[HAV_MAX_LAYERS];
+  if (P.fixed) return;
+  const int L = threadIdx.x;
+  if (L < P.nlayers) {
+    const Frame fl = frame_in;
+    SState* s0 = &s_pl[L];
+    s0->lo = 0.0f;
+    s0->hi = fl.hi0;
+    s0->c_hi = 0;
+    s0->c_lo = 0;
+    s0->evals = 0;
+    s0->done = 0;
+    s0->accepted = 0;
+    s0->set = 0;
+    s0->prev_set = 0;
+    s0->prev_nc = 0;
+    s0->prev_hashed = 0;
+    s0->s_final = 0.0f;
+    s0->c_final = 0;
+    plan_search(s0, P, fl, P.m[L], P.upper[L]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < P.nlayers * kPubWords; i += kThreads)
+    h->pub_first[i / kPubWords][i % kPubWords] =
+        reinterpret_cast<const uint32_t*>(&s_pl[i / kPubWords])[i % kPubWords];
+}
+
+__device__ void layer_init_ctrl(Header* h, const Plan& P, int L) {
   const Frame fl = h->frame;
   Ctrl* c = &h->ctrl;
   c->layer = L;
@@ -639,22 +666,7 @@ __device__ void layer_init_ctrl(Header* h, const Plan& P, int L, SState* s0) {
     }
     set_select_grid(c, P, fl);
   } else {
-    // the first pass's candidates, planned in LDS (published by layer_init)
     c->done = 0;
-    s0->lo = 0.0f;
-    s0->hi = fl.hi0;
-    s0->c_hi = 0;
-    s0->c_lo = 0;
-    s0->evals = 0;
-    s0->done = 0;
-    s0->accepted = 0;
-    s0->set = c->set;
-    s0->prev_set = 0;
-    s0->prev_nc = 0;
-    s0->prev_hashed = 0;
-    s0->s_final = 0.0f;
-    s0->c_final = 0;
-    plan_search(s0, P, fl, P.m[L], P.upper[L]);
   }
 }
 
@@ -1073,8 +1085,11 @@ __device__ void start_search(const Ws& w, const Plan& P) {
     c->pend_hashed = 0;
     w.h->binned_n = w.n;  // the sorted cloud (scattered by this launch) stays for grouping
   }
+  __shared__ Frame s_fr;
+  if (threadIdx.x == 0) s_fr = w.h->frame;  // (thread 0 wrote the prior above)
   __syncthreads();
   layer_init(w.h, P, 0);
+  first_plans(w.h, P, s_fr);
 }
 
 template <class Src>
@@ -1772,7 +1787,7 @@ __global__ void __launch_bounds__(kThreads) k_search(One src, int L, int split) 
   extern __shared__ uint64_t lds[];
   __shared__ SearchShared S;
   __shared__ uint32_t s_first;
-  const uint32_t pub0 = threadIdx.x < kPubWords ? ld_agent(&h->pub[threadIdx.x]) : 0u;
+  const uint32_t pub0 = threadIdx.x < kPubWords ? ld_agent(&h->pub_first[L][threadIdx.x]) : 0u;
   if (threadIdx.x == 0) {
     const int status = h->frame.status;
     const int done = h->ctrl.done;
@@ -3664,7 +3679,7 @@ __global__ void __launch_bounds__(kThreads) k_search_prep(Many src, int L) {
 // clouds (starting from a rotating position), one whose current pass still has tiles
 // to hand out, takes a ticket there and runs it. Waits are only for tiles that running
 // blocks hold, so any grid size makes progress.
-__global__ void __launch_bounds__(kThreads) k_search_many(Many src) {
+__global__ void __launch_bounds__(kThreads) k_search_many(Many src, int L) {
   BatchDev* bd = src.bd;
   const int nact = bd->nact;
   if (nact == 0) return;
@@ -3743,7 +3758,8 @@ __global__ void __launch_bounds__(kThreads) k_search_many(Many src) {
       if (S.go < 0) break;
       if (S.go == 0) continue;  // that cloud's search has ended: drop the ticket
       if (threadIdx.x < kPubWords)
-        reinterpret_cast<uint32_t*>(&S.st)[threadIdx.x] = ld_agent(&h->pub[threadIdx.x]);
+        reinterpret_cast<uint32_t*>(&S.st)[threadIdx.x] =
+            ld_agent(p == 0 ? &h->pub_first[L][threadIdx.x] : &h->pub[threadIdx.x]);
       __syncthreads();
       cur_c = c;
       cur_p = p;
@@ -4021,7 +4037,7 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
   for (int l = 0; l < max_layers; ++l) {
     if (any_search) {
       HAV_LAUNCH(k_search_prep, dim3(1), dim3(kThreads), 0, st, many, l);
-      HAV_LAUNCH(k_search_many, dim3(sgrid), dim3(kThreads), eval_lds, st, many);
+      HAV_LAUNCH(k_search_many, dim3(sgrid), dim3(kThreads), eval_lds, st, many, l);
     }
     HAV_LAUNCH(k_select<Many>, dim3(T[kKTile]), dim3(kThreads), sel_lds, st, many, l);
     for (int r = 0; r < max_rounds; ++r)
