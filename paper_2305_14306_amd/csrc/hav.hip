@@ -80,7 +80,9 @@ constexpr int kThreads = 256;
 constexpr int kTile = 2048;                     // points per search/select tile
 constexpr int kPerThread = kTile / kThreads;    // 8
 constexpr int kLdsCap = 4096;                   // select: LDS voxel map entries (2x tile)
-constexpr int kBrickCap = 1024;                 // search: LDS brick table per candidate
+constexpr int kBrickCap = 1024;                 // search: LDS hash slots per candidate
+constexpr int kCandWords = 2 * kBrickCap;        // search: LDS words per candidate (hash values
+                                                 // then keys, or one box of up to this many bricks)
 constexpr int kMaxCand = 7;                     // candidate scales per search pass
 constexpr int kSplitTickets = 512;              // search tickets per pass up to which a tile's
                                                 // candidates get tickets of their own
@@ -1210,7 +1212,9 @@ struct EvalShared {
   int ncl[kMaxCand];
   uint32_t fresh[kMaxCand];
   uint32_t box[kMaxCand][6];  // brick box: lo x,y,z, extent x,y, volume (0: hash)
-  float boxr[kMaxCand][2];    // 1 / extent x, y
+  uint32_t boxm[kMaxCand][2]; // exact-division multipliers of the box extents x, y
+  int nu;                     // flush units: a candidate, or each half of a box above kBrickCap
+  int unit_c[2 * kMaxCand], unit_h[2 * kMaxCand];
   uint32_t red[kThreads / 64][6];
   uint32_t tb[6];             // tile's min (0..2) and max (3..5) offset bits per axis
 };
@@ -1247,12 +1251,11 @@ __device__ __forceinline__ uint32_t dense_or(unsigned long long* masks, uint32_t
   return static_cast<uint32_t>(__popcll(bits & ~old));
 }
 
-// a / d for a < 1024 and 1 <= d <= 1024, from r = fl(1/d): the product's error is
-// far below the 1/2048 added, and a non-multiple of d is at least 1/1024 below the
-// next integer, so the truncation is exact.
-__device__ __forceinline__ uint32_t box_div(uint32_t a, float r) {
-  return static_cast<uint32_t>(static_cast<float>(a) * r + (1.0f / 2048.0f));
-}
+// a / d for a < 2^11 and 1 <= d <= 2^11, with m = div_magic(d): m = floor((2^32 - 1) / d)
+// + 1 exceeds 2^32 / d by less than 1 (equals it for a power of two), so a * m / 2^32 exceeds
+// a / d by less than 2^-21, below the distance 1/d of a non-multiple to the next integer.
+__device__ __forceinline__ uint32_t div_magic(uint32_t d) { return d <= 1u ? 0u : 0xFFFFFFFFu / d + 1u; }
+__device__ __forceinline__ uint32_t box_div(uint32_t a, uint32_t m) { return m ? __umulhi(a, m) : a; }
 
 // Issue the loads of a tile's points (thread t: the tile's points 8t..8t+7) and
 // their layer tags; every slot of a tile exists, so no load depends on another.
@@ -1305,8 +1308,10 @@ __device__ __forceinline__ void finish_tile_b(EvalShared& sh) {
 }
 
 // Cnt contributions of one loaded tile at the pass's candidates, added to sh.fresh.
-// The LDS tables (lvals: box words or hash values, lkeys: hash keys; slots per
-// candidate fixed by the launch's depth) are clean on entry and left clean.
+// Each candidate has kCandWords LDS words (from lvals, in the order of the launch's
+// candidates): a box of up to kCandWords brick words, or kBrickCap hash values followed by
+// kBrickCap hash keys (stored as key + 1, so that an empty slot reads 0). All are 0 on
+// entry and left 0.
 // `mid` runs (all threads) between the LDS phase and the global flush.
 template <class Mid>
 __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState& st,
@@ -1331,14 +1336,26 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
     sh.box[k][2] = l[2];
     sh.box[k][3] = static_cast<uint32_t>(dx);
     sh.box[k][4] = static_cast<uint32_t>(dy);
-    sh.box[k][5] = vol <= static_cast<uint64_t>(kBrickCap) ? static_cast<uint32_t>(vol) : 0u;
-    sh.boxr[k][0] = 1.0f / static_cast<float>(static_cast<uint32_t>(dx));
-    sh.boxr[k][1] = 1.0f / static_cast<float>(static_cast<uint32_t>(dy));
+    sh.box[k][5] = vol <= static_cast<uint64_t>(kCandWords) ? static_cast<uint32_t>(vol) : 0u;
+    sh.boxm[k][0] = div_magic(static_cast<uint32_t>(dx));
+    sh.boxm[k][1] = div_magic(static_cast<uint32_t>(dy));
   }
   __syncthreads();
+  if (threadIdx.x == 0) {
+    int nu = 0;
+    for (int ci = cb; ci < ce; ++ci) {
+      sh.unit_c[nu] = ci;
+      sh.unit_h[nu++] = 0;
+      if (sh.box[ci][5] > static_cast<uint32_t>(kBrickCap)) {
+        sh.unit_c[nu] = ci;
+        sh.unit_h[nu++] = 1;
+      }
+    }
+    sh.nu = nu;
+  }
   for (int ci = cb; ci < ce; ++ci) {
     const float ix = st.cand_inv[ci][0], iy = st.cand_inv[ci][1], iz = st.cand_inv[ci][2];
-    uint64_t* tv = lvals + (ci - lb) * kBrickCap;
+    uint64_t* tv = lvals + (ci - lb) * kCandWords;
     if (sh.box[ci][5] != 0) {
       const uint32_t bl0 = sh.box[ci][0], bl1 = sh.box[ci][1], bl2 = sh.box[ci][2];
       const uint32_t bdx = sh.box[ci][3], bdy = sh.box[ci][4];
@@ -1375,7 +1392,7 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
     // thread's runs are formed first (run q ends before point q).
     const int dense = st.cand_dense[ci];
     const uint64_t nbx = st.cand_nb[ci][0], nby = st.cand_nb[ci][1];
-    uint64_t* tk = lkeys + (ci - lb) * kBrickCap;
+    uint64_t* tk = tv + kBrickCap;  // keys + 1
     uint64_t rk[kPerThread + 1], rb[kPerThread + 1];
     uint32_t pend = 0;
     {
@@ -1420,14 +1437,14 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
 #pragma unroll
       for (int q = 0; q <= kPerThread; ++q)
         if ((pend >> q) & 1u)
-          __hip_atomic_store(&tk[base + ((hh[q] >> shift) & mask)], rk[q], __ATOMIC_RELAXED,
+          __hip_atomic_store(&tk[base + ((hh[q] >> shift) & mask)], rk[q] + 1ull, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
       __syncthreads();
 #pragma unroll
       for (int q = 0; q <= kPerThread; ++q) {
         const uint32_t e = base + ((hh[q] >> shift) & mask);
         if (((pend >> q) & 1u) &&
-            __hip_atomic_load(&tk[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == rk[q]) {
+            __hip_atomic_load(&tk[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == rk[q] + 1ull) {
           __hip_atomic_fetch_or(&tv[e], rb[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           pend &= ~(1u << q);
         }
@@ -1449,8 +1466,9 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
   __syncthreads();
   mid();
   // One global update per distinct brick of the tile, LDS entries emptied as read.
-  // Thread t owns entries t + j*kThreads (j < 4) of each candidate; the updates of up
-  // to three candidates are issued together so that their round trips overlap. A hot
+  // The flush goes by units of kBrickCap entries (a candidate, or each half of a box
+  // above kBrickCap bricks); thread t owns entries t + j*kThreads (j < 4) of a unit, and
+  // the updates of up to three units are issued together so that their round trips overlap. A hot
   // table (a brick grid of at most kHotCap words, shared by very many tiles) is first
   // ORed into the tile's replica (one of kReps, so a word sees a 1/kReps share of the
   // tiles) and only the bits new to the replica go on to the table; every bit still
@@ -1458,30 +1476,35 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
   static_assert(kBrickCap == 4 * kThreads, "four flush entries per thread");
   constexpr int kGrp = 3;
   const int rep = tile & (kReps - 1);
-  for (int c0 = cb; c0 < ce; c0 += kGrp) {
+  const int nu = sh.nu;
+  for (int u0 = 0; u0 < nu; u0 += kGrp) {
     uint32_t slot[4 * kGrp];
     uint64_t bits[4 * kGrp], hkey[4 * kGrp];
     uint32_t valid = 0, hot = 0, hm = 0;
     uint32_t f[kGrp] = {};
+    int uc[kGrp];
+#pragma unroll
+    for (int k = 0; k < kGrp; ++k) uc[k] = u0 + k < nu ? sh.unit_c[u0 + k] : cb;
 #pragma unroll
     for (int q = 0; q < 4 * kGrp; ++q) {
-      const int ci = c0 + q / 4;
-      const int le = (q % 4) * kThreads + threadIdx.x;
-      const int e = (ci - lb) * kBrickCap + le;
+      const int u = u0 + q / 4;
       slot[q] = 0;
       bits[q] = 0ull;
-      if (ci >= ce) continue;
+      if (u >= nu) continue;
+      const int ci = uc[q / 4];
+      const int le = sh.unit_h[u] * kBrickCap + (q % 4) * kThreads + threadIdx.x;
+      uint64_t* R = lvals + (ci - lb) * kCandWords;
       const uint32_t vol = sh.box[ci][5];
       const int dense = st.cand_dense[ci];
       uint64_t key, b;
       if (vol) {
         if (le >= static_cast<int>(vol)) continue;
-        b = lvals[e];
+        b = R[le];
         if (!b) continue;
-        lvals[e] = 0ull;
+        R[le] = 0ull;
         const uint32_t bdx = sh.box[ci][3], bdy = sh.box[ci][4];
-        const uint32_t t2 = box_div(static_cast<uint32_t>(le), sh.boxr[ci][0]);
-        const uint32_t t3 = box_div(t2, sh.boxr[ci][1]);
+        const uint32_t t2 = box_div(static_cast<uint32_t>(le), sh.boxm[ci][0]);
+        const uint32_t t3 = box_div(t2, sh.boxm[ci][1]);
         const uint32_t bx = sh.box[ci][0] + (static_cast<uint32_t>(le) - t2 * bdx);
         const uint32_t by = sh.box[ci][1] + (t2 - t3 * bdy);
         const uint32_t bz = sh.box[ci][2] + t3;
@@ -1490,11 +1513,12 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
                     : (static_cast<uint64_t>(bx) | (static_cast<uint64_t>(by) << kBrickCoordBits) |
                        (static_cast<uint64_t>(bz) << (2 * kBrickCoordBits)));
       } else {
-        key = lkeys[e];
-        if (key == kEmptyKey) continue;
-        b = lvals[e];
-        lkeys[e] = kEmptyKey;
-        lvals[e] = 0ull;
+        const uint64_t k1 = R[kBrickCap + le];
+        if (k1 == 0ull) continue;
+        key = k1 - 1ull;
+        b = R[le];
+        R[kBrickCap + le] = 0ull;
+        R[le] = 0ull;
       }
       if (!dense) {  // hashed table: the slot is found below
         slot[q] = table_hash(key) & w.cmask;
@@ -1517,14 +1541,14 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
       unsigned long long kk[4 * kGrp];
 #pragma unroll
       for (int q = 0; q < 4 * kGrp; ++q)
-        kk[q] = ((hm >> q) & 1u) ? atomicCAS(ctab_keys(w, set, c0 + q / 4) + slot[q], kEmptyKey,
+        kk[q] = ((hm >> q) & 1u) ? atomicCAS(ctab_keys(w, set, uc[q / 4]) + slot[q], kEmptyKey,
                                              static_cast<unsigned long long>(hkey[q]))
                                  : 0ull;
 #pragma unroll
       for (int q = 0; q < 4 * kGrp; ++q) {
         if (!((hm >> q) & 1u)) continue;
         if (kk[q] == kEmptyKey)
-          st_agent(claims(w, set, c0 + q / 4, tile) + atomicAdd(&sh.ncl[c0 + q / 4], 1),
+          st_agent(claims(w, set, uc[q / 4], tile) + atomicAdd(&sh.ncl[uc[q / 4]], 1),
                    static_cast<int32_t>(slot[q]));
         if (kk[q] == kEmptyKey || kk[q] == hkey[q]) {
           hm &= ~(1u << q);
@@ -1539,14 +1563,14 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
 #pragma unroll
     for (int q = 0; q < 4 * kGrp; ++q)
       old[q] = ((hot >> q) & 1u)
-                   ? atomicOr(hrep_of(w, set, c0 + q / 4, rep) + slot[q],
+                   ? atomicOr(hrep_of(w, set, uc[q / 4], rep) + slot[q],
                               static_cast<unsigned long long>(bits[q]))
                    : 0ull;
 #pragma unroll
     for (int q = 0; q < 4 * kGrp; ++q) {
       if (!((hot >> q) & 1u)) continue;
       if (old[q] == 0ull)
-        st_agent(claims(w, set, c0 + q / 4, tile) + atomicAdd(&sh.ncl[c0 + q / 4], 1),
+        st_agent(claims(w, set, uc[q / 4], tile) + atomicAdd(&sh.ncl[uc[q / 4]], 1),
                  static_cast<int32_t>(-1 - (rep * kHotCap + static_cast<int32_t>(slot[q]))));
       bits[q] &= ~old[q];
       if (!bits[q]) valid &= ~(1u << q);
@@ -1555,7 +1579,7 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
 #pragma unroll
     for (int q = 0; q < 4 * kGrp; ++q)
       old[q] = ((valid >> q) & 1u)
-                   ? atomicOr(ctab_masks(w, set, c0 + q / 4) + slot[q],
+                   ? atomicOr(ctab_masks(w, set, uc[q / 4]) + slot[q],
                               static_cast<unsigned long long>(bits[q]))
                    : ~0ull;
 #pragma unroll
@@ -1563,12 +1587,12 @@ __device__ __forceinline__ void eval_loaded(const Ws& w, int tile, const SState&
       if (!((valid >> q) & 1u)) continue;
       f[q / 4] += static_cast<uint32_t>(__popcll(bits[q] & ~old[q]));
       if (old[q] == 0ull && !((hashed >> q) & 1u))  // (a hashed slot was recorded when claimed)
-        st_agent(claims(w, set, c0 + q / 4, tile) + atomicAdd(&sh.ncl[c0 + q / 4], 1),
+        st_agent(claims(w, set, uc[q / 4], tile) + atomicAdd(&sh.ncl[uc[q / 4]], 1),
                  static_cast<int32_t>(slot[q]));
     }
 #pragma unroll
     for (int k = 0; k < kGrp; ++k)
-      if (f[k]) atomicAdd(&sh.fresh[c0 + k], f[k]);
+      if (f[k]) atomicAdd(&sh.fresh[uc[k]], f[k]);
   }
   __syncthreads();
   if (cb + static_cast<int>(threadIdx.x) < ce)
@@ -1755,11 +1779,8 @@ __device__ __forceinline__ void search_lds_init(uint64_t* lds, int depth, uint64
                                                 uint64_t*& lkeys) {
   const int ncap = depth;
   lvals = lds;
-  lkeys = lds + static_cast<size_t>(ncap) * kBrickCap;
-  for (int e = threadIdx.x; e < ncap * kBrickCap; e += kThreads) {
-    lvals[e] = 0ull;
-    lkeys[e] = kEmptyKey;
-  }
+  lkeys = nullptr;  // (keys live in each candidate's words)
+  for (int e = threadIdx.x; e < ncap * kCandWords; e += kThreads) lvals[e] = 0ull;
 }
 
 // A wait gave up: tables may hold claims nobody cleared, so the workspace needs
