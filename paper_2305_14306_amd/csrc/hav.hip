@@ -695,11 +695,24 @@ __global__ void __launch_bounds__(kThreads) k_bbox(Src src) {
       lo[a] = min(lo[a], o);
       hi[a] = max(hi[a], o);
     }
-    w.tag_o[i] = 0;
   }
-  for (int64_t S = bx * static_cast<int64_t>(kThreads) + threadIdx.x; S < w.npad;
-       S += static_cast<int64_t>(gx) * kThreads)
-    w.tag_s[S] = logical_of(S) < n ? 0 : 0xFF;  // 0xFF: empty slot, never a point
+  // tags cleared 16 at a time (both arrays start 256-byte aligned; tag_o's region is
+  // padded to a multiple of 256 bytes, tag_s holds whole tiles)
+  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+  const int64_t stride = static_cast<int64_t>(gx) * kThreads;
+  for (int64_t q = bx * static_cast<int64_t>(kThreads) + threadIdx.x; q < (n + 15) / 16; q += stride)
+    reinterpret_cast<uint4*>(w.tag_o)[q] = z4;
+  for (int64_t q = bx * static_cast<int64_t>(kThreads) + threadIdx.x; q < w.npad / 16; q += stride) {
+    const int64_t S0 = 16 * q;
+    if ((S0 / kTile + 1) * kTile <= n) {  // a whole tile of points: every slot holds one
+      reinterpret_cast<uint4*>(w.tag_s)[q] = z4;
+    } else {
+      uint32_t v[4] = {0u, 0u, 0u, 0u};
+      for (int b = 0; b < 16; ++b)
+        if (logical_of(S0 + b) >= n) v[b >> 2] |= 0xFFu << (8 * (b & 3));  // 0xFF: empty slot
+      reinterpret_cast<uint4*>(w.tag_s)[q] = make_uint4(v[0], v[1], v[2], v[3]);
+    }
+  }
   __shared__ uint32_t s_v[7][kThreads / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   uint32_t vals[7] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], bad};
@@ -876,13 +889,15 @@ __device__ __forceinline__ uint32_t cell_index(float r, const CellCoder& k, int 
   return !(q >= 0.0f) ? 0u : (q >= static_cast<float>(k.lim[a]) ? k.lim[a] : static_cast<uint32_t>(q));
 }
 // The cell number of cell indices (cx, cy, cz): their bits interleaved (Morton order).
+// Index bits at or above an axis's bit count are 0 (cell_index clamps) and their position
+// nibbles are 0, so every bit is deposited unconditionally.
 __device__ __forceinline__ uint32_t cell_code_of(const uint32_t (&c)[3], const CellCoder& k) {
   uint32_t code = 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
 #pragma unroll
     for (int j = 0; j < kBinBits; ++j)
-      if (j < k.bb[a]) code |= ((c[a] >> j) & 1u) << ((k.pos[a] >> (4 * j)) & 15u);
+      code |= ((c[a] >> j) & 1u) << ((k.pos[a] >> (4 * j)) & 15u);
   }
   return code;
 }
