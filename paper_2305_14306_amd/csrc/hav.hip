@@ -144,7 +144,9 @@ struct Ctrl {
   uint32_t rank;        // rank sought inside the trim bucket
   uint64_t prefix;      // radix rounds: decided top bits of the threshold
   int32_t rounds_done;
-  // trim bucket: 0 the radix prefix, 1 the priority window [blo, bhi], 2 every voxel
+  // trim bucket: 0 the radix prefix, 1 the priority window [blo, bhi], 2 every voxel;
+  // 3: no bucket, every voxel of priority at most bhi stays (the rank is the largest of the
+  // window bin that holds it)
   int32_t trim_mode;
   uint32_t c_final;     // voxels the search counted at s_final (0: no search)
   int32_t win;          // a window was set for the selection kernel to test
@@ -2194,7 +2196,7 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   if (!arrive_last(h, bx, gx)) return;
   __shared__ uint32_t s_sum[3];
   __shared__ int s_mode;
-  __shared__ uint32_t s_rank, s_bin, s_brank;
+  __shared__ uint32_t s_rank, s_bin, s_brank, s_top;
   __shared__ uint32_t s_tmp2[kThreads / 64];
   if (threadIdx.x < 3) s_sum[threadIdx.x] = 0;
   __syncthreads();
@@ -2207,7 +2209,11 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
   static_assert(kWinBins % kThreads == 0, "window bins per thread");
   uint32_t hv[kWB];
 #pragma unroll
-  for (int j = 0; j < kWB; ++j) hv[j] = win ? take(&whist[threadIdx.x * kWB + j]) : 0u;
+  for (int j = 0; j < kWB; ++j) hv[j] = win ? ld_agent(&whist[threadIdx.x * kWB + j]) : 0u;
+  // (emptied with plain stores: the next writers are a later launch's)
+  if (win)
+#pragma unroll
+    for (int j = 0; j < kWB; ++j) whist[threadIdx.x * kWB + j] = 0u;
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t nvox = s_sum[0], below = s_sum[1], inwin = s_sum[2];
@@ -2233,6 +2239,7 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
     s_rank = c->rank;
     s_bin = 0;
     s_brank = 0;
+    s_top = 0;
     const int Lc = c->layer;
     h->info.count[Lc] = static_cast<int32_t>(nvox);
     h->info.trimmed[Lc] = nvox > c->m ? static_cast<int32_t>(nvox - c->m) : 0;
@@ -2256,6 +2263,7 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
       if (rank >= e && rank < e + hv[j]) {
         s_bin = threadIdx.x * kWB + j;
         s_brank = rank - e;
+        s_top = rank - e + 1 == hv[j] ? 1u : 0u;
       }
       e += hv[j];
     }
@@ -2267,6 +2275,7 @@ __global__ void __launch_bounds__(kThreads) k_select(Src src, int L) {
     c->blo = lo_b;
     c->bhi = (bhi - lo_b > span) ? lo_b + span : bhi;
     c->rank = s_brank;
+    if (s_top) c->trim_mode = 3;  // the bin's members all stay: nothing to settle
   }
 }
 
@@ -2674,6 +2683,8 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
       } else if (mode == 1) {
         keep = p < blo;
         tie = !keep && p <= bhi;
+      } else if (mode == 3) {
+        keep = p <= bhi;
       } else {
         keep = false;
         tie = true;
@@ -2718,7 +2729,7 @@ __global__ void __launch_bounds__(kThreads) k_mark(Src src, int L) {
   }
   if (threadIdx.x == 0) w.scn[tile] = 0;
   if (!arrive_last(h, bx, gx)) return;
-  settle_ties(w, h);
+  if (trim && mode != 3) settle_ties(w, h);  // (no member was queued otherwise)
   __syncthreads();
   if (L + 1 < cd.P.nlayers) {  // (a cloud's last layer is padded by the output scan)
     if (c->need > 0) pad_lowest(w, L, c->need);
