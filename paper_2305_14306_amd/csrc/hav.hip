@@ -130,7 +130,6 @@ struct Ctrl {
   int32_t layer;
   uint32_t m, upper;
   int32_t evals, done, accepted;
-  float lo, hi;
   float s_final;
   float v_final[3], inv_final[3];
   int32_t set;          // table set the next search pass fills
@@ -636,15 +635,12 @@ __device__ void first_plans(Header* h, const Plan& P, const Frame& frame_in) {
 }
 
 __device__ void layer_init_ctrl(Header* h, const Plan& P, int L) {
-  const Frame fl = h->frame;
   Ctrl* c = &h->ctrl;
   c->layer = L;
   c->m = P.m[L];
   c->upper = P.upper[L];
   c->evals = 0;
   c->accepted = 0;
-  c->lo = 0.0f;
-  c->hi = fl.hi0;
   c->ncand = 0;
   c->trim = 0;
   c->need = 0;
@@ -662,6 +658,7 @@ __device__ void layer_init_ctrl(Header* h, const Plan& P, int L) {
   h->sq_fin[0] = 0;
   h->sq_err[0] = 0;
   if (P.fixed) {
+    const Frame fl = h->frame;
     c->done = 1;
     c->s_final = 0.0f;
     for (int ax = 0; ax < 3; ++ax) {
@@ -1745,8 +1742,6 @@ __device__ __forceinline__ int run_ticket(const Ws& w, const Plan& P, SearchShar
     if (threadIdx.x == 0) {
       c->evals = st.evals;
       c->accepted = st.accepted;
-      c->lo = st.lo;
-      c->hi = st.hi;
       c->done = 1;
       c->set = st.set;
       c->pend_set = st.prev_set;
