@@ -2865,9 +2865,20 @@ __global__ void __launch_bounds__(kThreads) k_out(Src src) {
     for (int64_t j = threadIdx.x; r0 + j < min(r1, M); j += kThreads) idx[r0 + j] = s_o[j];
   if (!arrive_last(h, bx, gx)) return;
   scan_reset(w, h, gx);
-  if (threadIdx.x == 0) {
-    if (take(&h->scan_bad[0])) h->info.status = HAV_ERR_HIP;
-    if (w.info_dev) *w.info_dev = h->info;
+  // the report: its words and the scan's failure flag load in one round trip, one word a
+  // thread, then go to the caller
+  constexpr int kInfoWords = static_cast<int>(sizeof(hav_info_t) / 4);
+  static_assert(kInfoWords <= kThreads, "report words per thread");
+  __shared__ uint32_t s_bad;
+  int32_t* iw = reinterpret_cast<int32_t*>(&h->info);
+  const int32_t word = threadIdx.x < kInfoWords ? iw[threadIdx.x] : 0;
+  if (threadIdx.x == 0) s_bad = take(&h->scan_bad[0]);
+  __syncthreads();
+  if (threadIdx.x < kInfoWords) {
+    // (status is the report's first word)
+    const int32_t v = (threadIdx.x == 0 && s_bad) ? static_cast<int32_t>(HAV_ERR_HIP) : word;
+    if (threadIdx.x == 0 && s_bad) iw[0] = v;
+    if (w.info_dev) reinterpret_cast<int32_t*>(w.info_dev)[threadIdx.x] = v;
   }
 }
 
