@@ -7,10 +7,10 @@
 //   k_bin_count    every block reduces the partial boxes (same bits everywhere),
 //                  derives the stage frame (origin = min corner, search bracket hi0)
 //                  and a 12-bit Morton cell per point; per-block cell histograms
-//   k_bin_scan     exclusive scan of the (cell, block) histogram; starts layer 1
+//   k_bin_scan     exclusive scan of the (cell, block) histogram
 //   k_bin_scatter  counting sort by cell into 16-byte records (r = p - origin, which
 //                  is exactly what Eq. 2 consumes, and the original index), so each
-//                  2048-point tile is spatially compact
+//                  2048-point tile is spatially compact; one more block starts layer 1
 //   per layer (Sec. 3.4, Eq. 3):
 //     k_search     adaptive voxel search (Sec. 3.3), one launch: a queue of (pass,
 //                  tile) tickets. A pass evaluates the voxel counter Cnt at up to
@@ -319,6 +319,15 @@ __host__ __device__ inline int bin_shift(int tcode) {
   return b == 1 ? 11 : (b == 2 ? 13 : 12);
 }
 
+// Chunks of kBinChunk cells one block of the histogram scan owns: the most (up to 8)
+// that leave each thread at most kMaxBinBlocks / 16 binning blocks' counts to hold, so a
+// small cloud's scan is a few blocks rather than kBinChunks nearly idle ones.
+__host__ __device__ inline int scan_group(int64_t nbb) {
+  int g = 1;
+  while (g < 8 && nbb * (2 * g) <= kMaxBinBlocks) g *= 2;
+  return g;
+}
+
 // bshift: log2 of the points of a binning block (a tuning field: the binning
 // workgroup's share of the cloud).
 __host__ __device__ inline int64_t blocks_of(int kind, int64_t n, int bshift = 12) {
@@ -328,7 +337,7 @@ __host__ __device__ inline int64_t blocks_of(int kind, int64_t n, int bshift = 1
       const int64_t bp = int64_t(1) << bshift;
       return n < bp ? 1 : (n + bp - 1) / bp < kMaxBinBlocks ? (n + bp - 1) / bp : kMaxBinBlocks;
     }
-    case kKBScan: return kBinChunks;
+    case kKBScan: return kBinChunks / scan_group(blocks_of(kKBin, n, bshift));
     case kKTile: return (n + kTile - 1) / kTile;
     case kKOne: return 1;
     case kKScat: return blocks_of(kKBin, n, bshift) + 1;
@@ -987,9 +996,10 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
 }
 
 // Offsets of every (block, cell) run of the counting sort. Block c of this kernel owns
-// cells [16c, 16c+16): sixteen threads per cell scan its counts over the binning
-// blocks (a sixteenth of them each), then the block scans its cells' totals; the
-// last block scans the chunk totals and starts layer 1.
+// the ncell = 16 G cells from c ncell on (G = scan_group(nbb)): kThreads / ncell threads
+// per cell scan its counts over the binning blocks (an equal share of them each), then
+// each 16-cell chunk is scanned within a 16-lane segment; the last block scans the
+// chunk totals.
 template <class Src>
 __global__ void __launch_bounds__(kThreads) k_bin_scan(Src src) {
   int bx, gx;
@@ -998,57 +1008,71 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Src src) {
   const Plan& P = cd.P;
   if (P.identity) return;
   if (w.h->frame.status != HAV_OK) return;
-  constexpr int kParts = kThreads / kBinChunk;  // 16
   __shared__ uint32_t s_tmp[kThreads / 64];
-  __shared__ uint32_t s_q[kParts][kBinChunk];
-  __shared__ uint32_t s_tot[kBinChunk];
-  const int lb = threadIdx.x & (kBinChunk - 1);
-  const int bin = bx * kBinChunk + lb;
-  const int q = threadIdx.x / kBinChunk;
-  const int nq = (w.nbb + kParts - 1) / kParts;
+  __shared__ uint32_t s_q[kThreads];
+  __shared__ uint32_t s_tot[kThreads];
+  const int ncell = scan_group(w.nbb) * kBinChunk;
+  const int parts = kThreads / ncell;
+  const int lb = threadIdx.x & (ncell - 1);
+  const int q = threadIdx.x / ncell;
+  const int bin = bx * ncell + lb;
+  const int nq = (w.nbb + parts - 1) / parts;
   const int b0 = q * nq, b1 = min(w.nbb, b0 + nq);
-  // this thread's counts (at most 32: nbb <= kMaxBinBlocks) in registers, one round trip
-  constexpr int kQ = kMaxBinBlocks / kParts;
-  static_assert(kMaxBinBlocks % kParts == 0, "bin blocks per part");
+  // this thread's counts (at most 32: scan_group keeps nbb * G <= kMaxBinBlocks) in
+  // registers, one round trip
+  constexpr int kQ = kMaxBinBlocks / (kThreads / kBinChunk);
   uint32_t v[kQ];
   uint32_t sum = 0;
 #pragma unroll
   for (int j = 0; j < kQ; ++j) v[j] = b0 + j < b1 ? w.bh[static_cast<size_t>(b0 + j) * kBins + bin] : 0u;
 #pragma unroll
   for (int j = 0; j < kQ; ++j) sum += v[j];
-  s_q[q][lb] = sum;
+  s_q[threadIdx.x] = sum;
   __syncthreads();
   uint32_t run = 0;
-  for (int qq = 0; qq < q; ++qq) run += s_q[qq][lb];
-  if (q == kParts - 1) s_tot[lb] = run + sum;
+  for (int qq = 0; qq < q; ++qq) run += s_q[qq * ncell + lb];
+  if (q == parts - 1) s_tot[lb] = run + sum;
 #pragma unroll
   for (int j = 0; j < kQ; ++j) {
     if (b0 + j < b1) w.bh[static_cast<size_t>(b0 + j) * kBins + bin] = run;
     run += v[j];
   }
   __syncthreads();
-  const uint32_t x = threadIdx.x < kBinChunk ? s_tot[threadIdx.x] : 0u;
+  const bool mine = static_cast<int>(threadIdx.x) < ncell;
+  const uint32_t x = mine ? s_tot[threadIdx.x] : 0u;
   // box counting for the search's prior: occupied cells, and occupied groups of 8
   // consecutive cells (the parent cells, each axis halved, when every axis has cell
-  // bits: the lowest three bits of a cell number are one bit of each axis). A block
-  // holds 16 cells, two whole groups; one packed atomic per block.
-  static_assert(kBinChunk == 16, "two parent groups per scan block");
+  // bits: the lowest three bits of a cell number are one bit of each axis). A wave
+  // holds whole groups; one packed atomic per wave.
+  static_assert(kBinChunk % 8 == 0, "whole parent groups per chunk");
   {
-    const uint64_t occ = __ballot(threadIdx.x < kBinChunk && x != 0u);
-    if (threadIdx.x == 0 && occ) {
-      const uint32_t groups = ((occ & 0xFFull) ? 1u : 0u) + ((occ & 0xFF00ull) ? 1u : 0u);
-      atomicAdd(&w.h->acc[3][bx & (kGroups - 1)][0], (groups << 16) | static_cast<uint32_t>(__popcll(occ)));
+    const uint64_t occ = __ballot(mine && x != 0u);
+    if ((threadIdx.x & 63) == 0 && occ) {
+      uint32_t groups = 0;
+#pragma unroll
+      for (int g = 0; g < 8; ++g) groups += ((occ >> (8 * g)) & 0xFFull) ? 1u : 0u;
+      atomicAdd(&w.h->acc[3][(bx * (kThreads / 64) + (threadIdx.x >> 6)) & (kGroups - 1)][0],
+                (groups << 16) | static_cast<uint32_t>(__popcll(occ)));
     }
   }
-  uint32_t ex;
-  const uint32_t chunk_total = block_exclusive_scan<kThreads>(x, &ex, s_tmp);
-  if (threadIdx.x < kBinChunk) w.binpre[bx * kBinChunk + threadIdx.x] = ex;
-  if (threadIdx.x == 0) atomicExch(&w.bsum[bx], chunk_total);
+  // each chunk's inclusive scan within its 16-lane segment
+  const int lc = threadIdx.x & (kBinChunk - 1);
+  uint32_t inc = x;
+#pragma unroll
+  for (int d = 1; d < kBinChunk; d <<= 1) {
+    const uint32_t y = __shfl_up(inc, d, kBinChunk);
+    if (lc >= d) inc += y;
+  }
+  if (mine) {
+    w.binpre[bx * ncell + threadIdx.x] = inc - x;
+    if (lc == kBinChunk - 1) atomicExch(&w.bsum[bx * (ncell / kBinChunk) + (threadIdx.x / kBinChunk)], inc);
+  }
   if (!arrive_last(w.h, bx, gx)) return;
-  const uint32_t y = threadIdx.x < static_cast<int>(gx) ? peek(&w.bsum[threadIdx.x]) : 0u;
+  static_assert(kBinChunks <= kThreads, "one chunk total per thread");
+  const uint32_t y = threadIdx.x < kBinChunks ? peek(&w.bsum[threadIdx.x]) : 0u;
   uint32_t ey;
   block_exclusive_scan<kThreads>(y, &ey, s_tmp);
-  if (threadIdx.x < static_cast<int>(gx)) w.bsum[threadIdx.x] = ey;
+  if (threadIdx.x < kBinChunks) w.bsum[threadIdx.x] = ey;
 }
 
 // The search's prior from the binning's occupancy counts, the controller's reset and
@@ -3920,7 +3944,7 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
     return HAV_OK;
   }
   HAV_LAUNCH(k_bin_count<One>, dim3(w.nbb), dim3(kThreads), 0, st, one);
-  HAV_LAUNCH(k_bin_scan<One>, dim3(kBinChunks), dim3(kThreads), 0, st, one);
+  HAV_LAUNCH(k_bin_scan<One>, dim3(kBinChunks / scan_group(w.nbb)), dim3(kThreads), 0, st, one);
   HAV_LAUNCH(k_bin_scatter<One>, dim3(w.nbb + 1), dim3(kThreads), 0, st, one);
   // a cloud of few tiles splits each tile's candidates over tickets of their own, so that
   // more blocks share a pass (each holds one candidate's LDS tables)
