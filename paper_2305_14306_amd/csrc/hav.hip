@@ -893,8 +893,8 @@ __device__ __forceinline__ CellCoder make_coder(const Frame& fr) {
 // (and to 0 below: a point's r is never negative, a bound of a search range can be).
 // Non-decreasing in r.
 __device__ __forceinline__ uint32_t cell_index(float r, const CellCoder& k, int a) {
-  const float q = r * k.scale[a];
-  return !(q >= 0.0f) ? 0u : (q >= static_cast<float>(k.lim[a]) ? k.lim[a] : static_cast<uint32_t>(q));
+  // (fmaxf takes 0 for a NaN product; the clamped value converts exactly)
+  return static_cast<uint32_t>(fminf(fmaxf(r * k.scale[a], 0.0f), static_cast<float>(k.lim[a])));
 }
 // The cell number of cell indices (cx, cy, cz): their bits interleaved (Morton order).
 // Index bits at or above an axis's bit count are 0 (cell_index clamps) and their position
@@ -913,6 +913,30 @@ __device__ __forceinline__ uint32_t cell_code_of(const uint32_t (&c)[3], const C
 __device__ __forceinline__ uint32_t cell_code_k(float rx, float ry, float rz, const CellCoder& k) {
   const uint32_t c[3] = {cell_index(rx, k, 0), cell_index(ry, k, 1), cell_index(rz, k, 2)};
   return cell_code_of(c, k);
+}
+
+// The same numbering by table lookup, for the binning's per-point loops: per axis, the
+// deposited bits of the low and of the high six bits of a cell index (12 bits at most),
+// so a point costs six LDS reads instead of a deposit of every index bit.
+struct CellLut {
+  uint32_t d[3][2][64];
+};
+// All threads call; the table is complete after the block's next barrier.
+__device__ __forceinline__ void build_lut(CellLut& L, const CellCoder& k) {
+  static_assert(kBinBits <= 12, "two six-bit halves per cell index");
+  for (int e = threadIdx.x; e < 3 * 2 * 64; e += kThreads) {
+    const int a = e >> 7, hf = (e >> 6) & 1, v = e & 63;
+    uint32_t code = 0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) code |= ((v >> j) & 1u) << ((k.pos[a] >> (4 * (6 * hf + j))) & 15u);
+    L.d[a][hf][v] = code;
+  }
+}
+__device__ __forceinline__ uint32_t cell_code_lut(float rx, float ry, float rz, const CellCoder& k,
+                                                  const CellLut& L) {
+  const uint32_t cx = cell_index(rx, k, 0), cy = cell_index(ry, k, 1), cz = cell_index(rz, k, 2);
+  return L.d[0][0][cx & 63u] | L.d[0][1][cx >> 6] | L.d[1][0][cy & 63u] | L.d[1][1][cy >> 6] |
+         L.d[2][0][cz & 63u] | L.d[2][1][cz >> 6];
 }
 
 
@@ -974,20 +998,22 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
   };
   load(beg);
   Frame f;
-  const int st = frame_from_partials(w, P, &f, 0);
+  const int st = frame_from_partials(w, P, &f, 0);  // (the same frame in every thread)
   if (threadIdx.x == 0) fr = f;
   for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0;
+  const CellCoder kc = make_coder(f);
+  __shared__ CellLut lut;
+  build_lut(lut, kc);
   __syncthreads();
   publish_frame(w, fr, bx);
   if (st != HAV_OK) return;
-  const CellCoder kc = make_coder(fr);
-  const float m0 = fr.mn[0], m1 = fr.mn[1], m2 = fr.mn[2];
+  const float m0 = f.mn[0], m1 = f.mn[1], m2 = f.mn[2];
   for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
     if (i0 != beg) load(i0);
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
       const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
-      if (i < end) atomicAdd(&hist[cell_code_k(px[k] - m0, py[k] - m1, pz[k] - m2, kc)], 1u);
+      if (i < end) atomicAdd(&hist[cell_code_lut(px[k] - m0, py[k] - m1, pz[k] - m2, kc, lut)], 1u);
     }
   }
   __syncthreads();
@@ -1171,6 +1197,9 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
   }
   __syncthreads();
   const CellCoder kc = make_coder(fr);
+  __shared__ CellLut lut;
+  build_lut(lut, kc);
+  __syncthreads();
   const float m0 = fr.mn[0], m1 = fr.mn[1], m2 = fr.mn[2];
   for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
     if (i0 != beg) load(i0);
@@ -1181,7 +1210,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
       const float rx = px[k] - m0;
       const float ry = py[k] - m1;
       const float rz = pz[k] - m2;
-      const uint32_t pos = atomicAdd(&off[cell_code_k(rx, ry, rz, kc)], 1u);
+      const uint32_t pos = atomicAdd(&off[cell_code_lut(rx, ry, rz, kc, lut)], 1u);
       if (pos < w.n) {
         const int64_t S = slot_of(pos);
         w.pts[S] = make_float4(rx, ry, rz, __int_as_float(static_cast<int32_t>(i)));
