@@ -693,16 +693,29 @@ __global__ void __launch_bounds__(kThreads) k_bbox(Src src) {
   uint32_t hi[3] = {0u, 0u, 0u};
   uint32_t bad = 0;
   const int64_t n = w.n;
-  for (int64_t i = bx * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gx) * kThreads) {
+  // a contiguous share of the cloud per block, eight points per thread per round with
+  // their loads in flight together; an index past the share reads its last point again
+  // (no effect on a min, a max or an or), so every load and its use are unconditional
+  constexpr int kBB = 8;
+  const int64_t chunk = (n + gx - 1) / gx;
+  const int64_t beg = bx * chunk, end = min(n, beg + chunk);
+  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBB) * kThreads) {
+    float c[kBB][3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float c = xyz[3 * i + a];
-      bad |= !isfinite(c);
-      const uint32_t o = float_to_ordered(c);
-      lo[a] = min(lo[a], o);
-      hi[a] = max(hi[a], o);
+    for (int k = 0; k < kBB; ++k) {
+      const int64_t i = min(end - 1, i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) c[k][a] = xyz[3 * i + a];
     }
+#pragma unroll
+    for (int k = 0; k < kBB; ++k)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        bad |= !isfinite(c[k][a]);
+        const uint32_t o = float_to_ordered(c[k][a]);
+        lo[a] = min(lo[a], o);
+        hi[a] = max(hi[a], o);
+      }
   }
   // tags cleared 16 at a time (both arrays start 256-byte aligned; tag_o's region is
   // padded to a multiple of 256 bytes, tag_s holds whole tiles)
@@ -1009,7 +1022,11 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
   if (st != HAV_OK) return;
   const float m0 = f.mn[0], m1 = f.mn[1], m2 = f.mn[2];
   for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
-    if (i0 != beg) load(i0);
+    // (every earlier load has landed: the compiler need not wait before each new one)
+    if (i0 != beg) {
+      __builtin_amdgcn_s_waitcnt(0);
+      load(i0);
+    }
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
       const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
@@ -1202,7 +1219,11 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
   __syncthreads();
   const float m0 = fr.mn[0], m1 = fr.mn[1], m2 = fr.mn[2];
   for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
-    if (i0 != beg) load(i0);
+    // (every earlier load has landed: the compiler need not wait before each new one)
+    if (i0 != beg) {
+      __builtin_amdgcn_s_waitcnt(0);
+      load(i0);
+    }
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
       const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
