@@ -371,6 +371,18 @@ struct Many {
   BatchDev* bd;
 };
 
+// Threads of a counting block (k_bin_count): a single cloud's 4,096-point blocks run at
+// 512 (two waves per SIMD at one block per CU); the batched path keeps 256, which
+// measured faster there, where several small blocks share a CU.
+template <class Src>
+struct CountThreads {
+  static constexpr int value = kThreads;
+};
+template <>
+struct CountThreads<One> {
+  static constexpr int value = 2 * kThreads;
+};
+
 // The block's cloud (by reference: fields are loaded where they are used) and its
 // block index and grid size within that cloud's share of the launch.
 __device__ __forceinline__ const Cloud& cloud_of(const One& s, int, int& b, int& nb) {
@@ -605,7 +617,7 @@ __device__ void layer_init_ctrl(Header* h, const Plan& P, int L);
 // the block, the controller is thread 0's. (The layer's first search pass was planned
 // when the call started: first_plans.)
 __device__ void layer_init(Header* h, const Plan& P, int L) {
-  for (int i = threadIdx.x; i < 2 * kMaxCand * kGroups; i += kThreads)
+  for (int i = threadIdx.x; i < 2 * kMaxCand * kGroups; i += blockDim.x)
     h->sacc[i / (kMaxCand * kGroups)][(i / kGroups) % kMaxCand][i % kGroups][0] = 0;
   if (threadIdx.x < kGroups) h->sq_dgrp[threadIdx.x][0] = 0;
   if (threadIdx.x == 0) layer_init_ctrl(h, P, L);
@@ -638,7 +650,7 @@ __device__ void first_plans(Header* h, const Plan& P, const Frame& frame_in) {
     plan_search(s0, P, fl, P.m[L], P.upper[L]);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < P.nlayers * kPubWords; i += kThreads)
+  for (int i = threadIdx.x; i < P.nlayers * kPubWords; i += blockDim.x)
     h->pub_first[i / kPubWords][i % kPubWords] =
         reinterpret_cast<const uint32_t*>(&s_pl[i / kPubWords])[i % kPubWords];
 }
@@ -760,17 +772,18 @@ __global__ void __launch_bounds__(kThreads) k_bbox(Src src) {
 // Reduce the k_bbox partials and derive the stage frame. Every block of the calling
 // kernel does this itself and gets the same bits; only block 0 publishes them.
 // Returns the status.
+template <int NT>
 __device__ int frame_from_partials(const Ws& w, const Plan& P, Frame* fr, int identity) {
-  __shared__ uint32_t s_v[7][kThreads / 64];
+  __shared__ uint32_t s_v[7][NT / 64];
   uint32_t v[7] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u, 0u};
   const uint64_t magic = w.h->magic;  // in flight with the partials
-  // every thread's partials (at most four: nbbox <= kMaxBBoxBlocks) in one round trip
-  static_assert(kMaxBBoxBlocks <= 4 * kThreads, "bbox partials per thread");
+  // every thread's partials (nbbox <= kMaxBBoxBlocks) in one round trip
+  constexpr int kJ = (kMaxBBoxBlocks + NT - 1) / NT;
   const uint4* p4 = reinterpret_cast<const uint4*>(w.part);
-  uint4 pa[4], pb[4];
+  uint4 pa[kJ], pb[kJ];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int b = threadIdx.x + j * kThreads;
+  for (int j = 0; j < kJ; ++j) {
+    const int b = threadIdx.x + j * NT;
     if (b < w.nbbox) {
       pa[j] = p4[2 * b];
       pb[j] = p4[2 * b + 1];
@@ -780,7 +793,7 @@ __device__ int frame_from_partials(const Ws& w, const Plan& P, Frame* fr, int id
     }
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < kJ; ++j) {
     v[0] = min(v[0], pa[j].x);
     v[1] = min(v[1], pa[j].y);
     v[2] = min(v[2], pa[j].z);
@@ -803,7 +816,7 @@ __device__ int frame_from_partials(const Ws& w, const Plan& P, Frame* fr, int id
   __syncthreads();
   for (int k = 0; k < 7; ++k) {
     uint32_t x = s_v[k][0];
-    for (int q = 1; q < kThreads / 64; ++q)
+    for (int q = 1; q < NT / 64; ++q)
       x = (k < 3) ? min(x, s_v[k][q]) : ((k < 6) ? max(x, s_v[k][q]) : (x | s_v[k][q]));
     v[k] = x;
   }
@@ -937,7 +950,7 @@ struct CellLut {
 // All threads call; the table is complete after the block's next barrier.
 __device__ __forceinline__ void build_lut(CellLut& L, const CellCoder& k) {
   static_assert(kBinBits <= 12, "two six-bit halves per cell index");
-  for (int e = threadIdx.x; e < 3 * 2 * 64; e += kThreads) {
+  for (int e = threadIdx.x; e < 3 * 2 * 64; e += blockDim.x) {
     const int a = e >> 7, hf = (e >> 6) & 1, v = e & 63;
     uint32_t code = 0;
 #pragma unroll
@@ -964,7 +977,7 @@ __global__ void __launch_bounds__(kThreads) k_identity(Src src) {
   hav_info_t* info_dev = w.info_dev;
   __shared__ Frame fr;
   Frame f;
-  const int st = frame_from_partials(w, P, &f, 1);
+  const int st = frame_from_partials<kThreads>(w, P, &f, 1);
   if (threadIdx.x == 0) fr = f;
   __syncthreads();
   if (bx == 0 && threadIdx.x == 0) {
@@ -983,7 +996,8 @@ __global__ void __launch_bounds__(kThreads) k_identity(Src src) {
 // ----------------------------------------------------------------------------- binning
 
 template <class Src>
-__global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
+__global__ void __launch_bounds__(CountThreads<Src>::value) k_bin_count(Src src) {
+  constexpr int kCountThreads = CountThreads<Src>::value;
   int bx, gx;
   const Cloud& cd = cloud_of(src, kKBin, bx, gx);
   const Ws& w = cd.w;
@@ -994,14 +1008,14 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
   __shared__ uint32_t hist[kBins];
   const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
   const int64_t beg = bx * chunk, end = min(w.n, beg + chunk);
-  // 16 points per thread per round, all loads in flight together; the first round's
+  // 4,096 points per block and round, all loads in flight together; the first round's
   // loads are issued before the frame's partials, so the two round trips overlap
-  constexpr int kBP = 16;
+  constexpr int kBP = 4096 / kCountThreads;
   float px[kBP], py[kBP], pz[kBP];
   auto load = [&](int64_t i0) {
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
-      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
+      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kCountThreads;
       if (i < end) {
         px[k] = xyz[3 * i];
         py[k] = xyz[3 * i + 1];
@@ -1011,9 +1025,9 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
   };
   load(beg);
   Frame f;
-  const int st = frame_from_partials(w, P, &f, 0);  // (the same frame in every thread)
+  const int st = frame_from_partials<kCountThreads>(w, P, &f, 0);  // (the same frame in every thread)
   if (threadIdx.x == 0) fr = f;
-  for (int i = threadIdx.x; i < kBins; i += kThreads) hist[i] = 0;
+  for (int i = threadIdx.x; i < kBins; i += kCountThreads) hist[i] = 0;
   const CellCoder kc = make_coder(f);
   __shared__ CellLut lut;
   build_lut(lut, kc);
@@ -1021,7 +1035,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
   publish_frame(w, fr, bx);
   if (st != HAV_OK) return;
   const float m0 = f.mn[0], m1 = f.mn[1], m2 = f.mn[2];
-  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
+  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kCountThreads) {
     // (every earlier load has landed: the compiler need not wait before each new one)
     if (i0 != beg) {
       __builtin_amdgcn_s_waitcnt(0);
@@ -1029,12 +1043,12 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Src src) {
     }
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
-      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
+      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kCountThreads;
       if (i < end) atomicAdd(&hist[cell_code_lut(px[k] - m0, py[k] - m1, pz[k] - m2, kc, lut)], 1u);
     }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < kBins; b += kThreads)
+  for (int b = threadIdx.x; b < kBins; b += kCountThreads)
     w.bh[static_cast<size_t>(bx) * kBins + b] = hist[b];
 }
 
@@ -4004,7 +4018,7 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
     HAV_LAUNCH(k_identity<One>, dim3(w.nscan), dim3(kThreads), 0, st, one);
     return HAV_OK;
   }
-  HAV_LAUNCH(k_bin_count<One>, dim3(w.nbb), dim3(kThreads), 0, st, one);
+  HAV_LAUNCH(k_bin_count<One>, dim3(w.nbb), dim3(CountThreads<One>::value), 0, st, one);
   HAV_LAUNCH(k_bin_scan<One>, dim3(kBinChunks / scan_group(w.nbb)), dim3(kThreads), 0, st, one);
   HAV_LAUNCH(k_bin_scatter<One>, dim3(w.nbb + 1), dim3(kThreads), 0, st, one);
   // a cloud of few tiles splits each tile's candidates over tickets of their own, so that
@@ -4166,7 +4180,7 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
   HAV_LAUNCH(k_bbox<Many>, dim3(T[kKBBox]), dim3(kThreads), 0, st, many);
   if (any_identity) HAV_LAUNCH(k_identity<Many>, dim3(T[kKScan]), dim3(kThreads), 0, st, many);
   if (!any_work) return HAV_OK;
-  HAV_LAUNCH(k_bin_count<Many>, dim3(T[kKBin]), dim3(kThreads), 0, st, many);
+  HAV_LAUNCH(k_bin_count<Many>, dim3(T[kKBin]), dim3(CountThreads<Many>::value), 0, st, many);
   HAV_LAUNCH(k_bin_scan<Many>, dim3(T[kKBScan]), dim3(kThreads), 0, st, many);
   HAV_LAUNCH(k_bin_scatter<Many>, dim3(T[kKScat]), dim3(kThreads), 0, st, many);
   const int sgrid = search_grid(T[kKTile], q.depth, true, p->search_blocks);
