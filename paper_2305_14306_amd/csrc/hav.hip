@@ -1189,8 +1189,11 @@ __device__ void start_search(const Ws& w, const Plan& P) {
   first_plans(w.h, P, s_fr);
 }
 
-template <class Src>
-__global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
+// NT: 512 for a single cloud of at most 256 binning blocks (one per CU), else 256 (at
+// two or more blocks per CU, and in a batch, 512-thread blocks measured slower).
+template <class Src, int NT>
+__global__ void __launch_bounds__(NT) k_bin_scatter(Src src) {
+  constexpr int kScatThreads = NT;
   int bx, gx;
   const Cloud& cd = cloud_of(src, kKScat, bx, gx);
   const Ws& w = cd.w;
@@ -1216,12 +1219,12 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
   }
   const int64_t chunk = (w.n + w.nbb - 1) / w.nbb;
   const int64_t beg = cb * chunk, end = min(w.n, beg + chunk);
-  constexpr int kBP = 16;
+  constexpr int kBP = 4096 / kScatThreads;  // points per thread per round
   float px[kBP], py[kBP], pz[kBP];
   auto load = [&](int64_t i0) {
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
-      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
+      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kScatThreads;
       if (i < end) {
         px[k] = xyz[3 * i];
         py[k] = xyz[3 * i + 1];
@@ -1231,10 +1234,10 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
   };
   load(beg);  // (in flight with the frame and the offsets)
   if (threadIdx.x == 0) fr = w.h->frame;
-  static_assert(kBins % kThreads == 0, "cells per thread");
+  static_assert(kBins % kScatThreads == 0, "cells per thread");
 #pragma unroll
-  for (int j = 0; j < kBins / kThreads; ++j) {
-    const int b = threadIdx.x + j * kThreads;
+  for (int j = 0; j < kBins / kScatThreads; ++j) {
+    const int b = threadIdx.x + j * kScatThreads;
     off[b] = w.bh[static_cast<size_t>(cb) * kBins + b] + w.binpre[b] + w.bsum[b / kBinChunk];
   }
   __syncthreads();
@@ -1243,7 +1246,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
   build_lut(lut, kc);
   __syncthreads();
   const float m0 = fr.mn[0], m1 = fr.mn[1], m2 = fr.mn[2];
-  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kThreads) {
+  for (int64_t i0 = beg; i0 < end; i0 += static_cast<int64_t>(kBP) * kScatThreads) {
     // (every earlier load has landed: the compiler need not wait before each new one)
     if (i0 != beg) {
       __builtin_amdgcn_s_waitcnt(0);
@@ -1251,7 +1254,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Src src) {
     }
 #pragma unroll
     for (int k = 0; k < kBP; ++k) {
-      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kThreads;
+      const int64_t i = i0 + threadIdx.x + static_cast<int64_t>(k) * kScatThreads;
       if (i >= end) continue;
       const float rx = px[k] - m0;
       const float ry = py[k] - m1;
@@ -4020,7 +4023,10 @@ hav_status_t run_stage(const float* xyz, int64_t N, int64_t M, const hav_params_
   }
   HAV_LAUNCH(k_bin_count<One>, dim3(w.nbb), dim3(CountThreads<One>::value), 0, st, one);
   HAV_LAUNCH(k_bin_scan<One>, dim3(kBinChunks / scan_group(w.nbb)), dim3(kThreads), 0, st, one);
-  HAV_LAUNCH(k_bin_scatter<One>, dim3(w.nbb + 1), dim3(kThreads), 0, st, one);
+  if (w.nbb <= 256)
+    HAV_LAUNCH((k_bin_scatter<One, 2 * kThreads>), dim3(w.nbb + 1), dim3(2 * kThreads), 0, st, one);
+  else
+    HAV_LAUNCH((k_bin_scatter<One, kThreads>), dim3(w.nbb + 1), dim3(kThreads), 0, st, one);
   // a cloud of few tiles splits each tile's candidates over tickets of their own, so that
   // more blocks share a pass (each holds one candidate's LDS tables)
   const int split = w.ntile * P.depth <= kSplitTickets ? P.depth : 1;
@@ -4182,7 +4188,7 @@ hav_status_t run_batch(const CloudSpec* specs, int32_t B, const hav_params_t* p,
   if (!any_work) return HAV_OK;
   HAV_LAUNCH(k_bin_count<Many>, dim3(T[kKBin]), dim3(CountThreads<Many>::value), 0, st, many);
   HAV_LAUNCH(k_bin_scan<Many>, dim3(T[kKBScan]), dim3(kThreads), 0, st, many);
-  HAV_LAUNCH(k_bin_scatter<Many>, dim3(T[kKScat]), dim3(kThreads), 0, st, many);
+  HAV_LAUNCH((k_bin_scatter<Many, kThreads>), dim3(T[kKScat]), dim3(kThreads), 0, st, many);
   const int sgrid = search_grid(T[kKTile], q.depth, true, p->search_blocks);
   const size_t eval_lds = 2 * static_cast<size_t>(q.depth) * kBrickCap * sizeof(uint64_t);
   const size_t sel_lds = 2 * static_cast<size_t>(kLdsCap) * sizeof(uint64_t);
@@ -4337,8 +4343,10 @@ hav_status_t hav_sample_points(const float* xyz, int64_t N, int64_t M, const hav
 }  // extern "C"
 
 namespace {
-// A kept launch name ("k_select<One>") matches the plain kernel name.
+// A kept launch name ("k_select<One>", or "(k_bin_scatter<One, 2 * kThreads>)" where the
+// template arguments hold a comma) matches the plain kernel name.
 bool same_kernel(const char* kept, const char* name) {
+  if (kept[0] == '(') ++kept;
   size_t i = 0;
   for (; name[i] && kept[i] == name[i]; ++i) {
   }
