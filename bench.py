@@ -548,6 +548,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batched leg")
+    ap.add_argument("--no-batch-tune", action="store_true",
+                    help="batched leg without the autotuner and the graph replay (for profiling)")
     ap.add_argument("--spec-depth", type=int, default=0,
                     help="tuning: voxel sizes per search pass (0 = library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
@@ -654,7 +656,7 @@ def main() -> int:
         "roofline": roofline,
     }
     if not args.no_batch:
-        result["batch"] = batch_leg(torch, hav, synth, max(3, min(args.steps, 10)))
+        result["batch"] = batch_leg(torch, hav, synth, max(3, min(args.steps, 10)), tune=not args.no_batch_tune)
         print(f"bench: batch {result['batch']}", file=sys.stderr, flush=True)
     if not args.no_serve:
         result["serve"] = serve_leg(torch, hav, synth, args.serve_requests,

@@ -51,7 +51,14 @@ def source_digest() -> str:
 def short_name(name: str) -> str:
     m = re.search(r"\b(k_\w+)\s*[<(]", name)
     if m:
-        return m.group(1)
+        # the batched path's instantiations (template argument Many) are named apart
+        rest, tmpl, depth = name[m.end(1):].lstrip(), "", 0
+        for ch in rest if rest.startswith("<") else "":
+            depth += (ch == "<") - (ch == ">")
+            tmpl += ch
+            if depth == 0:
+                break
+        return m.group(1) + (" (batch)" if re.search(r"\bMany\b", tmpl) else "")
     if "neg_kernel" in name:
         return "calib_neg (torch elementwise)"
     if "FillFunctor" in name:
